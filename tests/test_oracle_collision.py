@@ -1,0 +1,205 @@
+"""Pins of the oracle's collision (CPU only).
+
+* the whole D2Q9 fluid / thermal collision against the paper's hand-expanded
+  App. A / App. B algorithm;
+* the generic attractor recurrence against the attractor lists the paper
+  prints for D2Q9 (Eq. D2Q9attractors, Eq. MvT2D, Eq. MvT2DoptionB), D3Q27
+  (Sec. 5.2 list, with the printed kappa_122 term kappa~011 kappa~012 read as
+  kappa~110 kappa~012 as in the continuous list of Eq.
+  continouous-Markovian-CM-3D) and D3Q15 (Eq. g-attractorsD3Q15optionA; the
+  printed eta_012 attractor lacks the factor c^_s^2 that its continuous
+  counterpart carries);
+* collision invariants: mass, momentum + F, temperature;
+* the rest state as a fixed point;
+* with every rate 1 and no force, the closed-form product equilibrium.
+"""
+
+import pytest
+import torch
+
+from oracle import lattices as L
+from oracle.collision import fluid_collide, recurrence, rest_weights, thermal_collide
+from tests import paper_appendix_2d as A
+
+DT = torch.float64
+
+
+def _rand_state(lat, n, seed, amp=0.05, rho0=1.0):
+    g = torch.Generator().manual_seed(seed)
+    w = rest_weights(lat, thermal=False)
+    pert = (torch.rand(n, lat.Q, generator=g, dtype=DT) - 0.5) * 2 * amp
+    return rho0 * w[None, :] * (1.0 + pert)
+
+
+def _rand_rates(q, seed, lo=0.6, hi=1.9):
+    g = torch.Generator().manual_seed(seed)
+    return [float(x) for x in lo + (hi - lo) * torch.rand(q, generator=g, dtype=DT)]
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_fluid_collision_matches_appendix_A(seed):
+    f = _rand_state(L.D2Q9, 64, seed)
+    g = torch.Generator().manual_seed(100 + seed)
+    F = (torch.rand(64, 2, generator=g, dtype=DT) - 0.5) * 1e-2
+    w = _rand_rates(9, seed)
+    ft, rho, u = fluid_collide(f, F, L.D2Q9, w)
+    fa, rho_a, ux, uy = A.fluid_collide_appA([f[:, a] for a in range(9)], F[:, 0], F[:, 1], w)
+    fa = torch.stack(fa, 1)
+    assert torch.allclose(ft, fa, atol=2e-15, rtol=0)
+    assert torch.allclose(u[:, 0], ux, atol=1e-16, rtol=0)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_thermal_collision_matches_appendix_B(seed):
+    gen = torch.Generator().manual_seed(seed)
+    T = (torch.rand(64, generator=gen, dtype=DT) - 0.5)
+    w9 = rest_weights(L.D2Q9_T, thermal=True)
+    g9 = T[:, None] * w9[None, :] + 0.01 * (torch.rand(64, 9, generator=gen, dtype=DT) - 0.5)
+    u = (torch.rand(64, 2, generator=gen, dtype=DT) - 0.5) * 0.2
+    w = _rand_rates(9, 10 + seed)
+    gt, _ = thermal_collide(g9, u, L.D2Q9_T, w, 1.0 / 3.0)
+    ga, _ = A.thermal_collide_appB([g9[:, a] for a in range(9)], u[:, 0], u[:, 1], w)
+    assert torch.allclose(gt, torch.stack(ga, 1), atol=2e-15, rtol=0)
+
+
+def _lower_random(keys, seed):
+    g = torch.Generator().manual_seed(seed)
+    return {k: torch.rand(8, generator=g, dtype=DT) - 0.3 for k in keys}
+
+
+def test_recurrence_reproduces_2d_lists():
+    P = _lower_random([(0, 0), (1, 0), (0, 1), (2, 0), (0, 2), (1, 1)], 3)
+    rho, T = P[(0, 0)], P[(0, 0)]
+    # fluid (Eq. D2Q9attractors): D' = P2 / rho above second order, first order zero
+    D = [[P[(2, 0)] / rho, P[(1, 1)] / rho], [P[(1, 1)] / rho, P[(0, 2)] / rho]]
+    low = lambda m: rho if sum(m) == 0 else (0.0 * rho if sum(m) == 1 else P[m])
+    k22 = recurrence((2, 2), D, low)
+    assert torch.allclose(k22, (P[(2, 0)] * P[(0, 2)] + 2 * P[(1, 1)] ** 2) / rho, atol=1e-15)
+    assert torch.allclose(recurrence((2, 1), D, low), 0 * rho)
+    # thermal option A (Eq. MvT2D)
+    c = 0.3
+    iso = [[c, 0.0], [0.0, c]]
+    lowT = lambda m: T if sum(m) == 0 else P[m]
+    assert torch.allclose(recurrence((2, 1), iso, lowT), 2 / 3 * c * P[(0, 1)], atol=1e-15)
+    assert torch.allclose(recurrence((1, 2), iso, lowT), 2 / 3 * c * P[(1, 0)], atol=1e-15)
+    assert torch.allclose(recurrence((2, 2), iso, lowT), 0.5 * c * (P[(2, 0)] + P[(0, 2)]), atol=1e-15)
+    assert torch.allclose(recurrence((2, 0), iso, lowT), c * T, atol=1e-15)
+    # thermal option B (Eq. MvT2DoptionB)
+    DB = [[P[(2, 0)] / T, P[(1, 1)] / T], [P[(1, 1)] / T, P[(0, 2)] / T]]
+    assert torch.allclose(recurrence((2, 1), DB, lowT),
+                          2 / (3 * T) * (P[(2, 0)] * P[(0, 1)] + 2 * P[(1, 1)] * P[(1, 0)]), atol=1e-14)
+    assert torch.allclose(recurrence((1, 2), DB, lowT),
+                          2 / (3 * T) * (P[(0, 2)] * P[(1, 0)] + 2 * P[(1, 1)] * P[(0, 1)]), atol=1e-14)
+    assert torch.allclose(recurrence((2, 2), DB, lowT),
+                          (P[(2, 0)] * P[(0, 2)] + 2 * P[(1, 1)] ** 2) / T, atol=1e-14)
+
+
+def test_recurrence_reproduces_d3q27_list():
+    keys = [m for m in L.D3Q27.M if sum(m) in (2, 3, 4)] + [(0, 0, 0)]
+    K = _lower_random(keys, 5)
+    rho = K[(0, 0, 0)]
+
+    def k(a, b, c):
+        return K[(a, b, c)]
+
+    D = [[k(2, 0, 0), k(1, 1, 0), k(1, 0, 1)], [k(1, 1, 0), k(0, 2, 0), k(0, 1, 1)], [k(1, 0, 1), k(0, 1, 1), k(0, 0, 2)]]
+    D = [[x / rho for x in row] for row in D]
+    low = lambda m: rho if sum(m) == 0 else (0.0 * rho if sum(m) == 1 else K[m])
+    listed = {
+        (2, 2, 0): (k(2, 0, 0) * k(0, 2, 0) + 2 * k(1, 1, 0) ** 2) / rho,
+        (2, 0, 2): (k(2, 0, 0) * k(0, 0, 2) + 2 * k(1, 0, 1) ** 2) / rho,
+        (0, 2, 2): (k(0, 2, 0) * k(0, 0, 2) + 2 * k(0, 1, 1) ** 2) / rho,
+        (2, 1, 1): (k(2, 0, 0) * k(0, 1, 1) + 2 * k(1, 1, 0) * k(1, 0, 1)) / rho,
+        (1, 2, 1): (k(0, 2, 0) * k(1, 0, 1) + 2 * k(1, 1, 0) * k(0, 1, 1)) / rho,
+        (1, 1, 2): (k(0, 0, 2) * k(1, 1, 0) + 2 * k(0, 1, 1) * k(1, 0, 1)) / rho,
+        (1, 2, 2): 2 / (5 * rho) * (k(0, 2, 0) * k(1, 0, 2) + k(0, 0, 2) * k(1, 2, 0) + 4 * k(0, 1, 1) * k(1, 1, 1)
+                                    + 2 * (k(1, 0, 1) * k(0, 2, 1) + k(1, 1, 0) * k(0, 1, 2))),
+        (2, 1, 2): 2 / (5 * rho) * (k(2, 0, 0) * k(0, 1, 2) + k(0, 0, 2) * k(2, 1, 0) + 4 * k(1, 0, 1) * k(1, 1, 1)
+                                    + 2 * (k(1, 1, 0) * k(1, 0, 2) + k(0, 1, 1) * k(2, 0, 1))),
+        (2, 2, 1): 2 / (5 * rho) * (k(2, 0, 0) * k(0, 2, 1) + k(0, 2, 0) * k(2, 0, 1) + 4 * k(1, 1, 0) * k(1, 1, 1)
+                                    + 2 * (k(0, 1, 1) * k(2, 1, 0) + k(1, 0, 1) * k(1, 2, 0))),
+        (2, 2, 2): 1 / (3 * rho) * (k(2, 0, 0) * k(0, 2, 2) + k(0, 2, 0) * k(2, 0, 2) + k(0, 0, 2) * k(2, 2, 0)
+                                    + 4 * (k(1, 1, 0) * k(1, 1, 2) + k(1, 0, 1) * k(1, 2, 1) + k(0, 1, 1) * k(2, 1, 1))),
+    }
+    for m, v in listed.items():
+        assert torch.allclose(recurrence(m, D, low), v, atol=1e-14), m
+    for m in L.D3Q27.M:
+        if sum(m) == 3:
+            assert torch.allclose(recurrence(m, D, low), 0 * rho), m
+    # second order with D' = c_s^2 I: c_s^2 rho on the diagonal, zero off it
+    iso = [[1 / 3 if i == j else 0.0 for j in range(3)] for i in range(3)]
+    assert torch.allclose(recurrence((2, 0, 0), iso, low), rho / 3)
+    assert torch.allclose(recurrence((1, 1, 0), iso, low), 0 * rho)
+
+
+def test_recurrence_reproduces_d3q15_thermal_list():
+    keys = [m for m in L.D3Q15_T.M if sum(m) in (1, 2)] + [(0, 0, 0)]
+    K = _lower_random(keys, 9)
+    T = K[(0, 0, 0)]
+    c = 1 / 3
+    iso = [[c if i == j else 0.0 for j in range(3)] for i in range(3)]
+    low = lambda m: T if sum(m) == 0 else K[m]
+    assert torch.allclose(recurrence((1, 2, 0), iso, low), 2 / 3 * c * K[(1, 0, 0)])
+    assert torch.allclose(recurrence((0, 1, 2), iso, low), 2 / 3 * c * K[(0, 1, 0)])
+    assert torch.allclose(recurrence((2, 0, 1), iso, low), 2 / 3 * c * K[(0, 0, 1)])
+    assert torch.allclose(recurrence((1, 1, 1), iso, low), 0 * T)
+    assert torch.allclose(recurrence((2, 2, 0), iso, low), 0.5 * c * (K[(2, 0, 0)] + K[(0, 2, 0)]))
+
+
+@pytest.mark.parametrize("lat", [L.D2Q9, L.D3Q27])
+def test_fluid_invariants(lat):
+    """Sum f~ = sum f; sum f~ e = sum f e + F (kappa~_1 = F/2 for any rate)."""
+    f = _rand_state(lat, 40, 21)
+    g = torch.Generator().manual_seed(22)
+    F = (torch.rand(40, lat.d, generator=g, dtype=DT) - 0.5) * 1e-2
+    w = _rand_rates(lat.Q, 23)
+    ft, rho, u = fluid_collide(f, F, lat, w)
+    assert torch.allclose(ft.sum(1), f.sum(1), atol=1e-14, rtol=0)
+    assert torch.allclose(ft @ lat.E, f @ lat.E + F, atol=1e-14, rtol=0)
+
+
+@pytest.mark.parametrize("lat,c2", [(L.D2Q5, 1 / 3), (L.D3Q7, 0.25), (L.D2Q9_T, 1 / 3), (L.D3Q15_T, 1 / 3)])
+def test_thermal_invariant(lat, c2):
+    g = torch.Generator().manual_seed(31)
+    gp = torch.rand(40, lat.Q, generator=g, dtype=DT) - 0.3
+    u = (torch.rand(40, lat.d, generator=g, dtype=DT) - 0.5) * 0.2
+    gt, T = thermal_collide(gp, u, lat, _rand_rates(lat.Q, 32), c2)
+    assert torch.allclose(gt.sum(1), gp.sum(1), atol=1e-14, rtol=0)
+
+
+@pytest.mark.parametrize("lat", [L.D2Q9, L.D3Q27])
+def test_rest_state_fixed_point(lat):
+    w = rest_weights(lat)
+    f = 1.3 * w[None, :].repeat(3, 1)
+    ft, _, u = fluid_collide(f, torch.zeros(3, lat.d, dtype=DT), lat, _rand_rates(lat.Q, 41))
+    assert torch.allclose(ft, f, atol=1e-15, rtol=0)
+
+
+def _phi(e, u, cs2=1 / 3):
+    """1D factor of the product equilibrium: phi(0) = 1 - c^2 - u^2, phi(+-1) = (c^2 + u^2 +- u)/2."""
+    return torch.where(torch.as_tensor(e == 0), 1 - cs2 - u * u, 0.5 * (cs2 + u * u + e * u))
+
+
+@pytest.mark.parametrize("lat", [L.D2Q9, L.D3Q27])
+def test_unit_rates_give_product_equilibrium(lat):
+    f = _rand_state(lat, 30, 51, amp=0.2)
+    ft, rho, u = fluid_collide(f, torch.zeros(30, lat.d, dtype=DT), lat, [1.0] * lat.Q)
+    for a, e in enumerate(lat.vectors):
+        expect = rho.clone()
+        for i in range(lat.d):
+            expect = expect * _phi(float(e[i]), u[:, i])
+        assert torch.allclose(ft[:, a], expect, atol=1e-15, rtol=0), a
+
+
+@pytest.mark.parametrize("lat,c2", [(L.D2Q5, 1 / 3), (L.D3Q7, 0.25)])
+def test_unit_rates_give_advection_diffusion_equilibrium(lat, c2):
+    """Thermal D2Q5/D3Q7 with all rates 1: g_0 = T(1 - d c^2 - |u|^2), g_+-i = T(c^2 + u_i^2 +- u_i)/2."""
+    g = torch.Generator().manual_seed(61)
+    gp = torch.rand(30, lat.Q, generator=g, dtype=DT)
+    u = (torch.rand(30, lat.d, generator=g, dtype=DT) - 0.5) * 0.3
+    gt, T = thermal_collide(gp, u, lat, [1.0] * lat.Q, c2)
+    assert torch.allclose(gt[:, 0], T * (1 - lat.d * c2 - (u * u).sum(1)), atol=1e-15)
+    for a in range(1, lat.Q):
+        i = [j for j in range(lat.d) if lat.vectors[a][j] != 0][0]
+        s = lat.vectors[a][i]
+        assert torch.allclose(gt[:, a], T * (c2 + u[:, i] ** 2 + s * u[:, i]) / 2, atol=1e-15)
