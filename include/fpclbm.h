@@ -1,0 +1,211 @@
+/*
+ * fpclbm.h - C ABI of the MI355X (gfx950) implementation of the Fokker-Planck
+ * central-moment double-distribution lattice Boltzmann method for thermal
+ * convection (Schupbach & Premnath, arXiv 2504.09041).
+ *
+ * One time step n advances every lattice node by the fused update
+ *   pull-stream with wall rules  (Eq. LBMsteps-stream / LBMsteps-streamg, Sec. 6.1)
+ *   -> macros rho, u, T and the Boussinesq force   (App. A Step 7, Sec. 6.1)
+ *   -> fluid collision: central moments, relaxation toward the Fokker-Planck
+ *      attractors with renormalised diffusion tensor above second order and
+ *      body-force sources                          (Sec. 4.1-4.2, 5.1-5.2, App. A)
+ *   -> thermal collision with option-A attractors   (Sec. 4.3-4.4, 5.3, App. B/C)
+ *   -> store the post-collision populations.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Every function returns an int status: FPC_OK (0) or a negative FPC_ERR_*
+ *   code.  Nothing throws across the ABI.  After an error, fpc_last_error()
+ *   returns a message (thread-local, valid until the next call on that thread).
+ * - Arguments are validated on the host before any launch; a call that fails
+ *   validation has no side effect.
+ * - "device pointer" means memory on the GPU the simulation runs on
+ *   (e.g. a torch CUDA tensor's data_ptr); "host pointer" means CPU memory.
+ * - Grid: node (i, j, k), x fastest; nz = 1 in 2D.  N = nx * ny * nz.
+ *   Walls lie halfway between the outermost node and its missing neighbour.
+ * - Faces are indexed -x, +x, -y, +y, -z, +z (FPC_FACE_*).
+ * - All calls that launch work are asynchronous on the simulation's stream,
+ *   except those documented as synchronising.
+ * - The caller owns the two state buffers and the stream; the library owns
+ *   only small scratch buffers (reductions) freed by fpc_destroy.
+ */
+#ifndef FPCLBM_H
+#define FPCLBM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+#define FPC_OK 0
+#define FPC_ERR_ARG (-1)      /* invalid argument (null pointer, bad enum, rate outside (0,2), ...) */
+#define FPC_ERR_SIZE (-2)     /* sizes out of range or inconsistent */
+#define FPC_ERR_HIP (-3)      /* a HIP runtime call failed; message in fpc_last_error() */
+#define FPC_ERR_UNSTABLE (-4) /* diagnostics found NaN/Inf or |u| above the watchdog limit */
+#define FPC_ERR_STATE (-5)    /* the call does not fit the simulation's configuration */
+
+/* Lattice pairs (fluid + thermal). */
+#define FPC_D2Q9_D2Q5 1  /* D2Q9 fluid (Eqs. ex, ey) + D2Q5 thermal (axis subset of D2Q9) */
+#define FPC_D3Q27_D3Q7 2 /* D3Q27 fluid (Sec. 5.2) + D3Q7 thermal (axis subset of D3Q27) */
+
+/* Storage precision of the populations. */
+#define FPC_FP64 0     /* populations f, g stored and collided in FP64 */
+#define FPC_FP32_DEV 1 /* FP32 deviations f - w rho0 and g - w^T T0, collided in FP32 */
+
+/* Face kinds (fluid rule + thermal rule). */
+#define FPC_BC_PERIODIC 0          /* must be set on both faces of an axis */
+#define FPC_BC_NOSLIP_ADIABATIC 1  /* halfway bounce-back for f and g */
+#define FPC_BC_NOSLIP_DIRICHLET 2  /* bounce-back for f, anti-bounce-back for g at wall_T */
+#define FPC_BC_LID_ADIABATIC 3     /* moving-wall bounce-back (lid_u) for f, bounce-back for g */
+#define FPC_BC_LID_DIRICHLET 4     /* moving-wall bounce-back for f, anti-bounce-back for g */
+
+#define FPC_FACE_XM 0
+#define FPC_FACE_XP 1
+#define FPC_FACE_YM 2
+#define FPC_FACE_YP 3
+#define FPC_FACE_ZM 4
+#define FPC_FACE_ZP 5
+
+/*
+ * Simulation parameters.  Fill with fpc_params_default(), then one of the
+ * fpc_params_natural() / fpc_params_mixed() helpers or by hand.
+ *
+ * omega_f: fluid rates, one per central moment in the paper's order, with the
+ *   diagonal second-order slots holding the rates of their combinations:
+ *   2D (App. A Step 3): w0..w8 <-> (00, 10, 01, 20+02, 20-02, 11, 21, 12, 22).
+ *   3D: (000, 100, 010, 001, 110, 101, 011, 200+020+002, 200-020, 200-002,
+ *        120, 102, 210, 012, 201, 021, 111, 220, 202, 022, 211, 121, 112,
+ *        122, 212, 221, 222)  (moment order of Sec. 5.2).
+ *   Slot 0 has no effect (mass is conserved).
+ * omega_g: thermal rates.  D2Q5 (App. B Step 3): (00, 10, 01, 20+02, 20-02);
+ *   D3Q7 (App. C Step 3): (000, 100, 010, 001, 200, 020, 002).
+ * Every rate in use must lie in (0, 2).
+ */
+typedef struct fpc_params {
+  int lattice;   /* FPC_D2Q9_D2Q5 or FPC_D3Q27_D3Q7 */
+  int precision; /* FPC_FP64 or FPC_FP32_DEV */
+  int nx, ny, nz;
+  double omega_f[27];
+  double omega_g[7];
+  double cs2_T;  /* thermal diffusion parameter c^_s^2 (option A); default 1/3 (D2Q5), 1/4 (D3Q7) */
+  double g_beta; /* buoyancy per unit temperature: F = g_beta (T - T0) along up_axis */
+  double T0;     /* Boussinesq reference temperature; also the FP32-deviation offset of g */
+  double rho0;   /* reference density: initial density, moving-wall density, FP32-deviation offset of f */
+  double dT_ref; /* temperature difference used to scale the Nusselt number */
+  int up_axis;   /* 0, 1, 2: axis along which buoyancy acts (y in 2D, z in 3D typically) */
+  int bc[6];     /* FPC_BC_* per face */
+  double wall_T[6];   /* Dirichlet wall temperature per face (uniform) */
+  double lid_u[6][3]; /* wall velocity per face (lid faces only; must be tangential) */
+  /* Optional per-node Dirichlet temperature on a face (device pointer, FP64, or NULL).
+   * Layout: the face's two tangential axes, slower first (e.g. -y face in 3D: [z][x];
+   * in 2D a -y face profile has nx values).  Read on every step, so it can be changed
+   * between steps; the library never frees it. */
+  const double* wall_T_profile[6];
+} fpc_params;
+
+typedef struct fpc_sim fpc_sim;
+
+/* Library version (major*10000 + minor*100 + patch). */
+int fpc_version(void);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char* fpc_last_error(void);
+
+/* Zero *p, set lattice/precision/sizes, every rate to 1, cs2_T to the lattice
+ * default, rho0 = 1, dT_ref = 1, T0 = 0, up_axis = 1 (2D) or 2 (3D), all faces
+ * periodic.  Fails with FPC_ERR_ARG / FPC_ERR_SIZE on a bad lattice or size. */
+int fpc_params_default(fpc_params* p, int lattice, int precision, int nx, int ny, int nz);
+
+/*
+ * Natural convection (Sec. 6.1): from Ra = g beta dT L^3 / (nu alpha), Pr = nu / alpha
+ * and the force scale U0^2 / L = g beta dT, sets nu = U0 L sqrt(Pr / Ra),
+ * alpha = nu / Pr, g_beta = U0^2 / (L dT), the shear rates from
+ * nu = c_s^2 (1/w - 1/2) (Eq. transportcoeff2DFPCLBM, c_s^2 = 1/3) and the
+ * first-order thermal rates from alpha = c^_s^2 (1/w - 1/2)
+ * (Eq. thermaltransportcoeff2DFPCLBM).  Every other rate is set to 1.
+ * L = number of nodes along L_axis; dT = T_hot - T_cold (stored in dT_ref);
+ * T0 = (T_hot + T_cold) / 2.  Leaves bc/wall_T/lid_u untouched.
+ */
+int fpc_params_natural(fpc_params* p, double Ra, double Pr, double U0, int L_axis, double T_hot,
+                       double T_cold);
+
+/* Mixed convection (Sec. 7): nu = U L / Re, alpha = U L / Pe, g_beta = Ri U^2 / (L dT),
+ * rates as in fpc_params_natural. */
+int fpc_params_mixed(fpc_params* p, double Re, double Ri, double Pe, double U_lid, int L_axis,
+                     double T_hot, double T_cold);
+
+/* Bytes each of the two state buffers must hold, and the element stride
+ * between population planes (elements, not bytes).  State layout: plane q
+ * (fluid planes 0..Qf-1, then thermal planes) holds N values [z][y][x] of
+ * FP64 (FPC_FP64) or FP32 (FPC_FP32_DEV), starting at q * plane_stride. */
+int fpc_state_bytes(const fpc_params* p, size_t* bytes_per_buffer, size_t* plane_stride);
+
+/*
+ * Create a simulation that borrows two device buffers of at least
+ * fpc_state_bytes() bytes each (256-byte aligned) and a hipStream_t (may be
+ * NULL for the null stream).  Parameters are copied and validated.  Allocates
+ * only small reduction scratch.  *out is set on success.
+ */
+int fpc_create(const fpc_params* p, void* bufA, void* bufB, void* hip_stream, fpc_sim** out);
+
+/* Free the library-owned scratch and the handle (not the caller's buffers). */
+int fpc_destroy(fpc_sim* s);
+
+/* Change the stream later calls launch on. */
+int fpc_set_stream(fpc_sim* s, void* hip_stream);
+
+/*
+ * Initial state: pre-collision f = w rho0, g = w^T T_init(x) (fluid at rest),
+ * then one collision at every node (force from T_init), stored as S_0.
+ * T_init: device pointer to N FP64 values [z][y][x].  Resets the step counter.
+ */
+int fpc_init(fpc_sim* s, const double* T_init);
+
+/* Advance nsteps >= 0 time steps (fused pull-stream-collide), asynchronously. */
+int fpc_step(fpc_sim* s, int nsteps);
+
+/* Steps taken since the last fpc_init / fpc_load. */
+int fpc_get_step(const fpc_sim* s, long long* step);
+
+/*
+ * Macros of the current time level n (from the stored post-collision state:
+ * rho = sum f, T = sum g, rho u = sum f e - F/2, equal to the pre-collision
+ * values by conservation).  Device pointers to N FP64 values each, u holds
+ * d planes [x-comp][N], [y-comp][N] (, [z-comp][N]).  Any pointer may be NULL.
+ */
+int fpc_macros(fpc_sim* s, double* rho, double* u, double* T);
+
+/*
+ * FP64 diagnostics of the current time level, reduced on the GPU with a fixed
+ * (deterministic) order.  Synchronises the stream.  Host outputs (any may be NULL):
+ *   nu_mean: mean wall Nusselt number on face `wall_face` (Sec. 6.1):
+ *            dT/dn = -8/3 T_w + 3 T(1/2) - 1/3 T(3/2) along the inward normal,
+ *            Nu = -(L / dT_ref) dT/dn, L = nodes along the face normal
+ *            (pass wall_face = -1 to skip);
+ *   ke:      1/2 sum rho |u|^2;   sumT: sum T;   umax: max |u|.
+ * Returns FPC_ERR_UNSTABLE (outputs still written) if any macro is NaN/Inf or
+ * umax exceeds 0.5.
+ */
+int fpc_diagnostics(fpc_sim* s, int wall_face, double* nu_mean, double* ke, double* sumT, double* umax);
+
+/* Copy the current state (fpc_state_bytes() bytes, storage format) to / from
+ * device memory.  fpc_load resets the step counter to `step`. */
+int fpc_save(const fpc_sim* s, void* dst);
+int fpc_load(fpc_sim* s, const void* src, long long step);
+
+/* Current state as full FP64 populations (f = w rho0 + stored deviation in
+ * FP32_DEV mode): (Qf + Qg) planes of N values, contiguous, no padding. */
+int fpc_export_fp64(const fpc_sim* s, double* dst);
+/* Replace the current state from full FP64 populations in the same layout. */
+int fpc_import_fp64(fpc_sim* s, const double* src, long long step);
+
+/* Device pointer of the buffer that holds the current state. */
+int fpc_current_buffer(const fpc_sim* s, void** ptr);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FPCLBM_H */

@@ -108,11 +108,12 @@ def _profile_value(face_idx, prof, coords):
     return p[idx]
 
 
-def pull(S, lat, prm: Params, thermal: bool, wall_T=None):
-    """Pull-stream one distribution with the wall rules; S is (Q, nz, ny, nx)."""
+def pull_at(get, lat, prm: Params, thermal: bool, coords, wall_T=None):
+    """Incoming populations at the nodes ``coords`` = (x, y, z) (integer tensors
+    of one shape), read through ``get(a, z, y, x)`` which returns the stored
+    post-collision population a at those nodes.  Returns (Q,) + coords shape."""
     nx, ny, nz = prm.shape
     n = (nx, ny, nz)
-    coords = _coords(prm.shape)
     w = rest_weights(lat, thermal=thermal, cs2=prm.cs2T if thermal else prm.cs2)
     out = []
     for a in range(lat.Q):
@@ -128,12 +129,12 @@ def pull(S, lat, prm: Params, thermal: bool, wall_T=None):
                 crossed.append((2 * k + 1, s >= n[k]))
                 s = s.clamp(0, n[k] - 1)
             src.append(s)
-        val = S[a][src[2], src[1], src[0]]
+        val = get(a, src[2], src[1], src[0])
         if not crossed:
             out.append(val)
             continue
         ncross = sum(m.to(torch.int64) for _, m in crossed)
-        bb = S[lat.opp[a]]
+        bb = get(lat.opp[a], coords[2], coords[1], coords[0])
         if not thermal:
             wall_val = bb
             for fi, m in crossed:
@@ -158,6 +159,20 @@ def pull(S, lat, prm: Params, thermal: bool, wall_T=None):
             wall_val = torch.where(ndir > 0, -bb + 2.0 * w[a] * tw_mean, bb)
         out.append(torch.where(ncross > 0, wall_val, val))
     return torch.stack(out, 0)
+
+
+def pull(S, lat, prm: Params, thermal: bool, wall_T=None):
+    """Pull-stream one distribution with the wall rules; S is (Q, nz, ny, nx)."""
+    return pull_at(lambda a, z, y, x: S[a][z, y, x], lat, prm, thermal, _coords(prm.shape), wall_T)
+
+
+def step_at(prm: Params, get_f, get_g, coords, wall_T=None):
+    """The time step evaluated only at the nodes ``coords``: (f~, g~, macros),
+    each with the shape of ``coords`` after the population axis."""
+    lf, lg = prm.lattices
+    fp = pull_at(get_f, lf, prm, False, coords)
+    gp = pull_at(get_g, lg, prm, True, coords, wall_T)
+    return collide(prm, fp, gp)
 
 
 def _force(prm: Params, T):

@@ -1,0 +1,447 @@
+// C-ABI implementation (see include/fpclbm.h for the contract of each call).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "../../include/fpclbm.h"
+#include "fpc_kernels.h"
+
+using namespace fpc;
+
+struct fpc_sim {
+  fpc_params p;
+  void* buf[2];
+  int cur;  // index of the buffer holding the current state
+  hipStream_t stream;
+  long long step;
+  size_t plane;
+  size_t bytes;
+  int Qf, Qg, dim;
+  double* scratch;  // reduction partials, then 8 doubles of results
+  size_t scratch_elems;
+  double* result_host;  // pinned, 8 doubles
+  int device;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char msg[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(msg, sizeof msg, fmt, ap);
+  va_end(ap);
+  g_err = msg;
+  return code;
+}
+
+int hipfail(hipError_t e, const char* what) {
+  return fail(FPC_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+int lattice_dims(int lattice, int* Qf, int* Qg, int* dim) {
+  if (lattice == FPC_D2Q9_D2Q5) {
+    *Qf = 9; *Qg = 5; *dim = 2;
+    return FPC_OK;
+  }
+  if (lattice == FPC_D3Q27_D3Q7) {
+    *Qf = 27; *Qg = 7; *dim = 3;
+    return FPC_OK;
+  }
+  return fail(FPC_ERR_ARG, "unknown lattice %d", lattice);
+}
+
+size_t elem_size(int precision) { return precision == FPC_FP64 ? 8 : 4; }
+
+// Element stride between planes: N rounded up to 64 elements (256 B in FP32).
+size_t plane_of(const fpc_params* p) {
+  const size_t N = (size_t)p->nx * p->ny * p->nz;
+  return (N + 63) / 64 * 64;
+}
+
+bool rate_ok(double w) { return std::isfinite(w) && w > 0.0 && w < 2.0; }
+
+int validate(const fpc_params* p) {
+  if (!p) return fail(FPC_ERR_ARG, "params is NULL");
+  int Qf, Qg, dim;
+  int rc = lattice_dims(p->lattice, &Qf, &Qg, &dim);
+  if (rc) return rc;
+  if (p->precision != FPC_FP64 && p->precision != FPC_FP32_DEV)
+    return fail(FPC_ERR_ARG, "unknown precision %d", p->precision);
+  if (p->nx <= 0 || p->ny <= 0 || p->nz <= 0) return fail(FPC_ERR_SIZE, "grid sizes must be positive");
+  if (dim == 2 && p->nz != 1) return fail(FPC_ERR_SIZE, "2D lattice needs nz == 1");
+  const double N = (double)p->nx * p->ny * p->nz;
+  if (N * (Qf + Qg) > 4.0e10) return fail(FPC_ERR_SIZE, "grid too large");
+  if (p->nx > (1 << 24) || p->ny > (1 << 24) || p->nz > 65535) return fail(FPC_ERR_SIZE, "axis too long");
+  for (int k = 1; k < Qf; ++k)
+    if (!rate_ok(p->omega_f[k])) return fail(FPC_ERR_ARG, "omega_f[%d] = %g outside (0, 2)", k, p->omega_f[k]);
+  for (int k = 1; k < Qg; ++k)
+    if (!rate_ok(p->omega_g[k])) return fail(FPC_ERR_ARG, "omega_g[%d] = %g outside (0, 2)", k, p->omega_g[k]);
+  if (!(p->cs2_T > 0.0 && p->cs2_T <= 1.0 / dim)) return fail(FPC_ERR_ARG, "cs2_T must lie in (0, 1/%d]", dim);
+  if (!(p->rho0 > 0.0) || !std::isfinite(p->rho0)) return fail(FPC_ERR_ARG, "rho0 must be positive");
+  if (!std::isfinite(p->g_beta) || !std::isfinite(p->T0)) return fail(FPC_ERR_ARG, "g_beta / T0 not finite");
+  if (!(p->dT_ref != 0.0) || !std::isfinite(p->dT_ref)) return fail(FPC_ERR_ARG, "dT_ref must be non-zero");
+  if (p->up_axis < 0 || p->up_axis >= dim) return fail(FPC_ERR_ARG, "up_axis %d invalid", p->up_axis);
+  for (int f = 0; f < 6; ++f) {
+    if (p->bc[f] < FPC_BC_PERIODIC || p->bc[f] > FPC_BC_LID_DIRICHLET) return fail(FPC_ERR_ARG, "bc[%d] invalid", f);
+    if (dim == 2 && f >= 4 && p->bc[f] != FPC_BC_PERIODIC) return fail(FPC_ERR_ARG, "2D z faces must be periodic");
+    const int k = f >> 1;
+    if ((p->bc[f] == FPC_BC_PERIODIC) != (p->bc[f ^ 1] == FPC_BC_PERIODIC))
+      return fail(FPC_ERR_ARG, "axis %d: periodic on one face only", k);
+    if (p->bc[f] == FPC_BC_LID_ADIABATIC || p->bc[f] == FPC_BC_LID_DIRICHLET) {
+      if (p->lid_u[f][k] != 0.0) return fail(FPC_ERR_ARG, "lid velocity of face %d is not tangential", f);
+      for (int i = 0; i < 3; ++i)
+        if (!std::isfinite(p->lid_u[f][i])) return fail(FPC_ERR_ARG, "lid velocity not finite");
+      if (dim == 2 && p->lid_u[f][2] != 0.0) return fail(FPC_ERR_ARG, "2D lid velocity has a z component");
+    }
+    if (!std::isfinite(p->wall_T[f])) return fail(FPC_ERR_ARG, "wall_T[%d] not finite", f);
+    if (p->bc[f] != FPC_BC_PERIODIC) {
+      const int n[3] = {p->nx, p->ny, p->nz};
+      if (n[k] < 2) return fail(FPC_ERR_SIZE, "a walled axis needs at least 2 nodes");
+    }
+  }
+  return FPC_OK;
+}
+
+template <class R>
+StepArgs<R> make_args(const fpc_sim* s, const void* src, void* dst) {
+  StepArgs<R> a;
+  std::memset(&a, 0, sizeof a);
+  const fpc_params& p = s->p;
+  a.src = static_cast<const R*>(src);
+  a.dst = static_cast<R*>(dst);
+  a.nx = p.nx;
+  a.ny = p.ny;
+  a.nz = p.nz;
+  for (int k = 0; k < 3; ++k) a.per[k] = p.bc[2 * k] == FPC_BC_PERIODIC;
+  a.plane = s->plane;
+  for (int k = 0; k < 27; ++k) a.c.om[k] = (R)p.omega_f[k];
+  for (int k = 0; k < 7; ++k) a.c.omg[k] = (R)p.omega_g[k];
+  a.c.cs2T = (R)p.cs2_T;
+  a.c.gbeta = (R)p.g_beta;
+  a.c.T0 = (R)p.T0;
+  const bool dev = p.precision == FPC_FP32_DEV;
+  a.c.rho_r = dev ? (R)p.rho0 : R(0);
+  a.c.T_r = dev ? (R)p.T0 : R(0);
+  a.rho_w = (R)p.rho0;
+  for (int f = 0; f < 6; ++f) {
+    const int bc = p.bc[f];
+    a.face[f].wall = bc != FPC_BC_PERIODIC;
+    a.face[f].lid = bc == FPC_BC_LID_ADIABATIC || bc == FPC_BC_LID_DIRICHLET;
+    a.face[f].dirichlet = bc == FPC_BC_NOSLIP_DIRICHLET || bc == FPC_BC_LID_DIRICHLET;
+    a.face[f].Tw = p.wall_T[f];
+    a.face[f].Tprof = p.wall_T_profile[f];
+    for (int i = 0; i < 3; ++i) a.face[f].uw[i] = p.lid_u[f][i];
+  }
+  return a;
+}
+
+int launch_update(fpc_sim* s, const void* src, void* dst, const double* T_init, int mode) {
+  hipError_t e;
+  const int up = s->p.up_axis;
+  if (s->p.precision == FPC_FP64) {
+    const StepArgs<double> a = make_args<double>(s, src, dst);
+    e = s->dim == 2 ? launch_step2d<double>(a, up, T_init, mode, s->stream)
+                    : launch_step3d<double>(a, up, T_init, mode, s->stream);
+  } else {
+    const StepArgs<float> a = make_args<float>(s, src, dst);
+    e = s->dim == 2 ? launch_step2d<float>(a, up, T_init, mode, s->stream)
+                    : launch_step3d<float>(a, up, T_init, mode, s->stream);
+  }
+  if (e != hipSuccess) return hipfail(e, "kernel launch");
+  return FPC_OK;
+}
+
+StateDesc desc_of(const fpc_sim* s) {
+  StateDesc d;
+  const fpc_params& p = s->p;
+  d.src = s->buf[s->cur];
+  d.precision = p.precision;
+  d.lattice = p.lattice;
+  d.nx = p.nx;
+  d.ny = p.ny;
+  d.nz = p.nz;
+  d.plane = s->plane;
+  const bool dev = p.precision == FPC_FP32_DEV;
+  d.rho_r = dev ? p.rho0 : 0.0;
+  d.T_r = dev ? p.T0 : 0.0;
+  d.cs2T = p.cs2_T;
+  d.gbeta = p.g_beta;
+  d.T0 = p.T0;
+  d.up = p.up_axis;
+  return d;
+}
+
+bool aligned256(const void* ptr) { return (reinterpret_cast<uintptr_t>(ptr) & 255u) == 0; }
+
+double rate_from(double D, double c2) { return 1.0 / (D / c2 + 0.5); }
+
+void set_rates(fpc_params* p, double nu, double alpha) {
+  const double wn = rate_from(nu, 1.0 / 3.0);
+  const double wa = rate_from(alpha, p->cs2_T);
+  for (int k = 0; k < 27; ++k) p->omega_f[k] = 1.0;
+  for (int k = 0; k < 7; ++k) p->omega_g[k] = 1.0;
+  if (p->lattice == FPC_D2Q9_D2Q5) {
+    p->omega_f[4] = wn;  // 20 - 02
+    p->omega_f[5] = wn;  // 11
+    p->omega_g[1] = p->omega_g[2] = wa;
+  } else {
+    const int shear[5] = {4, 5, 6, 8, 9};  // off-diagonals and the two deviators
+    for (int k : shear) p->omega_f[k] = wn;
+    p->omega_g[1] = p->omega_g[2] = p->omega_g[3] = wa;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int fpc_version(void) { return 10000; }
+
+const char* fpc_last_error(void) { return g_err.c_str(); }
+
+int fpc_params_default(fpc_params* p, int lattice, int precision, int nx, int ny, int nz) {
+  if (!p) return fail(FPC_ERR_ARG, "params is NULL");
+  int Qf, Qg, dim;
+  int rc = lattice_dims(lattice, &Qf, &Qg, &dim);
+  if (rc) return rc;
+  if (precision != FPC_FP64 && precision != FPC_FP32_DEV) return fail(FPC_ERR_ARG, "unknown precision %d", precision);
+  if (nx <= 0 || ny <= 0 || nz <= 0 || (dim == 2 && nz != 1)) return fail(FPC_ERR_SIZE, "bad grid size");
+  std::memset(p, 0, sizeof *p);
+  p->lattice = lattice;
+  p->precision = precision;
+  p->nx = nx;
+  p->ny = ny;
+  p->nz = nz;
+  for (int k = 0; k < 27; ++k) p->omega_f[k] = 1.0;
+  for (int k = 0; k < 7; ++k) p->omega_g[k] = 1.0;
+  p->cs2_T = dim == 2 ? 1.0 / 3.0 : 0.25;
+  p->rho0 = 1.0;
+  p->dT_ref = 1.0;
+  p->up_axis = dim == 2 ? 1 : 2;
+  for (int f = 0; f < 6; ++f) p->bc[f] = FPC_BC_PERIODIC;
+  return FPC_OK;
+}
+
+int fpc_params_natural(fpc_params* p, double Ra, double Pr, double U0, int L_axis, double T_hot, double T_cold) {
+  if (!p) return fail(FPC_ERR_ARG, "params is NULL");
+  int Qf, Qg, dim;
+  int rc = lattice_dims(p->lattice, &Qf, &Qg, &dim);
+  if (rc) return rc;
+  if (!(Ra > 0 && Pr > 0 && U0 > 0) || L_axis < 0 || L_axis >= dim || !(T_hot != T_cold))
+    return fail(FPC_ERR_ARG, "natural convection: need Ra, Pr, U0 > 0, valid L_axis, T_hot != T_cold");
+  const int n[3] = {p->nx, p->ny, p->nz};
+  const double L = n[L_axis];
+  const double dT = T_hot - T_cold;
+  const double nu = U0 * L * std::sqrt(Pr / Ra);
+  const double alpha = nu / Pr;
+  set_rates(p, nu, alpha);
+  p->g_beta = U0 * U0 / (L * dT);
+  p->T0 = 0.5 * (T_hot + T_cold);
+  p->dT_ref = dT;
+  return FPC_OK;
+}
+
+int fpc_params_mixed(fpc_params* p, double Re, double Ri, double Pe, double U_lid, int L_axis, double T_hot,
+                     double T_cold) {
+  if (!p) return fail(FPC_ERR_ARG, "params is NULL");
+  int Qf, Qg, dim;
+  int rc = lattice_dims(p->lattice, &Qf, &Qg, &dim);
+  if (rc) return rc;
+  if (!(Re > 0 && Pe > 0 && U_lid > 0 && Ri >= 0) || L_axis < 0 || L_axis >= dim || !(T_hot != T_cold))
+    return fail(FPC_ERR_ARG, "mixed convection: need Re, Pe, U_lid > 0, Ri >= 0, valid L_axis, T_hot != T_cold");
+  const int n[3] = {p->nx, p->ny, p->nz};
+  const double L = n[L_axis];
+  const double dT = T_hot - T_cold;
+  set_rates(p, U_lid * L / Re, U_lid * L / Pe);
+  p->g_beta = Ri * U_lid * U_lid / (L * dT);
+  p->T0 = 0.5 * (T_hot + T_cold);
+  p->dT_ref = dT;
+  return FPC_OK;
+}
+
+int fpc_state_bytes(const fpc_params* p, size_t* bytes_per_buffer, size_t* plane_stride) {
+  int rc = validate(p);
+  if (rc) return rc;
+  int Qf, Qg, dim;
+  lattice_dims(p->lattice, &Qf, &Qg, &dim);
+  const size_t plane = plane_of(p);
+  if (bytes_per_buffer) *bytes_per_buffer = plane * (Qf + Qg) * elem_size(p->precision);
+  if (plane_stride) *plane_stride = plane;
+  return FPC_OK;
+}
+
+int fpc_create(const fpc_params* p, void* bufA, void* bufB, void* hip_stream, fpc_sim** out) {
+  if (!out) return fail(FPC_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  int rc = validate(p);
+  if (rc) return rc;
+  if (!bufA || !bufB || bufA == bufB) return fail(FPC_ERR_ARG, "need two distinct state buffers");
+  if (!aligned256(bufA) || !aligned256(bufB)) return fail(FPC_ERR_ARG, "state buffers must be 256-byte aligned");
+  fpc_sim* s = new (std::nothrow) fpc_sim;
+  if (!s) return fail(FPC_ERR_ARG, "out of host memory");
+  std::memset(s, 0, sizeof *s);
+  s->p = *p;
+  s->buf[0] = bufA;
+  s->buf[1] = bufB;
+  s->cur = 0;
+  s->stream = static_cast<hipStream_t>(hip_stream);
+  lattice_dims(p->lattice, &s->Qf, &s->Qg, &s->dim);
+  s->plane = plane_of(p);
+  s->bytes = s->plane * (s->Qf + s->Qg) * elem_size(p->precision);
+  hipError_t e = hipGetDevice(&s->device);
+  if (e != hipSuccess) {
+    delete s;
+    return hipfail(e, "hipGetDevice");
+  }
+  s->scratch_elems = diag_partials_needed(desc_of(s)) + 8;
+  e = hipMalloc(&s->scratch, s->scratch_elems * sizeof(double));
+  if (e != hipSuccess) {
+    delete s;
+    return hipfail(e, "hipMalloc(scratch)");
+  }
+  e = hipHostMalloc(&s->result_host, 8 * sizeof(double), hipHostMallocDefault);
+  if (e != hipSuccess) {
+    hipFree(s->scratch);
+    delete s;
+    return hipfail(e, "hipHostMalloc(result)");
+  }
+  *out = s;
+  return FPC_OK;
+}
+
+int fpc_destroy(fpc_sim* s) {
+  if (!s) return fail(FPC_ERR_ARG, "sim is NULL");
+  hipError_t e1 = hipStreamSynchronize(s->stream);
+  hipError_t e2 = hipFree(s->scratch);
+  hipError_t e3 = hipHostFree(s->result_host);
+  delete s;
+  if (e1 != hipSuccess) return hipfail(e1, "hipStreamSynchronize");
+  if (e2 != hipSuccess) return hipfail(e2, "hipFree");
+  if (e3 != hipSuccess) return hipfail(e3, "hipHostFree");
+  return FPC_OK;
+}
+
+int fpc_set_stream(fpc_sim* s, void* hip_stream) {
+  if (!s) return fail(FPC_ERR_ARG, "sim is NULL");
+  s->stream = static_cast<hipStream_t>(hip_stream);
+  return FPC_OK;
+}
+
+int fpc_init(fpc_sim* s, const double* T_init) {
+  if (!s) return fail(FPC_ERR_ARG, "sim is NULL");
+  if (!T_init) return fail(FPC_ERR_ARG, "T_init is NULL");
+  int rc = launch_update(s, nullptr, s->buf[s->cur], T_init, 1);
+  if (rc) return rc;
+  s->step = 0;
+  return FPC_OK;
+}
+
+int fpc_step(fpc_sim* s, int nsteps) {
+  if (!s) return fail(FPC_ERR_ARG, "sim is NULL");
+  if (nsteps < 0) return fail(FPC_ERR_ARG, "nsteps < 0");
+  for (int i = 0; i < nsteps; ++i) {
+    int rc = launch_update(s, s->buf[s->cur], s->buf[s->cur ^ 1], nullptr, 0);
+    if (rc) return rc;
+    s->cur ^= 1;
+    ++s->step;
+  }
+  return FPC_OK;
+}
+
+int fpc_get_step(const fpc_sim* s, long long* step) {
+  if (!s || !step) return fail(FPC_ERR_ARG, "NULL argument");
+  *step = s->step;
+  return FPC_OK;
+}
+
+int fpc_macros(fpc_sim* s, double* rho, double* u, double* T) {
+  if (!s) return fail(FPC_ERR_ARG, "sim is NULL");
+  if (!rho && !u && !T) return FPC_OK;
+  hipError_t e = launch_macros(desc_of(s), rho, u, T, s->stream);
+  if (e != hipSuccess) return hipfail(e, "macros kernel");
+  return FPC_OK;
+}
+
+int fpc_diagnostics(fpc_sim* s, int wall_face, double* nu_mean, double* ke, double* sumT, double* umax) {
+  if (!s) return fail(FPC_ERR_ARG, "sim is NULL");
+  if (wall_face < -1 || wall_face > 5) return fail(FPC_ERR_ARG, "wall_face %d invalid", wall_face);
+  if (wall_face >= 0 && s->p.bc[wall_face] == FPC_BC_PERIODIC)
+    return fail(FPC_ERR_STATE, "face %d is periodic: no wall Nusselt number", wall_face);
+  if (wall_face >= 4 && s->dim == 2) return fail(FPC_ERR_STATE, "2D has no z faces");
+  FaceDev fd;
+  std::memset(&fd, 0, sizeof fd);
+  if (wall_face >= 0) {
+    fd.Tw = s->p.wall_T[wall_face];
+    fd.Tprof = s->p.wall_T_profile[wall_face];
+  }
+  double* out = s->scratch + (s->scratch_elems - 8);
+  hipError_t e = launch_diagnostics(desc_of(s), wall_face, fd, s->p.dT_ref, s->scratch, out, s->stream);
+  if (e != hipSuccess) return hipfail(e, "diagnostics kernels");
+  e = hipMemcpyAsync(s->result_host, out, 5 * sizeof(double), hipMemcpyDeviceToHost, s->stream);
+  if (e != hipSuccess) return hipfail(e, "hipMemcpyAsync");
+  e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) return hipfail(e, "hipStreamSynchronize");
+  const double* r = s->result_host;
+  if (nu_mean) {
+    if (wall_face >= 0) {
+      const int k = wall_face >> 1;
+      const int n[3] = {s->p.nx, s->p.ny, s->p.nz};
+      const double m = (double)n[(k + 1) % 3] * n[(k + 2) % 3];
+      *nu_mean = r[0] / m;
+    } else {
+      *nu_mean = 0.0;
+    }
+  }
+  if (ke) *ke = r[1];
+  if (sumT) *sumT = r[2];
+  if (umax) *umax = r[3];
+  if (r[4] != 0.0 || !std::isfinite(r[3]) || r[3] > 0.5)
+    return fail(FPC_ERR_UNSTABLE, "unstable: %g non-finite nodes, max|u| = %g", r[4], r[3]);
+  return FPC_OK;
+}
+
+int fpc_save(const fpc_sim* s, void* dst) {
+  if (!s || !dst) return fail(FPC_ERR_ARG, "NULL argument");
+  hipError_t e = hipMemcpyAsync(dst, s->buf[s->cur], s->bytes, hipMemcpyDeviceToDevice, s->stream);
+  if (e != hipSuccess) return hipfail(e, "hipMemcpyAsync");
+  return FPC_OK;
+}
+
+int fpc_load(fpc_sim* s, const void* src, long long step) {
+  if (!s || !src) return fail(FPC_ERR_ARG, "NULL argument");
+  hipError_t e = hipMemcpyAsync(s->buf[s->cur], src, s->bytes, hipMemcpyDeviceToDevice, s->stream);
+  if (e != hipSuccess) return hipfail(e, "hipMemcpyAsync");
+  s->step = step;
+  return FPC_OK;
+}
+
+int fpc_export_fp64(const fpc_sim* s, double* dst) {
+  if (!s || !dst) return fail(FPC_ERR_ARG, "NULL argument");
+  hipError_t e = launch_export(desc_of(s), dst, s->stream);
+  if (e != hipSuccess) return hipfail(e, "export kernel");
+  return FPC_OK;
+}
+
+int fpc_import_fp64(fpc_sim* s, const double* src, long long step) {
+  if (!s || !src) return fail(FPC_ERR_ARG, "NULL argument");
+  hipError_t e = launch_import(desc_of(s), s->buf[s->cur], src, s->stream);
+  if (e != hipSuccess) return hipfail(e, "import kernel");
+  s->step = step;
+  return FPC_OK;
+}
+
+int fpc_current_buffer(const fpc_sim* s, void** ptr) {
+  if (!s || !ptr) return fail(FPC_ERR_ARG, "NULL argument");
+  *ptr = s->buf[s->cur];
+  return FPC_OK;
+}
+
+}  // extern "C"

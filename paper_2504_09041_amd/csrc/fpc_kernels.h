@@ -1,0 +1,64 @@
+// Kernel argument blocks and launcher declarations shared by the kernel
+// translation units and the C-ABI implementation.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+
+#include "fpc_collide.h"
+
+namespace fpc {
+
+// One outer face of the box as the kernels see it.
+struct FaceDev {
+  int wall;             // 1: wall rules apply; 0: periodic
+  int lid;              // moving wall for f
+  int dirichlet;        // anti-bounce-back for g
+  double Tw;            // uniform wall temperature
+  const double* Tprof;  // optional per-node wall temperature (tangential axes, slower first)
+  double uw[3];         // wall velocity
+};
+
+template <class R>
+struct StepArgs {
+  const R* __restrict__ src;  // S_{n-1}
+  R* __restrict__ dst;        // S_n
+  int nx, ny, nz;
+  int per[3];                 // axis periodic flags
+  size_t plane;               // element stride between population planes
+  CollParams<R> c;
+  R rho_w;                    // moving-wall density
+  FaceDev face[6];
+};
+
+// Launchers (defined in fpc_kernels_2d.hip / fpc_kernels_3d.hip).
+// mode: 0 = step (pull from args.src), 1 = init (equilibrium from T_init).
+template <class R>
+hipError_t launch_step2d(const StepArgs<R>& a, int up, const double* T_init, int mode, hipStream_t s);
+template <class R>
+hipError_t launch_step3d(const StepArgs<R>& a, int up, const double* T_init, int mode, hipStream_t s);
+
+// Node-level utilities (fpc_kernels_util.hip).
+struct StateDesc {
+  const void* src;
+  int precision;  // 0 FP64, 1 FP32 deviations
+  int lattice;    // 1 = 2D, 2 = 3D
+  int nx, ny, nz;
+  size_t plane;
+  double rho_r, T_r;  // storage offsets
+  double cs2T;
+  double gbeta, T0;
+  int up;
+};
+
+hipError_t launch_macros(const StateDesc& d, double* rho, double* u, double* T, hipStream_t s);
+hipError_t launch_export(const StateDesc& d, double* dst, hipStream_t s);
+hipError_t launch_import(const StateDesc& d, void* dst, const double* src, hipStream_t s);
+// Writes out[0..4] = (sum Nu_local over the face or 0, KE, sum T, max|u|, #non-finite).
+// `partials` must hold at least diag_partials_needed(...) doubles.
+size_t diag_partials_needed(const StateDesc& d);
+hipError_t launch_diagnostics(const StateDesc& d, int face, const FaceDev& fd, double dT_ref,
+                              double* partials, double* out, hipStream_t s);
+
+}  // namespace fpc

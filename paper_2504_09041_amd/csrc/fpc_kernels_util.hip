@@ -1,0 +1,273 @@
+// Node-level utilities on a stored state: macros, FP64 export / import, and
+// the FP64 diagnostics reductions (wall Nusselt number, kinetic energy,
+// sum of T, max |u|, non-finite count).
+//
+// Macros of the time level are recovered from the post-collision state S_n:
+// rho = sum f, T = sum g and rho u = sum f e - F/2 (the collision leaves
+// rho and T unchanged and sets the first central moment to F/2, App. A
+// Step 3 with Eq. sourceCM2D), F = g beta (T - T0) along the up axis
+// (Boussinesq force, Sec. 6.1).
+//
+// Reductions are two-stage with a fixed tree in each block and a single-block
+// final pass, so results are bit-reproducible for a given grid.
+#include "fpc_kernels.h"
+
+namespace fpc {
+namespace {
+
+constexpr int kBlock = 256;
+
+__device__ __forceinline__ double wfluid(int lattice, int q) { return lattice == 1 ? w2(q) : w3(q); }
+
+__device__ __forceinline__ double wtherm(int d, double cs2T, int q) {
+  return q == 0 ? 1.0 - d * cs2T : 0.5 * cs2T;
+}
+
+__device__ __forceinline__ int ex_of(int lattice, int q) { return lattice == 1 ? D2_EX[q] : D3_EX[q]; }
+__device__ __forceinline__ int ey_of(int lattice, int q) { return lattice == 1 ? D2_EY[q] : D3_EY[q]; }
+__device__ __forceinline__ int ez_of(int lattice, int q) { return lattice == 1 ? 0 : D3_EZ[q]; }
+
+template <class R>
+__device__ __forceinline__ double ld(const StateDesc& d, int q, size_t node) {
+  return (double)static_cast<const R*>(d.src)[q * d.plane + node];
+}
+
+// FP64 macros of one node (rho, u[3], T).
+template <class R>
+__device__ void node_macros(const StateDesc& d, size_t node, double& rho, double u[3], double& T) {
+  const int Qf = d.lattice == 1 ? kQ2 : kQ3;
+  const int Qg = d.lattice == 1 ? kQ2T : kQ3T;
+  double s = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+  for (int q = 0; q < Qf; ++q) {
+    const double v = ld<R>(d, q, node);
+    s += v;
+    jx += ex_of(d.lattice, q) * v;
+    jy += ey_of(d.lattice, q) * v;
+    jz += ez_of(d.lattice, q) * v;
+  }
+  double t = 0.0;
+  for (int q = 0; q < Qg; ++q) t += ld<R>(d, Qf + q, node);
+  rho = d.rho_r + s;
+  T = d.T_r + t;
+  const double Fb = d.gbeta * (T - d.T0);
+  const double ir = 1.0 / rho;
+  u[0] = (jx - (d.up == 0 ? 0.5 * Fb : 0.0)) * ir;
+  u[1] = (jy - (d.up == 1 ? 0.5 * Fb : 0.0)) * ir;
+  u[2] = (jz - (d.up == 2 ? 0.5 * Fb : 0.0)) * ir;
+}
+
+template <class R>
+__global__ void __launch_bounds__(kBlock) macros_kernel(StateDesc d, double* rho, double* u, double* T) {
+  const size_t N = (size_t)d.nx * d.ny * d.nz;
+  const size_t node = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (node >= N) return;
+  double r, uu[3], t;
+  node_macros<R>(d, node, r, uu, t);
+  if (rho) rho[node] = r;
+  if (T) T[node] = t;
+  if (u) {
+    const int dim = d.lattice == 1 ? 2 : 3;
+    for (int i = 0; i < dim; ++i) u[i * N + node] = uu[i];
+  }
+}
+
+template <class R>
+__global__ void __launch_bounds__(kBlock) export_kernel(StateDesc d, double* dst) {
+  const size_t N = (size_t)d.nx * d.ny * d.nz;
+  const size_t node = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (node >= N) return;
+  const int Qf = d.lattice == 1 ? kQ2 : kQ3;
+  const int Qg = d.lattice == 1 ? kQ2T : kQ3T;
+  const int dim = d.lattice == 1 ? 2 : 3;
+  for (int q = 0; q < Qf; ++q) dst[q * N + node] = ld<R>(d, q, node) + wfluid(d.lattice, q) * d.rho_r;
+  for (int q = 0; q < Qg; ++q)
+    dst[(Qf + q) * N + node] = ld<R>(d, Qf + q, node) + wtherm(dim, d.cs2T, q) * d.T_r;
+}
+
+template <class R>
+__global__ void __launch_bounds__(kBlock) import_kernel(StateDesc d, R* out, const double* src) {
+  const size_t N = (size_t)d.nx * d.ny * d.nz;
+  const size_t node = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (node >= N) return;
+  const int Qf = d.lattice == 1 ? kQ2 : kQ3;
+  const int Qg = d.lattice == 1 ? kQ2T : kQ3T;
+  const int dim = d.lattice == 1 ? 2 : 3;
+  for (int q = 0; q < Qf; ++q) out[q * d.plane + node] = (R)(src[q * N + node] - wfluid(d.lattice, q) * d.rho_r);
+  for (int q = 0; q < Qg; ++q)
+    out[(Qf + q) * d.plane + node] = (R)(src[(Qf + q) * N + node] - wtherm(dim, d.cs2T, q) * d.T_r);
+}
+
+// Deterministic block reduction: sum (op 0) or max (op 1) over kBlock values.
+__device__ double block_reduce(double v, double* sh, int op) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int s = kBlock / 2; s > 0; s >>= 1) {
+    if (t < s) sh[t] = op == 0 ? sh[t] + sh[t + s] : fmax(sh[t], sh[t + s]);
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// Stage 1 over nodes: partials[b * 4 + (KE, sumT, umax, nonfinite)].
+template <class R>
+__global__ void __launch_bounds__(kBlock) diag_nodes_kernel(StateDesc d, double* partials) {
+  __shared__ double sh[kBlock];
+  const size_t N = (size_t)d.nx * d.ny * d.nz;
+  const size_t node = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double ke = 0.0, st = 0.0, um = 0.0, bad = 0.0;
+  if (node < N) {
+    double r, u[3], t;
+    node_macros<R>(d, node, r, u, t);
+    const double u2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    ke = 0.5 * r * u2;
+    st = t;
+    um = sqrt(u2);
+    if (!isfinite(r) || !isfinite(t) || !isfinite(u2)) {
+      bad = 1.0;
+      ke = 0.0;
+      st = 0.0;
+      um = 0.0;
+    }
+  }
+  ke = block_reduce(ke, sh, 0);
+  st = block_reduce(st, sh, 0);
+  um = block_reduce(um, sh, 1);
+  bad = block_reduce(bad, sh, 0);
+  if (threadIdx.x == 0) {
+    partials[blockIdx.x * 4 + 0] = ke;
+    partials[blockIdx.x * 4 + 1] = st;
+    partials[blockIdx.x * 4 + 2] = um;
+    partials[blockIdx.x * 4 + 3] = bad;
+  }
+}
+
+// Stage 1 over the nodes of one face: local Nusselt numbers.
+template <class R>
+__global__ void __launch_bounds__(kBlock) diag_face_kernel(StateDesc d, int face, FaceDev fd, double dT_ref,
+                                                           double* partials) {
+  __shared__ double sh[kBlock];
+  const int k = face >> 1;
+  const int n[3] = {d.nx, d.ny, d.nz};
+  const int t1 = k == 0 ? 1 : 0;  // faster tangential axis
+  const int t2 = k == 2 ? 1 : 2;  // slower tangential axis
+  const size_t M = (size_t)n[t1] * n[t2];
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double nu = 0.0;
+  if (i < M) {
+    int c[3];
+    c[t1] = (int)(i % n[t1]);
+    c[t2] = (int)(i / n[t1]);
+    const int L = n[k];
+    const int Qf = d.lattice == 1 ? kQ2 : kQ3;
+    const int Qg = d.lattice == 1 ? kQ2T : kQ3T;
+    double Tl[2];
+    for (int layer = 0; layer < 2; ++layer) {
+      c[k] = (face & 1) ? L - 1 - layer : layer;
+      const size_t node = ((size_t)c[2] * d.ny + c[1]) * d.nx + c[0];
+      double t = 0.0;
+      for (int q = 0; q < Qg; ++q) t += ld<R>(d, Qf + q, node);
+      Tl[layer] = d.T_r + t;
+    }
+    const double Tw = fd.Tprof ? fd.Tprof[i] : fd.Tw;
+    const double dTdn = -8.0 / 3.0 * Tw + 3.0 * Tl[0] - Tl[1] / 3.0;
+    nu = -((double)L / dT_ref) * dTdn;
+  }
+  nu = block_reduce(nu, sh, 0);
+  if (threadIdx.x == 0) partials[blockIdx.x] = nu;
+}
+
+__global__ void __launch_bounds__(kBlock) diag_final_kernel(const double* pn, int nb, const double* pf, int nf,
+                                                            double* out) {
+  __shared__ double sh[kBlock];
+  double ke = 0.0, st = 0.0, um = 0.0, bad = 0.0, nu = 0.0;
+  for (int b = threadIdx.x; b < nb; b += kBlock) {
+    ke += pn[b * 4 + 0];
+    st += pn[b * 4 + 1];
+    um = fmax(um, pn[b * 4 + 2]);
+    bad += pn[b * 4 + 3];
+  }
+  for (int b = threadIdx.x; b < nf; b += kBlock) nu += pf[b];
+  nu = block_reduce(nu, sh, 0);
+  ke = block_reduce(ke, sh, 0);
+  st = block_reduce(st, sh, 0);
+  um = block_reduce(um, sh, 1);
+  bad = block_reduce(bad, sh, 0);
+  if (threadIdx.x == 0) {
+    out[0] = nu;
+    out[1] = ke;
+    out[2] = st;
+    out[3] = um;
+    out[4] = bad;
+  }
+}
+
+size_t node_blocks(const StateDesc& d) {
+  const size_t N = (size_t)d.nx * d.ny * d.nz;
+  return (N + kBlock - 1) / kBlock;
+}
+
+size_t face_nodes(const StateDesc& d, int face) {
+  const int k = face >> 1;
+  const size_t n[3] = {(size_t)d.nx, (size_t)d.ny, (size_t)d.nz};
+  return n[(k + 1) % 3] * n[(k + 2) % 3];
+}
+
+}  // namespace
+
+hipError_t launch_macros(const StateDesc& d, double* rho, double* u, double* T, hipStream_t s) {
+  const unsigned nb = (unsigned)node_blocks(d);
+  if (d.precision == 0)
+    macros_kernel<double><<<nb, kBlock, 0, s>>>(d, rho, u, T);
+  else
+    macros_kernel<float><<<nb, kBlock, 0, s>>>(d, rho, u, T);
+  return hipGetLastError();
+}
+
+hipError_t launch_export(const StateDesc& d, double* dst, hipStream_t s) {
+  const unsigned nb = (unsigned)node_blocks(d);
+  if (d.precision == 0)
+    export_kernel<double><<<nb, kBlock, 0, s>>>(d, dst);
+  else
+    export_kernel<float><<<nb, kBlock, 0, s>>>(d, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_import(const StateDesc& d, void* dst, const double* src, hipStream_t s) {
+  const unsigned nb = (unsigned)node_blocks(d);
+  if (d.precision == 0)
+    import_kernel<double><<<nb, kBlock, 0, s>>>(d, static_cast<double*>(dst), src);
+  else
+    import_kernel<float><<<nb, kBlock, 0, s>>>(d, static_cast<float*>(dst), src);
+  return hipGetLastError();
+}
+
+size_t diag_partials_needed(const StateDesc& d) {
+  size_t mf = 0;
+  for (int f = 0; f < 6; ++f) mf = face_nodes(d, f) > mf ? face_nodes(d, f) : mf;
+  return node_blocks(d) * 4 + (mf + kBlock - 1) / kBlock + 8;
+}
+
+hipError_t launch_diagnostics(const StateDesc& d, int face, const FaceDev& fd, double dT_ref, double* partials,
+                              double* out, hipStream_t s) {
+  const unsigned nb = (unsigned)node_blocks(d);
+  double* pf = partials + (size_t)nb * 4;
+  unsigned nf = 0;
+  if (d.precision == 0)
+    diag_nodes_kernel<double><<<nb, kBlock, 0, s>>>(d, partials);
+  else
+    diag_nodes_kernel<float><<<nb, kBlock, 0, s>>>(d, partials);
+  if (face >= 0) {
+    nf = (unsigned)((face_nodes(d, face) + kBlock - 1) / kBlock);
+    if (d.precision == 0)
+      diag_face_kernel<double><<<nf, kBlock, 0, s>>>(d, face, fd, dT_ref, pf);
+    else
+      diag_face_kernel<float><<<nf, kBlock, 0, s>>>(d, face, fd, dT_ref, pf);
+  }
+  diag_final_kernel<<<1, kBlock, 0, s>>>(partials, (int)nb, pf, (int)nf, out);
+  return hipGetLastError();
+}
+
+}  // namespace fpc

@@ -1,0 +1,197 @@
+"""Python front end of the C ABI: a simulation whose state lives in torch
+device memory and whose kernels run on torch's current HIP stream.
+
+Every step of the method runs in the HIP kernels of ``libfpclbm.so``; this
+module only allocates buffers, marshals arguments and reshapes outputs.
+"""
+
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _abi as A
+
+FACE_INDEX = {"-x": 0, "+x": 1, "-y": 2, "+y": 3, "-z": 4, "+z": 5}
+LATTICES = {"D2Q9-D2Q5": A.FPC_D2Q9_D2Q5, "D3Q27-D3Q7": A.FPC_D3Q27_D3Q7}
+PRECISIONS = {"f64": A.FPC_FP64, "f32dev": A.FPC_FP32_DEV}
+Q = {A.FPC_D2Q9_D2Q5: (9, 5, 2), A.FPC_D3Q27_D3Q7: (27, 7, 3)}
+
+
+def face_code(fluid, thermal):
+    if fluid == "periodic" or thermal == "periodic":
+        if not (fluid == "periodic" and thermal == "periodic"):
+            raise ValueError("a periodic face must be periodic for both distributions")
+        return A.FPC_BC_PERIODIC
+    table = {
+        ("noslip", "adiabatic"): A.FPC_BC_NOSLIP_ADIABATIC,
+        ("noslip", "dirichlet"): A.FPC_BC_NOSLIP_DIRICHLET,
+        ("lid", "adiabatic"): A.FPC_BC_LID_ADIABATIC,
+        ("lid", "dirichlet"): A.FPC_BC_LID_DIRICHLET,
+    }
+    return table[(fluid, thermal)]
+
+
+def default_params(lattice, precision, shape):
+    p = A.fpc_params()
+    nx, ny, nz = shape
+    A.call("fpc_params_default", ctypes.byref(p), LATTICES.get(lattice, lattice),
+           PRECISIONS.get(precision, precision), nx, ny, nz)
+    return p
+
+
+def set_faces(p, faces):
+    """faces: 6 dicts {fluid, thermal, T, u_w} in the order -x, +x, -y, +y, -z, +z."""
+    for f, fd in enumerate(faces):
+        p.bc[f] = face_code(fd["fluid"], fd["thermal"])
+        p.wall_T[f] = float(fd.get("T", 0.0))
+        for i, v in enumerate(fd.get("u_w", (0.0, 0.0, 0.0))):
+            p.lid_u[f][i] = float(v)
+    return p
+
+
+def params_from_workload(cfg, precision="f64", shape=None, cs2_T=None):
+    """C parameters of a workload description (``workloads.CONFIGS`` entry).
+
+    The physical -> lattice mapping runs in the library
+    (fpc_params_natural / fpc_params_mixed)."""
+    shape = tuple(cfg["shape"]) if shape is None else tuple(shape)
+    p = default_params(cfg["pair"], precision, shape)
+    if cs2_T is not None:
+        p.cs2_T = float(cs2_T)
+    if cfg["flow"] == "natural":
+        A.call("fpc_params_natural", ctypes.byref(p), cfg["Ra"], cfg["Pr"], cfg["U0"], cfg["L_axis"],
+               cfg["T_hot"], cfg["T_cold"])
+    else:
+        A.call("fpc_params_mixed", ctypes.byref(p), cfg["Re"], cfg["Ri"], cfg["Pe"], cfg["U_lid"],
+               cfg["L_axis"], cfg["T_hot"], cfg["T_cold"])
+    p.up_axis = cfg["up_axis"]
+    set_faces(p, cfg["faces"])
+    return p
+
+
+def state_bytes(p):
+    nb = ctypes.c_size_t()
+    ps = ctypes.c_size_t()
+    A.call("fpc_state_bytes", ctypes.byref(p), ctypes.byref(nb), ctypes.byref(ps))
+    return nb.value, ps.value
+
+
+class Simulation:
+    """One FP central-moment thermal LBM simulation on a GPU."""
+
+    def __init__(self, params, device=None, wall_profiles=None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("Simulation needs a HIP GPU (torch.cuda is not available)")
+        A.load()
+        self.device = torch.device("cuda" if device is None else device)
+        self.params = A.fpc_params()
+        ctypes.memmove(ctypes.byref(self.params), ctypes.byref(params), ctypes.sizeof(params))
+        self._profiles = {}
+        for f, t in (wall_profiles or {}).items():
+            fi = FACE_INDEX.get(f, f)
+            t = t.to(self.device, torch.float64).contiguous()
+            self._profiles[fi] = t
+            self.params.wall_T_profile[fi] = t.data_ptr()
+        self.nbytes, self.plane = state_bytes(self.params)
+        self.Qf, self.Qg, self.dim = Q[self.params.lattice]
+        self.shape = (self.params.nx, self.params.ny, self.params.nz)
+        self.N = self.params.nx * self.params.ny * self.params.nz
+        with torch.cuda.device(self.device):
+            self.buffers = [torch.empty(self.nbytes, dtype=torch.uint8, device=self.device) for _ in range(2)]
+            self.stream = torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        A.call("fpc_create", ctypes.byref(self.params), self.buffers[0].data_ptr(), self.buffers[1].data_ptr(),
+               ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        self._h = h
+
+    # -- lifecycle ---------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            A.call("fpc_destroy", self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    # -- stepping ----------------------------------------------------------
+    def init(self, T_init):
+        """T_init: (nz, ny, nx) temperature field (any device / dtype)."""
+        T = torch.as_tensor(T_init).to(self.device, torch.float64).contiguous()
+        if T.numel() != self.N:
+            raise ValueError(f"T_init has {T.numel()} values, grid has {self.N}")
+        self._tinit = T  # keep alive until the kernel has read it
+        A.call("fpc_init", self._h, ctypes.c_void_p(T.data_ptr()))
+
+    def step(self, n=1):
+        A.call("fpc_step", self._h, int(n))
+
+    @property
+    def step_count(self):
+        v = ctypes.c_longlong()
+        A.call("fpc_get_step", self._h, ctypes.byref(v))
+        return v.value
+
+    # -- outputs -----------------------------------------------------------
+    def macros(self):
+        nx, ny, nz = self.shape
+        rho = torch.empty((nz, ny, nx), dtype=torch.float64, device=self.device)
+        T = torch.empty_like(rho)
+        u = torch.empty((self.dim, nz, ny, nx), dtype=torch.float64, device=self.device)
+        A.call("fpc_macros", self._h, ctypes.c_void_p(rho.data_ptr()), ctypes.c_void_p(u.data_ptr()),
+               ctypes.c_void_p(T.data_ptr()))
+        return {"rho": rho, "u": u, "T": T}
+
+    def diagnostics(self, face=-1):
+        """FP64 GPU reductions; returns dict(nu, ke, sumT, umax, unstable)."""
+        fi = FACE_INDEX.get(face, face)
+        vals = [ctypes.c_double() for _ in range(4)]
+        rc = A.load().fpc_diagnostics(self._h, int(fi), *[ctypes.byref(v) for v in vals])
+        if rc not in (A.FPC_OK, A.FPC_ERR_UNSTABLE):
+            A.check(rc, "fpc_diagnostics")
+        return {"nu": vals[0].value, "ke": vals[1].value, "sumT": vals[2].value, "umax": vals[3].value,
+                "unstable": rc == A.FPC_ERR_UNSTABLE}
+
+    def export_fp64(self):
+        """Current state as full FP64 populations, shape (Qf + Qg, nz, ny, nx)."""
+        nx, ny, nz = self.shape
+        out = torch.empty((self.Qf + self.Qg, nz, ny, nx), dtype=torch.float64, device=self.device)
+        A.call("fpc_export_fp64", self._h, ctypes.c_void_p(out.data_ptr()))
+        return out
+
+    def import_fp64(self, S, step=0):
+        S = torch.as_tensor(S).to(self.device, torch.float64).contiguous()
+        if S.numel() != (self.Qf + self.Qg) * self.N:
+            raise ValueError("state has the wrong size")
+        self._imp = S
+        A.call("fpc_import_fp64", self._h, ctypes.c_void_p(S.data_ptr()), int(step))
+
+    def save(self):
+        out = torch.empty(self.nbytes, dtype=torch.uint8, device=self.device)
+        A.call("fpc_save", self._h, ctypes.c_void_p(out.data_ptr()))
+        return out
+
+    def load(self, buf, step=0):
+        if buf.numel() != self.nbytes or buf.dtype != torch.uint8:
+            raise ValueError("snapshot has the wrong size")
+        A.call("fpc_load", self._h, ctypes.c_void_p(buf.data_ptr()), int(step))
+
+    def current_buffer(self):
+        p = ctypes.c_void_p()
+        A.call("fpc_current_buffer", self._h, ctypes.byref(p))
+        return p.value
+
+    def state_view(self):
+        """The current state buffer viewed in storage format, shape (Qf+Qg, plane)."""
+        ptr = self.current_buffer()
+        buf = self.buffers[0] if ptr == self.buffers[0].data_ptr() else self.buffers[1]
+        dt = torch.float64 if self.params.precision == A.FPC_FP64 else torch.float32
+        return buf.view(dt).view(self.Qf + self.Qg, self.plane)

@@ -1,0 +1,95 @@
+"""C-ABI checks that need no GPU: symbols, host-side validation, and the
+library's physical -> lattice parameter mapping against the oracle's."""
+
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+import workloads
+from oracle.params import params_from_config
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fpclbm.h")
+
+A = pytest.importorskip("paper_2504_09041_amd._abi")
+
+
+def _lib():
+    if not os.path.exists(A.LIB_PATH):
+        pytest.skip("libfpclbm.so not built")
+    return A.load()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fpc_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_binding_names():
+    assert declared_functions() == sorted(A.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert lib.fpc_version() >= 10000
+
+
+def test_params_struct_layout_matches_header():
+    # offsets of the trailing members pin the struct layout used by ctypes
+    p = A.fpc_params
+    assert p.omega_f.offset == 20 + 4  # 5 ints, padded to 8
+    assert ctypes.sizeof(p) == p.wall_T_profile.offset + 6 * 8
+
+
+def test_validation_errors():
+    lib = _lib()
+    p = A.fpc_params()
+    assert lib.fpc_params_default(ctypes.byref(p), 7, 0, 8, 8, 1) == A.FPC_ERR_ARG
+    assert lib.fpc_params_default(ctypes.byref(p), A.FPC_D2Q9_D2Q5, 0, 8, 8, 2) == A.FPC_ERR_SIZE
+    assert lib.fpc_params_default(ctypes.byref(p), A.FPC_D2Q9_D2Q5, 0, 8, 8, 1) == A.FPC_OK
+    nb, ps = ctypes.c_size_t(), ctypes.c_size_t()
+    assert lib.fpc_state_bytes(ctypes.byref(p), ctypes.byref(nb), ctypes.byref(ps)) == A.FPC_OK
+    assert ps.value == 64 and nb.value == 64 * 14 * 8
+    p.omega_f[4] = 2.0
+    assert lib.fpc_state_bytes(ctypes.byref(p), ctypes.byref(nb), None) == A.FPC_ERR_ARG
+    assert "omega_f[4]" in A.last_error()
+    p.omega_f[4] = 1.0
+    p.bc[0] = A.FPC_BC_NOSLIP_ADIABATIC  # periodic on +x only
+    assert lib.fpc_state_bytes(ctypes.byref(p), ctypes.byref(nb), None) == A.FPC_ERR_ARG
+    p.bc[1] = A.FPC_BC_LID_ADIABATIC
+    p.lid_u[1][0] = 0.1  # normal component on an x face
+    assert lib.fpc_state_bytes(ctypes.byref(p), ctypes.byref(nb), None) == A.FPC_ERR_ARG
+    p.lid_u[1][0] = 0.0
+    p.lid_u[1][1] = 0.1
+    assert lib.fpc_state_bytes(ctypes.byref(p), ctypes.byref(nb), None) == A.FPC_OK
+    p.bc[4] = A.FPC_BC_NOSLIP_ADIABATIC
+    p.bc[5] = A.FPC_BC_NOSLIP_ADIABATIC
+    assert lib.fpc_state_bytes(ctypes.byref(p), ctypes.byref(nb), None) == A.FPC_ERR_ARG
+    h = ctypes.c_void_p()
+    assert lib.fpc_create(None, None, None, None, ctypes.byref(h)) == A.FPC_ERR_ARG
+    assert lib.fpc_step(None, 1) == A.FPC_ERR_ARG
+
+
+@pytest.mark.parametrize("name", list(workloads.CONFIGS))
+def test_parameter_mapping_matches_oracle(name):
+    from paper_2504_09041_amd.sim import params_from_workload
+
+    _lib()
+    cfg = workloads.config(name)
+    for prec in ("f64", "f32dev"):
+        p = params_from_workload(cfg, prec)
+        o = params_from_config(cfg)
+        lf, lg = o.lattices
+        for k in range(1, lf.Q):
+            assert math.isclose(p.omega_f[k], o.omega_f[k], rel_tol=1e-14), (k, p.omega_f[k], o.omega_f[k])
+        for k in range(1, lg.Q):
+            assert math.isclose(p.omega_g[k], o.omega_g[k], rel_tol=1e-14)
+        assert math.isclose(p.g_beta, o.g_beta, rel_tol=1e-14)
+        assert math.isclose(p.cs2_T, o.cs2T, rel_tol=1e-15)
+        assert p.T0 == o.T0 and p.up_axis == o.up_axis

@@ -1,0 +1,184 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Bars (from the target of this implementation): the FP64 form within 1e-13
+relative after one step and 1e-12 after 100 steps / a full 2000-step run; the
+FP32 deviation form within 1e-4 dT on the temperature and 1e-3 relative on
+the wall Nusselt number (the population bound below is tighter).
+Relative errors are max |gpu - oracle| / max |oracle| per distribution.
+"""
+
+import pytest
+import torch
+
+import workloads
+from oracle import sim as osim
+from oracle.collision import rest_weights
+from oracle.params import params_from_config
+from tests import gpu_common as G
+
+pytestmark = pytest.mark.gpu
+
+CASES = list(G.SMALL_CASES)
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    G.need_gpu()
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_init_matches_oracle(case):
+    cfg = G.small_config(case)
+    T = G.initial_T(cfg)
+    sim = G.make_sim(cfg, "f64")
+    sim.init(T.cuda())
+    f, g = G.read_state(sim)
+    fo, go = osim.init_state(params_from_config(cfg), T)
+    assert G.rel_err(f, fo) < 1e-14
+    assert G.rel_err(g, go) < 1e-14
+
+
+@pytest.mark.parametrize("case", CASES)
+@pytest.mark.parametrize("nsteps,tol", [(1, 1e-13), (100, 1e-12)])
+def test_fp64_steps_match_oracle(case, nsteps, tol):
+    print(f"case={case} nsteps={nsteps}", flush=True)
+    cfg = G.small_config(case)
+    f0, g0 = G.perturbed_state(cfg, seed=11)
+    sim = G.make_sim(cfg, "f64")
+    G.load_state(sim, f0, g0)
+    sim.step(nsteps)
+    f, g = G.read_state(sim)
+    fo, go, mac, prm = G.oracle_run(cfg, f0, g0, nsteps)
+    assert G.rel_err(f, fo) < tol
+    assert G.rel_err(g, go) < tol
+    # macros and diagnostics of time level n
+    m = sim.macros()
+    assert G.rel_err(m["rho"].cpu(), mac["rho"]) < tol
+    assert G.rel_err(m["T"].cpu(), mac["T"]) < tol
+    # u is a small difference of O(1) sums: bound its error on the population scale
+    assert float((m["u"].cpu() - mac["u"]).abs().max()) <= 10 * tol
+    d = sim.diagnostics(cfg["nu_face"])
+    nu_o = float(osim.nusselt(prm, mac["T"], cfg["nu_face"]))
+    ke_o = float(osim.kinetic_energy(mac))
+    assert abs(d["nu"] - nu_o) <= tol * max(1.0, abs(nu_o))
+    assert abs(d["ke"] - ke_o) <= 1e-9 * ke_o
+    assert abs(d["sumT"] - float(mac["T"].sum())) <= tol * float(mac["T"].abs().sum())
+    assert not d["unstable"]
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_fp32_deviation_steps_match_oracle(case):
+    cfg = G.small_config(case)
+    f0, g0 = G.perturbed_state(cfg, seed=12)
+    sim = G.make_sim(cfg, "f32dev")
+    G.load_state(sim, f0, g0)
+    sim.step(100)
+    f, g = G.read_state(sim)
+    fo, go, mac, prm = G.oracle_run(cfg, f0, g0, 100)
+    m = sim.macros()
+    d = sim.diagnostics(cfg["nu_face"])
+    nu_o = float(osim.nusselt(prm, mac["T"], cfg["nu_face"]))
+    dT = cfg["T_hot"] - cfg["T_cold"]
+    eT = float((m["T"].cpu() - mac["T"]).abs().max())
+    print(f"case={case} f32dev: rel f {G.rel_err(f, fo):.2e} rel g {G.rel_err(g, go):.2e} "
+          f"max|dT| {eT:.2e} Nu gpu {d['nu']:.8f} oracle {nu_o:.8f}")
+    # round-off of FP32 storage over 100 steps (the thermal rates of the
+    # mixed-convection case are close to 2, so that error is barely damped)
+    assert G.rel_err(f, fo) < 1e-5
+    assert G.rel_err(g, go) < 1e-5
+    assert eT < 1e-4 * dT
+    assert abs(d["nu"] - nu_o) <= 1e-3 * max(abs(nu_o), 1e-3)
+
+
+def test_wall_temperature_profile():
+    cfg = G.small_config("mixed2d")
+    nx = cfg["shape"][0]
+    prof = 0.5 * torch.tensor(workloads.uniform_field((nx,), 5)) - 0.5
+    f0, g0 = G.perturbed_state(cfg, seed=13)
+    sim = G.make_sim(cfg, "f64", wall_profiles={"-y": prof})
+    G.load_state(sim, f0, g0)
+    sim.step(20)
+    f, g = G.read_state(sim)
+    fo, go, mac, prm = G.oracle_run(cfg, f0, g0, 20, wall_T={2: prof})
+    assert G.rel_err(g, go) < 1e-12
+    assert G.rel_err(f, fo) < 1e-12
+    d = sim.diagnostics("-y")
+    nu_o = float(osim.nusselt(prm, mac["T"], 2, wall_T={2: prof}))
+    assert abs(d["nu"] - nu_o) < 1e-12 * max(1.0, abs(nu_o))
+
+
+def test_config1_full_run_matches_oracle():
+    """64x64 cavity, Ra 1e4, 2000 steps from the seeded initial field."""
+    cfg = workloads.config("dhc2d_64")
+    T = G.initial_T(cfg)
+    sim = G.make_sim(cfg, "f64")
+    sim.init(T.cuda())
+    sim.step(cfg["steps"])
+    f, g = G.read_state(sim)
+    prm = params_from_config(cfg)
+    fo, go = osim.init_state(prm, T)
+    fo, go, mac = osim.run(prm, fo, go, cfg["steps"])
+    assert G.rel_err(f, fo) < 1e-12
+    assert G.rel_err(g, go) < 1e-12
+    d = sim.diagnostics(0)
+    nu_o = float(osim.nusselt(prm, mac["T"], 0))
+    assert abs(d["nu"] - nu_o) < 1e-12 * abs(nu_o)
+    print(f"config1: Nu_hot(2000) gpu={d['nu']:.15f} oracle={nu_o:.15f}")
+
+
+def test_save_load_resume_is_bit_identical():
+    cfg = G.small_config("dhc3d")
+    f0, g0 = G.perturbed_state(cfg, seed=14)
+    a = G.make_sim(cfg, "f32dev")
+    G.load_state(a, f0, g0)
+    a.step(10)
+    snap = a.save()
+    a.step(10)
+    ref = a.export_fp64()
+    b = G.make_sim(cfg, "f32dev")
+    b.load(snap, step=10)
+    b.step(10)
+    assert torch.equal(b.export_fp64(), ref)
+    assert b.step_count == 20
+
+
+def test_nan_is_reported_unstable():
+    cfg = G.small_config("dhc2d")
+    f0, g0 = G.perturbed_state(cfg, seed=15)
+    f0[3, 0, 2, 2] = float("nan")
+    sim = G.make_sim(cfg, "f64")
+    G.load_state(sim, f0, g0)
+    sim.step(2)
+    assert sim.diagnostics(0)["unstable"]
+
+
+@pytest.mark.parametrize("workload,precision,tol", [
+    ("rb2d_1024x512", "f64", 1e-13),
+    ("rb2d_1024x512", "f32dev", 2e-6),
+    ("mixed2d_512", "f32dev", 2e-6),
+    ("dhc3d_256", "f32dev", 2e-6),
+    ("rb3d_128", "f32dev", 2e-6),
+])
+def test_full_size_step_on_sampled_nodes(workload, precision, tol):
+    """One step at the full workload size from a hashed input state; the
+    oracle evaluates the same step at ~2000 sampled nodes (plus corners and
+    face bands)."""
+    print(f"workload={workload} precision={precision}", flush=True)
+    cfg = workloads.config(workload)
+    prm = params_from_config(cfg)
+    lf, lg = prm.lattices
+    wf = rest_weights(lf)
+    wg = rest_weights(lg, thermal=True, cs2=prm.cs2T)
+    sim = G.make_sim(cfg, precision)
+    S = G.full_hashed_state(cfg["shape"], lf.Q, lg.Q, wf, wg, seed=21, device="cuda")
+    sim.import_fp64(S)
+    del S
+    sim.step(1)
+    out = sim.export_fp64()
+    x, y, z = G.sample_nodes(cfg["shape"], 2000, seed=22)
+    got = out[:, z.cuda(), y.cuda(), x.cuda()].cpu()
+    del out
+    gf, gg = G.hashed_state_getters(cfg["shape"], lf.Q, lg.Q, wf, wg, seed=21)
+    fo, go, _ = osim.step_at(prm, gf, gg, (x, y, z))
+    assert G.rel_err(got[: lf.Q], fo) < tol
+    assert G.rel_err(got[lf.Q:], go) < tol

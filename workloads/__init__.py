@@ -2,8 +2,9 @@
 
 This module holds none of the method's arithmetic.  It is imported by both the
 oracle-driven tests and the HIP path's callers (tests, ``bench.py``), so that
-both see bit-identical inputs.  All random numbers are drawn on the host in
-FP64 with ``numpy.random.default_rng(seed)``.
+both see bit-identical inputs.  Random fields are drawn on the host in FP64
+with ``numpy.random.default_rng(seed)``, except ``hashed_uniform`` (a
+stateless counter-based generator for inputs too large to build on the host).
 
 Set-ups (shapes and boundary kinds of the paper's benchmark problems,
 Sec. 6.1 cavity, Sec. 6.2 cube, Sec. 7 lid-driven mixed convection, plus
@@ -134,3 +135,39 @@ def unit_directions(n, count, seed0=0):
         v = np.random.default_rng(s).standard_normal(n)
         out.append(v / np.linalg.norm(v))
     return np.stack(out)
+
+
+# --- counter-based noise -------------------------------------------------
+# A stateless generator, so that an input of any size can be built on the GPU
+# in full and re-evaluated on the CPU at sampled entries only.  The mixing
+# function is the "lowbias32" integer hash (C. Wellons, hash-prospector):
+#   x ^= x >> 16; x *= 0x7feb352d; x ^= x >> 15; x *= 0x846ca68b; x ^= x >> 16
+# (all arithmetic modulo 2^32).  It is written here with int64 tensors and a
+# 16-bit split multiply so that no intermediate overflows on any device.
+
+_M32 = 0xFFFFFFFF
+
+
+def _mulmod32(x, c):
+    lo = (x & 0xFFFF) * c
+    hi = (((x >> 16) * c) & 0xFFFF) << 16
+    return (lo + hi) & _M32
+
+
+def _lowbias32(x):
+    x = x ^ (x >> 16)
+    x = _mulmod32(x, 0x7FEB352D)
+    x = x ^ (x >> 15)
+    x = _mulmod32(x, 0x846CA68B)
+    x = x ^ (x >> 16)
+    return x
+
+
+def hashed_uniform(index, seed):
+    """Uniform values in [-1, 1) for integer counters ``index`` (an int64
+    torch tensor on any device, values < 2^32) and an integer ``seed``."""
+    import torch
+
+    s = _lowbias32(torch.full_like(index, (seed * 0x9E3779B9) & _M32))
+    h = _lowbias32((index & _M32) ^ s)
+    return h.to(torch.float64) * (2.0 / 4294967296.0) - 1.0
