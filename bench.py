@@ -16,6 +16,13 @@ algorithmic bytes of one launch (every population read once and written
 once: 2 (Qf + Qg) sizeof(real) per node) over the average launch duration.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+
+Profiling helpers (used for the rocprofv3 summaries under profiles/):
+    python bench.py --mode single --workload dhc3d_256 --precision f32dev --steps 5
+        runs one workload only (init + W warm-up + K steps) and prints its timing;
+    python bench.py --mode copy --mib 4096 --reps 10
+        a plain device copy (torch) of a buffer of that size: the attainable
+        read+write bandwidth and the reference for the HBM byte counters.
 """
 
 from __future__ import annotations
@@ -40,7 +47,41 @@ def _args():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=12)
+    ap.add_argument("--mode", choices=("bench", "single", "copy", "pmc-summary"), default="bench")
+    ap.add_argument("--fetch", help="rocprofv3 --pmc FETCH_SIZE output dir (kernel run)")
+    ap.add_argument("--write", help="rocprofv3 --pmc WRITE_SIZE output dir (kernel run)")
+    ap.add_argument("--copy-fetch", help="rocprofv3 --pmc FETCH_SIZE output dir (copy run)")
+    ap.add_argument("--copy-write", help="rocprofv3 --pmc WRITE_SIZE output dir (copy run)")
+    ap.add_argument("--kernel-regex", default="step_kernel")
+    ap.add_argument("--key", default="rb2d_1024x512_f64")
+    ap.add_argument("--workload", default="rb2d_1024x512")
+    ap.add_argument("--precision", default="f64")
+    ap.add_argument("--mib", type=int, default=4096)
+    ap.add_argument("--reps", type=int, default=10)
     return ap.parse_args()
+
+
+def copy_bandwidth(mib, reps):
+    import torch
+
+    n = mib * 1024 * 1024 // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    # an elementwise kernel (torch's vectorised streaming loop), not the
+    # runtime's blit copy
+    torch.mul(a, 1.0, out=b)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        torch.mul(a, 1.0, out=b)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    nbytes = 2 * n * 4
+    return {"mode": "copy", "bytes_read_plus_written": nbytes, "ms_per_copy": ms,
+            "GBs": nbytes / (ms * 1e-3) / 1e9}
 
 
 def _traffic_record():
@@ -50,6 +91,46 @@ def _traffic_record():
         with open(path) as fh:
             return json.load(fh)
     return {}
+
+
+def _pmc_per_dispatch(d, regex):
+    """Mean counter value (KiB, summed over the counter's instances) per
+    dispatch of the kernels matching ``regex`` in a rocprofv3 csv directory."""
+    import csv
+    import glob
+    import re
+
+    path = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)[0]
+    per = {}
+    for r in csv.DictReader(open(path)):
+        if re.search(regex, r["Kernel_Name"]):
+            per[r["Dispatch_Id"]] = per.get(r["Dispatch_Id"], 0.0) + float(r["Counter_Value"])
+    vals = sorted(per.values())
+    # drop the first dispatch of a run when it differs (initial collision)
+    return sum(vals[len(vals) // 2:]) / len(vals[len(vals) // 2:]), len(vals)
+
+
+def pmc_summary(a):
+    """Scale the TCC byte counters by what they read for a plain copy of
+    known size and record bytes per launch in profiles/traffic.json."""
+    copy_bytes = a.mib * 1024 * 1024
+    cf, _ = _pmc_per_dispatch(a.copy_fetch, "elementwise")
+    cw, _ = _pmc_per_dispatch(a.copy_write, "elementwise")
+    kf, nf = _pmc_per_dispatch(a.fetch, a.kernel_regex)
+    kw, nw = _pmc_per_dispatch(a.write, a.kernel_regex)
+    sf = copy_bytes / (cf * 1024.0)
+    sw = copy_bytes / (cw * 1024.0)
+    rec = {
+        "fetch_bytes": kf * 1024.0 * sf, "write_bytes": kw * 1024.0 * sw,
+        "fetch_scale": sf, "write_scale": sw, "dispatches": [nf, nw],
+    }
+    rec["traffic_bytes"] = rec["fetch_bytes"] + rec["write_bytes"]
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    allrec = _traffic_record()
+    allrec[a.key] = rec
+    with open(path, "w") as fh:
+        json.dump(allrec, fh, indent=1, sort_keys=True)
+    return rec
 
 
 def time_workload(name, precision, steps, warmup, shape=None):
@@ -136,24 +217,35 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); "
               "multi-GPU sharding is not part of this build", file=sys.stderr)
         sys.exit(2)
+    if a.mode == "pmc-summary":
+        print(json.dumps(pmc_summary(a)))
+        return
     import torch
 
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if a.mode == "copy":
+        print(json.dumps(copy_bandwidth(a.mib, a.reps)))
+        return
+    if a.mode == "single":
+        print(json.dumps(time_workload(a.workload, a.precision, a.steps, a.warmup)))
+        return
     head = time_workload("rb2d_1024x512", "f64", a.steps, a.warmup)
     extra = {}
     if not a.no_extra:
         extra["rb2d_1024x512_f32dev"] = time_workload("rb2d_1024x512", "f32dev", a.steps, a.warmup)
         extra["dhc3d_256_f32dev"] = time_workload("dhc3d_256", "f32dev", a.steps3d, max(5, a.warmup // 10))
-    traffic = _traffic_record().get("step2d_f64_rb2d_1024x512")
+    tr = _traffic_record().get("rb2d_1024x512_f64")
     roof = {
         "bound": "hbm",
         "achieved": head["achieved_GBs"],
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": head["achieved_GBs"] / HBM_PEAK_GBS,
-        "traffic": traffic,
+        # HBM-side bytes per launch from the scaled FETCH_SIZE + WRITE_SIZE counters
+        "traffic": tr["traffic_bytes"] if tr else None,
+        "algorithmic_bytes": head["bytes_per_node"] * head["nodes"],
     }
     cpu = None
     if not a.no_cpu_baseline:

@@ -14,7 +14,9 @@ import os
 import torch  # noqa: F401  (load torch's HIP runtime first)
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libfpclbm.so")
+# FPCLBM_LIB may point at another build of the same library (e.g. a variant
+# compiled with different tuning macros).
+LIB_PATH = os.environ.get("FPCLBM_LIB") or os.path.join(_PKG, "libfpclbm.so")
 
 FPC_OK = 0
 FPC_ERR_ARG = -1

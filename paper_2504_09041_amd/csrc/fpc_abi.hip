@@ -46,6 +46,8 @@ int hipfail(hipError_t e, const char* what) {
   return fail(FPC_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
 }
 
+size_t elem_size(int precision) { return precision == FPC_FP64 ? 8 : 4; }
+
 int lattice_dims(int lattice, int* Qf, int* Qg, int* dim) {
   if (lattice == FPC_D2Q9_D2Q5) {
     *Qf = 9; *Qg = 5; *dim = 2;
@@ -58,12 +60,15 @@ int lattice_dims(int lattice, int* Qf, int* Qg, int* dim) {
   return fail(FPC_ERR_ARG, "unknown lattice %d", lattice);
 }
 
-size_t elem_size(int precision) { return precision == FPC_FP64 ? 8 : 4; }
-
-// Element stride between planes: N rounded up to 64 elements (256 B in FP32).
+// Element stride between population planes: N rounded up to 64 elements
+// (256 B in FP32), plus FPC_PLANE_PAD elements so that the planes of one
+// node do not all start at the same offset modulo a large power of two.
+#ifndef FPC_PLANE_PAD
+#define FPC_PLANE_PAD 320
+#endif
 size_t plane_of(const fpc_params* p) {
   const size_t N = (size_t)p->nx * p->ny * p->nz;
-  return (N + 63) / 64 * 64;
+  return (N + 63) / 64 * 64 + FPC_PLANE_PAD;
 }
 
 bool rate_ok(double w) { return std::isfinite(w) && w > 0.0 && w < 2.0; }
@@ -79,6 +84,9 @@ int validate(const fpc_params* p) {
   if (dim == 2 && p->nz != 1) return fail(FPC_ERR_SIZE, "2D lattice needs nz == 1");
   const double N = (double)p->nx * p->ny * p->nz;
   if (N * (Qf + Qg) > 4.0e10) return fail(FPC_ERR_SIZE, "grid too large");
+  // kernels address a population plane with 32-bit byte offsets
+  if (N * (double)elem_size(p->precision) >= 4294967296.0)
+    return fail(FPC_ERR_SIZE, "grid too large for 32-bit plane offsets (N * sizeof(real) must be < 4 GiB)");
   if (p->nx > (1 << 24) || p->ny > (1 << 24) || p->nz > 65535) return fail(FPC_ERR_SIZE, "axis too long");
   for (int k = 1; k < Qf; ++k)
     if (!rate_ok(p->omega_f[k])) return fail(FPC_ERR_ARG, "omega_f[%d] = %g outside (0, 2)", k, p->omega_f[k]);

@@ -1,0 +1,306 @@
+// Fused pull-stream + collide kernel (D2Q9 + D2Q5 and D3Q27 + D3Q7).
+//
+// One thread per node.  Each thread gathers its incoming populations
+// f_a(x) = f~_a(x - e_a) from S_{n-1} (Eq. LBMsteps-stream, LBMsteps-streamg);
+// where x - e_a lies outside a wall face it applies the halfway wall rule at
+// its own node (Sec. 6.1):
+//   no-slip      f_a = f~_abar
+//   moving wall  f_a = f~_abar + 2 w_a rho_w (e_a . u_w) / c_s^2
+//   adiabatic    g_a = g~_abar
+//   Dirichlet    g_a = -g~_abar + 2 w^T_a T_w
+// then collides in registers (fpc_collide.h) and stores its own values to S_n.
+//
+// Layout: SoA planes, plane q holds the N node values [z][y][x]; a wavefront
+// covers 64 consecutive x of one row, so every load is a contiguous run of one
+// plane (shifted by at most one element) and every store is fully coalesced.
+//
+// Boundary handling is resolved per wavefront: a ballot tells whether any lane
+// of the wave sits on an x, y or z edge of the box, and the gather is
+// instantiated with range checks only on those axes.  Interior wavefronts (the
+// vast majority) load every population from a wave-uniform plane base with a
+// 32-bit lane offset and no checks at all; x-edge wavefronts check only the
+// links that move along x.  Checked links stay branch-free: a wall redirects
+// the single load of the link to the node's own opposite slot.
+//
+// Stores are non-temporal when the state is too large to stay in the
+// last-level cache (it then streams through HBM anyway); smaller states keep
+// ordinary stores so that the next step reads them from the cache.
+#include "fpc_kernels.h"
+
+
+namespace fpc {
+namespace {
+
+struct Lat2 {
+  static constexpr int D = 2, Qf = kQ2, Qg = kQ2T;
+  static constexpr int ex(int a) { return D2_EX[a]; }
+  static constexpr int ey(int a) { return D2_EY[a]; }
+  static constexpr int ez(int) { return 0; }
+  static constexpr int opp(int a) { return D2_OPP[a]; }
+  static constexpr double w(int a) { return w2(a); }
+};
+
+struct Lat3 {
+  static constexpr int D = 3, Qf = kQ3, Qg = kQ3T;
+  static constexpr int ex(int a) { return D3_EX[a]; }
+  static constexpr int ey(int a) { return D3_EY[a]; }
+  static constexpr int ez(int a) { return D3_EZ[a]; }
+  static constexpr int opp(int a) { return d3_opp(a); }
+  static constexpr double w(int a) { return w3(a); }
+};
+
+// Load base[idx] with a 32-bit byte offset (uniform base + lane offset).
+template <class R>
+__device__ __forceinline__ R ld(const R* base, unsigned idx) {
+  return *reinterpret_cast<const R*>(reinterpret_cast<const char*>(base) + idx * (unsigned)sizeof(R));
+}
+// FPC_BUFFER_OPS = 1 routes unchecked loads and all stores through raw buffer
+// instructions (a wave-uniform descriptor per plane and one 32-bit lane offset
+// shared by every access).  It lowers the register count of the 3D FP32 kernel
+// but measured ~2-4 % slower than global loads on gfx950, so it is off.
+#ifndef FPC_BUFFER_OPS
+#define FPC_BUFFER_OPS 0
+#endif
+constexpr int kBufDword3 = 0x00020000;  // raw (untyped) buffer, gfx9 family
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+
+template <class R>
+__device__ __forceinline__ R ldb(const R* base, unsigned idx) {
+#if FPC_BUFFER_OPS
+  const auto rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<R*>(base), 0, -1, kBufDword3);
+  if constexpr (sizeof(R) == 4)
+    return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b32(rs, idx * 4u, 0, 0));
+  else
+    return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b64(rs, idx * 8u, 0, 0));
+#else
+  return ld(base, idx);
+#endif
+}
+
+template <class R, bool NT>
+__device__ __forceinline__ void st(R* base, unsigned idx, R v) {
+#if FPC_BUFFER_OPS
+  const auto rs = __builtin_amdgcn_make_buffer_rsrc(base, 0, -1, kBufDword3);
+  constexpr int aux = NT ? 2 : 0;  // cache policy: non-temporal
+  if constexpr (sizeof(R) == 4)
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), rs, idx * 4u, 0, aux);
+  else
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), rs, idx * 8u, 0, aux);
+#else
+  R* p = reinterpret_cast<R*>(reinterpret_cast<char*>(base) + idx * (unsigned)sizeof(R));
+  if constexpr (NT)
+    __builtin_nontemporal_store(v, p);
+  else
+    *p = v;
+#endif
+}
+
+template <class L, class R, bool CX, bool CY, bool CZ>
+struct Gather {
+  const StepArgs<R>& a;
+  int x, y, z;
+  unsigned node;
+
+  // Source coordinate along one axis with periodic wrap; `wall` is set when the
+  // link leaves the box through a wall face.
+  template <int E, bool CHECK>
+  __device__ __forceinline__ int src_coord(int c, int n, int per, bool& wall) const {
+    if (E == 0 || !CHECK) return c - E;
+    const int s = c - E;
+    const bool out = E > 0 ? (s < 0) : (s >= n);
+    wall = wall || (out && !per);
+    return out ? (per ? (E > 0 ? n - 1 : 0) : c) : s;
+  }
+
+  // Incoming population of link A of one distribution whose planes start at
+  // `plane0` (fluid: 0, thermal: Qf).  Returns the raw pulled / bounced value
+  // and reports which face was crossed.
+  template <int A, int QBASE>
+  __device__ __forceinline__ R pull(bool& wx, bool& wy, bool& wz) const {
+    constexpr int ex = L::ex(A), ey = L::ey(A), ez = L::ez(A);
+    const R* pA = a.src + (size_t)(QBASE + A) * a.plane;
+    constexpr bool checked = (CX && ex != 0) || (CY && ey != 0) || (CZ && ez != 0);
+    if (!checked) {
+      const long long shift = (long long)ex + (long long)ey * a.nx + (long long)ez * a.nx * a.ny;
+      return ldb(pA - shift, node);
+    }
+    const int xs = src_coord<ex, CX>(x, a.nx, a.per[0], wx);
+    const int ys = src_coord<ey, CY>(y, a.ny, a.per[1], wy);
+    const int zs = src_coord<ez, CZ>(z, a.nz, a.per[2], wz);
+    const bool wall = wx || wy || wz;
+    const unsigned sidx = ((unsigned)zs * (unsigned)a.ny + (unsigned)ys) * (unsigned)a.nx + (unsigned)xs;
+    const R* pO = a.src + (size_t)(QBASE + L::opp(A)) * a.plane;
+    const R* p = wall ? pO : pA;
+    return ld(p, wall ? node : sidx);
+  }
+
+  template <int F>
+  __device__ __forceinline__ R lid_term(int A_ex, int A_ey, int A_ez, double w) const {
+    if (!a.face[F].lid) return R(0);
+    const double eu = A_ex * a.face[F].uw[0] + A_ey * a.face[F].uw[1] + A_ez * a.face[F].uw[2];
+    return R(2.0 * 3.0 * w) * a.rho_w * R(eu);
+  }
+
+  template <int A>
+  __device__ __forceinline__ R f() const {
+    bool wx = false, wy = false, wz = false;
+    R v = pull<A, 0>(wx, wy, wz);
+    constexpr int ex = L::ex(A), ey = L::ey(A), ez = L::ez(A);
+    constexpr bool checked = (CX && ex != 0) || (CY && ey != 0) || (CZ && ez != 0);
+    if (checked) {
+      // moving wall: only when exactly one face is crossed
+      constexpr int FX = ex > 0 ? 0 : 1, FY = ey > 0 ? 2 : 3, FZ = ez > 0 ? 4 : 5;
+      const int nc = (int)wx + (int)wy + (int)wz;
+      R add = R(0);
+      if (ex != 0) add = (nc == 1 && wx) ? lid_term<FX>(ex, ey, ez, L::w(A)) : add;
+      if (ey != 0) add = (nc == 1 && wy) ? lid_term<FY>(ex, ey, ez, L::w(A)) : add;
+      if (ez != 0) add = (nc == 1 && wz) ? lid_term<FZ>(ex, ey, ez, L::w(A)) : add;
+      v += add;
+    }
+    return v;
+  }
+
+  // Thermal link A (axis links: at most one face can be crossed).
+  template <int A>
+  __device__ __forceinline__ R g() const {
+    bool wx = false, wy = false, wz = false;
+    R v = pull<A, L::Qf>(wx, wy, wz);
+    constexpr int ex = L::ex(A), ey = L::ey(A), ez = L::ez(A);
+    constexpr bool checked = (CX && ex != 0) || (CY && ey != 0) || (CZ && ez != 0);
+    if (checked) {
+      constexpr int F = ex > 0 ? 0 : (ex < 0 ? 1 : (ey > 0 ? 2 : (ey < 0 ? 3 : (ez > 0 ? 4 : 5))));
+      constexpr int k = F >> 1;
+      const bool wall = wx || wy || wz;
+      if (a.face[F].dirichlet && wall) {
+        double Tw = a.face[F].Tw;
+        if (a.face[F].Tprof) {
+          const size_t t = k == 0 ? (size_t)z * a.ny + y : (k == 1 ? (size_t)z * a.nx + x : (size_t)y * a.nx + x);
+          Tw = a.face[F].Tprof[t];
+        }
+        v = -v + a.c.cs2T * (R(Tw) - a.c.T_r);  // 2 w^T_a = c^_s^2 on axis links
+      }
+    }
+    return v;
+  }
+};
+
+template <class L, class R, bool CX, bool CY, bool CZ>
+__device__ __forceinline__ void gather(const StepArgs<R>& a, int x, int y, int z, unsigned node, R (&f)[L::Qf],
+                                       R (&g)[L::Qg]) {
+  const Gather<L, R, CX, CY, CZ> p{a, x, y, z, node};
+  if constexpr (L::D == 2) {
+    f[0] = p.template f<0>(); f[1] = p.template f<1>(); f[2] = p.template f<2>();
+    f[3] = p.template f<3>(); f[4] = p.template f<4>(); f[5] = p.template f<5>();
+    f[6] = p.template f<6>(); f[7] = p.template f<7>(); f[8] = p.template f<8>();
+    g[0] = p.template g<0>(); g[1] = p.template g<1>(); g[2] = p.template g<2>();
+    g[3] = p.template g<3>(); g[4] = p.template g<4>();
+  } else {
+#define FPC_F(A) f[A] = p.template f<A>();
+    FPC_F(0) FPC_F(1) FPC_F(2) FPC_F(3) FPC_F(4) FPC_F(5) FPC_F(6) FPC_F(7) FPC_F(8)
+    FPC_F(9) FPC_F(10) FPC_F(11) FPC_F(12) FPC_F(13) FPC_F(14) FPC_F(15) FPC_F(16) FPC_F(17)
+    FPC_F(18) FPC_F(19) FPC_F(20) FPC_F(21) FPC_F(22) FPC_F(23) FPC_F(24) FPC_F(25) FPC_F(26)
+#undef FPC_F
+    g[0] = p.template g<0>(); g[1] = p.template g<1>(); g[2] = p.template g<2>();
+    g[3] = p.template g<3>(); g[4] = p.template g<4>(); g[5] = p.template g<5>();
+    g[6] = p.template g<6>();
+  }
+}
+
+template <class L, class R, int UP, bool NT>
+__device__ __forceinline__ void collide_store(const StepArgs<R>& a, unsigned node, R (&f)[L::Qf], R (&g)[L::Qg]) {
+  if constexpr (L::D == 2)
+    collide2d<R, UP>(f, g, a.c, (Macros<R>*)nullptr);
+  else
+    collide3d<R, UP>(f, g, a.c, (Macros<R>*)nullptr);
+#pragma unroll
+  for (int q = 0; q < L::Qf; ++q) st<R, NT>(a.dst + (size_t)q * a.plane, node, f[q]);
+#pragma unroll
+  for (int q = 0; q < L::Qg; ++q) st<R, NT>(a.dst + (size_t)(L::Qf + q) * a.plane, node, g[q]);
+}
+
+__device__ __forceinline__ unsigned node_of(int x, int y, int z, int nx, int ny) {
+  return ((unsigned)z * (unsigned)ny + (unsigned)y) * (unsigned)nx + (unsigned)x;
+}
+
+template <class L, class R, int UP, bool NT>
+__global__ void __launch_bounds__(256) step_kernel(StepArgs<R> a) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= a.nx || y >= a.ny) return;
+  const unsigned node = node_of(x, y, z, a.nx, a.ny);
+  R f[L::Qf], g[L::Qg];
+  // which axes have an edge node in this wavefront (wave-uniform)
+  const bool needx = __any(x == 0 || x == a.nx - 1);
+  const bool needy = __any(y == 0 || y == a.ny - 1);
+  const bool needz = L::D == 3 && __any(z == 0 || z == a.nz - 1);
+  if (!needy && !needz) {
+    if (!needx)
+      gather<L, R, false, false, false>(a, x, y, z, node, f, g);
+    else
+      gather<L, R, true, false, false>(a, x, y, z, node, f, g);
+  } else {
+    gather<L, R, true, true, L::D == 3>(a, x, y, z, node, f, g);
+  }
+  collide_store<L, R, UP, NT>(a, node, f, g);
+}
+
+// Initial state: the collision of f = w rho0, g = w^T T_init at every node.
+template <class L, class R, int UP>
+__global__ void __launch_bounds__(256) init_kernel(StepArgs<R> a, const double* __restrict__ T_init) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= a.nx || y >= a.ny) return;
+  const unsigned node = node_of(x, y, z, a.nx, a.ny);
+  R f[L::Qf], g[L::Qg];
+  const R drw = a.rho_w - a.c.rho_r;
+#pragma unroll
+  for (int q = 0; q < L::Qf; ++q) f[q] = R(L::w(q)) * drw;
+  const R dT = R(T_init[node]) - a.c.T_r;
+  g[0] = (R(1) - R(L::D) * a.c.cs2T) * dT;
+#pragma unroll
+  for (int q = 1; q < L::Qg; ++q) g[q] = R(0.5) * a.c.cs2T * dT;
+  collide_store<L, R, UP, false>(a, node, f, g);
+}
+
+template <class L, class R, int UP>
+hipError_t launch_up(const StepArgs<R>& a, const double* T_init, int mode, hipStream_t s) {
+  const int bx = a.nx >= 256 ? 256 : (a.nx >= 128 ? 128 : 64);
+  const int by = 256 / bx;
+  const dim3 block(bx, by, 1);
+  const dim3 grid((a.nx + bx - 1) / bx, (a.ny + by - 1) / by, a.nz);
+  if (mode == 1) {
+    init_kernel<L, R, UP><<<grid, block, 0, s>>>(a, T_init);
+    return hipGetLastError();
+  }
+  const double state_bytes = (double)a.plane * (L::Qf + L::Qg) * sizeof(R);
+  if (state_bytes > 128.0 * 1024 * 1024)
+    step_kernel<L, R, UP, true><<<grid, block, 0, s>>>(a);
+  else
+    step_kernel<L, R, UP, false><<<grid, block, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+template <class R>
+hipError_t launch_step2d(const StepArgs<R>& a, int up, const double* T_init, int mode, hipStream_t s) {
+  return up == 0 ? launch_up<Lat2, R, 0>(a, T_init, mode, s) : launch_up<Lat2, R, 1>(a, T_init, mode, s);
+}
+
+template <class R>
+hipError_t launch_step3d(const StepArgs<R>& a, int up, const double* T_init, int mode, hipStream_t s) {
+  switch (up) {
+    case 0: return launch_up<Lat3, R, 0>(a, T_init, mode, s);
+    case 1: return launch_up<Lat3, R, 1>(a, T_init, mode, s);
+    default: return launch_up<Lat3, R, 2>(a, T_init, mode, s);
+  }
+}
+
+template hipError_t launch_step2d<double>(const StepArgs<double>&, int, const double*, int, hipStream_t);
+template hipError_t launch_step2d<float>(const StepArgs<float>&, int, const double*, int, hipStream_t);
+template hipError_t launch_step3d<double>(const StepArgs<double>&, int, const double*, int, hipStream_t);
+template hipError_t launch_step3d<float>(const StepArgs<float>&, int, const double*, int, hipStream_t);
+
+}  // namespace fpc
