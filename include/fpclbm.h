@@ -204,6 +204,33 @@ int fpc_import_fp64(fpc_sim* s, const double* src, long long step);
 /* Device pointer of the buffer that holds the current state. */
 int fpc_current_buffer(const fpc_sim* s, void** ptr);
 
+/*
+ * Adjoint (reverse mode) of one time step S_n = Phi(S_{n-1}), for an objective
+ * J whose direct dependence on S_n is through the time-n macros.  Computes
+ *   lam_out = (d S_n / d S_{n-1})^T (lam_in + dJ/dS_n)
+ * where dJ/dS_n is formed in the kernel from
+ *   dJdT[x]    weight of T_n(x)  (device, N FP64 values, or NULL), and
+ *   ke_weight  weight of the kinetic energy 1/2 sum rho |u|^2 of time n,
+ * and accumulates (+=) the gradient with respect to the per-node Dirichlet
+ * wall temperature of face f into dJdtheta[f] (device, FP64, profile layout
+ * of fpc_params.wall_T_profile; dJdtheta may be NULL, or hold NULL entries).
+ * S_prev: S_{n-1} in storage format (fpc_state_bytes()).  lam_in, lam_out:
+ * adjoint states in the same layout and element type as the state (FP64 or
+ * FP32), holding adjoints of the stored values; every element of lam_out that
+ * belongs to a node is written (padding is not).  The method is not part of
+ * the paper: this is the exact adjoint of the discrete update above.
+ */
+int fpc_adjoint_step(fpc_sim* s, const void* S_prev, const void* lam_in, void* lam_out, const double* dJdT,
+                     double ke_weight, double* const* dJdtheta);
+
+/*
+ * Adjoint of the initial collision (fpc_init): given lam0 = dJ/dS_0 without
+ * the level-0 seed, adds the seed (dJdT, ke_weight as in fpc_adjoint_step) and
+ * writes dJ/dT_init[x] (device, N FP64 values).
+ */
+int fpc_adjoint_init(fpc_sim* s, const double* T_init, const void* lam0, const double* dJdT, double ke_weight,
+                     double* dJdT_init);
+
 #ifdef __cplusplus
 }
 #endif

@@ -40,7 +40,7 @@ EXPORTED = (
     "fpc_version", "fpc_last_error", "fpc_params_default", "fpc_params_natural", "fpc_params_mixed",
     "fpc_state_bytes", "fpc_create", "fpc_destroy", "fpc_set_stream", "fpc_init", "fpc_step",
     "fpc_get_step", "fpc_macros", "fpc_diagnostics", "fpc_save", "fpc_load", "fpc_export_fp64",
-    "fpc_import_fp64", "fpc_current_buffer",
+    "fpc_import_fp64", "fpc_current_buffer", "fpc_adjoint_step", "fpc_adjoint_init",
 )
 
 
@@ -112,6 +112,8 @@ def load():
         "fpc_export_fp64": (i, [vp, vp]),
         "fpc_import_fp64": (i, [vp, vp, ll]),
         "fpc_current_buffer": (i, [vp, ctypes.POINTER(vp)]),
+        "fpc_adjoint_step": (i, [vp, vp, vp, vp, vp, d, ctypes.POINTER(vp)]),
+        "fpc_adjoint_init": (i, [vp, vp, vp, vp, d, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

@@ -17,7 +17,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libfpclbm.so")
-SOURCES = ["fpc_abi.hip", "fpc_step.hip", "fpc_kernels_util.hip"]
+SOURCES = ["fpc_abi.hip", "fpc_step.hip", "fpc_adjoint.hip", "fpc_kernels_util.hip"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [

@@ -446,6 +446,45 @@ int fpc_import_fp64(fpc_sim* s, const double* src, long long step) {
   return FPC_OK;
 }
 
+int fpc_adjoint_step(fpc_sim* s, const void* S_prev, const void* lam_in, void* lam_out, const double* dJdT,
+                     double ke_weight, double* const* dJdtheta) {
+  if (!s || !S_prev || !lam_in || !lam_out) return fail(FPC_ERR_ARG, "NULL argument");
+  if (lam_in == lam_out || lam_out == S_prev) return fail(FPC_ERR_ARG, "lam_out must not alias lam_in or S_prev");
+  if (!std::isfinite(ke_weight)) return fail(FPC_ERR_ARG, "ke_weight not finite");
+  double* dth[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  if (dJdtheta)
+    for (int f = 0; f < 6; ++f) dth[f] = dJdtheta[f];
+  for (int f = 0; f < 6; ++f)
+    if (dth[f] && !(s->p.bc[f] == FPC_BC_NOSLIP_DIRICHLET || s->p.bc[f] == FPC_BC_LID_DIRICHLET))
+      return fail(FPC_ERR_STATE, "dJdtheta[%d] given for a face without a Dirichlet temperature", f);
+  hipError_t e;
+  if (s->p.precision == FPC_FP64) {
+    const StepArgs<double> a = make_args<double>(s, S_prev, nullptr);
+    e = launch_adjoint_step<double>(a, s->dim, s->p.up_axis, lam_in, lam_out, dJdT, ke_weight, dth, s->stream);
+  } else {
+    const StepArgs<float> a = make_args<float>(s, S_prev, nullptr);
+    e = launch_adjoint_step<float>(a, s->dim, s->p.up_axis, lam_in, lam_out, dJdT, ke_weight, dth, s->stream);
+  }
+  if (e != hipSuccess) return hipfail(e, "adjoint step kernel");
+  return FPC_OK;
+}
+
+int fpc_adjoint_init(fpc_sim* s, const double* T_init, const void* lam0, const double* dJdT, double ke_weight,
+                     double* dJdT_init) {
+  if (!s || !T_init || !lam0 || !dJdT_init) return fail(FPC_ERR_ARG, "NULL argument");
+  if (!std::isfinite(ke_weight)) return fail(FPC_ERR_ARG, "ke_weight not finite");
+  hipError_t e;
+  if (s->p.precision == FPC_FP64) {
+    const StepArgs<double> a = make_args<double>(s, nullptr, nullptr);
+    e = launch_adjoint_init<double>(a, s->dim, s->p.up_axis, T_init, lam0, dJdT, ke_weight, dJdT_init, s->stream);
+  } else {
+    const StepArgs<float> a = make_args<float>(s, nullptr, nullptr);
+    e = launch_adjoint_init<float>(a, s->dim, s->p.up_axis, T_init, lam0, dJdT, ke_weight, dJdT_init, s->stream);
+  }
+  if (e != hipSuccess) return hipfail(e, "adjoint init kernel");
+  return FPC_OK;
+}
+
 int fpc_current_buffer(const fpc_sim* s, void** ptr) {
   if (!s || !ptr) return fail(FPC_ERR_ARG, "NULL argument");
   *ptr = s->buf[s->cur];

@@ -1,0 +1,470 @@
+// Reverse-mode (adjoint) of the node-local collision, written by hand.
+//
+// The forward map differentiated here is the same collision as in
+// fpc_collide.h (Sec. 4.1-4.2, 5.1-5.2 and App. A for f; Sec. 4.3-4.4, 5.3 and
+// App. B/C, option A, for g), evaluated on plain populations:
+//   rho = sum f, j = sum f e, T = sum g, F = g beta (T - T0) e_up,
+//   u = (j + F/2) / rho                                         (App. A Step 7)
+//   kappa = C(u) f        (central moments, tensor product of 1D shifts)
+//   kappa~: relaxation order by order, attractors from the recurrence with
+//           D' = c_s^2 I up to second order and D'_ab = kappa~_ab / rho above,
+//           sources sigma_m = m_up (F/rho) kappa_{m - e_up}     (Eq. sourceCM2D)
+//   f~ = C(u)^-1 kappa~
+//   eta = C_g(u) g, eta~ (option A), g~ = C_g(u)^-1 eta~.
+//
+// Reverse-mode identities used (no intermediate of the shift passes is kept):
+//   d kappa_m / d u_i = -m_i kappa_{m - e_i}, so for kappa = C(u) f
+//     fbar = C(u)^T kappabar,  ubar_i -= sum_m kappabar_m m_i kappa_{m - e_i};
+//   for f~ = C(u)^-1 kappa~ (C(u) f~ = kappa~):
+//     kappa~bar = C(u)^-T f~bar,  ubar_i += sum_m kappa~bar_m m_i kappa~_{m - e_i}.
+// C(u)^T and C(u)^-T are applied as the transposed 1D maps in reverse pass order.
+#pragma once
+
+#include "fpc_collide.h"
+
+namespace fpc {
+namespace adj {
+
+// Moment / population work space of the tensor-product lattice (3^D entries):
+// entry (a, b, c) with a, b, c in {0, 1, 2} is either the link (a-1, b-1, c-1)
+// or the central moment with exponents (a, b, c).
+template <int D>
+struct MS {
+  static constexpr int NM = D == 2 ? 9 : 27;
+  static constexpr int at(int a, int b, int c) { return D == 2 ? a * 3 + b : a * 9 + b * 3 + c; }
+  static constexpr int ma(int i) { return D == 2 ? i / 3 : i / 9; }
+  static constexpr int mb(int i) { return D == 2 ? i % 3 : (i / 3) % 3; }
+  static constexpr int mc(int i) { return D == 2 ? 0 : i % 3; }
+  static constexpr int m(int i, int ax) { return ax == 0 ? ma(i) : (ax == 1 ? mb(i) : mc(i)); }
+  static constexpr int order(int i) { return ma(i) + mb(i) + mc(i); }
+  // index of the moment m - e_ax (caller guarantees m_ax > 0)
+  static constexpr int down(int i, int ax) {
+    return at(ma(i) - (ax == 0), mb(i) - (ax == 1), mc(i) - (ax == 2));
+  }
+  // population index (paper order) of entry i read as a link
+  static constexpr int pop(int i) {
+    return D == 2 ? d2_index(ma(i) - 1, mb(i) - 1) : d3_index(ma(i) - 1, mb(i) - 1, mc(i) - 1);
+  }
+  // relaxation-rate slot of moment i (paper order of the moment vector; the
+  // diagonal second-order slots hold the rates of their combinations)
+  static constexpr int slot(int i) {
+    if (D == 2) {
+      constexpr int s2[9] = {0, 2, 4, 1, 5, 7, 3, 6, 8};  // at(a,b) -> slot
+      return s2[i];
+    }
+    constexpr int list[27][3] = {{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {1, 1, 0}, {1, 0, 1}, {0, 1, 1},
+                                 {2, 0, 0}, {0, 2, 0}, {0, 0, 2}, {1, 2, 0}, {1, 0, 2}, {2, 1, 0}, {0, 1, 2},
+                                 {2, 0, 1}, {0, 2, 1}, {1, 1, 1}, {2, 2, 0}, {2, 0, 2}, {0, 2, 2}, {2, 1, 1},
+                                 {1, 2, 1}, {1, 1, 2}, {1, 2, 2}, {2, 1, 2}, {2, 2, 1}, {2, 2, 2}};
+    for (int k = 0; k < 27; ++k)
+      if (list[k][0] == ma(i) && list[k][1] == mb(i) && list[k][2] == mc(i)) return k;
+    return -1;
+  }
+};
+
+// Transposed 1D maps.  S(u): (a-, a0, a+) -> (k0, k1, k2) is shift_fwd.
+template <class R>
+__device__ __forceinline__ void shift_fwd_T(R k0, R k1, R k2, R u, R& am, R& a0, R& ap) {
+  am = k0 + (R(-1) - u) * k1 + (R(1) + u) * (R(1) + u) * k2;
+  a0 = k0 - u * k1 + u * u * k2;
+  ap = k0 + (R(1) - u) * k1 + (R(1) - u) * (R(1) - u) * k2;
+}
+// S(u)^-1: (k0, k1, k2) -> (a-, a0, a+) is shift_inv; its transpose maps
+// (a-bar, a0bar, a+bar) -> (k0bar, k1bar, k2bar).
+template <class R>
+__device__ __forceinline__ void shift_inv_T(R am, R a0, R ap, R u, R& k0, R& k1, R& k2) {
+  k0 = (R(1) - u * u) * a0 + R(0.5) * (u * u + u) * ap + R(0.5) * (u * u - u) * am;
+  k1 = R(-2) * u * a0 + R(0.5) * (R(2) * u + R(1)) * ap + R(0.5) * (R(2) * u - R(1)) * am;
+  k2 = -a0 + R(0.5) * ap + R(0.5) * am;
+}
+
+// Apply C(u) (mode 0), C(u)^-1 (mode 1), C(u)^T (mode 2) or C(u)^-T (mode 3)
+// in place to a work array of the tensor-product lattice.
+template <class R, int D, int MODE>
+__device__ __forceinline__ void apply(R (&w)[MS<D>::NM], const R (&u)[3]) {
+  using M = MS<D>;
+  auto pass = [&](int ax) {
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+      for (int q = 0; q < (D == 2 ? 1 : 3); ++q) {
+        int i0, i1, i2;
+        if (D == 2) {
+          i0 = ax == 0 ? M::at(0, p, 0) : M::at(p, 0, 0);
+          i1 = ax == 0 ? M::at(1, p, 0) : M::at(p, 1, 0);
+          i2 = ax == 0 ? M::at(2, p, 0) : M::at(p, 2, 0);
+        } else {
+          i0 = ax == 0 ? M::at(0, p, q) : (ax == 1 ? M::at(p, 0, q) : M::at(p, q, 0));
+          i1 = ax == 0 ? M::at(1, p, q) : (ax == 1 ? M::at(p, 1, q) : M::at(p, q, 1));
+          i2 = ax == 0 ? M::at(2, p, q) : (ax == 1 ? M::at(p, 2, q) : M::at(p, q, 2));
+        }
+        const R a = w[i0], b = w[i1], c = w[i2];
+        if (MODE == 0) shift_fwd(a, b, c, u[ax], w[i0], w[i1], w[i2]);
+        if (MODE == 1) shift_inv(a, b, c, u[ax], w[i0], w[i1], w[i2]);
+        if (MODE == 2) shift_fwd_T(a, b, c, u[ax], w[i0], w[i1], w[i2]);
+        if (MODE == 3) shift_inv_T(a, b, c, u[ax], w[i0], w[i1], w[i2]);
+      }
+  };
+  // C = Z Y X (x pass first); C^-1 = X^-1 Y^-1 Z^-1 (z pass first);
+  // C^T = X^T Y^T Z^T (z pass first); C^-T = Z^-T Y^-T X^-T (x pass first).
+  if (MODE == 0 || MODE == 3) {
+    pass(0);
+    pass(1);
+    if (D == 3) pass(2);
+  } else {
+    if (D == 3) pass(2);
+    pass(1);
+    pass(0);
+  }
+}
+
+// Attractor terms of the recurrence (Eq. Mvcmattractor2D / 3D) for moment i of
+// order s >= 3 with D'_ab = kappa~_ab / rho: Mv_i = sum_t c_t kt[A_t] kt[B_t] / (s rho)
+// over t = (axis pair), A_t the second-order moment, B_t = i - A_t; terms whose
+// B_t has order 1 vanish (first-order moments taken as zero).
+template <int D>
+struct Terms {
+  using M = MS<D>;
+  // enumerate: t in [0, D*(D+1)/2): (i, i) then (i, j) i < j
+  static constexpr int npairs = D == 2 ? 3 : 6;
+  static constexpr int axA(int t) { return D == 2 ? (t == 0 ? 0 : (t == 1 ? 1 : 0)) : (t < 3 ? t : (t == 3 ? 0 : (t == 4 ? 0 : 1))); }
+  static constexpr int axB(int t) { return D == 2 ? (t == 0 ? 0 : (t == 1 ? 1 : 1)) : (t < 3 ? t : (t == 3 ? 1 : 2)); }
+  static constexpr int coef(int i, int t) {
+    const int a = axA(t), b = axB(t);
+    return a == b ? M::m(i, a) * (M::m(i, a) - 1) : 2 * M::m(i, a) * M::m(i, b);
+  }
+  static constexpr int A(int t) {
+    const int a = axA(t), b = axB(t);
+    return M::at((a == 0) + (b == 0), (a == 1) + (b == 1), (a == 2) + (b == 2));
+  }
+  static constexpr bool valid(int i, int t) {
+    if (coef(i, t) == 0) return false;
+    const int a = axA(t), b = axB(t);
+    const int ra = M::m(i, 0) - (a == 0) - (b == 0), rb = M::m(i, 1) - (a == 1) - (b == 1),
+              rc = M::m(i, 2) - (a == 2) - (b == 2);
+    return ra >= 0 && rb >= 0 && rc >= 0 && ra + rb + rc != 1;
+  }
+  static constexpr int B(int i, int t) {
+    const int a = axA(t), b = axB(t);
+    return M::at(M::m(i, 0) - (a == 0) - (b == 0), M::m(i, 1) - (a == 1) - (b == 1), M::m(i, 2) - (a == 2) - (b == 2));
+  }
+};
+
+// Forward collision on plain populations with everything the reverse needs.
+template <class R, int D>
+struct Tape {
+  static constexpr int NM = MS<D>::NM;
+  static constexpr int NG = 2 * D + 1;
+  R rho, T, Fb, u[3];
+  R k[NM];   // pre-collision central moments
+  R kt[NM];  // post-collision central moments
+  R e[NG];   // thermal central moments (0, +-axis order 1, order 2 per axis)
+  R et[NG];  // post-collision thermal central moments
+};
+
+// Thermal moment layout (D2Q5 / D3Q7): e[0] = eta_0, e[1+ax] = eta_{e_ax},
+// e[1+D+ax] = eta_{2 e_ax}.  Populations: g[0] rest, g[1+2ax] = +ax link,
+// g[2+2ax] = -ax link (this is the D3Q7 order; for D2Q5 the paper order
+// 0, +x, +y, -x, -y is mapped by tlink()).
+template <int D>
+__device__ constexpr int tlink(int ax, int sgn) {
+  return D == 2 ? (sgn > 0 ? 1 + ax : 3 + ax) : (sgn > 0 ? 1 + 2 * ax : 2 + 2 * ax);
+}
+
+template <class R, int D, int UP>
+__device__ __forceinline__ void forward(const R* f, const R* g, const CollParams<R>& c, Tape<R, D>& t) {
+  using M = MS<D>;
+  constexpr int NM = M::NM;
+  constexpr R cs2 = R(1) / R(3);
+  R rho = R(0), j[3] = {R(0), R(0), R(0)};
+#pragma unroll
+  for (int i = 0; i < NM; ++i) {
+    const R v = f[M::pop(i)];
+    rho += v;
+    if (M::ma(i) != 1) j[0] += M::ma(i) == 2 ? v : -v;
+    if (M::mb(i) != 1) j[1] += M::mb(i) == 2 ? v : -v;
+    if (D == 3 && M::mc(i) != 1) j[2] += M::mc(i) == 2 ? v : -v;
+  }
+  R T = R(0);
+#pragma unroll
+  for (int q = 0; q < 2 * D + 1; ++q) T += g[q];
+  const R Fb = c.gbeta * (T - c.T0);
+  t.rho = rho;
+  t.T = T;
+  t.Fb = Fb;
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax) t.u[ax] = ax < D ? (j[ax] + (ax == UP ? R(0.5) * Fb : R(0))) / rho : R(0);
+#pragma unroll
+  for (int i = 0; i < NM; ++i) t.k[i] = f[M::pop(i)];
+  apply<R, D, 0>(t.k, t.u);
+  // relaxation, order by order
+  const R* om = c.om;
+  const R Fr = Fb / rho;
+#pragma unroll
+  for (int i = 0; i < NM; ++i) {
+    const int s = M::order(i);
+    if (s == 0) t.kt[i] = rho;
+    if (s == 1) {
+      const int ax = M::ma(i) ? 0 : (M::mb(i) ? 1 : 2);
+      const R w = om[M::slot(i)];
+      t.kt[i] = t.k[i] - w * t.k[i] + (R(1) - R(0.5) * w) * (ax == UP ? Fb : R(0));
+    }
+    if (s == 2 && (M::ma(i) == 1 || M::mb(i) == 1 || M::mc(i) == 1)) t.kt[i] = (R(1) - om[M::slot(i)]) * t.k[i];
+  }
+  // diagonal second order as combinations (trace / deviators in 3D, 2s / 2d in 2D)
+  if (D == 2) {
+    const int a = M::at(2, 0, 0), b = M::at(0, 2, 0);
+    const R s2 = t.k[a] + t.k[b], d2 = t.k[a] - t.k[b];
+    const R ts = s2 + om[3] * (R(2) * cs2 * rho - s2);
+    const R td = d2 - om[4] * d2;
+    t.kt[a] = R(0.5) * (ts + td);
+    t.kt[b] = R(0.5) * (ts - td);
+  } else {
+    const int a = M::at(2, 0, 0), b = M::at(0, 2, 0), cc = M::at(0, 0, 2);
+    const R tr = t.k[a] + t.k[b] + t.k[cc], d1 = t.k[a] - t.k[b], d2 = t.k[a] - t.k[cc];
+    const R ttr = tr + om[7] * (R(3) * cs2 * rho - tr);
+    const R t1 = d1 - om[8] * d1, t2 = d2 - om[9] * d2;
+    const R t200 = (ttr + t1 + t2) * (R(1) / R(3));
+    t.kt[a] = t200;
+    t.kt[b] = t200 - t1;
+    t.kt[cc] = t200 - t2;
+  }
+  // orders >= 3
+#pragma unroll
+  for (int s = 3; s <= 2 * D; ++s) {
+#pragma unroll
+    for (int i = 0; i < NM; ++i) {
+      if (M::order(i) != s) continue;
+      R mv = R(0);
+#pragma unroll
+      for (int p = 0; p < Terms<D>::npairs; ++p)
+        if (Terms<D>::valid(i, p)) mv += R(Terms<D>::coef(i, p)) * t.kt[Terms<D>::A(p)] * t.kt[Terms<D>::B(i, p)];
+      mv = mv / (R(s) * rho);
+      R sig = R(0);
+      const int mu = M::m(i, UP);
+      if (mu > 0 && M::order(M::down(i, UP)) >= 2) sig = R(mu) * Fr * t.k[M::down(i, UP)];
+      const R w = om[M::slot(i)];
+      t.kt[i] = t.k[i] + w * (mv - t.k[i]) + (R(1) - R(0.5) * w) * sig;
+    }
+  }
+  // thermal: raw -> central
+  R n[2 * D + 1];
+  n[0] = T;
+#pragma unroll
+  for (int ax = 0; ax < D; ++ax) {
+    const R gp = g[tlink<D>(ax, 1)], gm = g[tlink<D>(ax, -1)];
+    n[1 + ax] = gp - gm;
+    n[1 + D + ax] = gp + gm;
+  }
+  t.e[0] = T;
+#pragma unroll
+  for (int ax = 0; ax < D; ++ax) {
+    t.e[1 + ax] = n[1 + ax] - t.u[ax] * T;
+    t.e[1 + D + ax] = n[1 + D + ax] - R(2) * t.u[ax] * n[1 + ax] + t.u[ax] * t.u[ax] * T;
+  }
+  const R* og = c.omg;
+  t.et[0] = T;
+#pragma unroll
+  for (int ax = 0; ax < D; ++ax) t.et[1 + ax] = (R(1) - og[1 + ax]) * t.e[1 + ax];
+  if (D == 2) {
+    const R s2 = t.e[3] + t.e[4], d2 = t.e[3] - t.e[4];
+    const R ts = s2 + og[3] * (R(2) * c.cs2T * T - s2);
+    const R td = d2 - og[4] * d2;
+    t.et[3] = R(0.5) * (ts + td);
+    t.et[4] = R(0.5) * (ts - td);
+  } else {
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) t.et[4 + ax] = t.e[4 + ax] + og[4 + ax] * (c.cs2T * T - t.e[4 + ax]);
+  }
+}
+
+// Reverse of forward(): given fb (= f~bar) and gb (= g~bar) on the post-collision
+// populations, overwrite them with the adjoints of the pre-collision ones.
+template <class R, int D, int UP>
+__device__ __forceinline__ void reverse(const Tape<R, D>& t, const CollParams<R>& c, R* fb, R* gb) {
+  using M = MS<D>;
+  constexpr int NM = M::NM;
+  constexpr R cs2 = R(1) / R(3);
+  R ub[3] = {R(0), R(0), R(0)};
+  R rhob = R(0), Fbb = R(0), Tb = R(0);
+  const R* og = c.omg;
+
+  // ---- thermal: g~ = P_g^-1 F_g(u)^-1 eta~ ----
+  {
+    R mb[2 * D + 1];  // adjoint of the post-collision raw moments
+    R etb[2 * D + 1];
+    // g~_0 = m0 - sum_ax m_{2ax};  g~_{+-ax} = (m_{2ax} +- m_{ax}) / 2
+    mb[0] = gb[0];
+#pragma unroll
+    for (int ax = 0; ax < D; ++ax) {
+      const R gp = gb[tlink<D>(ax, 1)], gm = gb[tlink<D>(ax, -1)];
+      mb[1 + ax] = R(0.5) * (gp - gm);
+      mb[1 + D + ax] = R(0.5) * (gp + gm) - gb[0];
+    }
+    // m_ax = et_ax + u_ax T ; m_2ax = et_2ax + 2 u_ax et_ax + u_ax^2 T ; m_0 = T
+    etb[0] = mb[0];
+#pragma unroll
+    for (int ax = 0; ax < D; ++ax) {
+      const R ua = t.u[ax];
+      etb[1 + D + ax] = mb[1 + D + ax];
+      etb[1 + ax] = mb[1 + ax] + R(2) * ua * mb[1 + D + ax];
+      etb[0] += ua * mb[1 + ax] + ua * ua * mb[1 + D + ax];
+      ub[ax] += t.T * mb[1 + ax] + (R(2) * t.et[1 + ax] + R(2) * ua * t.T) * mb[1 + D + ax];
+    }
+    // relaxation: et_0 = T; et_ax = (1 - w) e_ax; second order toward c^2 T
+    R eb[2 * D + 1];
+    Tb += etb[0];
+#pragma unroll
+    for (int ax = 0; ax < D; ++ax) eb[1 + ax] = (R(1) - og[1 + ax]) * etb[1 + ax];
+    if (D == 2) {
+      const R tsb = R(0.5) * (etb[3] + etb[4]), tdb = R(0.5) * (etb[3] - etb[4]);
+      const R s2b = (R(1) - og[3]) * tsb, d2b = (R(1) - og[4]) * tdb;
+      Tb += og[3] * R(2) * c.cs2T * tsb;
+      eb[3] = s2b + d2b;
+      eb[4] = s2b - d2b;
+    } else {
+#pragma unroll
+      for (int ax = 0; ax < 3; ++ax) {
+        eb[4 + ax] = (R(1) - og[4 + ax]) * etb[4 + ax];
+        Tb += og[4 + ax] * c.cs2T * etb[4 + ax];
+      }
+    }
+    // e_ax = n_ax - u_ax T ; e_2ax = n_2ax - 2 u_ax n_ax + u_ax^2 T ; e_0 = T
+    R nb[2 * D + 1];
+    nb[0] = R(0);
+#pragma unroll
+    for (int ax = 0; ax < D; ++ax) {
+      const R ua = t.u[ax];
+      const R nax = t.e[1 + ax] + ua * t.T;  // n_ax
+      nb[1 + D + ax] = eb[1 + D + ax];
+      nb[1 + ax] = eb[1 + ax] - R(2) * ua * eb[1 + D + ax];
+      Tb += -ua * eb[1 + ax] + ua * ua * eb[1 + D + ax];
+      ub[ax] += -t.T * eb[1 + ax] + (R(-2) * nax + R(2) * ua * t.T) * eb[1 + D + ax];
+    }
+    // n_ax = g+ - g- ; n_2ax = g+ + g- ; T = sum g
+    gb[0] = R(0);
+#pragma unroll
+    for (int ax = 0; ax < D; ++ax) {
+      gb[tlink<D>(ax, 1)] = nb[1 + ax] + nb[1 + D + ax];
+      gb[tlink<D>(ax, -1)] = -nb[1 + ax] + nb[1 + D + ax];
+    }
+  }
+
+  // ---- fluid: f~ = C(u)^-1 kappa~ ----
+  R kb[NM];
+#pragma unroll
+  for (int i = 0; i < NM; ++i) kb[i] = fb[M::pop(i)];
+  apply<R, D, 3>(kb, t.u);  // kappa~bar
+#pragma unroll
+  for (int i = 0; i < NM; ++i)
+#pragma unroll
+    for (int ax = 0; ax < D; ++ax)
+      if (M::m(i, ax) > 0) ub[ax] += kb[i] * R(M::m(i, ax)) * t.kt[M::down(i, ax)];
+  // relaxation reverse, highest order first; kb holds kappa~bar, kp the
+  // adjoint of the pre-collision moments
+  R kp[NM];
+#pragma unroll
+  for (int i = 0; i < NM; ++i) kp[i] = R(0);
+  const R* om = c.om;
+  const R Fr = t.Fb / t.rho;
+#pragma unroll
+  for (int s = 2 * D; s >= 3; --s) {
+#pragma unroll
+    for (int i = 0; i < NM; ++i) {
+      if (M::order(i) != s) continue;
+      const R w = om[M::slot(i)];
+      const R ktb = kb[i];
+      kp[i] += (R(1) - w) * ktb;
+      // attractor
+      const R mvb = w * ktb;
+      R mv = R(0);
+#pragma unroll
+      for (int p = 0; p < Terms<D>::npairs; ++p)
+        if (Terms<D>::valid(i, p)) {
+          const int A = Terms<D>::A(p), B = Terms<D>::B(i, p);
+          const R cf = R(Terms<D>::coef(i, p)) / (R(s) * t.rho);
+          mv += cf * t.kt[A] * t.kt[B];
+          kb[A] += mvb * cf * t.kt[B];
+          kb[B] += mvb * cf * t.kt[A];
+        }
+      rhob -= mvb * mv / t.rho;
+      // source
+      const int mu = M::m(i, UP);
+      if (mu > 0 && M::order(M::down(i, UP)) >= 2) {
+        const R sb = (R(1) - R(0.5) * w) * ktb;
+        const int p = M::down(i, UP);
+        const R sig = R(mu) * Fr * t.k[p];
+        Fbb += sb * R(mu) * t.k[p] / t.rho;
+        kp[p] += sb * R(mu) * Fr;
+        rhob -= sb * sig / t.rho;
+      }
+    }
+  }
+  // second order: off-diagonal
+#pragma unroll
+  for (int i = 0; i < NM; ++i)
+    if (M::order(i) == 2 && (M::ma(i) == 1 || M::mb(i) == 1 || M::mc(i) == 1))
+      kp[i] += (R(1) - om[M::slot(i)]) * kb[i];
+  // second order: diagonal combinations
+  if (D == 2) {
+    const int a = M::at(2, 0, 0), b = M::at(0, 2, 0);
+    const R tsb = R(0.5) * (kb[a] + kb[b]), tdb = R(0.5) * (kb[a] - kb[b]);
+    const R s2b = (R(1) - om[3]) * tsb, d2b = (R(1) - om[4]) * tdb;
+    rhob += om[3] * R(2) * cs2 * tsb;
+    kp[a] += s2b + d2b;
+    kp[b] += s2b - d2b;
+  } else {
+    const int a = M::at(2, 0, 0), b = M::at(0, 2, 0), cc = M::at(0, 0, 2);
+    const R third = R(1) / R(3);
+    const R ttrb = (kb[a] + kb[b] + kb[cc]) * third;
+    const R t1b = (kb[a] - R(2) * kb[b] + kb[cc]) * third;
+    const R t2b = (kb[a] + kb[b] - R(2) * kb[cc]) * third;
+    const R trb = (R(1) - om[7]) * ttrb, d1b = (R(1) - om[8]) * t1b, d2b = (R(1) - om[9]) * t2b;
+    rhob += om[7] * R(3) * cs2 * ttrb;
+    kp[a] += trb + d1b + d2b;
+    kp[b] += trb - d1b;
+    kp[cc] += trb - d2b;
+  }
+  // first order: kt = (1 - w) k + (1 - w/2) F
+#pragma unroll
+  for (int i = 0; i < NM; ++i)
+    if (M::order(i) == 1) {
+      const int ax = M::ma(i) ? 0 : (M::mb(i) ? 1 : 2);
+      const R w = om[M::slot(i)];
+      kp[i] += (R(1) - w) * kb[i];
+      if (ax == UP) Fbb += (R(1) - R(0.5) * w) * kb[i];
+    }
+  // zeroth order: kt_0 = rho
+  rhob += kb[M::at(0, 0, 0)];
+  // kappa = C(u) f
+#pragma unroll
+  for (int i = 0; i < NM; ++i)
+#pragma unroll
+    for (int ax = 0; ax < D; ++ax)
+      if (M::m(i, ax) > 0) ub[ax] -= kp[i] * R(M::m(i, ax)) * t.k[M::down(i, ax)];
+  apply<R, D, 2>(kp, t.u);  // C^T kappabar -> fbar (in work layout)
+  // u = (j + F/2) / rho
+  R jb[3];
+  R udotub = R(0);
+#pragma unroll
+  for (int ax = 0; ax < D; ++ax) {
+    jb[ax] = ub[ax] / t.rho;
+    udotub += t.u[ax] * ub[ax];
+  }
+  Fbb += ub[UP] / (R(2) * t.rho);
+  rhob -= udotub / t.rho;
+#pragma unroll
+  for (int i = 0; i < NM; ++i) {
+    R v = kp[i] + rhob;
+    v += R(M::ma(i) - 1) * jb[0] + R(M::mb(i) - 1) * jb[1];
+    if (D == 3) v += R(M::mc(i) - 1) * jb[2];
+    fb[M::pop(i)] = v;
+  }
+  // T enters through the buoyancy force
+  Tb += c.gbeta * Fbb;
+#pragma unroll
+  for (int q = 0; q < 2 * D + 1; ++q) gb[q] += Tb;
+}
+
+}  // namespace adj
+}  // namespace fpc

@@ -32,12 +32,21 @@ struct StepArgs {
   FaceDev face[6];
 };
 
-// Launchers (defined in fpc_kernels_2d.hip / fpc_kernels_3d.hip).
+// Launchers of the fused step (defined in fpc_step.hip).
 // mode: 0 = step (pull from args.src), 1 = init (equilibrium from T_init).
 template <class R>
 hipError_t launch_step2d(const StepArgs<R>& a, int up, const double* T_init, int mode, hipStream_t s);
 template <class R>
 hipError_t launch_step3d(const StepArgs<R>& a, int up, const double* T_init, int mode, hipStream_t s);
+
+// Adjoint kernels (fpc_adjoint.hip).  `a.src` is S_{n-1} (adjoint step) or
+// unused (adjoint of the initial collision).
+template <class R>
+hipError_t launch_adjoint_step(const StepArgs<R>& a, int dim, int up, const void* lam_in, void* lam_out,
+                               const double* dJdT, double ke, double* const dtheta[6], hipStream_t s);
+template <class R>
+hipError_t launch_adjoint_init(const StepArgs<R>& a, int dim, int up, const double* T_init, const void* lam0,
+                               const double* dJdT, double ke, double* dTinit, hipStream_t s);
 
 // Node-level utilities (fpc_kernels_util.hip).
 struct StateDesc {

@@ -1,0 +1,245 @@
+"""The hand-written adjoint (through the C ABI) against the oracle's autograd
+gradients and against central finite differences of the GPU forward run.
+
+Bars: one adjoint step and the adjoint of the initial collision equal the
+oracle's vector-Jacobian products to 1e-12 (FP64); full checkpointed
+gradients equal the oracle's autograd gradients to 1e-10; directional
+derivatives agree with central differences to 1e-6 relative at the plateau of
+an h-sweep; the FP32 adjoint agrees with the FP64 one to 1e-3.
+"""
+
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from oracle import gradient as ograd
+from oracle import sim as osim
+from oracle.params import params_from_config
+from tests import gpu_common as G
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    G.need_gpu()
+
+
+def _dirichlet_face(cfg):
+    for f, fd in enumerate(cfg["faces"]):
+        if fd["thermal"] == "dirichlet":
+            return f
+    return None
+
+
+def _profile_shape(cfg, face):
+    nx, ny, nz = cfg["shape"]
+    return {0: (nz, ny), 1: (nz, nx), 2: (ny, nx)}[face // 2]
+
+
+def _lam_buffer(sim, values, dtype):
+    out = torch.zeros((sim.Qf + sim.Qg, sim.plane), dtype=dtype, device="cuda")
+    out[:, : sim.N] = values.reshape(sim.Qf + sim.Qg, sim.N).to("cuda", dtype)
+    return out
+
+
+def _from_lam(sim, lam):
+    nx, ny, nz = sim.shape
+    return lam[:, : sim.N].double().cpu().reshape(sim.Qf + sim.Qg, nz, ny, nx)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+@pytest.mark.parametrize("case", list(G.SMALL_CASES))
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-12), ("f32dev", 2e-5)])
+def test_adjoint_step_matches_oracle_vjp(case, precision, tol):
+    from paper_2504_09041_amd import _abi as A
+
+    print(f"case={case} precision={precision}", flush=True)
+    cfg = G.small_config(case)
+    prm = params_from_config(cfg)
+    f0, g0 = G.perturbed_state(cfg, seed=31)
+    face = _dirichlet_face(cfg)
+    theta = None
+    if face is not None:
+        shp = _profile_shape(cfg, face)
+        theta = cfg["faces"][face]["T"] + 0.1 * torch.tensor(workloads.uniform_field(shp, 32))
+    Q = f0.shape[0] + g0.shape[0]
+    lam = torch.tensor(workloads.uniform_field((Q,) + tuple(f0.shape[1:]), 33))
+    dJdT = torch.tensor(workloads.uniform_field(tuple(f0.shape[1:]), 34))
+    ke = 0.7
+    # oracle vector-Jacobian product
+    f = f0.clone().requires_grad_(True)
+    g = g0.clone().requires_grad_(True)
+    th = theta.clone().requires_grad_(True) if theta is not None else None
+    fn, gn, mac = osim.step(prm, f, g, {face: th} if th is not None else None)
+    L = (lam[: f0.shape[0]] * fn).sum() + (lam[f0.shape[0]:] * gn).sum() + (dJdT * mac["T"]).sum() \
+        + ke * osim.kinetic_energy(mac)
+    ins = [f, g] + ([th] if th is not None else [])
+    grads = torch.autograd.grad(L, ins)
+    # GPU adjoint step
+    sim = G.make_sim(cfg, precision, wall_profiles={face: theta} if theta is not None else None)
+    G.load_state(sim, f0, g0)
+    S_prev = sim.save()
+    dt = torch.float64 if precision == "f64" else torch.float32
+    lin = _lam_buffer(sim, lam, dt)
+    lout = torch.full_like(lin, float("nan"))
+    dth = torch.zeros(theta.shape, dtype=torch.float64, device="cuda") if theta is not None else None
+    arr = (ctypes.c_void_p * 6)()
+    if dth is not None:
+        arr[face] = dth.data_ptr()
+    w = dJdT.cuda().contiguous()
+    A.check(A.load().fpc_adjoint_step(sim.handle, _ptr(S_prev), _ptr(lin), _ptr(lout), _ptr(w),
+                                      ctypes.c_double(ke), arr), "fpc_adjoint_step")
+    torch.cuda.synchronize()
+    got = _from_lam(sim, lout)
+    assert torch.isfinite(got).all(), "a slot of lambda_{n-1} was not written"
+    ref = torch.cat([grads[0], grads[1]], 0)
+    err = G.rel_err(got, ref)
+    print(f"  rel err lambda {err:.2e}")
+    assert err < tol
+    if th is not None:
+        e2 = G.rel_err(dth.cpu(), grads[2])
+        print(f"  rel err dtheta {e2:.2e}")
+        assert e2 < tol
+
+
+@pytest.mark.parametrize("case", list(G.SMALL_CASES))
+def test_adjoint_init_matches_oracle(case):
+    from paper_2504_09041_amd import _abi as A
+
+    cfg = G.small_config(case)
+    prm = params_from_config(cfg)
+    T0 = G.initial_T(cfg) + 0.2 * torch.tensor(workloads.uniform_field(tuple(cfg["shape"][::-1]), 41))
+    T = T0.clone().requires_grad_(True)
+    fo, go = osim.init_state(prm, T)
+    Q = fo.shape[0] + go.shape[0]
+    lam = torch.tensor(workloads.uniform_field((Q,) + tuple(fo.shape[1:]), 42))
+    dJdT = torch.tensor(workloads.uniform_field(tuple(fo.shape[1:]), 43))
+    mac = osim.macros_of_state(prm, fo, go)
+    L = (lam[: fo.shape[0]] * fo).sum() + (lam[fo.shape[0]:] * go).sum() + (dJdT * mac["T"]).sum() \
+        + 0.3 * osim.kinetic_energy(mac)
+    (gT,) = torch.autograd.grad(L, [T])
+    sim = G.make_sim(cfg, "f64")
+    lin = _lam_buffer(sim, lam, torch.float64)
+    out = torch.empty(tuple(fo.shape[1:]), dtype=torch.float64, device="cuda")
+    Tc = T0.cuda().contiguous()
+    w = dJdT.cuda().contiguous()
+    A.check(A.load().fpc_adjoint_init(sim.handle, _ptr(Tc), _ptr(lin), _ptr(w), ctypes.c_double(0.3), _ptr(out)),
+            "fpc_adjoint_init")
+    torch.cuda.synchronize()
+    assert G.rel_err(out.cpu(), gT) < 1e-12
+
+
+GRAD_CASES = {
+    # name: (workload, shape, objective, N, K, theta face)
+    "mixed2d_nu_bottom_theta": ("mixed2d_512", (12, 10, 1), ("nu", 3, (20, 40)), 40, 7, 2),
+    "dhc2d_nu_on_theta_face": ("dhc2d_64", (10, 8, 1), ("nu", 0, (10, 30)), 30, 8, 0),
+    "rb3d_ke": ("rb3d_128", (6, 5, 6), ("ke", None, 20), 20, 6, 4),
+}
+
+
+def _solver(cfg, precision, kind, face, window, N, K, theta_face):
+    from paper_2504_09041_amd import adjoint as adj
+    from paper_2504_09041_amd.sim import params_from_workload
+
+    p = params_from_workload(cfg, precision)
+    obj = adj.WallNusselt(face, *window) if kind == "nu" else adj.KineticEnergy(window)
+    return adj.AdjointSolver(p, N, K, obj, theta_face=theta_face)
+
+
+def _theta0(cfg, face, seed):
+    shp = _profile_shape(cfg, face)
+    return cfg["faces"][face]["T"] + 0.05 * torch.tensor(workloads.uniform_field(shp, seed))
+
+
+@pytest.mark.parametrize("name", list(GRAD_CASES))
+def test_checkpointed_gradient_matches_oracle_autograd(name):
+    wl, shape, (kind, face, window), N, K, tf = GRAD_CASES[name]
+    print(f"case={name}", flush=True)
+    cfg = workloads.config(wl, shape=shape)
+    prm = params_from_config(cfg)
+    T0 = G.initial_T(cfg) + 0.05 * torch.tensor(workloads.uniform_field(tuple(shape[::-1]), 51))
+    th0 = _theta0(cfg, tf, 52)
+    J_o, gth_o, gT_o = ograd.gradient(prm, T0, N, kind, face=face, window=window if kind == "nu" else None,
+                                      theta_face=tf, theta=th0, at=window if kind == "ke" else None)
+    s = _solver(cfg, "f64", kind, face, window, N, K, tf)
+    J = s.forward(th0.cuda(), T0.cuda())
+    gth, gT = s.backward()
+    print(f"  J gpu {J:.15e} oracle {J_o:.15e}")
+    assert abs(J - J_o) <= 1e-12 * max(1.0, abs(J_o))
+    e1 = G.rel_err(gT.cpu(), gT_o)
+    e2 = G.rel_err(gth.cpu(), gth_o)
+    print(f"  rel err dJ/dT_init {e1:.2e}  dJ/dtheta {e2:.2e}")
+    assert e1 < 1e-10
+    assert e2 < 1e-10
+
+
+def test_gradient_matches_central_differences():
+    """16 seeded directions in theta space and 16 in T_init space; each
+    directional derivative must agree with a central difference of the GPU
+    FP64 forward run to 1e-6 relative at the best step of h in 1e-2..1e-6."""
+    cfg = workloads.config("mixed2d_512", shape=(32, 24, 1))
+    N, K, window = 120, 25, (60, 120)
+    s = _solver(cfg, "f64", "nu", 3, window, N, K, 2)
+    th0 = _theta0(cfg, 2, 61).cuda()
+    T0 = (G.initial_T(cfg) + 0.05 * torch.tensor(workloads.uniform_field((1, 24, 32), 62))).cuda()
+    s.forward(th0, T0)
+    gth, gT = s.backward()
+    dth = torch.tensor(workloads.unit_directions(th0.numel(), 16, seed0=0)).cuda()
+    dT = torch.tensor(workloads.unit_directions(T0.numel(), 16, seed0=100)).cuda()
+    worst = 0.0
+    for which, dirs, grad in (("theta", dth, gth), ("T_init", dT, gT)):
+        for i in range(dirs.shape[0]):
+            d = dirs[i].reshape(grad.shape)
+            an = float((grad * d).sum())
+            best = float("inf")
+            for h in (1e-2, 1e-3, 1e-4, 1e-5, 1e-6):
+                if which == "theta":
+                    jp = s.forward(th0 + h * d, T0)
+                    jm = s.forward(th0 - h * d, T0)
+                else:
+                    jp = s.forward(th0, T0 + h * d)
+                    jm = s.forward(th0, T0 - h * d)
+                fd = (jp - jm) / (2 * h)
+                best = min(best, abs(fd - an) / max(abs(an), 1e-12))
+            worst = max(worst, best)
+            assert best < 1e-6, (which, i, an, best)
+    print(f"worst directional relative error at the plateau: {worst:.2e}")
+
+
+def test_fp32_adjoint_close_to_fp64():
+    cfg = workloads.config("mixed2d_512", shape=(24, 20, 1))
+    N, K, window = 60, 15, (30, 60)
+    th0 = _theta0(cfg, 2, 71).cuda()
+    T0 = (G.initial_T(cfg)).cuda()
+    res = {}
+    for prec in ("f64", "f32dev"):
+        s = _solver(cfg, prec, "nu", 3, window, N, K, 2)
+        J = s.forward(th0, T0)
+        gth, gT = s.backward()
+        res[prec] = (J, gth.cpu(), gT.cpu())
+    e_th = G.rel_err(res["f32dev"][1], res["f64"][1])
+    e_T = G.rel_err(res["f32dev"][2], res["f64"][2])
+    print(f"FP32 vs FP64: J {res['f32dev'][0]:.8f} {res['f64'][0]:.8f}, dtheta {e_th:.2e}, dT_init {e_T:.2e}")
+    assert abs(res["f32dev"][0] - res["f64"][0]) <= 1e-3 * abs(res["f64"][0])
+    assert e_th < 1e-3 and e_T < 1e-3
+
+
+def test_autograd_function_wrapper():
+    from paper_2504_09041_amd import adjoint as adj
+
+    cfg = workloads.config("mixed2d_512", shape=(12, 10, 1))
+    s = _solver(cfg, "f64", "nu", 3, (5, 20), 20, 6, 2)
+    th = _theta0(cfg, 2, 81).cuda().requires_grad_(True)
+    T0 = G.initial_T(cfg).cuda().requires_grad_(True)
+    J = adj.ObjectiveFunction.apply(th, T0, s)
+    (2.0 * J).backward()
+    gth, gT = s.backward()
+    assert torch.allclose(th.grad, 2.0 * gth, rtol=1e-14, atol=0)
+    assert torch.allclose(T0.grad, 2.0 * gT, rtol=1e-14, atol=0)
