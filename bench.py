@@ -47,7 +47,9 @@ def _args():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=12)
-    ap.add_argument("--mode", choices=("bench", "single", "copy", "pmc-summary"), default="bench")
+    ap.add_argument("--mode", choices=("bench", "single", "copy", "pmc-summary", "precision", "adjoint"),
+                    default="bench")
+    ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--fetch", help="rocprofv3 --pmc FETCH_SIZE output dir (kernel run)")
     ap.add_argument("--write", help="rocprofv3 --pmc WRITE_SIZE output dir (kernel run)")
     ap.add_argument("--copy-fetch", help="rocprofv3 --pmc FETCH_SIZE output dir (copy run)")
@@ -82,6 +84,20 @@ def copy_bandwidth(mib, reps):
     nbytes = 2 * n * 4
     return {"mode": "copy", "bytes_read_plus_written": nbytes, "ms_per_copy": ms,
             "GBs": nbytes / (ms * 1e-3) / 1e9}
+
+
+def kernel_fingerprint():
+    """sha256 over the HIP sources of the library: counters recorded for other
+    sources do not describe the kernels that run."""
+    import hashlib
+
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2504_09041_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".h")):
+            with open(os.path.join(csrc, name), "rb") as fh:
+                h.update(name.encode() + b"\0" + fh.read())
+    return h.hexdigest()[:16]
 
 
 def _traffic_record():
@@ -125,6 +141,7 @@ def pmc_summary(a):
         "fetch_scale": sf, "write_scale": sw, "dispatches": [nf, nw],
     }
     rec["traffic_bytes"] = rec["fetch_bytes"] + rec["write_bytes"]
+    rec["sources"] = kernel_fingerprint()
     path = os.path.join(ROOT, "profiles", "traffic.json")
     allrec = _traffic_record()
     allrec[a.key] = rec
@@ -142,7 +159,10 @@ def time_workload(name, precision, steps, warmup, shape=None):
     cfg = workloads.config(name)
     if shape is not None:
         cfg["shape"] = tuple(shape)
-    p = params_from_workload(cfg, precision)
+    if precision == "f32cond":
+        p = params_from_workload(cfg, "f32dev", T_reference="conduction")
+    else:
+        p = params_from_workload(cfg, precision)
     sim = Simulation(p)
     T = torch.tensor(workloads.initial_temperature(cfg), device="cuda")
     sim.init(T)
@@ -182,6 +202,120 @@ def time_workload(name, precision, steps, warmup, shape=None):
     return out
 
 
+def adjoint_cost(name, nsteps, every, reps=20):
+    """Cost of the adjoint relative to the forward step (FP32-deviation form).
+
+    kernel_ratio: one adjoint_step launch / one forward step launch (HIP events);
+    sweep_ratio: the whole checkpointed reverse sweep (segment recompute, state
+    saves, adjoint steps) per step / one forward step."""
+    import ctypes
+
+    import torch
+
+    import workloads
+    from paper_2504_09041_amd import _abi as A
+    from paper_2504_09041_amd import adjoint as adj
+    from paper_2504_09041_amd.sim import params_from_workload
+
+    cfg = workloads.config(name)
+    p = params_from_workload(cfg, "f32dev")
+    if name.startswith("mixed"):
+        obj = adj.WallNusselt(cfg["nu_face"], nsteps // 2, nsteps)
+        solver = adj.AdjointSolver(p, nsteps, every, obj, theta_face=cfg.get("grad_face", 2))
+    else:
+        obj = adj.KineticEnergy(nsteps)
+        solver = adj.AdjointSolver(p, nsteps, every, obj)
+    T = torch.tensor(workloads.initial_temperature(cfg), device="cuda")
+    solver.forward(None, T)
+    sim = solver.sim
+    ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+    # forward step alone
+    sim.step(5)
+    e0, e1 = ev(), ev()
+    torch.cuda.synchronize()
+    e0.record()
+    sim.step(reps)
+    e1.record()
+    torch.cuda.synchronize()
+    t_fwd = e0.elapsed_time(e1) / reps
+    # adjoint step alone
+    S = sim.save()
+    lam = torch.zeros((sim.Qf + sim.Qg, sim.plane), dtype=torch.float32, device="cuda")
+    lam2 = torch.empty_like(lam)
+    lib = A.load()
+    vp = lambda t: ctypes.c_void_p(t.data_ptr())  # noqa: E731
+    for _ in range(3):
+        lib.fpc_adjoint_step(sim.handle, vp(S), vp(lam), vp(lam2), None, ctypes.c_double(1.0), None)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        A.check(lib.fpc_adjoint_step(sim.handle, vp(S), vp(lam), vp(lam2), None, ctypes.c_double(1.0), None),
+                "fpc_adjoint_step")
+        lam, lam2 = lam2, lam
+    e1.record()
+    torch.cuda.synchronize()
+    t_adj = e0.elapsed_time(e1) / reps
+    # whole reverse sweep
+    solver.forward(None, T)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    solver.backward()
+    torch.cuda.synchronize()
+    t_sweep = (time.perf_counter() - t0) * 1e3 / nsteps
+    sim.close()
+    return {
+        "workload": name, "precision": "f32dev", "steps": nsteps, "checkpoint_every": every,
+        "forward_ms_per_step": t_fwd, "adjoint_kernel_ms": t_adj, "sweep_ms_per_step": t_sweep,
+        "kernel_ratio": t_adj / t_fwd, "sweep_ratio": t_sweep / t_fwd,
+    }
+
+
+def precision_study(name, nsteps, every, noise=1e-7):
+    """FP32-deviation forms against FP64 on the same run, every `every` steps:
+    max |T - T64| / dT and |Nu - Nu64| / |Nu64| for
+      f32dev   FP32 deviations from the uniform reference T0,
+      f32cond  FP32 deviations from the conduction profile (affine reference),
+      f64pert  FP64 from an initial temperature perturbed by `noise` dT
+               (uniform noise): the divergence the flow itself produces from
+               a perturbation of FP32 rounding size, the yardstick for the
+               other two."""
+    import torch
+
+    import workloads
+    from paper_2504_09041_amd.sim import Simulation, params_from_workload
+
+    cfg = workloads.config(name)
+    dT = cfg["T_hot"] - cfg["T_cold"]
+    T = torch.tensor(workloads.initial_temperature(cfg), device="cuda")
+    Tp = T + noise * dT * torch.tensor(workloads.uniform_field(tuple(T.shape), 77), device="cuda")
+    variants = {
+        "f64": (params_from_workload(cfg, "f64"), T),
+        "f32dev": (params_from_workload(cfg, "f32dev"), T),
+        "f32cond": (params_from_workload(cfg, "f32dev", T_reference="conduction"), T),
+        "f64pert": (params_from_workload(cfg, "f64"), Tp),
+    }
+    sims = {}
+    for k, (p, T_init) in variants.items():
+        s = Simulation(p)
+        s.init(T_init)
+        sims[k] = s
+    rows = []
+    for n in range(every, nsteps + 1, every):
+        out = {}
+        for k, s in sims.items():
+            s.step(every)
+            out[k] = (s.diagnostics(cfg["nu_face"])["nu"], s.macros()["T"])
+        row = {"step": n, "nu_f64": out["f64"][0]}
+        for k in ("f32dev", "f32cond", "f64pert"):
+            row[k] = {"max_dT_over_DeltaT": float((out[k][1] - out["f64"][1]).abs().max()) / dT,
+                      "rel_dNu": abs(out[k][0] - out["f64"][0]) / abs(out["f64"][0])}
+        rows.append(row)
+        print(json.dumps(row), file=sys.stderr, flush=True)
+    for s in sims.values():
+        s.close()
+    return {"workload": name, "noise": noise, "rows": rows}
+
+
 def cpu_baseline(name, nsteps):
     """The FP64 CPU oracle on the host cores, on a bounded sample of the same
     workload (nsteps steps of the full grid after its initial collision)."""
@@ -214,8 +348,8 @@ def cpu_baseline(name, nsteps):
 def main():
     a = _args()
     if a.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); "
-              "multi-GPU sharding is not part of this build", file=sys.stderr)
+        print(f"bench.py measures one GPU (asked for --gpus {a.gpus}); "
+              "sharding across GPUs is not implemented", file=sys.stderr)
         sys.exit(2)
     if a.mode == "pmc-summary":
         print(json.dumps(pmc_summary(a)))
@@ -231,12 +365,24 @@ def main():
     if a.mode == "single":
         print(json.dumps(time_workload(a.workload, a.precision, a.steps, a.warmup)))
         return
+    if a.mode == "precision":
+        print(json.dumps(precision_study(a.workload, a.steps, max(1, a.steps // 50))))
+        return
+    if a.mode == "adjoint":
+        print(json.dumps(adjoint_cost(a.workload, a.steps, max(1, int(round(a.steps ** 0.5))))))
+        return
     head = time_workload("rb2d_1024x512", "f64", a.steps, a.warmup)
     extra = {}
     if not a.no_extra:
         extra["rb2d_1024x512_f32dev"] = time_workload("rb2d_1024x512", "f32dev", a.steps, a.warmup)
+        extra["rb2d_1024x512_f32cond"] = time_workload("rb2d_1024x512", "f32cond", a.steps, a.warmup)
         extra["dhc3d_256_f32dev"] = time_workload("dhc3d_256", "f32dev", a.steps3d, max(5, a.warmup // 10))
+    if not a.no_extra and not a.no_adjoint:
+        extra["adjoint_mixed2d_512_f32dev"] = adjoint_cost("mixed2d_512", 400, 100)
+        extra["adjoint_rb3d_128_f32dev"] = adjoint_cost("rb3d_128", 64, 8)
     tr = _traffic_record().get("rb2d_1024x512_f64")
+    if tr and tr.get("sources") != kernel_fingerprint():
+        tr = None  # the kernels changed since the counters were taken
     roof = {
         "bound": "hbm",
         "achieved": head["achieved_GBs"],
@@ -251,7 +397,7 @@ def main():
     if not a.no_cpu_baseline:
         cpu = cpu_baseline("rb2d_1024x512", a.cpu_sample_steps)
     line = {
-        "metric": "MLUPS (fluid+thermal)",
+        "metric": "MLUPS (fluid+thermal) & % HBM roofline; FP32 vs FP64 at stated Nu error; adjoint/fwd",
         "value": head["mlups"],
         "unit": "MLUPS",
         "n_gpus": 1,

@@ -52,7 +52,7 @@ extern "C" {
 
 /* Storage precision of the populations. */
 #define FPC_FP64 0     /* populations f, g stored and collided in FP64 */
-#define FPC_FP32_DEV 1 /* FP32 deviations f - w rho0 and g - w^T T0, collided in FP32 */
+#define FPC_FP32_DEV 1 /* FP32 deviations f - w rho0 and g - w^T Tr (Tr: T_ref_slope/axis), collided in FP32 */
 
 /* Face kinds (fluid rule + thermal rule). */
 #define FPC_BC_PERIODIC 0          /* must be set on both faces of an axis */
@@ -103,6 +103,15 @@ typedef struct fpc_params {
    * in 2D a -y face profile has nx values).  Read on every step, so it can be changed
    * between steps; the library never frees it. */
   const double* wall_T_profile[6];
+  /* FP32-deviation storage reference of g (ignored for FPC_FP64).  With slope s
+   * and axis k >= 0, g is stored as g - w^T Tr(x) with
+   *   Tr(x) = T0 + s (x_k - (n_k - 1) / 2),
+   * an affine profile across the box (e.g. the conduction profile between two
+   * Dirichlet walls, so the stored deviations carry only the departure from
+   * it).  s = 0 or k < 0: the uniform reference T0.  Axis k must not be
+   * periodic; s must be finite.  Defaults: s = 0, k = -1. */
+  double T_ref_slope;
+  int T_ref_axis;
 } fpc_params;
 
 typedef struct fpc_sim fpc_sim;

@@ -69,6 +69,8 @@ class fpc_params(ctypes.Structure):
         ("wall_T", ctypes.c_double * 6),
         ("lid_u", (ctypes.c_double * 3) * 6),
         ("wall_T_profile", ctypes.c_void_p * 6),
+        ("T_ref_slope", ctypes.c_double),
+        ("T_ref_axis", ctypes.c_int),
     ]
 
 

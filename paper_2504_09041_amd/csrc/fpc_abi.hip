@@ -115,7 +115,27 @@ int validate(const fpc_params* p) {
       if (n[k] < 2) return fail(FPC_ERR_SIZE, "a walled axis needs at least 2 nodes");
     }
   }
+  if (!std::isfinite(p->T_ref_slope)) return fail(FPC_ERR_ARG, "T_ref_slope not finite");
+  if (p->T_ref_axis >= dim) return fail(FPC_ERR_ARG, "T_ref_axis %d invalid", p->T_ref_axis);
+  if (p->T_ref_axis >= 0 && p->bc[2 * p->T_ref_axis] == FPC_BC_PERIODIC && p->T_ref_slope != 0.0)
+    return fail(FPC_ERR_ARG, "T_ref_axis %d is periodic", p->T_ref_axis);
   return FPC_OK;
+}
+
+// Thermal storage reference Tr(x) = To + Tg . x of the stored g: T0 plus the
+// optional slope along T_ref_axis (centred on the box) for FP32 deviations,
+// zero for plain FP64 populations.
+void thermal_reference(const fpc_params& p, double& To, double Tg[3]) {
+  Tg[0] = Tg[1] = Tg[2] = 0.0;
+  To = 0.0;
+  if (p.precision != FPC_FP32_DEV) return;
+  To = p.T0;
+  if (p.T_ref_axis >= 0 && p.T_ref_slope != 0.0) {
+    const int n[3] = {p.nx, p.ny, p.nz};
+    const int k = p.T_ref_axis;
+    Tg[k] = p.T_ref_slope;
+    To -= p.T_ref_slope * 0.5 * (n[k] - 1);
+  }
 }
 
 template <class R>
@@ -138,6 +158,12 @@ StepArgs<R> make_args(const fpc_sim* s, const void* src, void* dst) {
   const bool dev = p.precision == FPC_FP32_DEV;
   a.c.rho_r = dev ? (R)p.rho0 : R(0);
   a.c.T_r = dev ? (R)p.T0 : R(0);
+  {
+    double To, Tg[3];
+    thermal_reference(p, To, Tg);
+    a.T_o = (R)To;
+    for (int k = 0; k < 3; ++k) a.Tg[k] = (R)Tg[k];
+  }
   a.rho_w = (R)p.rho0;
   for (int f = 0; f < 6; ++f) {
     const int bc = p.bc[f];
@@ -180,6 +206,7 @@ StateDesc desc_of(const fpc_sim* s) {
   const bool dev = p.precision == FPC_FP32_DEV;
   d.rho_r = dev ? p.rho0 : 0.0;
   d.T_r = dev ? p.T0 : 0.0;
+  thermal_reference(p, d.T_o, d.Tg);
   d.cs2T = p.cs2_T;
   d.gbeta = p.g_beta;
   d.T0 = p.T0;
@@ -235,6 +262,8 @@ int fpc_params_default(fpc_params* p, int lattice, int precision, int nx, int ny
   p->dT_ref = 1.0;
   p->up_axis = dim == 2 ? 1 : 2;
   for (int f = 0; f < 6; ++f) p->bc[f] = FPC_BC_PERIODIC;
+  p->T_ref_slope = 0.0;
+  p->T_ref_axis = -1;
   return FPC_OK;
 }
 

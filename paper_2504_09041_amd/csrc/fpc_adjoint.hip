@@ -111,6 +111,7 @@ __device__ void pull_plain(const StepArgs<R>& a, int x, int y, int z, unsigned n
     }
     f[q] = v + R(Lk::w(q)) * a.c.rho_r;
   }
+  const R Tr = tref(a, x, y, z);
 #pragma unroll
   for (int q = 0; q < Lk::Qg; ++q) {
     unsigned src;
@@ -118,15 +119,17 @@ __device__ void pull_plain(const StepArgs<R>& a, int x, int y, int z, unsigned n
     R v;
     const R wq = q == 0 ? R(1) - R(D) * a.c.cs2T : R(0.5) * a.c.cs2T;
     if (link_source(a, x, y, z, Lk::ex(q), Lk::ey(q), Lk::ez(q), src, nc, F)) {
-      v = a.src[(size_t)(Lk::Qf + q) * a.plane + src];
+      // stored against the source node's reference Tr(x - e)
+      const R Trs = Tr - (R(Lk::ex(q)) * a.Tg[0] + R(Lk::ey(q)) * a.Tg[1] + R(Lk::ez(q)) * a.Tg[2]);
+      v = a.src[(size_t)(Lk::Qf + q) * a.plane + src] + wq * Trs;
     } else {
-      v = a.src[(size_t)(Lk::Qf + Lk::opp(q)) * a.plane + node];
+      v = a.src[(size_t)(Lk::Qf + Lk::opp(q)) * a.plane + node] + wq * Tr;
       bool lid, dir;
       double uw[3];
       face_flags(a, F, lid, dir, uw);
-      if (dir) v = -v + a.c.cs2T * (R(face_temperature<R, D>(a, F, x, y, z)) - a.c.T_r);
+      if (dir) v = -v + a.c.cs2T * R(face_temperature<R, D>(a, F, x, y, z));
     }
-    g[q] = v + wq * a.c.T_r;
+    g[q] = v;
   }
 }
 

@@ -43,7 +43,7 @@ struct CollParams {
   R gbeta;    // buoyancy per unit temperature along the up axis
   R T0;       // Boussinesq reference temperature
   R rho_r;    // storage offset of f (0: plain populations)
-  R T_r;      // storage offset of g (0: plain populations)
+  R T_r;      // storage offset of g at the box centre (0: plain populations)
 };
 
 // Macros of the time level, produced by the collision for diagnostics.
@@ -84,8 +84,9 @@ __device__ __forceinline__ R dprod(R rr, R RX, R dx, R RY, R dy) {
 // 2D: D2Q9 fluid + D2Q5 thermal.  f, g hold the pulled (pre-collision) stored
 // values on entry and the post-collision stored values on exit.
 // ---------------------------------------------------------------------------
+// Tr: storage reference of g at this node (g is stored as g - w^T Tr).
 template <class R, int UP>
-__device__ __forceinline__ void collide2d(R (&f)[kQ2], R (&g)[kQ2T], const CollParams<R>& c,
+__device__ __forceinline__ void collide2d(R (&f)[kQ2], R (&g)[kQ2T], const CollParams<R>& c, R Tr,
                                           Macros<R>* mac) {
   constexpr R cs2 = R(1) / R(3);
   const R rr = c.rho_r;
@@ -93,7 +94,7 @@ __device__ __forceinline__ void collide2d(R (&f)[kQ2], R (&g)[kQ2T], const CollP
   const R jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
   const R jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
   const R dT = ((g[0] + g[1]) + (g[2] + g[3])) + g[4];
-  const R T = c.T_r + dT;
+  const R T = Tr + dT;
   const R rho = rr + drho;
   const R Fb = c.gbeta * (T - c.T0);
   const R Fx = UP == 0 ? Fb : R(0);
@@ -160,7 +161,7 @@ __device__ __forceinline__ void collide2d(R (&f)[kQ2], R (&g)[kQ2T], const CollP
   shift_inv(x0p, x1p, x2p, ux, f[6], f[2], f[5]);
 
   // thermal D2Q5: raw moments (00, 10, 01, 20, 02) -> central -> relax -> back
-  const R cT = c.cs2T, Tr = c.T_r;
+  const R cT = c.cs2T;
   const R* og = c.omg;
   const R n10 = g[1] - g[3], n01 = g[2] - g[4], n20 = g[1] + g[3], n02 = g[2] + g[4];
   const R e10 = n10 - ux * dT;
@@ -198,7 +199,7 @@ __device__ __forceinline__ R cpow(int m, R u, R cs2) {
 }
 
 template <class R, int UP>
-__device__ __forceinline__ void collide3d(R (&f)[kQ3], R (&g)[kQ3T], const CollParams<R>& c,
+__device__ __forceinline__ void collide3d(R (&f)[kQ3], R (&g)[kQ3T], const CollParams<R>& c, R Tr,
                                           Macros<R>* mac) {
   constexpr R cs2 = R(1) / R(3);
   const R rr = c.rho_r;
@@ -213,7 +214,7 @@ __device__ __forceinline__ void collide3d(R (&f)[kQ3], R (&g)[kQ3T], const CollP
     if (D3_EZ[a] != 0) jz += D3_EZ[a] > 0 ? f[a] : -f[a];
   }
   const R dT = ((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + g[6]);
-  const R T = c.T_r + dT;
+  const R T = Tr + dT;
   const R rho = rr + drho;
   const R Fb = c.gbeta * (T - c.T0);
   const R Fx = UP == 0 ? Fb : R(0);
@@ -384,7 +385,7 @@ __device__ __forceinline__ void collide3d(R (&f)[kQ3], R (&g)[kQ3T], const CollP
                 f[d3_index(-1, ey, ez)], f[d3_index(0, ey, ez)], f[d3_index(1, ey, ez)]);
 
   // thermal D3Q7: links 1/2 = +-x, 3/4 = +-y, 5/6 = +-z
-  const R cT = c.cs2T, Tr = c.T_r;
+  const R cT = c.cs2T;
   const R* og = c.omg;
   const R n100 = g[1] - g[2], n010 = g[3] - g[4], n001 = g[5] - g[6];
   const R n200 = g[1] + g[2], n020 = g[3] + g[4], n002 = g[5] + g[6];

@@ -29,9 +29,24 @@ struct StepArgs {
   size_t plane;               // element stride between population planes
   CollParams<R> c;
   R rho_w;                    // moving-wall density
+  // storage reference of g: Tr(x, y, z) = T_o + Tg . (x, y, z)
+  // (uniform: T_o = c.T_r, Tg = 0)
+  R T_o;
+  R Tg[3];
   FaceDev face[6];
 };
 
+// FP32 storage holds deviations from the references; FP64 storage holds the
+// plain populations (references zero), so the FP64 kernels compile them out.
+template <class R>
+constexpr bool kDeviations = sizeof(R) == 4;
+
+// Storage reference of the thermal populations at node (x, y, z).
+template <class R>
+__device__ __forceinline__ R tref(const StepArgs<R>& a, int x, int y, int z) {
+  if constexpr (!kDeviations<R>) return R(0);
+  return a.T_o + (a.Tg[0] * R(x) + a.Tg[1] * R(y) + a.Tg[2] * R(z));
+}
 // Launchers of the fused step (defined in fpc_step.hip).
 // mode: 0 = step (pull from args.src), 1 = init (equilibrium from T_init).
 template <class R>
@@ -55,7 +70,8 @@ struct StateDesc {
   int lattice;    // 1 = 2D, 2 = 3D
   int nx, ny, nz;
   size_t plane;
-  double rho_r, T_r;  // storage offsets
+  double rho_r, T_r;  // storage offsets (T_r at the box centre)
+  double T_o, Tg[3];  // thermal storage reference Tr(x, y, z) = T_o + Tg . (x, y, z)
   double cs2T;
   double gbeta, T0;
   int up;

@@ -27,6 +27,12 @@ __device__ __forceinline__ int ex_of(int lattice, int q) { return lattice == 1 ?
 __device__ __forceinline__ int ey_of(int lattice, int q) { return lattice == 1 ? D2_EY[q] : D3_EY[q]; }
 __device__ __forceinline__ int ez_of(int lattice, int q) { return lattice == 1 ? 0 : D3_EZ[q]; }
 
+// thermal storage reference at a node
+__device__ __forceinline__ double tref_node(const StateDesc& d, size_t node) {
+  const size_t x = node % d.nx, y = (node / d.nx) % d.ny, z = node / ((size_t)d.nx * d.ny);
+  return d.T_o + (d.Tg[0] * (double)x + d.Tg[1] * (double)y + d.Tg[2] * (double)z);
+}
+
 template <class R>
 __device__ __forceinline__ double ld(const StateDesc& d, int q, size_t node) {
   return (double)static_cast<const R*>(d.src)[q * d.plane + node];
@@ -48,7 +54,7 @@ __device__ void node_macros(const StateDesc& d, size_t node, double& rho, double
   double t = 0.0;
   for (int q = 0; q < Qg; ++q) t += ld<R>(d, Qf + q, node);
   rho = d.rho_r + s;
-  T = d.T_r + t;
+  T = tref_node(d, node) + t;
   const double Fb = d.gbeta * (T - d.T0);
   const double ir = 1.0 / rho;
   u[0] = (jx - (d.up == 0 ? 0.5 * Fb : 0.0)) * ir;
@@ -80,8 +86,9 @@ __global__ void __launch_bounds__(kBlock) export_kernel(StateDesc d, double* dst
   const int Qg = d.lattice == 1 ? kQ2T : kQ3T;
   const int dim = d.lattice == 1 ? 2 : 3;
   for (int q = 0; q < Qf; ++q) dst[q * N + node] = ld<R>(d, q, node) + wfluid(d.lattice, q) * d.rho_r;
+  const double tr = tref_node(d, node);
   for (int q = 0; q < Qg; ++q)
-    dst[(Qf + q) * N + node] = ld<R>(d, Qf + q, node) + wtherm(dim, d.cs2T, q) * d.T_r;
+    dst[(Qf + q) * N + node] = ld<R>(d, Qf + q, node) + wtherm(dim, d.cs2T, q) * tr;
 }
 
 template <class R>
@@ -93,8 +100,9 @@ __global__ void __launch_bounds__(kBlock) import_kernel(StateDesc d, R* out, con
   const int Qg = d.lattice == 1 ? kQ2T : kQ3T;
   const int dim = d.lattice == 1 ? 2 : 3;
   for (int q = 0; q < Qf; ++q) out[q * d.plane + node] = (R)(src[q * N + node] - wfluid(d.lattice, q) * d.rho_r);
+  const double tr = tref_node(d, node);
   for (int q = 0; q < Qg; ++q)
-    out[(Qf + q) * d.plane + node] = (R)(src[(Qf + q) * N + node] - wtherm(dim, d.cs2T, q) * d.T_r);
+    out[(Qf + q) * d.plane + node] = (R)(src[(Qf + q) * N + node] - wtherm(dim, d.cs2T, q) * tr);
 }
 
 // Deterministic block reduction: sum (op 0) or max (op 1) over kBlock values.
@@ -169,7 +177,7 @@ __global__ void __launch_bounds__(kBlock) diag_face_kernel(StateDesc d, int face
       const size_t node = ((size_t)c[2] * d.ny + c[1]) * d.nx + c[0];
       double t = 0.0;
       for (int q = 0; q < Qg; ++q) t += ld<R>(d, Qf + q, node);
-      Tl[layer] = d.T_r + t;
+      Tl[layer] = tref_node(d, node) + t;
     }
     const double Tw = fd.Tprof ? fd.Tprof[i] : fd.Tw;
     const double dTdn = -8.0 / 3.0 * Tw + 3.0 * Tl[0] - Tl[1] / 3.0;

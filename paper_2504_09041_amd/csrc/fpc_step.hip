@@ -100,6 +100,7 @@ struct Gather {
   const StepArgs<R>& a;
   int x, y, z;
   unsigned node;
+  R Tr;  // thermal storage reference of this node
 
   // Source coordinate along one axis with periodic wrap; `wall` is set when the
   // link leaves the box through a wall face.
@@ -165,29 +166,34 @@ struct Gather {
   __device__ __forceinline__ R g() const {
     bool wx = false, wy = false, wz = false;
     R v = pull<A, L::Qf>(wx, wy, wz);
+    if (A == 0) return v;
     constexpr int ex = L::ex(A), ey = L::ey(A), ez = L::ez(A);
     constexpr bool checked = (CX && ex != 0) || (CY && ey != 0) || (CZ && ez != 0);
-    if (checked) {
-      constexpr int F = ex > 0 ? 0 : (ex < 0 ? 1 : (ey > 0 ? 2 : (ey < 0 ? 3 : (ez > 0 ? 4 : 5))));
-      constexpr int k = F >> 1;
-      const bool wall = wx || wy || wz;
-      if (a.face[F].dirichlet && wall) {
+    constexpr int F = ex > 0 ? 0 : (ex < 0 ? 1 : (ey > 0 ? 2 : (ey < 0 ? 3 : (ez > 0 ? 4 : 5))));
+    constexpr int k = F >> 1;
+    constexpr int e = ex + ey + ez;  // axis link: the one non-zero component
+    const bool wall = checked && (wx || wy || wz);
+    if (wall) {
+      if (a.face[F].dirichlet) {
         double Tw = a.face[F].Tw;
         if (a.face[F].Tprof) {
           const size_t t = k == 0 ? (size_t)z * a.ny + y : (k == 1 ? (size_t)z * a.nx + x : (size_t)y * a.nx + x);
           Tw = a.face[F].Tprof[t];
         }
-        v = -v + a.c.cs2T * (R(Tw) - a.c.T_r);  // 2 w^T_a = c^_s^2 on axis links
+        v = -v + a.c.cs2T * (R(Tw) - Tr);  // 2 w^T_a = c^_s^2 on axis links
       }
+    } else if constexpr (kDeviations<R>) {
+      // the value was stored against the source node's reference Tr(x - e_A)
+      v -= R(0.5) * a.c.cs2T * (R(e) * a.Tg[k]);
     }
     return v;
   }
 };
 
 template <class L, class R, bool CX, bool CY, bool CZ>
-__device__ __forceinline__ void gather(const StepArgs<R>& a, int x, int y, int z, unsigned node, R (&f)[L::Qf],
-                                       R (&g)[L::Qg]) {
-  const Gather<L, R, CX, CY, CZ> p{a, x, y, z, node};
+__device__ __forceinline__ void gather(const StepArgs<R>& a, int x, int y, int z, unsigned node, R Tr,
+                                       R (&f)[L::Qf], R (&g)[L::Qg]) {
+  const Gather<L, R, CX, CY, CZ> p{a, x, y, z, node, Tr};
   if constexpr (L::D == 2) {
     f[0] = p.template f<0>(); f[1] = p.template f<1>(); f[2] = p.template f<2>();
     f[3] = p.template f<3>(); f[4] = p.template f<4>(); f[5] = p.template f<5>();
@@ -207,11 +213,12 @@ __device__ __forceinline__ void gather(const StepArgs<R>& a, int x, int y, int z
 }
 
 template <class L, class R, int UP, bool NT>
-__device__ __forceinline__ void collide_store(const StepArgs<R>& a, unsigned node, R (&f)[L::Qf], R (&g)[L::Qg]) {
+__device__ __forceinline__ void collide_store(const StepArgs<R>& a, unsigned node, R Tr, R (&f)[L::Qf],
+                                              R (&g)[L::Qg]) {
   if constexpr (L::D == 2)
-    collide2d<R, UP>(f, g, a.c, (Macros<R>*)nullptr);
+    collide2d<R, UP>(f, g, a.c, Tr, (Macros<R>*)nullptr);
   else
-    collide3d<R, UP>(f, g, a.c, (Macros<R>*)nullptr);
+    collide3d<R, UP>(f, g, a.c, Tr, (Macros<R>*)nullptr);
 #pragma unroll
   for (int q = 0; q < L::Qf; ++q) st<R, NT>(a.dst + (size_t)q * a.plane, node, f[q]);
 #pragma unroll
@@ -229,6 +236,7 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs<R> a) {
   const int z = blockIdx.z;
   if (x >= a.nx || y >= a.ny) return;
   const unsigned node = node_of(x, y, z, a.nx, a.ny);
+  const R Tr = tref(a, x, y, z);
   R f[L::Qf], g[L::Qg];
   // which axes have an edge node in this wavefront (wave-uniform)
   const bool needx = __any(x == 0 || x == a.nx - 1);
@@ -236,13 +244,13 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs<R> a) {
   const bool needz = L::D == 3 && __any(z == 0 || z == a.nz - 1);
   if (!needy && !needz) {
     if (!needx)
-      gather<L, R, false, false, false>(a, x, y, z, node, f, g);
+      gather<L, R, false, false, false>(a, x, y, z, node, Tr, f, g);
     else
-      gather<L, R, true, false, false>(a, x, y, z, node, f, g);
+      gather<L, R, true, false, false>(a, x, y, z, node, Tr, f, g);
   } else {
-    gather<L, R, true, true, L::D == 3>(a, x, y, z, node, f, g);
+    gather<L, R, true, true, L::D == 3>(a, x, y, z, node, Tr, f, g);
   }
-  collide_store<L, R, UP, NT>(a, node, f, g);
+  collide_store<L, R, UP, NT>(a, node, Tr, f, g);
 }
 
 // Initial state: the collision of f = w rho0, g = w^T T_init at every node.
@@ -257,11 +265,12 @@ __global__ void __launch_bounds__(256) init_kernel(StepArgs<R> a, const double* 
   const R drw = a.rho_w - a.c.rho_r;
 #pragma unroll
   for (int q = 0; q < L::Qf; ++q) f[q] = R(L::w(q)) * drw;
-  const R dT = R(T_init[node]) - a.c.T_r;
+  const R Tr = tref(a, x, y, z);
+  const R dT = R(T_init[node]) - Tr;
   g[0] = (R(1) - R(L::D) * a.c.cs2T) * dT;
 #pragma unroll
   for (int q = 1; q < L::Qg; ++q) g[q] = R(0.5) * a.c.cs2T * dT;
-  collide_store<L, R, UP, false>(a, node, f, g);
+  collide_store<L, R, UP, false>(a, node, Tr, f, g);
 }
 
 template <class L, class R, int UP>

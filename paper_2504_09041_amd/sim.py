@@ -51,11 +51,30 @@ def set_faces(p, faces):
     return p
 
 
-def params_from_workload(cfg, precision="f64", shape=None, cs2_T=None):
+def conduction_reference(p, axis):
+    """Set the FP32-deviation thermal storage reference to the conduction
+    profile between the two Dirichlet walls normal to ``axis`` (their wall
+    temperatures, walls halfway outside the outermost nodes)."""
+    lo, hi = 2 * axis, 2 * axis + 1
+    dirichlet = (A.FPC_BC_NOSLIP_DIRICHLET, A.FPC_BC_LID_DIRICHLET)
+    if p.bc[lo] not in dirichlet or p.bc[hi] not in dirichlet:
+        raise ValueError("conduction reference needs Dirichlet walls on both faces of axis %d" % axis)
+    n = (p.nx, p.ny, p.nz)[axis]
+    p.T_ref_axis = axis
+    # with T0 the mean of the two wall temperatures (as the natural and mixed
+    # helpers set it), Tr(x) = T0 + slope (x - (n-1)/2) meets the wall values
+    # at x = -1/2 and n - 1/2
+    p.T_ref_slope = (p.wall_T[hi] - p.wall_T[lo]) / n
+    return p
+
+
+def params_from_workload(cfg, precision="f64", shape=None, cs2_T=None, T_reference="uniform"):
     """C parameters of a workload description (``workloads.CONFIGS`` entry).
 
     The physical -> lattice mapping runs in the library
-    (fpc_params_natural / fpc_params_mixed)."""
+    (fpc_params_natural / fpc_params_mixed).  ``T_reference`` picks the
+    FP32-deviation storage reference of g: "uniform" (T0) or "conduction"
+    (affine between the Dirichlet walls normal to the workload's L axis)."""
     shape = tuple(cfg["shape"]) if shape is None else tuple(shape)
     p = default_params(cfg["pair"], precision, shape)
     if cs2_T is not None:
@@ -68,6 +87,10 @@ def params_from_workload(cfg, precision="f64", shape=None, cs2_T=None):
                cfg["L_axis"], cfg["T_hot"], cfg["T_cold"])
     p.up_axis = cfg["up_axis"]
     set_faces(p, cfg["faces"])
+    if T_reference == "conduction":
+        conduction_reference(p, cfg["L_axis"])
+    elif T_reference != "uniform":
+        raise ValueError("T_reference must be 'uniform' or 'conduction'")
     return p
 
 

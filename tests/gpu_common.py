@@ -62,11 +62,21 @@ def perturbed_state(cfg, seed, amp=1e-2):
     return f * (1 + amp * pf), g * (1 + amp * pg)
 
 
-def make_sim(cfg, precision, wall_profiles=None):
-    from paper_2504_09041_amd.sim import Simulation, params_from_workload
+def workload_params(cfg, precision):
+    """C parameters; precision "f64", "f32dev" (uniform thermal storage
+    reference T0) or "f32cond" (FP32 deviations from the conduction profile
+    between the Dirichlet walls of the workload's L axis)."""
+    from paper_2504_09041_amd.sim import params_from_workload
 
-    p = params_from_workload(cfg, precision)
-    return Simulation(p, wall_profiles=wall_profiles)
+    if precision == "f32cond":
+        return params_from_workload(cfg, "f32dev", T_reference="conduction")
+    return params_from_workload(cfg, precision)
+
+
+def make_sim(cfg, precision, wall_profiles=None):
+    from paper_2504_09041_amd.sim import Simulation
+
+    return Simulation(workload_params(cfg, precision), wall_profiles=wall_profiles)
 
 
 def load_state(sim, f, g, step=0):

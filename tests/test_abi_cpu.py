@@ -44,7 +44,9 @@ def test_params_struct_layout_matches_header():
     # offsets of the trailing members pin the struct layout used by ctypes
     p = A.fpc_params
     assert p.omega_f.offset == 20 + 4  # 5 ints, padded to 8
-    assert ctypes.sizeof(p) == p.wall_T_profile.offset + 6 * 8
+    assert p.T_ref_slope.offset == p.wall_T_profile.offset + 6 * 8
+    assert p.T_ref_axis.offset == p.T_ref_slope.offset + 8
+    assert ctypes.sizeof(p) == p.T_ref_axis.offset + 8  # int padded to the struct's 8-byte alignment
 
 
 def test_validation_errors():
@@ -71,6 +73,20 @@ def test_validation_errors():
     p.bc[4] = A.FPC_BC_NOSLIP_ADIABATIC
     p.bc[5] = A.FPC_BC_NOSLIP_ADIABATIC
     assert lib.fpc_state_bytes(ctypes.byref(p), ctypes.byref(nb), None) == A.FPC_ERR_ARG
+    p.bc[4] = p.bc[5] = A.FPC_BC_PERIODIC
+    # thermal storage reference: axis in range, not periodic, finite slope
+    assert p.T_ref_axis == -1 and p.T_ref_slope == 0.0
+    p.T_ref_slope = 0.01
+    p.T_ref_axis = 2
+    assert lib.fpc_state_bytes(ctypes.byref(p), ctypes.byref(nb), None) == A.FPC_ERR_ARG
+    p.T_ref_axis = 0  # x is walled by now
+    assert lib.fpc_state_bytes(ctypes.byref(p), ctypes.byref(nb), None) == A.FPC_OK
+    p.T_ref_axis = 1  # y is periodic
+    assert lib.fpc_state_bytes(ctypes.byref(p), ctypes.byref(nb), None) == A.FPC_ERR_ARG
+    p.T_ref_axis = 0
+    p.T_ref_slope = float("nan")
+    assert lib.fpc_state_bytes(ctypes.byref(p), ctypes.byref(nb), None) == A.FPC_ERR_ARG
+    p.T_ref_slope = 0.0
     h = ctypes.c_void_p()
     assert lib.fpc_create(None, None, None, None, ctypes.byref(h)) == A.FPC_ERR_ARG
     assert lib.fpc_step(None, 1) == A.FPC_ERR_ARG

@@ -56,7 +56,7 @@ def _ptr(t):
 
 
 @pytest.mark.parametrize("case", list(G.SMALL_CASES))
-@pytest.mark.parametrize("precision,tol", [("f64", 1e-12), ("f32dev", 2e-5)])
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-12), ("f32dev", 2e-5), ("f32cond", 2e-5)])
 def test_adjoint_step_matches_oracle_vjp(case, precision, tol):
     from paper_2504_09041_amd import _abi as A
 

@@ -67,10 +67,26 @@ def test_fp64_steps_match_oracle(case, nsteps, tol):
 
 
 @pytest.mark.parametrize("case", CASES)
-def test_fp32_deviation_steps_match_oracle(case):
+def test_init_with_conduction_reference(case):
+    """FP32 deviations from the affine reference: the stored state, exported to
+    FP64, is the oracle's initial state up to FP32 rounding of the deviations."""
+    cfg = G.small_config(case)
+    T = G.initial_T(cfg) + 0.2 * torch.tensor(workloads.uniform_field(tuple(cfg["shape"][::-1]), 14))
+    sim = G.make_sim(cfg, "f32cond")
+    sim.init(T.cuda())
+    f, g = G.read_state(sim)
+    fo, go = osim.init_state(params_from_config(cfg), T)
+    assert G.rel_err(f, fo) < 1e-6
+    assert G.rel_err(g, go) < 1e-6
+    assert float((sim.macros()["T"].cpu() - T).abs().max()) < 1e-6
+
+
+@pytest.mark.parametrize("case", CASES)
+@pytest.mark.parametrize("precision", ["f32dev", "f32cond"])
+def test_fp32_deviation_steps_match_oracle(case, precision):
     cfg = G.small_config(case)
     f0, g0 = G.perturbed_state(cfg, seed=12)
-    sim = G.make_sim(cfg, "f32dev")
+    sim = G.make_sim(cfg, precision)
     G.load_state(sim, f0, g0)
     sim.step(100)
     f, g = G.read_state(sim)
@@ -80,7 +96,7 @@ def test_fp32_deviation_steps_match_oracle(case):
     nu_o = float(osim.nusselt(prm, mac["T"], cfg["nu_face"]))
     dT = cfg["T_hot"] - cfg["T_cold"]
     eT = float((m["T"].cpu() - mac["T"]).abs().max())
-    print(f"case={case} f32dev: rel f {G.rel_err(f, fo):.2e} rel g {G.rel_err(g, go):.2e} "
+    print(f"case={case} {precision}: rel f {G.rel_err(f, fo):.2e} rel g {G.rel_err(g, go):.2e} "
           f"max|dT| {eT:.2e} Nu gpu {d['nu']:.8f} oracle {nu_o:.8f}")
     # round-off of FP32 storage over 100 steps (the thermal rates of the
     # mixed-convection case are close to 2, so that error is barely damped)
@@ -158,6 +174,8 @@ def test_nan_is_reported_unstable():
     ("mixed2d_512", "f32dev", 2e-6),
     ("dhc3d_256", "f32dev", 2e-6),
     ("rb3d_128", "f32dev", 2e-6),
+    ("rb2d_1024x512", "f32cond", 2e-6),
+    ("dhc3d_256", "f32cond", 2e-6),
 ])
 def test_full_size_step_on_sampled_nodes(workload, precision, tol):
     """One step at the full workload size from a hashed input state; the
