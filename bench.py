@@ -87,16 +87,16 @@ def copy_bandwidth(mib, reps):
 
 
 def kernel_fingerprint():
-    """sha256 over the HIP sources of the library: counters recorded for other
-    sources do not describe the kernels that run."""
+    """sha256 over the sources of the forward step kernel: counters recorded
+    for other sources do not describe the kernel that runs."""
     import hashlib
 
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2504_09041_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".h")):
-            with open(os.path.join(csrc, name), "rb") as fh:
-                h.update(name.encode() + b"\0" + fh.read())
+    # the forward step kernel and everything it includes
+    for name in ("fpc_step.hip", "fpc_collide.h", "fpc_kernels.h", "fpc_lattice.h"):
+        with open(os.path.join(csrc, name), "rb") as fh:
+            h.update(name.encode() + b"\0" + fh.read())
     return h.hexdigest()[:16]
 
 
@@ -316,32 +316,55 @@ def precision_study(name, nsteps, every, noise=1e-7):
     return {"workload": name, "noise": noise, "rows": rows}
 
 
-def cpu_baseline(name, nsteps):
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(name, nsteps, nsteps_1t=2):
     """The FP64 CPU oracle on the host cores, on a bounded sample of the same
-    workload (nsteps steps of the full grid after its initial collision)."""
+    workload (nsteps steps of the full grid after its initial collision), with
+    all threads and with one thread."""
     import torch
 
     import workloads
     from oracle import sim as osim
     from oracle.params import params_from_config
 
-    torch.set_num_threads(os.cpu_count() or 1)
     cfg = workloads.config(name)
     prm = params_from_config(cfg)
-    T = torch.tensor(workloads.initial_temperature(cfg))
-    f, g = osim.init_state(prm, T)
-    f, g, _ = osim.step(prm, f, g)  # warm-up step (not timed)
-    t0 = time.perf_counter()
-    f, g, _ = osim.run(prm, f, g, nsteps)
-    dt = time.perf_counter() - t0
     N = cfg["shape"][0] * cfg["shape"][1] * cfg["shape"][2]
+    T = torch.tensor(workloads.initial_temperature(cfg))
+    f0, g0 = osim.init_state(prm, T)
+
+    def timed(threads, n):
+        torch.set_num_threads(threads)
+        f, g, _ = osim.step(prm, f0, g0)  # warm-up step (not timed)
+        t0 = time.perf_counter()
+        osim.run(prm, f, g, n)
+        return time.perf_counter() - t0
+
+    threads = os.cpu_count() or 1
+    dt = timed(threads, nsteps)
+    dt1 = timed(1, nsteps_1t) if nsteps_1t > 0 else None
+    torch.set_num_threads(threads)
     return {
         "value": N * nsteps / dt / 1e6,
         "unit": "MLUPS",
-        "cores": torch.get_num_threads(),
+        "cores": threads,
         "kind": "oracle",
         "sample": f"{nsteps} FP64 oracle steps of the full {cfg['shape'][0]}x{cfg['shape'][1]} grid "
-                  f"({dt:.1f} s)",
+                  f"({dt:.1f} s, {threads} threads)",
+        "value_1_thread": N * nsteps_1t / dt1 / 1e6 if dt1 else None,
+        "sample_1_thread": f"{nsteps_1t} steps ({dt1:.1f} s)" if dt1 else None,
+        "cpu_model": _cpu_model(),
+        "nproc": os.cpu_count(),
     }
 
 
@@ -377,12 +400,21 @@ def main():
         extra["rb2d_1024x512_f32dev"] = time_workload("rb2d_1024x512", "f32dev", a.steps, a.warmup)
         extra["rb2d_1024x512_f32cond"] = time_workload("rb2d_1024x512", "f32cond", a.steps, a.warmup)
         extra["dhc3d_256_f32dev"] = time_workload("dhc3d_256", "f32dev", a.steps3d, max(5, a.warmup // 10))
+        extra["rb3d_128_f32dev"] = time_workload("rb3d_128", "f32dev", 5 * a.steps3d, max(5, a.warmup // 10))
+        # the same 2D physics on a grid whose state (3.8 GB) does not fit the
+        # last-level cache: a pure-HBM figure for the FP64 kernel
+        extra["rb2d_4096x4096_f64"] = time_workload("rb2d_1024x512", "f64", a.steps3d, max(5, a.warmup // 10),
+                                                    shape=(4096, 4096, 1))
+        # the 64 x 64 cavity: launch-bound (4096 nodes per launch)
+        extra["dhc2d_64_f64"] = time_workload("dhc2d_64", "f64", a.steps, a.warmup)
+        extra["copy_4GiB"] = copy_bandwidth(4096, 20)
     if not a.no_extra and not a.no_adjoint:
         extra["adjoint_mixed2d_512_f32dev"] = adjoint_cost("mixed2d_512", 400, 100)
         extra["adjoint_rb3d_128_f32dev"] = adjoint_cost("rb3d_128", 64, 8)
     tr = _traffic_record().get("rb2d_1024x512_f64")
     if tr and tr.get("sources") != kernel_fingerprint():
         tr = None  # the kernels changed since the counters were taken
+    copy = extra.get("copy_4GiB")
     roof = {
         "bound": "hbm",
         "achieved": head["achieved_GBs"],
@@ -392,6 +424,8 @@ def main():
         # HBM-side bytes per launch from the scaled FETCH_SIZE + WRITE_SIZE counters
         "traffic": tr["traffic_bytes"] if tr else None,
         "algorithmic_bytes": head["bytes_per_node"] * head["nodes"],
+        # fraction of what a plain elementwise copy attains on this device
+        "frac_of_copy": head["achieved_GBs"] / copy["GBs"] if copy else None,
     }
     cpu = None
     if not a.no_cpu_baseline:

@@ -80,16 +80,41 @@ __device__ __forceinline__ R dprod(R rr, R RX, R dx, R RY, R dy) {
   return rr * (RX * dy + RY * dx) + dx * dy;
 }
 
+// Relaxation rates.  STD = true: the standard rate set, where only the slots
+// carrying the viscosity (2D: 20-02 and 11; 3D: the off-diagonals and the two
+// deviators) and the thermal first-order slots relax at the runtime rates
+// c.om[4] and c.omg[1], and every other slot at 1 (compile-time, so the
+// algebra of those slots folds).  STD = false: every slot at its own rate.
+template <int D, bool STD, class R>
+__device__ __forceinline__ R rate_f(const CollParams<R>& c, int k) {
+  if (!STD) return c.om[k];
+  const bool nu = D == 2 ? (k == 4 || k == 5) : (k == 4 || k == 5 || k == 6 || k == 8 || k == 9);
+  return nu ? c.om[4] : R(1);
+}
+template <int D, bool STD, class R>
+__device__ __forceinline__ R rate_g(const CollParams<R>& c, int k) {
+  if (!STD) return c.omg[k];
+  return (k >= 1 && k <= D) ? c.omg[1] : R(1);
+}
+
+// FP32 storage holds deviations from rho_r; FP64 storage holds the plain
+// populations (rho_r = 0, folded at compile time).
+template <class R>
+__device__ __forceinline__ R rho_ref(const CollParams<R>& c) {
+  if constexpr (sizeof(R) == 4) return c.rho_r;
+  return R(0);
+}
+
 // ---------------------------------------------------------------------------
 // 2D: D2Q9 fluid + D2Q5 thermal.  f, g hold the pulled (pre-collision) stored
 // values on entry and the post-collision stored values on exit.
 // ---------------------------------------------------------------------------
 // Tr: storage reference of g at this node (g is stored as g - w^T Tr).
-template <class R, int UP>
+template <class R, int UP, bool STD = false>
 __device__ __forceinline__ void collide2d(R (&f)[kQ2], R (&g)[kQ2T], const CollParams<R>& c, R Tr,
                                           Macros<R>* mac) {
   constexpr R cs2 = R(1) / R(3);
-  const R rr = c.rho_r;
+  const R rr = rho_ref(c);
   const R drho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
   const R jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
   const R jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
@@ -136,21 +161,21 @@ __device__ __forceinline__ void collide2d(R (&f)[kQ2], R (&g)[kQ2T], const CollP
   }
 
   // relaxation (deviation form; attractor deviations dMv = Mv - rho_r kappa_rest)
-  const R* om = c.om;
-  const R t10 = k10 + om[1] * (rr * ux - k10) + (R(1) - R(0.5) * om[1]) * Fx;
-  const R t01 = k01 + om[2] * (rr * uy - k01) + (R(1) - R(0.5) * om[2]) * Fy;
+  auto om = [&](int k) -> R { return rate_f<2, STD>(c, k); };
+  const R t10 = k10 + om(1) * (rr * ux - k10) + (R(1) - R(0.5) * om(1)) * Fx;
+  const R t01 = k01 + om(2) * (rr * uy - k01) + (R(1) - R(0.5) * om(2)) * Fy;
   const R k2s = k20 + k02, k2d = k20 - k02;
-  const R t2s = k2s + om[3] * ((R(2) * cs2 * drho - rr * (uxx + uyy)) - k2s);
-  const R t2d = k2d + om[4] * (-rr * (uxx - uyy) - k2d);
-  const R t11 = k11 + om[5] * (-rr * uxy - k11);
+  const R t2s = k2s + om(3) * ((R(2) * cs2 * drho - rr * (uxx + uyy)) - k2s);
+  const R t2d = k2d + om(4) * (-rr * (uxx - uyy) - k2d);
+  const R t11 = k11 + om(5) * (-rr * uxy - k11);
   const R t20 = R(0.5) * (t2s + t2d);
   const R t02 = R(0.5) * (t2s - t2d);
-  const R t21 = k21 + om[6] * (rr * A * uy - k21) + (R(1) - R(0.5) * om[6]) * s21;
-  const R t12 = k12 + om[7] * (rr * ux * B - k12) + (R(1) - R(0.5) * om[7]) * s12;
+  const R t21 = k21 + om(6) * (rr * A * uy - k21) + (R(1) - R(0.5) * om(6)) * s21;
+  const R t12 = k12 + om(7) * (rr * ux * B - k12) + (R(1) - R(0.5) * om(7)) * s12;
   // kappa^Mv_22 = (kappa~20 kappa~02 + 2 kappa~11^2) / rho
   const R mv22 = (dprod(rr, A, t20, B, t02) + R(2) * dprod(rr, uxy, t11, uxy, t11) +
                   rr * rr * (R(2) * uxx * uyy) - rr * A * B * drho) * irho;
-  const R t22 = k22 + om[8] * (mv22 - k22) + (R(1) - R(0.5) * om[8]) * s22;
+  const R t22 = k22 + om(8) * (mv22 - k22) + (R(1) - R(0.5) * om(8)) * s22;
 
   // central -> populations: y shifts per mx, then x shifts per row ey
   shift_inv(drho, t01, t02, uy, x0m, x0z, x0p);
@@ -162,17 +187,17 @@ __device__ __forceinline__ void collide2d(R (&f)[kQ2], R (&g)[kQ2T], const CollP
 
   // thermal D2Q5: raw moments (00, 10, 01, 20, 02) -> central -> relax -> back
   const R cT = c.cs2T;
-  const R* og = c.omg;
+  auto og = [&](int k) -> R { return rate_g<2, STD>(c, k); };
   const R n10 = g[1] - g[3], n01 = g[2] - g[4], n20 = g[1] + g[3], n02 = g[2] + g[4];
   const R e10 = n10 - ux * dT;
   const R e01 = n01 - uy * dT;
   const R e20 = n20 - R(2) * ux * n10 + uxx * dT;
   const R e02 = n02 - R(2) * uy * n01 + uyy * dT;
-  const R te10 = e10 + og[1] * (Tr * ux - e10);
-  const R te01 = e01 + og[2] * (Tr * uy - e01);
+  const R te10 = e10 + og(1) * (Tr * ux - e10);
+  const R te01 = e01 + og(2) * (Tr * uy - e01);
   const R e2s = e20 + e02, e2d = e20 - e02;
-  const R te2s = e2s + og[3] * ((R(2) * cT * dT - Tr * (uxx + uyy)) - e2s);
-  const R te2d = e2d + og[4] * (-Tr * (uxx - uyy) - e2d);
+  const R te2s = e2s + og(3) * ((R(2) * cT * dT - Tr * (uxx + uyy)) - e2s);
+  const R te2d = e2d + og(4) * (-Tr * (uxx - uyy) - e2d);
   const R te20 = R(0.5) * (te2s + te2d);
   const R te02 = R(0.5) * (te2s - te2d);
   const R m10 = te10 + ux * dT;
@@ -198,11 +223,11 @@ __device__ __forceinline__ R cpow(int m, R u, R cs2) {
   return m == 0 ? R(1) : (m == 1 ? -u : cs2 + u * u);
 }
 
-template <class R, int UP>
+template <class R, int UP, bool STD = false>
 __device__ __forceinline__ void collide3d(R (&f)[kQ3], R (&g)[kQ3T], const CollParams<R>& c, R Tr,
                                           Macros<R>* mac) {
   constexpr R cs2 = R(1) / R(3);
-  const R rr = c.rho_r;
+  const R rr = rho_ref(c);
 
   // macros
   R drho = R(0), jx = R(0), jy = R(0), jz = R(0);
@@ -273,7 +298,7 @@ __device__ __forceinline__ void collide3d(R (&f)[kQ3], R (&g)[kQ3T], const CollP
     if (m2 + n2 + p2 == 1) return R(0);
     return R(mu) * Fr * Kfull(m2, n2, p2);
   };
-  const R* om = c.om;
+  auto om = [&](int k) -> R { return rate_f<3, STD>(c, k); };
   auto relax = [&](R k, R dmv, R w_, R s) -> R { return k + w_ * (dmv - k) + (R(1) - R(0.5) * w_) * s; };
 
   // sources of orders 3-6 from pre-collision moments, before anything is overwritten
@@ -285,31 +310,31 @@ __device__ __forceinline__ void collide3d(R (&f)[kQ3], R (&g)[kQ3T], const CollP
 
   // order 0 and 1
   w[I3(0, 0, 0)] = drho;
-  w[I3(1, 0, 0)] = relax(w[I3(1, 0, 0)], rr * ux, om[1], Fx);
-  w[I3(0, 1, 0)] = relax(w[I3(0, 1, 0)], rr * uy, om[2], Fy);
-  w[I3(0, 0, 1)] = relax(w[I3(0, 0, 1)], rr * uz, om[3], Fz);
+  w[I3(1, 0, 0)] = relax(w[I3(1, 0, 0)], rr * ux, om(1), Fx);
+  w[I3(0, 1, 0)] = relax(w[I3(0, 1, 0)], rr * uy, om(2), Fy);
+  w[I3(0, 0, 1)] = relax(w[I3(0, 0, 1)], rr * uz, om(3), Fz);
   // order 2: off-diagonal, then trace and the two deviators
-  w[I3(1, 1, 0)] = relax(w[I3(1, 1, 0)], -rr * uxy, om[4], R(0));
-  w[I3(1, 0, 1)] = relax(w[I3(1, 0, 1)], -rr * uxz, om[5], R(0));
-  w[I3(0, 1, 1)] = relax(w[I3(0, 1, 1)], -rr * uyz, om[6], R(0));
+  w[I3(1, 1, 0)] = relax(w[I3(1, 1, 0)], -rr * uxy, om(4), R(0));
+  w[I3(1, 0, 1)] = relax(w[I3(1, 0, 1)], -rr * uxz, om(5), R(0));
+  w[I3(0, 1, 1)] = relax(w[I3(0, 1, 1)], -rr * uyz, om(6), R(0));
   {
     const R a = w[I3(2, 0, 0)], b = w[I3(0, 2, 0)], d = w[I3(0, 0, 2)];
-    const R ts = relax(a + b + d, R(3) * cs2 * drho - rr * (uxx + uyy + uzz), om[7], R(0));
-    const R t1 = relax(a - b, -rr * (uxx - uyy), om[8], R(0));
-    const R t2 = relax(a - d, -rr * (uxx - uzz), om[9], R(0));
+    const R ts = relax(a + b + d, R(3) * cs2 * drho - rr * (uxx + uyy + uzz), om(7), R(0));
+    const R t1 = relax(a - b, -rr * (uxx - uyy), om(8), R(0));
+    const R t2 = relax(a - d, -rr * (uxx - uzz), om(9), R(0));
     const R t200 = (ts + t1 + t2) * (R(1) / R(3));
     w[I3(2, 0, 0)] = t200;
     w[I3(0, 2, 0)] = t200 - t1;
     w[I3(0, 0, 2)] = t200 - t2;
   }
   // order 3: attractors zero, deviation -rho_r kappa_rest
-  w[I3(1, 2, 0)] = relax(w[I3(1, 2, 0)], -rr * Rst(1, 2, 0), om[10], s120);
-  w[I3(1, 0, 2)] = relax(w[I3(1, 0, 2)], -rr * Rst(1, 0, 2), om[11], s102);
-  w[I3(2, 1, 0)] = relax(w[I3(2, 1, 0)], -rr * Rst(2, 1, 0), om[12], s210);
-  w[I3(0, 1, 2)] = relax(w[I3(0, 1, 2)], -rr * Rst(0, 1, 2), om[13], s012);
-  w[I3(2, 0, 1)] = relax(w[I3(2, 0, 1)], -rr * Rst(2, 0, 1), om[14], s201);
-  w[I3(0, 2, 1)] = relax(w[I3(0, 2, 1)], -rr * Rst(0, 2, 1), om[15], s021);
-  w[I3(1, 1, 1)] = relax(w[I3(1, 1, 1)], -rr * Rst(1, 1, 1), om[16], s111);
+  w[I3(1, 2, 0)] = relax(w[I3(1, 2, 0)], -rr * Rst(1, 2, 0), om(10), s120);
+  w[I3(1, 0, 2)] = relax(w[I3(1, 0, 2)], -rr * Rst(1, 0, 2), om(11), s102);
+  w[I3(2, 1, 0)] = relax(w[I3(2, 1, 0)], -rr * Rst(2, 1, 0), om(12), s210);
+  w[I3(0, 1, 2)] = relax(w[I3(0, 1, 2)], -rr * Rst(0, 1, 2), om(13), s012);
+  w[I3(2, 0, 1)] = relax(w[I3(2, 0, 1)], -rr * Rst(2, 0, 1), om(14), s201);
+  w[I3(0, 2, 1)] = relax(w[I3(0, 2, 1)], -rr * Rst(0, 2, 1), om(15), s021);
+  w[I3(1, 1, 1)] = relax(w[I3(1, 1, 1)], -rr * Rst(1, 1, 1), om(16), s111);
 
   // order 4: products of post-collision second-order moments
   const R rr2 = rr * rr;
@@ -323,12 +348,12 @@ __device__ __forceinline__ void collide3d(R (&f)[kQ3], R (&g)[kQ3T], const CollP
     const R mv211 = (P(2, 0, 0, 0, 1, 1) + R(2) * P(1, 1, 0, 1, 0, 1) + rr2 * (R(2) * uxx * uyz) - rr * A * uyz * drho) * irho;
     const R mv121 = (P(0, 2, 0, 1, 0, 1) + R(2) * P(1, 1, 0, 0, 1, 1) + rr2 * (R(2) * uyy * uxz) - rr * B * uxz * drho) * irho;
     const R mv112 = (P(0, 0, 2, 1, 1, 0) + R(2) * P(0, 1, 1, 1, 0, 1) + rr2 * (R(2) * uzz * uxy) - rr * C * uxy * drho) * irho;
-    w[I3(2, 2, 0)] = relax(w[I3(2, 2, 0)], mv220, om[17], s220);
-    w[I3(2, 0, 2)] = relax(w[I3(2, 0, 2)], mv202, om[18], s202);
-    w[I3(0, 2, 2)] = relax(w[I3(0, 2, 2)], mv022, om[19], s022);
-    w[I3(2, 1, 1)] = relax(w[I3(2, 1, 1)], mv211, om[20], s211);
-    w[I3(1, 2, 1)] = relax(w[I3(1, 2, 1)], mv121, om[21], s121);
-    w[I3(1, 1, 2)] = relax(w[I3(1, 1, 2)], mv112, om[22], s112);
+    w[I3(2, 2, 0)] = relax(w[I3(2, 2, 0)], mv220, om(17), s220);
+    w[I3(2, 0, 2)] = relax(w[I3(2, 0, 2)], mv202, om(18), s202);
+    w[I3(0, 2, 2)] = relax(w[I3(0, 2, 2)], mv022, om(19), s022);
+    w[I3(2, 1, 1)] = relax(w[I3(2, 1, 1)], mv211, om(20), s211);
+    w[I3(1, 2, 1)] = relax(w[I3(1, 2, 1)], mv121, om(21), s121);
+    w[I3(1, 1, 2)] = relax(w[I3(1, 1, 2)], mv112, om(22), s112);
   }
   // order 5: (2 / 5 rho) [...] from post-collision second x third order
   {
@@ -348,9 +373,9 @@ __device__ __forceinline__ void collide3d(R (&f)[kQ3], R (&g)[kQ3T], const CollP
     const R mv221 = (f25 * (P(2, 0, 0, 0, 2, 1) + P(0, 2, 0, 2, 0, 1) + R(4) * P(1, 1, 0, 1, 1, 1) +
                             R(2) * (P(0, 1, 1, 2, 1, 0) + P(1, 0, 1, 1, 2, 0))) +
                      rr2 * r221 - rr * Rst(2, 2, 1) * drho) * irho;
-    w[I3(1, 2, 2)] = relax(w[I3(1, 2, 2)], mv122, om[23], s122);
-    w[I3(2, 1, 2)] = relax(w[I3(2, 1, 2)], mv212, om[24], s212);
-    w[I3(2, 2, 1)] = relax(w[I3(2, 2, 1)], mv221, om[25], s221);
+    w[I3(1, 2, 2)] = relax(w[I3(1, 2, 2)], mv122, om(23), s122);
+    w[I3(2, 1, 2)] = relax(w[I3(2, 1, 2)], mv212, om(24), s212);
+    w[I3(2, 2, 1)] = relax(w[I3(2, 2, 1)], mv221, om(25), s221);
   }
   // order 6: (1 / 3 rho) [...] from post-collision second x fourth order
   {
@@ -359,7 +384,7 @@ __device__ __forceinline__ void collide3d(R (&f)[kQ3], R (&g)[kQ3T], const CollP
                             R(4) * (P(1, 1, 0, 1, 1, 2) + P(1, 0, 1, 1, 2, 1) + P(0, 1, 1, 2, 1, 1))) +
                      rr2 * (R(4) / R(3)) * (uxx * uyy * C + uxx * uzz * B + uyy * uzz * A) -
                      rr * A * B * C * drho) * irho;
-    w[I3(2, 2, 2)] = relax(w[I3(2, 2, 2)], mv222, om[26], s222);
+    w[I3(2, 2, 2)] = relax(w[I3(2, 2, 2)], mv222, om(26), s222);
   }
 
   // central -> populations: z shifts, then y, then x
@@ -386,19 +411,19 @@ __device__ __forceinline__ void collide3d(R (&f)[kQ3], R (&g)[kQ3T], const CollP
 
   // thermal D3Q7: links 1/2 = +-x, 3/4 = +-y, 5/6 = +-z
   const R cT = c.cs2T;
-  const R* og = c.omg;
+  auto og = [&](int k) -> R { return rate_g<3, STD>(c, k); };
   const R n100 = g[1] - g[2], n010 = g[3] - g[4], n001 = g[5] - g[6];
   const R n200 = g[1] + g[2], n020 = g[3] + g[4], n002 = g[5] + g[6];
   const R e100 = n100 - ux * dT, e010 = n010 - uy * dT, e001 = n001 - uz * dT;
   const R e200 = n200 - R(2) * ux * n100 + uxx * dT;
   const R e020 = n020 - R(2) * uy * n010 + uyy * dT;
   const R e002 = n002 - R(2) * uz * n001 + uzz * dT;
-  const R te100 = e100 + og[1] * (Tr * ux - e100);
-  const R te010 = e010 + og[2] * (Tr * uy - e010);
-  const R te001 = e001 + og[3] * (Tr * uz - e001);
-  const R te200 = e200 + og[4] * ((cT * dT - Tr * uxx) - e200);
-  const R te020 = e020 + og[5] * ((cT * dT - Tr * uyy) - e020);
-  const R te002 = e002 + og[6] * ((cT * dT - Tr * uzz) - e002);
+  const R te100 = e100 + og(1) * (Tr * ux - e100);
+  const R te010 = e010 + og(2) * (Tr * uy - e010);
+  const R te001 = e001 + og(3) * (Tr * uz - e001);
+  const R te200 = e200 + og(4) * ((cT * dT - Tr * uxx) - e200);
+  const R te020 = e020 + og(5) * ((cT * dT - Tr * uyy) - e020);
+  const R te002 = e002 + og(6) * ((cT * dT - Tr * uzz) - e002);
   const R m100 = te100 + ux * dT, m010 = te010 + uy * dT, m001 = te001 + uz * dT;
   const R m200 = te200 + R(2) * ux * te100 + uxx * dT;
   const R m020 = te020 + R(2) * uy * te010 + uyy * dT;

@@ -49,90 +49,154 @@ struct Lat3 {
   static constexpr double w(int a) { return w3(a); }
 };
 
-// Load base[idx] with a 32-bit byte offset (uniform base + lane offset).
-template <class R>
-__device__ __forceinline__ R ld(const R* base, unsigned idx) {
-  return *reinterpret_cast<const R*>(reinterpret_cast<const char*>(base) + idx * (unsigned)sizeof(R));
-}
-// FPC_BUFFER_OPS = 1 routes unchecked loads and all stores through raw buffer
-// instructions (a wave-uniform descriptor per plane and one 32-bit lane offset
-// shared by every access).  It lowers the register count of the 3D FP32 kernel
-// but measured ~2-4 % slower than global loads on gfx950, so it is off.
-#ifndef FPC_BUFFER_OPS
-#define FPC_BUFFER_OPS 0
-#endif
+// ---------------------------------------------------------------------------
+// State addressing.  Two policies with the same interface:
+//   load(q, shift, idx)   plane q at lane index idx - shift (shift wave-uniform)
+//   load_sel(w, qw, iw, q, shift, idx)  per lane: plane qw at iw if w, else as load
+//   store<NT>(q, idx, v)
+// Buf32: the whole buffer through one raw buffer descriptor; the lane supplies
+//   a 32-bit byte offset and the plane offset is a wave-uniform scalar
+//   (usable while the buffer is below 4 GiB).  Keeps the address arithmetic
+//   off the vector ALU and the scalar register file small.
+// Glob64: 64-bit plane base pointers plus a 32-bit lane offset (any size).
+// ---------------------------------------------------------------------------
 constexpr int kBufDword3 = 0x00020000;  // raw (untyped) buffer, gfx9 family
 typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
 
 template <class R>
-__device__ __forceinline__ R ldb(const R* base, unsigned idx) {
-#if FPC_BUFFER_OPS
-  const auto rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<R*>(base), 0, -1, kBufDword3);
-  if constexpr (sizeof(R) == 4)
-    return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b32(rs, idx * 4u, 0, 0));
-  else
-    return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b64(rs, idx * 8u, 0, 0));
-#else
-  return ld(base, idx);
-#endif
-}
+struct Buf32 {
+  const StepArgs<R>& a;
+  unsigned nbytes;  // buffer size (bytes)
+  static constexpr unsigned S = sizeof(R);
 
-template <class R, bool NT>
-__device__ __forceinline__ void st(R* base, unsigned idx, R v) {
-#if FPC_BUFFER_OPS
-  const auto rs = __builtin_amdgcn_make_buffer_rsrc(base, 0, -1, kBufDword3);
-  constexpr int aux = NT ? 2 : 0;  // cache policy: non-temporal
-  if constexpr (sizeof(R) == 4)
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), rs, idx * 4u, 0, aux);
-  else
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), rs, idx * 8u, 0, aux);
-#else
-  R* p = reinterpret_cast<R*>(reinterpret_cast<char*>(base) + idx * (unsigned)sizeof(R));
-  if constexpr (NT)
-    __builtin_nontemporal_store(v, p);
-  else
-    *p = v;
-#endif
-}
+  __device__ __forceinline__ Buf32(const StepArgs<R>& a_, unsigned total_bytes) : a(a_), nbytes(total_bytes) {}
 
-template <class L, class R, bool CX, bool CY, bool CZ>
+  // descriptors built at each use from the kernel arguments (wave-uniform,
+  // so they stay in scalar registers and are shared by CSE)
+  __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc_src() const {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<R*>(a.src), 0, (int)nbytes, kBufDword3);
+  }
+  __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc_dst() const {
+    return __builtin_amdgcn_make_buffer_rsrc(a.dst, 0, (int)nbytes, kBufDword3);
+  }
+  __device__ __forceinline__ unsigned pb() const { return (unsigned)a.plane * S; }
+
+  __device__ __forceinline__ R raw(unsigned voff, unsigned soff) const {
+    if constexpr (sizeof(R) == 4)
+      return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b32(rsrc_src(), (int)voff, (int)soff, 0));
+    else
+      return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b64(rsrc_src(), (int)voff, (int)soff, 0));
+  }
+  // byte offset of plane q minus the streaming shift (non-negative for q >= 1
+  // or shift == 0, as every plane is longer than any shift)
+  __device__ __forceinline__ unsigned base(int q, long long shift) const {
+    return (unsigned)q * pb() - (unsigned)(shift * (long long)S);
+  }
+  __device__ __forceinline__ R load(int q, long long shift, unsigned idx) const {
+    return raw(idx * S, base(q, shift));
+  }
+  __device__ __forceinline__ R load_sel(bool w, int qw, unsigned iw, int q, long long shift, unsigned idx) const {
+    const unsigned vs = idx * S + base(q, shift);
+    const unsigned vw = iw * S + (unsigned)qw * pb();
+    return raw(w ? vw : vs, 0u);
+  }
+  template <bool NT>
+  __device__ __forceinline__ void store(int q, unsigned idx, R v) const {
+    constexpr int aux = NT ? 2 : 0;  // cache policy: non-temporal
+    // plane offset on the lane side: one add per store, no scalar register
+    // per plane held across the collision
+    const int vo = (int)(idx * S + (unsigned)q * pb());
+    if constexpr (sizeof(R) == 4)
+      __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), rsrc_dst(), vo, 0, aux);
+    else
+      __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), rsrc_dst(), vo, 0, aux);
+  }
+};
+
+template <class R>
+struct Glob64 {
+  const R* src;
+  R* dst;
+  size_t plane;
+
+  __device__ __forceinline__ Glob64(const StepArgs<R>& a, unsigned) : src(a.src), dst(a.dst), plane(a.plane) {}
+
+  // base[idx] with a 32-bit byte offset (uniform base + lane offset)
+  static __device__ __forceinline__ R ld(const R* base, unsigned idx) {
+    return *reinterpret_cast<const R*>(reinterpret_cast<const char*>(base) + idx * (unsigned)sizeof(R));
+  }
+  __device__ __forceinline__ R load(int q, long long shift, unsigned idx) const {
+    return ld(src + (size_t)q * plane - shift, idx);
+  }
+  __device__ __forceinline__ R load_sel(bool w, int qw, unsigned iw, int q, long long shift, unsigned idx) const {
+    const R* pw = src + (size_t)qw * plane;
+    const R* ps = src + (size_t)q * plane - shift;
+    return ld(w ? pw : ps, w ? iw : idx);
+  }
+  template <bool NT>
+  __device__ __forceinline__ void store(int q, unsigned idx, R v) const {
+    R* p = reinterpret_cast<R*>(reinterpret_cast<char*>(dst + (size_t)q * plane) + idx * (unsigned)sizeof(R));
+    if constexpr (NT)
+      __builtin_nontemporal_store(v, p);
+    else
+      *p = v;
+  }
+};
+
+template <class L, class R, class M, bool CX, bool CY, bool CZ, bool PX>
 struct Gather {
   const StepArgs<R>& a;
+  const M& m;
   int x, y, z;
   unsigned node;
   R Tr;  // thermal storage reference of this node
+  // Lane on the low / high edge of a checked axis.  A link with e_k = +1
+  // crossing the low edge (or e_k = -1 crossing the high edge) either wraps
+  // (periodic axis: the source index moves by +-n_k times the axis stride) or
+  // meets a wall.  PX: x is known to be periodic.
+  bool xlo = false, xhi = false, ylo = false, yhi = false, zlo = false, zhi = false;
+  unsigned nxm = 0, nxp = 0;  // node index with the x wrap of an e_x = -1 / +1 link applied
 
-  // Source coordinate along one axis with periodic wrap; `wall` is set when the
-  // link leaves the box through a wall face.
-  template <int E, bool CHECK>
-  __device__ __forceinline__ int src_coord(int c, int n, int per, bool& wall) const {
-    if (E == 0 || !CHECK) return c - E;
-    const int s = c - E;
-    const bool out = E > 0 ? (s < 0) : (s >= n);
-    wall = wall || (out && !per);
-    return out ? (per ? (E > 0 ? n - 1 : 0) : c) : s;
+  __device__ __forceinline__ Gather(const StepArgs<R>& a_, const M& m_, int x_, int y_, int z_, unsigned node_,
+                                    R Tr_)
+      : a(a_), m(m_), x(x_), y(y_), z(z_), node(node_), Tr(Tr_) {
+    if (CX) {
+      xlo = x == 0;
+      xhi = x == a.nx - 1;
+      nxp = node + (xlo ? (unsigned)a.nx : 0u);
+      nxm = node - (xhi ? (unsigned)a.nx : 0u);
+    }
+    if (CY) {
+      ylo = y == 0;
+      yhi = y == a.ny - 1;
+    }
+    if (CZ) {
+      zlo = z == 0;
+      zhi = z == a.nz - 1;
+    }
   }
 
   // Incoming population of link A of one distribution whose planes start at
-  // `plane0` (fluid: 0, thermal: Qf).  Returns the raw pulled / bounced value
-  // and reports which face was crossed.
+  // QBASE (fluid: 0, thermal: Qf).  Returns the pulled or bounced value and
+  // reports per axis whether the link met a wall there.
   template <int A, int QBASE>
   __device__ __forceinline__ R pull(bool& wx, bool& wy, bool& wz) const {
     constexpr int ex = L::ex(A), ey = L::ey(A), ez = L::ez(A);
-    const R* pA = a.src + (size_t)(QBASE + A) * a.plane;
-    constexpr bool checked = (CX && ex != 0) || (CY && ey != 0) || (CZ && ez != 0);
-    if (!checked) {
-      const long long shift = (long long)ex + (long long)ey * a.nx + (long long)ez * a.nx * a.ny;
-      return ldb(pA - shift, node);
-    }
-    const int xs = src_coord<ex, CX>(x, a.nx, a.per[0], wx);
-    const int ys = src_coord<ey, CY>(y, a.ny, a.per[1], wy);
-    const int zs = src_coord<ez, CZ>(z, a.nz, a.per[2], wz);
+    const long long shift = (long long)ex + (long long)ey * a.nx + (long long)ez * a.nx * a.ny;
+    constexpr bool cx = CX && ex != 0, cy = CY && ey != 0, cz = CZ && ez != 0;
+    if (!cx && !cy && !cz) return m.load(QBASE + A, shift, node);
+    const bool ox = cx && (ex > 0 ? xlo : xhi);
+    const bool oy = cy && (ey > 0 ? ylo : yhi);
+    const bool oz = cz && (ez > 0 ? zlo : zhi);
+    unsigned idx = cx ? (ex > 0 ? nxp : nxm) : node;
+    if (cy) idx += oy ? (unsigned)(ey * a.ny) * (unsigned)a.nx : 0u;
+    if (cz) idx += oz ? (unsigned)(ez * a.nz) * (unsigned)a.nx * (unsigned)a.ny : 0u;
+    wx = ox && !PX && !a.per[0];
+    wy = oy && !a.per[1];
+    wz = oz && !a.per[2];
+    if (PX && !cy && !cz) return m.load(QBASE + A, shift, idx);  // periodic x only: never a wall
     const bool wall = wx || wy || wz;
-    const unsigned sidx = ((unsigned)zs * (unsigned)a.ny + (unsigned)ys) * (unsigned)a.nx + (unsigned)xs;
-    const R* pO = a.src + (size_t)(QBASE + L::opp(A)) * a.plane;
-    const R* p = wall ? pO : pA;
-    return ld(p, wall ? node : sidx);
+    return m.load_sel(wall, QBASE + L::opp(A), node, QBASE + A, shift, idx);
   }
 
   template <int F>
@@ -190,10 +254,10 @@ struct Gather {
   }
 };
 
-template <class L, class R, bool CX, bool CY, bool CZ>
-__device__ __forceinline__ void gather(const StepArgs<R>& a, int x, int y, int z, unsigned node, R Tr,
+template <class L, class R, class M, bool CX, bool CY, bool CZ, bool PX = false>
+__device__ __forceinline__ void gather(const StepArgs<R>& a, const M& m, int x, int y, int z, unsigned node, R Tr,
                                        R (&f)[L::Qf], R (&g)[L::Qg]) {
-  const Gather<L, R, CX, CY, CZ> p{a, x, y, z, node, Tr};
+  const Gather<L, R, M, CX, CY, CZ, PX> p(a, m, x, y, z, node, Tr);
   if constexpr (L::D == 2) {
     f[0] = p.template f<0>(); f[1] = p.template f<1>(); f[2] = p.template f<2>();
     f[3] = p.template f<3>(); f[4] = p.template f<4>(); f[5] = p.template f<5>();
@@ -212,29 +276,32 @@ __device__ __forceinline__ void gather(const StepArgs<R>& a, int x, int y, int z
   }
 }
 
-template <class L, class R, int UP, bool NT>
-__device__ __forceinline__ void collide_store(const StepArgs<R>& a, unsigned node, R Tr, R (&f)[L::Qf],
+template <class L, class R, class M, int UP, bool NT, bool STD>
+__device__ __forceinline__ void collide_store(const StepArgs<R>& a, const M& m, unsigned node, R Tr, R (&f)[L::Qf],
                                               R (&g)[L::Qg]) {
   if constexpr (L::D == 2)
-    collide2d<R, UP>(f, g, a.c, Tr, (Macros<R>*)nullptr);
+    collide2d<R, UP, STD>(f, g, a.c, Tr, (Macros<R>*)nullptr);
   else
-    collide3d<R, UP>(f, g, a.c, Tr, (Macros<R>*)nullptr);
+    collide3d<R, UP, STD>(f, g, a.c, Tr, (Macros<R>*)nullptr);
 #pragma unroll
-  for (int q = 0; q < L::Qf; ++q) st<R, NT>(a.dst + (size_t)q * a.plane, node, f[q]);
+  for (int q = 0; q < L::Qf; ++q) m.template store<NT>(q, node, f[q]);
 #pragma unroll
-  for (int q = 0; q < L::Qg; ++q) st<R, NT>(a.dst + (size_t)(L::Qf + q) * a.plane, node, g[q]);
+  for (int q = 0; q < L::Qg; ++q) m.template store<NT>(L::Qf + q, node, g[q]);
 }
 
 __device__ __forceinline__ unsigned node_of(int x, int y, int z, int nx, int ny) {
   return ((unsigned)z * (unsigned)ny + (unsigned)y) * (unsigned)nx + (unsigned)x;
 }
 
-template <class L, class R, int UP, bool NT>
-__global__ void __launch_bounds__(256) step_kernel(StepArgs<R> a) {
+// M: addressing policy (Buf32 when the buffer is below 4 GiB, else Glob64).
+// STD: the standard rate set (see rate_f / rate_g).
+template <class L, class R, class M, int UP, bool NT, bool STD>
+__global__ void __launch_bounds__(256) step_kernel(StepArgs<R> a, unsigned total_bytes) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
   const int z = blockIdx.z;
   if (x >= a.nx || y >= a.ny) return;
+  const M m(a, total_bytes);
   const unsigned node = node_of(x, y, z, a.nx, a.ny);
   const R Tr = tref(a, x, y, z);
   R f[L::Qf], g[L::Qg];
@@ -244,13 +311,15 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs<R> a) {
   const bool needz = L::D == 3 && __any(z == 0 || z == a.nz - 1);
   if (!needy && !needz) {
     if (!needx)
-      gather<L, R, false, false, false>(a, x, y, z, node, Tr, f, g);
+      gather<L, R, M, false, false, false>(a, m, x, y, z, node, Tr, f, g);
+    else if (a.per[0])
+      gather<L, R, M, true, false, false, true>(a, m, x, y, z, node, Tr, f, g);
     else
-      gather<L, R, true, false, false>(a, x, y, z, node, Tr, f, g);
+      gather<L, R, M, true, false, false>(a, m, x, y, z, node, Tr, f, g);
   } else {
-    gather<L, R, true, true, L::D == 3>(a, x, y, z, node, Tr, f, g);
+    gather<L, R, M, true, true, L::D == 3>(a, m, x, y, z, node, Tr, f, g);
   }
-  collide_store<L, R, UP, NT>(a, node, Tr, f, g);
+  collide_store<L, R, M, UP, NT, STD>(a, m, node, Tr, f, g);
 }
 
 // Initial state: the collision of f = w rho0, g = w^T T_init at every node.
@@ -260,6 +329,7 @@ __global__ void __launch_bounds__(256) init_kernel(StepArgs<R> a, const double* 
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
   const int z = blockIdx.z;
   if (x >= a.nx || y >= a.ny) return;
+  const Glob64<R> m(a, 0u);
   const unsigned node = node_of(x, y, z, a.nx, a.ny);
   R f[L::Qf], g[L::Qg];
   const R drw = a.rho_w - a.c.rho_r;
@@ -270,7 +340,25 @@ __global__ void __launch_bounds__(256) init_kernel(StepArgs<R> a, const double* 
   g[0] = (R(1) - R(L::D) * a.c.cs2T) * dT;
 #pragma unroll
   for (int q = 1; q < L::Qg; ++q) g[q] = R(0.5) * a.c.cs2T * dT;
-  collide_store<L, R, UP, false>(a, node, Tr, f, g);
+  collide_store<L, R, Glob64<R>, UP, false, false>(a, m, node, Tr, f, g);
+}
+
+// Whether the rates form the standard set of rate_f / rate_g: the viscous
+// slots share one rate, the thermal first-order slots share one rate, and
+// every other slot in use relaxes at exactly 1.
+template <class R>
+bool standard_rates(const StepArgs<R>& a, int D) {
+  const int Qf = D == 2 ? kQ2 : kQ3;
+  for (int k = 1; k < Qf; ++k) {
+    const bool nu = D == 2 ? (k == 4 || k == 5) : (k == 4 || k == 5 || k == 6 || k == 8 || k == 9);
+    if (nu ? a.c.om[k] != a.c.om[4] : a.c.om[k] != R(1)) return false;
+  }
+  const int Qg = D == 2 ? kQ2T : kQ3T;
+  for (int k = 1; k < Qg; ++k) {
+    const bool first = k <= D;
+    if (first ? a.c.omg[k] != a.c.omg[1] : a.c.omg[k] != R(1)) return false;
+  }
+  return true;
 }
 
 template <class L, class R, int UP>
@@ -284,10 +372,27 @@ hipError_t launch_up(const StepArgs<R>& a, const double* T_init, int mode, hipSt
     return hipGetLastError();
   }
   const double state_bytes = (double)a.plane * (L::Qf + L::Qg) * sizeof(R);
-  if (state_bytes > 128.0 * 1024 * 1024)
-    step_kernel<L, R, UP, true><<<grid, block, 0, s>>>(a);
-  else
-    step_kernel<L, R, UP, false><<<grid, block, 0, s>>>(a);
+  const bool nt = state_bytes > 128.0 * 1024 * 1024;
+  const bool std_rates = standard_rates(a, L::D);
+  if (state_bytes < 4294967296.0) {
+    const unsigned tb = (unsigned)state_bytes;
+    if (nt) {
+      if (std_rates)
+        step_kernel<L, R, Buf32<R>, UP, true, true><<<grid, block, 0, s>>>(a, tb);
+      else
+        step_kernel<L, R, Buf32<R>, UP, true, false><<<grid, block, 0, s>>>(a, tb);
+    } else {
+      if (std_rates)
+        step_kernel<L, R, Buf32<R>, UP, false, true><<<grid, block, 0, s>>>(a, tb);
+      else
+        step_kernel<L, R, Buf32<R>, UP, false, false><<<grid, block, 0, s>>>(a, tb);
+    }
+  } else {
+    if (std_rates)
+      step_kernel<L, R, Glob64<R>, UP, true, true><<<grid, block, 0, s>>>(a, 0u);
+    else
+      step_kernel<L, R, Glob64<R>, UP, true, false><<<grid, block, 0, s>>>(a, 0u);
+  }
   return hipGetLastError();
 }
 
