@@ -17,11 +17,15 @@
 // Streaming plus the wall rules read every slot of S_{n-1} exactly once, so
 // every slot of lambda_{n-1} is written exactly once: no atomics, and each
 // wall-temperature gradient entry has a single owner thread per launch.
+#include <type_traits>
+
 #include "fpc_adjoint.h"
-#include "fpc_kernels.h"
+#include "fpc_gather.h"
 
 namespace fpc {
 namespace {
+
+using namespace stream;
 
 template <int D>
 struct LinkOf {
@@ -33,105 +37,6 @@ struct LinkOf {
   static constexpr int opp(int a) { return D == 2 ? D2_OPP[a] : d3_opp(a); }
   static constexpr double w(int a) { return D == 2 ? w2(a) : w3(a); }
 };
-
-// Source of link (ex, ey, ez) pulled at (x, y, z): returns false for a wall
-// link (then `face` is the face crossed if exactly one), true otherwise with
-// the wrapped source node in `src`.
-template <class R>
-__device__ __forceinline__ bool link_source(const StepArgs<R>& a, int x, int y, int z, int ex, int ey, int ez,
-                                            unsigned& src, int& ncross, int& face) {
-  int c[3] = {x - ex, y - ey, z - ez};
-  const int n[3] = {a.nx, a.ny, a.nz};
-  const int e[3] = {ex, ey, ez};
-  ncross = 0;
-  face = -1;
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    if (e[k] != 0 && (c[k] < 0 || c[k] >= n[k])) {
-      if (a.per[k]) {
-        c[k] = c[k] < 0 ? n[k] - 1 : 0;
-      } else {
-        ++ncross;
-        face = 2 * k + (c[k] < 0 ? 0 : 1);
-      }
-    }
-  }
-  src = ((unsigned)c[2] * (unsigned)a.ny + (unsigned)c[1]) * (unsigned)a.nx + (unsigned)c[0];
-  return ncross == 0;
-}
-
-__device__ __forceinline__ size_t profile_index(int face, int x, int y, int z, int nx, int ny) {
-  const int k = face >> 1;
-  return k == 0 ? (size_t)z * ny + y : (k == 1 ? (size_t)z * nx + x : (size_t)y * nx + x);
-}
-
-template <class R, int D>
-__device__ __forceinline__ double face_temperature(const StepArgs<R>& a, int F, int x, int y, int z) {
-  double Tw = 0.0;
-#pragma unroll
-  for (int f = 0; f < 6; ++f)
-    if (f == F) Tw = a.face[f].Tprof ? a.face[f].Tprof[profile_index(f, x, y, z, a.nx, a.ny)] : a.face[f].Tw;
-  return Tw;
-}
-
-template <class R>
-__device__ __forceinline__ void face_flags(const StepArgs<R>& a, int F, bool& lid, bool& dir, double uw[3]) {
-  lid = false;
-  dir = false;
-  uw[0] = uw[1] = uw[2] = 0.0;
-#pragma unroll
-  for (int f = 0; f < 6; ++f)
-    if (f == F) {
-      lid = a.face[f].lid;
-      dir = a.face[f].dirichlet;
-      uw[0] = a.face[f].uw[0];
-      uw[1] = a.face[f].uw[1];
-      uw[2] = a.face[f].uw[2];
-    }
-}
-
-// Pulled populations of node (x, y, z) as plain values (storage offsets added).
-template <class R, int D>
-__device__ void pull_plain(const StepArgs<R>& a, int x, int y, int z, unsigned node, R* f, R* g) {
-  using Lk = LinkOf<D>;
-#pragma unroll
-  for (int q = 0; q < Lk::Qf; ++q) {
-    unsigned src;
-    int nc, F;
-    R v;
-    if (link_source(a, x, y, z, Lk::ex(q), Lk::ey(q), Lk::ez(q), src, nc, F)) {
-      v = a.src[(size_t)q * a.plane + src];
-    } else {
-      v = a.src[(size_t)Lk::opp(q) * a.plane + node];
-      bool lid, dir;
-      double uw[3];
-      face_flags(a, F, lid, dir, uw);
-      if (nc == 1 && lid)
-        v += R(2.0 * 3.0 * Lk::w(q)) * a.rho_w * R(Lk::ex(q) * uw[0] + Lk::ey(q) * uw[1] + Lk::ez(q) * uw[2]);
-    }
-    f[q] = v + R(Lk::w(q)) * a.c.rho_r;
-  }
-  const R Tr = tref(a, x, y, z);
-#pragma unroll
-  for (int q = 0; q < Lk::Qg; ++q) {
-    unsigned src;
-    int nc, F;
-    R v;
-    const R wq = q == 0 ? R(1) - R(D) * a.c.cs2T : R(0.5) * a.c.cs2T;
-    if (link_source(a, x, y, z, Lk::ex(q), Lk::ey(q), Lk::ez(q), src, nc, F)) {
-      // stored against the source node's reference Tr(x - e)
-      const R Trs = Tr - (R(Lk::ex(q)) * a.Tg[0] + R(Lk::ey(q)) * a.Tg[1] + R(Lk::ez(q)) * a.Tg[2]);
-      v = a.src[(size_t)(Lk::Qf + q) * a.plane + src] + wq * Trs;
-    } else {
-      v = a.src[(size_t)(Lk::Qf + Lk::opp(q)) * a.plane + node] + wq * Tr;
-      bool lid, dir;
-      double uw[3];
-      face_flags(a, F, lid, dir, uw);
-      if (dir) v = -v + a.c.cs2T * R(face_temperature<R, D>(a, F, x, y, z));
-    }
-    g[q] = v;
-  }
-}
 
 // Seed of the objective on S_n(x): weights on T_n(x) and on the kinetic energy.
 template <class R, int D, int UP>
@@ -166,56 +71,129 @@ struct AdjArgs {
   double* dtheta[6];  // per-face wall-temperature gradient (accumulated), or null
 };
 
-template <int D, class R, int UP>
-__global__ void __launch_bounds__(256) adjoint_step_kernel(AdjArgs<R> A) {
-  using Lk = LinkOf<D>;
+// Adjoint of the streaming step for one node: push the adjoint of each
+// incoming link to the slot it was read from (Edges: same classification as
+// the gather).  Thermal Dirichlet links carry the factor -1 of the
+// anti-bounce-back; their wall temperature receives 2 w^T_a = c^_s^2 times the
+// link adjoint.
+template <class L, class R, class M, bool CX, bool CY, bool CZ, bool PX>
+struct Scatter {
+  using E = Edges<L, R, CX, CY, CZ, PX>;
+  const AdjArgs<R>& A;
+  const M& m;
+  E e;
+  int x, y, z;
+
+  __device__ __forceinline__ Scatter(const AdjArgs<R>& A_, const M& m_, int x_, int y_, int z_, unsigned node)
+      : A(A_), m(m_), e(A_.s, x_, y_, z_, node), x(x_), y(y_), z(z_) {}
+
+  template <int Q, int QBASE>
+  __device__ __forceinline__ void push(R v) const {
+    const long long sh = e.template shift<Q>();
+    if (!E::template checked<Q>()) {
+      m.store_at(QBASE + Q, sh, e.node, v);
+      return;
+    }
+    bool wx = false, wy = false, wz = false;
+    const unsigned idx = e.template source<Q>(wx, wy, wz);
+    if (E::template wrap_only<Q>()) {
+      m.store_at(QBASE + Q, sh, idx, v);
+      return;
+    }
+    const bool wall = wx || wy || wz;
+    R out = v;
+    if (QBASE != 0 && Q != 0) {
+      constexpr int ex = L::ex(Q), ey = L::ey(Q), ez = L::ez(Q);
+      constexpr int F = ex > 0 ? 0 : (ex < 0 ? 1 : (ey > 0 ? 2 : (ey < 0 ? 3 : (ez > 0 ? 4 : 5))));
+      constexpr int k = F >> 1;
+      const StepArgs<R>& a = A.s;
+      if (wall && a.face[F].dirichlet) {
+        out = -v;
+        if (A.dtheta[F]) {
+          const size_t t = k == 0 ? (size_t)z * a.ny + y : (k == 1 ? (size_t)z * a.nx + x : (size_t)y * a.nx + x);
+          A.dtheta[F][t] += (double)(a.c.cs2T * v);
+        }
+      }
+    }
+    m.store_sel(wall, QBASE + L::opp(Q), e.node, QBASE + Q, sh, idx, out);
+  }
+};
+
+template <class L, class R, class M, bool CX, bool CY, bool CZ, bool PX = false>
+__device__ __forceinline__ void scatter(const AdjArgs<R>& A, const M& mL, int x, int y, int z, unsigned node,
+                                        const R (&fb)[L::Qf], const R (&gb)[L::Qg]) {
+  const Scatter<L, R, M, CX, CY, CZ, PX> sc(A, mL, x, y, z, node);
+  if constexpr (L::D == 2) {
+    sc.template push<0, 0>(fb[0]); sc.template push<1, 0>(fb[1]); sc.template push<2, 0>(fb[2]);
+    sc.template push<3, 0>(fb[3]); sc.template push<4, 0>(fb[4]); sc.template push<5, 0>(fb[5]);
+    sc.template push<6, 0>(fb[6]); sc.template push<7, 0>(fb[7]); sc.template push<8, 0>(fb[8]);
+    sc.template push<0, kQ2>(gb[0]); sc.template push<1, kQ2>(gb[1]); sc.template push<2, kQ2>(gb[2]);
+    sc.template push<3, kQ2>(gb[3]); sc.template push<4, kQ2>(gb[4]);
+  } else {
+#define FPC_P(Q) sc.template push<Q, 0>(fb[Q]);
+    FPC_P(0) FPC_P(1) FPC_P(2) FPC_P(3) FPC_P(4) FPC_P(5) FPC_P(6) FPC_P(7) FPC_P(8)
+    FPC_P(9) FPC_P(10) FPC_P(11) FPC_P(12) FPC_P(13) FPC_P(14) FPC_P(15) FPC_P(16) FPC_P(17)
+    FPC_P(18) FPC_P(19) FPC_P(20) FPC_P(21) FPC_P(22) FPC_P(23) FPC_P(24) FPC_P(25) FPC_P(26)
+#undef FPC_P
+    sc.template push<0, kQ3>(gb[0]); sc.template push<1, kQ3>(gb[1]); sc.template push<2, kQ3>(gb[2]);
+    sc.template push<3, kQ3>(gb[3]); sc.template push<4, kQ3>(gb[4]); sc.template push<5, kQ3>(gb[5]);
+    sc.template push<6, kQ3>(gb[6]);
+  }
+}
+
+// M: addressing policy of S_{n-1} (read) and of the adjoint pair (lam_in
+// read, lam_out written); Buf32 below 4 GiB per buffer, else Glob64.
+// The edge variant is chosen per wavefront (ballot) for the gather and again
+// for the scatter; the collision and its adjoint in between are shared.
+template <class L, class R, class M, int UP>
+__global__ void __launch_bounds__(256) adjoint_step_kernel(AdjArgs<R> A, unsigned total_bytes) {
+  constexpr int D = L::D;
   const StepArgs<R>& a = A.s;
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
   const int z = blockIdx.z;
   if (x >= a.nx || y >= a.ny) return;
-  const unsigned node = ((unsigned)z * (unsigned)a.ny + (unsigned)y) * (unsigned)a.nx + (unsigned)x;
-  R f[Lk::Qf], g[Lk::Qg];
-  pull_plain<R, D>(a, x, y, z, node, f, g);
+  const M mS(a.src, nullptr, a.plane, total_bytes);
+  const M mL(A.lam_in, A.lam_out, a.plane, total_bytes);
+  const unsigned node = node_of(x, y, z, a.nx, a.ny);
+  // which axes have an edge node in this wavefront (wave-uniform)
+  const bool needx = __any(x == 0 || x == a.nx - 1);
+  const bool needyz = __any(y == 0 || y == a.ny - 1) || (D == 3 && __any(z == 0 || z == a.nz - 1));
+  const int variant = needyz ? 3 : (!needx ? 0 : (a.per[0] ? 1 : 2));
+  const R Tr = tref(a, x, y, z);
+  R f[L::Qf], g[L::Qg];
+  if (variant == 0)
+    gather<L, R, M, false, false, false>(a, mS, x, y, z, node, Tr, f, g);
+  else if (variant == 1)
+    gather<L, R, M, true, false, false, true>(a, mS, x, y, z, node, Tr, f, g);
+  else if (variant == 2)
+    gather<L, R, M, true, false, false>(a, mS, x, y, z, node, Tr, f, g);
+  else
+    gather<L, R, M, true, true, D == 3>(a, mS, x, y, z, node, Tr, f, g);
+  if constexpr (kDeviations<R>) {
+    // plain populations: add this node's storage references
+#pragma unroll
+    for (int q = 0; q < L::Qf; ++q) f[q] += R(L::w(q)) * a.c.rho_r;
+#pragma unroll
+    for (int q = 0; q < L::Qg; ++q) g[q] += (q == 0 ? R(1) - R(D) * a.c.cs2T : R(0.5) * a.c.cs2T) * Tr;
+  }
   adj::Tape<R, D> t;
   adj::forward<R, D, UP>(f, g, a.c, t);
-  R fb[Lk::Qf], gb[Lk::Qg];
+  R fb[L::Qf], gb[L::Qg];
 #pragma unroll
-  for (int q = 0; q < Lk::Qf; ++q) fb[q] = A.lam_in[(size_t)q * a.plane + node];
+  for (int q = 0; q < L::Qf; ++q) fb[q] = mL.load(q, 0, node);
 #pragma unroll
-  for (int q = 0; q < Lk::Qg; ++q) gb[q] = A.lam_in[(size_t)(Lk::Qf + q) * a.plane + node];
+  for (int q = 0; q < L::Qg; ++q) gb[q] = mL.load(L::Qf + q, 0, node);
   add_seed<R, D, UP>(t, a.c, A.dJdT ? A.dJdT[node] : 0.0, A.ke, fb, gb);
   adj::reverse<R, D, UP>(t, a.c, fb, gb);
-  // push the link adjoints to the slots they were pulled from
-#pragma unroll
-  for (int q = 0; q < Lk::Qf; ++q) {
-    unsigned src;
-    int nc, F;
-    if (link_source(a, x, y, z, Lk::ex(q), Lk::ey(q), Lk::ez(q), src, nc, F))
-      A.lam_out[(size_t)q * a.plane + src] = fb[q];
-    else
-      A.lam_out[(size_t)Lk::opp(q) * a.plane + node] = fb[q];
-  }
-#pragma unroll
-  for (int q = 0; q < Lk::Qg; ++q) {
-    unsigned src;
-    int nc, F;
-    if (link_source(a, x, y, z, Lk::ex(q), Lk::ey(q), Lk::ez(q), src, nc, F)) {
-      A.lam_out[(size_t)(Lk::Qf + q) * a.plane + src] = gb[q];
-    } else {
-      bool lid, dir;
-      double uw[3];
-      face_flags(a, F, lid, dir, uw);
-      A.lam_out[(size_t)(Lk::Qf + Lk::opp(q)) * a.plane + node] = dir ? -gb[q] : gb[q];
-      if (dir) {
-        double* dt = nullptr;
-#pragma unroll
-        for (int ff = 0; ff < 6; ++ff)
-          if (ff == F) dt = A.dtheta[ff];
-        if (dt) dt[profile_index(F, x, y, z, a.nx, a.ny)] += (double)(a.c.cs2T * gb[q]);
-      }
-    }
-  }
+  if (variant == 0)
+    scatter<L, R, M, false, false, false>(A, mL, x, y, z, node, fb, gb);
+  else if (variant == 1)
+    scatter<L, R, M, true, false, false, true>(A, mL, x, y, z, node, fb, gb);
+  else if (variant == 2)
+    scatter<L, R, M, true, false, false>(A, mL, x, y, z, node, fb, gb);
+  else
+    scatter<L, R, M, true, true, D == 3>(A, mL, x, y, z, node, fb, gb);
 }
 
 template <class R>
@@ -263,15 +241,21 @@ __global__ void __launch_bounds__(256) adjoint_init_kernel(AdjInitArgs<R> A) {
 
 template <int D, class R, int UP>
 hipError_t launch_adj(const AdjArgs<R>* step, const AdjInitArgs<R>* init, hipStream_t st) {
+  using L = typename std::conditional<D == 2, Lat2, Lat3>::type;
   const StepArgs<R>& a = step ? step->s : init->s;
   const int bx = a.nx >= 256 ? 256 : (a.nx >= 128 ? 128 : 64);
   const int by = 256 / bx;
   const dim3 block(bx, by, 1);
   const dim3 grid((a.nx + bx - 1) / bx, (a.ny + by - 1) / by, a.nz);
-  if (step)
-    adjoint_step_kernel<D, R, UP><<<grid, block, 0, st>>>(*step);
-  else
+  if (step) {
+    const double bytes = (double)a.plane * (L::Qf + L::Qg) * sizeof(R);
+    if (bytes < 4294967296.0)
+      adjoint_step_kernel<L, R, Buf32<R>, UP><<<grid, block, 0, st>>>(*step, (unsigned)bytes);
+    else
+      adjoint_step_kernel<L, R, Glob64<R>, UP><<<grid, block, 0, st>>>(*step, 0u);
+  } else {
     adjoint_init_kernel<D, R, UP><<<grid, block, 0, st>>>(*init);
+  }
   return hipGetLastError();
 }
 

@@ -1,0 +1,352 @@
+// Streaming access shared by the forward step and the adjoint step.
+//
+// Forward (gather): each node pulls f_a(x) = f~_a(x - e_a) from the previous
+// state (Eq. LBMsteps-stream, LBMsteps-streamg); where x - e_a lies beyond a
+// wall face it applies the halfway wall rule at its own node (Sec. 6.1):
+//   no-slip      f_a = f~_abar
+//   moving wall  f_a = f~_abar + 2 w_a rho_w (e_a . u_w) / c_s^2
+//   adiabatic    g_a = g~_abar
+//   Dirichlet    g_a = -g~_abar + 2 w^T_a T_w
+// Adjoint (scatter): the transpose of that selection; each node pushes the
+// adjoint of an incoming link back to the slot it was read from, so every
+// slot of the output is written exactly once.
+//
+// Layout: SoA planes, plane q holds the N node values [z][y][x]; a wavefront
+// covers 64 consecutive x of one row, so every access is a contiguous run of
+// one plane (shifted by at most one element).
+//
+// Boundary handling is resolved per wavefront by the caller (a ballot over
+// the edge tests) and compiled in: CX / CY / CZ enable the range checks of an
+// axis; PX states that x is periodic (x-edge waves then only wrap).  Checked
+// links stay branch-free: a wall redirects the single access of the link to
+// the node's own opposite slot.
+#pragma once
+
+#include "fpc_kernels.h"
+
+namespace fpc {
+namespace stream {
+
+struct Lat2 {
+  static constexpr int D = 2, Qf = kQ2, Qg = kQ2T;
+  static constexpr int ex(int a) { return D2_EX[a]; }
+  static constexpr int ey(int a) { return D2_EY[a]; }
+  static constexpr int ez(int) { return 0; }
+  static constexpr int opp(int a) { return D2_OPP[a]; }
+  static constexpr double w(int a) { return w2(a); }
+};
+
+struct Lat3 {
+  static constexpr int D = 3, Qf = kQ3, Qg = kQ3T;
+  static constexpr int ex(int a) { return D3_EX[a]; }
+  static constexpr int ey(int a) { return D3_EY[a]; }
+  static constexpr int ez(int a) { return D3_EZ[a]; }
+  static constexpr int opp(int a) { return d3_opp(a); }
+  static constexpr double w(int a) { return w3(a); }
+};
+
+__device__ __forceinline__ unsigned node_of(int x, int y, int z, int nx, int ny) {
+  return ((unsigned)z * (unsigned)ny + (unsigned)y) * (unsigned)nx + (unsigned)x;
+}
+
+// ---------------------------------------------------------------------------
+// Addressing of a pair of state-layout buffers (read side `src`, write side
+// `dst`).  Two policies with the same interface:
+//   load(q, shift, idx)                  plane q at lane index idx - shift
+//   load_sel(w, qw, iw, q, shift, idx)   per lane: plane qw at iw if w, else as load
+//   store<NT>(q, idx, v)                 plane q at idx
+//   store_at(q, shift, idx, v)           plane q at idx - shift
+//   store_sel(w, qw, iw, q, shift, idx, v)
+// (shift is wave-uniform.)
+// Buf32: each buffer through one raw buffer descriptor; the lane supplies a
+//   32-bit byte offset, the plane offset of loads is a wave-uniform scalar
+//   (usable while a buffer is below 4 GiB).  Keeps the address arithmetic off
+//   the vector ALU and the scalar register file small.
+// Glob64: 64-bit plane base pointers plus a 32-bit lane offset (any size).
+// ---------------------------------------------------------------------------
+constexpr int kBufDword3 = 0x00020000;  // raw (untyped) buffer, gfx9 family
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+
+template <class R>
+struct Buf32 {
+  __amdgpu_buffer_rsrc_t rsrc_s, rsrc_d;
+  unsigned pb;  // plane stride in bytes
+  static constexpr unsigned S = sizeof(R);
+
+  __device__ __forceinline__ Buf32(const R* s, R* d, size_t plane, unsigned total_bytes)
+      : rsrc_s(__builtin_amdgcn_make_buffer_rsrc(const_cast<R*>(s), 0, (int)total_bytes, kBufDword3)),
+        rsrc_d(__builtin_amdgcn_make_buffer_rsrc(d, 0, (int)total_bytes, kBufDword3)),
+        pb((unsigned)plane * S) {}
+
+  __device__ __forceinline__ __amdgpu_buffer_rsrc_t rs_src() const { return rsrc_s; }
+  __device__ __forceinline__ __amdgpu_buffer_rsrc_t rs_dst() const { return rsrc_d; }
+  __device__ __forceinline__ R raw(unsigned voff, unsigned soff) const {
+    if constexpr (sizeof(R) == 4)
+      return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b32(rs_src(), (int)voff, (int)soff, 0));
+    else
+      return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b64(rs_src(), (int)voff, (int)soff, 0));
+  }
+  template <bool NT>
+  __device__ __forceinline__ void raw_store(unsigned voff, R v) const {
+    constexpr int aux = NT ? 2 : 0;  // cache policy: non-temporal
+    if constexpr (sizeof(R) == 4)
+      __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), rs_dst(), (int)voff, 0, aux);
+    else
+      __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), rs_dst(), (int)voff, 0, aux);
+  }
+  // byte offset of plane q minus the streaming shift (non-negative for q >= 1
+  // or shift == 0, as every plane is longer than any shift)
+  __device__ __forceinline__ unsigned base(int q, long long shift) const {
+    return (unsigned)q * pb - (unsigned)(shift * (long long)S);
+  }
+  __device__ __forceinline__ R load(int q, long long shift, unsigned idx) const {
+    return raw(idx * S, base(q, shift));
+  }
+  __device__ __forceinline__ R load_sel(bool w, int qw, unsigned iw, int q, long long shift, unsigned idx) const {
+    const unsigned vs = idx * S + base(q, shift);
+    const unsigned vw = iw * S + (unsigned)qw * pb;
+    return raw(w ? vw : vs, 0u);
+  }
+  // stores take the plane offset on the lane side: one add per store and no
+  // scalar register per plane held across the collision
+  template <bool NT>
+  __device__ __forceinline__ void store(int q, unsigned idx, R v) const {
+    raw_store<NT>(idx * S + (unsigned)q * pb, v);
+  }
+  // store the planes of one node in order: cursor starts at cursor(idx) and
+  // advances by one plane per store
+  __device__ __forceinline__ unsigned cursor(unsigned idx) const { return idx * S; }
+  template <bool NT>
+  __device__ __forceinline__ void store_next(unsigned& cur, R v) const {
+    raw_store<NT>(cur, v);
+    cur += pb;
+  }
+  __device__ __forceinline__ void store_at(int q, long long shift, unsigned idx, R v) const {
+    raw_store<false>(idx * S + base(q, shift), v);
+  }
+  __device__ __forceinline__ void store_sel(bool w, int qw, unsigned iw, int q, long long shift, unsigned idx,
+                                            R v) const {
+    const unsigned vs = idx * S + base(q, shift);
+    const unsigned vw = iw * S + (unsigned)qw * pb;
+    raw_store<false>(w ? vw : vs, v);
+  }
+};
+
+template <class R>
+struct Glob64 {
+  const R* src;
+  R* dst;
+  size_t plane;
+
+  __device__ __forceinline__ Glob64(const R* s, R* d, size_t plane_, unsigned) : src(s), dst(d), plane(plane_) {}
+
+  // p[idx] with a 32-bit byte offset (uniform base + lane offset)
+  template <class P>
+  static __device__ __forceinline__ P* at(P* p, unsigned idx) {
+    return reinterpret_cast<P*>(reinterpret_cast<char*>(const_cast<R*>(p)) + idx * (unsigned)sizeof(R));
+  }
+  __device__ __forceinline__ R load(int q, long long shift, unsigned idx) const {
+    return *at(src + (size_t)q * plane - shift, idx);
+  }
+  __device__ __forceinline__ R load_sel(bool w, int qw, unsigned iw, int q, long long shift, unsigned idx) const {
+    const R* pw = src + (size_t)qw * plane;
+    const R* ps = src + (size_t)q * plane - shift;
+    return *at(w ? pw : ps, w ? iw : idx);
+  }
+  template <bool NT>
+  __device__ __forceinline__ void store(int q, unsigned idx, R v) const {
+    R* p = at(dst + (size_t)q * plane, idx);
+    if constexpr (NT)
+      __builtin_nontemporal_store(v, p);
+    else
+      *p = v;
+  }
+  __device__ __forceinline__ void store_at(int q, long long shift, unsigned idx, R v) const {
+    *at(dst + (size_t)q * plane - shift, idx) = v;
+  }
+  __device__ __forceinline__ R* cursor(unsigned idx) const { return at(dst, idx); }
+  template <bool NT>
+  __device__ __forceinline__ void store_next(R*& cur, R v) const {
+    if constexpr (NT)
+      __builtin_nontemporal_store(v, cur);
+    else
+      *cur = v;
+    cur += plane;
+  }
+  __device__ __forceinline__ void store_sel(bool w, int qw, unsigned iw, int q, long long shift, unsigned idx,
+                                            R v) const {
+    R* pw = dst + (size_t)qw * plane;
+    R* ps = dst + (size_t)q * plane - shift;
+    *at(w ? pw : ps, w ? iw : idx) = v;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Per-lane edge state of one node and the source slot of each link.
+// ---------------------------------------------------------------------------
+template <class L, class R, bool CX, bool CY, bool CZ, bool PX>
+struct Edges {
+  const StepArgs<R>& a;
+  unsigned node;
+  // Lane on the low / high edge of a checked axis.  A link with e_k = +1
+  // crossing the low edge (or e_k = -1 crossing the high edge) either wraps
+  // (periodic axis: the source index moves by +-n_k times the axis stride) or
+  // meets a wall.  PX: x is known to be periodic.
+  bool xlo = false, xhi = false, ylo = false, yhi = false, zlo = false, zhi = false;
+  unsigned nxm = 0, nxp = 0;  // node index with the x wrap of an e_x = -1 / +1 link applied
+
+  __device__ __forceinline__ Edges(const StepArgs<R>& a_, int x, int y, int z, unsigned node_) : a(a_), node(node_) {
+    if (CX) {
+      xlo = x == 0;
+      xhi = x == a.nx - 1;
+      nxp = node + (xlo ? (unsigned)a.nx : 0u);
+      nxm = node - (xhi ? (unsigned)a.nx : 0u);
+    }
+    if (CY) {
+      ylo = y == 0;
+      yhi = y == a.ny - 1;
+    }
+    if (CZ) {
+      zlo = z == 0;
+      zhi = z == a.nz - 1;
+    }
+  }
+
+  template <int A>
+  static constexpr bool checked() {
+    return (CX && L::ex(A) != 0) || (CY && L::ey(A) != 0) || (CZ && L::ez(A) != 0);
+  }
+  template <int A>
+  __device__ __forceinline__ long long shift() const {
+    return (long long)L::ex(A) + (long long)L::ey(A) * a.nx + (long long)L::ez(A) * a.nx * a.ny;
+  }
+  // Checked link A: the wrapped source index (used with shift()) and the
+  // axes on which the link meets a wall.
+  template <int A>
+  __device__ __forceinline__ unsigned source(bool& wx, bool& wy, bool& wz) const {
+    constexpr int ex = L::ex(A), ey = L::ey(A), ez = L::ez(A);
+    constexpr bool cx = CX && ex != 0, cy = CY && ey != 0, cz = CZ && ez != 0;
+    const bool ox = cx && (ex > 0 ? xlo : xhi);
+    const bool oy = cy && (ey > 0 ? ylo : yhi);
+    const bool oz = cz && (ez > 0 ? zlo : zhi);
+    unsigned idx = cx ? (ex > 0 ? nxp : nxm) : node;
+    if (cy) idx += oy ? (unsigned)(ey * a.ny) * (unsigned)a.nx : 0u;
+    if (cz) idx += oz ? (unsigned)(ez * a.nz) * (unsigned)a.nx * (unsigned)a.ny : 0u;
+    wx = ox && !PX && !a.per[0];
+    wy = oy && !a.per[1];
+    wz = oz && !a.per[2];
+    return idx;
+  }
+  // only periodic wraps are possible on this link (no wall test needed)
+  template <int A>
+  static constexpr bool wrap_only() {
+    return PX && !(CY && L::ey(A) != 0) && !(CZ && L::ez(A) != 0);
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Gather: the incoming (pre-collision) populations of one node, in storage
+// form relative to this node's references.
+// ---------------------------------------------------------------------------
+template <class L, class R, class M, bool CX, bool CY, bool CZ, bool PX>
+struct Gather {
+  using E = Edges<L, R, CX, CY, CZ, PX>;
+  const StepArgs<R>& a;
+  const M& m;
+  E e;
+  int x, y, z;
+  R Tr;  // thermal storage reference of this node
+
+  __device__ __forceinline__ Gather(const StepArgs<R>& a_, const M& m_, int x_, int y_, int z_, unsigned node_, R Tr_)
+      : a(a_), m(m_), e(a_, x_, y_, z_, node_), x(x_), y(y_), z(z_), Tr(Tr_) {}
+
+  // Incoming population of link A of one distribution whose planes start at
+  // QBASE (fluid: 0, thermal: Qf), pulled or bounced; reports per axis
+  // whether the link met a wall there.
+  template <int A, int QBASE>
+  __device__ __forceinline__ R pull(bool& wx, bool& wy, bool& wz) const {
+    const long long sh = e.template shift<A>();
+    if (!E::template checked<A>()) return m.load(QBASE + A, sh, e.node);
+    const unsigned idx = e.template source<A>(wx, wy, wz);
+    if (E::template wrap_only<A>()) return m.load(QBASE + A, sh, idx);
+    const bool wall = wx || wy || wz;
+    return m.load_sel(wall, QBASE + L::opp(A), e.node, QBASE + A, sh, idx);
+  }
+
+  template <int F>
+  __device__ __forceinline__ R lid_term(int A_ex, int A_ey, int A_ez, double w) const {
+    if (!a.face[F].lid) return R(0);
+    const double eu = A_ex * a.face[F].uw[0] + A_ey * a.face[F].uw[1] + A_ez * a.face[F].uw[2];
+    return R(2.0 * 3.0 * w) * a.rho_w * R(eu);
+  }
+
+  template <int A>
+  __device__ __forceinline__ R f() const {
+    bool wx = false, wy = false, wz = false;
+    R v = pull<A, 0>(wx, wy, wz);
+    constexpr int ex = L::ex(A), ey = L::ey(A), ez = L::ez(A);
+    if (E::template checked<A>()) {
+      // moving wall: only when exactly one face is crossed
+      constexpr int FX = ex > 0 ? 0 : 1, FY = ey > 0 ? 2 : 3, FZ = ez > 0 ? 4 : 5;
+      const int nc = (int)wx + (int)wy + (int)wz;
+      R add = R(0);
+      if (ex != 0) add = (nc == 1 && wx) ? lid_term<FX>(ex, ey, ez, L::w(A)) : add;
+      if (ey != 0) add = (nc == 1 && wy) ? lid_term<FY>(ex, ey, ez, L::w(A)) : add;
+      if (ez != 0) add = (nc == 1 && wz) ? lid_term<FZ>(ex, ey, ez, L::w(A)) : add;
+      v += add;
+    }
+    return v;
+  }
+
+  // Thermal link A (axis links: at most one face can be crossed).
+  template <int A>
+  __device__ __forceinline__ R g() const {
+    bool wx = false, wy = false, wz = false;
+    R v = pull<A, L::Qf>(wx, wy, wz);
+    if (A == 0) return v;
+    constexpr int ex = L::ex(A), ey = L::ey(A), ez = L::ez(A);
+    constexpr int F = ex > 0 ? 0 : (ex < 0 ? 1 : (ey > 0 ? 2 : (ey < 0 ? 3 : (ez > 0 ? 4 : 5))));
+    constexpr int k = F >> 1;
+    constexpr int ea = ex + ey + ez;  // axis link: the one non-zero component
+    const bool wall = E::template checked<A>() && (wx || wy || wz);
+    if (wall) {
+      if (a.face[F].dirichlet) {
+        double Tw = a.face[F].Tw;
+        if (a.face[F].Tprof) {
+          const size_t t = k == 0 ? (size_t)z * a.ny + y : (k == 1 ? (size_t)z * a.nx + x : (size_t)y * a.nx + x);
+          Tw = a.face[F].Tprof[t];
+        }
+        v = -v + a.c.cs2T * (R(Tw) - Tr);  // 2 w^T_a = c^_s^2 on axis links
+      }
+    } else if constexpr (kDeviations<R>) {
+      // the value was stored against the source node's reference Tr(x - e_A)
+      v -= R(0.5) * a.c.cs2T * (R(ea) * a.Tg[k]);
+    }
+    return v;
+  }
+};
+
+template <class L, class R, class M, bool CX, bool CY, bool CZ, bool PX = false>
+__device__ __forceinline__ void gather(const StepArgs<R>& a, const M& m, int x, int y, int z, unsigned node, R Tr,
+                                       R (&f)[L::Qf], R (&g)[L::Qg]) {
+  const Gather<L, R, M, CX, CY, CZ, PX> p(a, m, x, y, z, node, Tr);
+  if constexpr (L::D == 2) {
+    f[0] = p.template f<0>(); f[1] = p.template f<1>(); f[2] = p.template f<2>();
+    f[3] = p.template f<3>(); f[4] = p.template f<4>(); f[5] = p.template f<5>();
+    f[6] = p.template f<6>(); f[7] = p.template f<7>(); f[8] = p.template f<8>();
+    g[0] = p.template g<0>(); g[1] = p.template g<1>(); g[2] = p.template g<2>();
+    g[3] = p.template g<3>(); g[4] = p.template g<4>();
+  } else {
+#define FPC_F(A) f[A] = p.template f<A>();
+    FPC_F(0) FPC_F(1) FPC_F(2) FPC_F(3) FPC_F(4) FPC_F(5) FPC_F(6) FPC_F(7) FPC_F(8)
+    FPC_F(9) FPC_F(10) FPC_F(11) FPC_F(12) FPC_F(13) FPC_F(14) FPC_F(15) FPC_F(16) FPC_F(17)
+    FPC_F(18) FPC_F(19) FPC_F(20) FPC_F(21) FPC_F(22) FPC_F(23) FPC_F(24) FPC_F(25) FPC_F(26)
+#undef FPC_F
+    g[0] = p.template g<0>(); g[1] = p.template g<1>(); g[2] = p.template g<2>();
+    g[3] = p.template g<3>(); g[4] = p.template g<4>(); g[5] = p.template g<5>();
+    g[6] = p.template g<6>();
+  }
+}
+
+}  // namespace stream
+}  // namespace fpc
