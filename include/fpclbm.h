@@ -175,6 +175,17 @@ int fpc_init(fpc_sim* s, const double* T_init);
 /* Advance nsteps >= 0 time steps (fused pull-stream-collide), asynchronously. */
 int fpc_step(fpc_sim* s, int nsteps);
 
+/*
+ * One time step from a caller-owned state into another caller-owned state:
+ * S_dst = Phi(S_src) (the fused pull-stream-collide of fpc_step), with this
+ * simulation's parameters.  src, dst: device pointers, 256-byte aligned, each
+ * of fpc_state_bytes() bytes in the storage layout (as written by fpc_save).
+ * They must not overlap.  The simulation's own buffers and step counter are
+ * untouched; asynchronous on the simulation's stream.  Lets a reverse sweep
+ * rebuild the states of a checkpoint segment in place, without copies.
+ */
+int fpc_step_from(fpc_sim* s, const void* src, void* dst);
+
 /* Steps taken since the last fpc_init / fpc_load. */
 int fpc_get_step(const fpc_sim* s, long long* step);
 

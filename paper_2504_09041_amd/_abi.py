@@ -38,7 +38,7 @@ FPC_BC_LID_DIRICHLET = 4
 
 EXPORTED = (
     "fpc_version", "fpc_last_error", "fpc_params_default", "fpc_params_natural", "fpc_params_mixed",
-    "fpc_state_bytes", "fpc_create", "fpc_destroy", "fpc_set_stream", "fpc_init", "fpc_step",
+    "fpc_state_bytes", "fpc_create", "fpc_destroy", "fpc_set_stream", "fpc_init", "fpc_step", "fpc_step_from",
     "fpc_get_step", "fpc_macros", "fpc_diagnostics", "fpc_save", "fpc_load", "fpc_export_fp64",
     "fpc_import_fp64", "fpc_current_buffer", "fpc_adjoint_step", "fpc_adjoint_init",
 )
@@ -106,6 +106,7 @@ def load():
         "fpc_set_stream": (i, [vp, vp]),
         "fpc_init": (i, [vp, vp]),
         "fpc_step": (i, [vp, i]),
+        "fpc_step_from": (i, [vp, vp, vp]),
         "fpc_get_step": (i, [vp, ctypes.POINTER(ll)]),
         "fpc_macros": (i, [vp, vp, vp, vp]),
         "fpc_diagnostics": (i, [vp, i, dp, dp, dp, dp]),

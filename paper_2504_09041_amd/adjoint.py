@@ -153,19 +153,22 @@ class AdjointSolver:
             arr = (ctypes.c_void_p * 6)()
             arr[self.theta_face] = dth.data_ptr()
             ptrs = arr
+        # segment buffers, reused by every segment: the states S_{s0+1} ..
+        # S_{s1-1} are rebuilt in place from the checkpoint S_{s0}
+        seg = [sim.new_state() for _ in range(self.K - 1)]
         for s0 in reversed(range(0, self.N, self.K)):
             s1 = min(s0 + self.K, self.N)
-            sim.load(self.ckpt[s0 // self.K], step=s0)
             states = [self.ckpt[s0 // self.K]]
-            for _ in range(s0 + 1, s1):
-                sim.step(1)
-                states.append(sim.save())
+            for k in range(s1 - s0 - 1):
+                sim.step_from(states[-1], seg[k])
+                states.append(seg[k])
             for n in range(s1, s0, -1):
                 w, ke = self.obj.seed(n)
                 A.check(lib.fpc_adjoint_step(sim.handle, _ptr(states[n - 1 - s0]), _ptr(lam), _ptr(lam2),
                                              _ptr(w), ctypes.c_double(ke), ptrs), "fpc_adjoint_step")
                 lam, lam2 = lam2, lam
             del states
+        del seg
         w0, ke0 = self.obj.seed(0)
         dT = torch.empty_like(self.T_init)
         A.check(lib.fpc_adjoint_init(sim.handle, _ptr(self.T_init), _ptr(lam), _ptr(w0), ctypes.c_double(ke0),

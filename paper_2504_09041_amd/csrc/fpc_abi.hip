@@ -393,6 +393,15 @@ int fpc_step(fpc_sim* s, int nsteps) {
   return FPC_OK;
 }
 
+int fpc_step_from(fpc_sim* s, const void* src, void* dst) {
+  if (!s || !src || !dst) return fail(FPC_ERR_ARG, "NULL argument");
+  if (!aligned256(src) || !aligned256(dst)) return fail(FPC_ERR_ARG, "state buffers must be 256-byte aligned");
+  const char* a = static_cast<const char*>(src);
+  const char* b = static_cast<const char*>(dst);
+  if (a < b + s->bytes && b < a + s->bytes) return fail(FPC_ERR_ARG, "src and dst overlap");
+  return launch_update(s, src, dst, nullptr, 0);
+}
+
 int fpc_get_step(const fpc_sim* s, long long* step) {
   if (!s || !step) return fail(FPC_ERR_ARG, "NULL argument");
   *step = s->step;

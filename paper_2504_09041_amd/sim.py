@@ -197,10 +197,23 @@ class Simulation:
         self._imp = S
         A.call("fpc_import_fp64", self._h, ctypes.c_void_p(S.data_ptr()), int(step))
 
-    def save(self):
-        out = torch.empty(self.nbytes, dtype=torch.uint8, device=self.device)
+    def save(self, out=None):
+        if out is None:
+            out = torch.empty(self.nbytes, dtype=torch.uint8, device=self.device)
         A.call("fpc_save", self._h, ctypes.c_void_p(out.data_ptr()))
         return out
+
+    def new_state(self):
+        """An uninitialised state buffer of this simulation's layout."""
+        return torch.empty(self.nbytes, dtype=torch.uint8, device=self.device)
+
+    def step_from(self, src, dst):
+        """dst = one step of src (caller-owned state buffers); the simulation's
+        own state and step counter are untouched."""
+        for b in (src, dst):
+            if b.numel() != self.nbytes or b.dtype != torch.uint8 or not b.is_cuda:
+                raise ValueError("state buffer has the wrong size, type or device")
+        A.call("fpc_step_from", self._h, ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()))
 
     def load(self, buf, step=0):
         if buf.numel() != self.nbytes or buf.dtype != torch.uint8:

@@ -158,6 +158,31 @@ def test_save_load_resume_is_bit_identical():
     assert b.step_count == 20
 
 
+@pytest.mark.parametrize("case,precision", [("mixed2d", "f32cond"), ("lid3d", "f64")])
+def test_step_from_matches_step(case, precision):
+    """One step between caller-owned buffers is bit-identical to fpc_step and
+    leaves the simulation's own state and counter alone."""
+    cfg = G.small_config(case)
+    f0, g0 = G.perturbed_state(cfg, seed=15)
+    sim = G.make_sim(cfg, precision)
+    G.load_state(sim, f0, g0, step=7)
+    src = sim.save()
+    dst = sim.new_state()
+    sim.step_from(src, dst)
+    assert sim.step_count == 7
+    assert torch.equal(sim.save(), src)
+    sim.step(1)
+    torch.cuda.synchronize()
+    ref = sim.save()
+    # compare the node planes (padding is never written)
+    n = sim.N * (8 if precision == "f64" else 4)
+    pb = sim.plane * (8 if precision == "f64" else 4)
+    for q in range(sim.Qf + sim.Qg):
+        assert torch.equal(dst[q * pb:q * pb + n], ref[q * pb:q * pb + n]), q
+    with pytest.raises(Exception):
+        sim.step_from(src, src)
+
+
 def test_nan_is_reported_unstable():
     cfg = G.small_config("dhc2d")
     f0, g0 = G.perturbed_state(cfg, seed=15)
