@@ -408,6 +408,17 @@ def main():
         # the 64 x 64 cavity: launch-bound (4096 nodes per launch)
         extra["dhc2d_64_f64"] = time_workload("dhc2d_64", "f64", a.steps, a.warmup)
         extra["copy_4GiB"] = copy_bandwidth(4096, 20)
+        # FP32 against FP64 over the workload's full run (the precision half of
+        # the metric): errors of T and of the bottom-wall Nu at the end
+        cfg_steps = 50000
+        st = precision_study("rb2d_1024x512", cfg_steps, cfg_steps // 5)
+        last = st["rows"][-1]
+        extra["fp32_vs_fp64_rb2d_1024x512"] = {
+            "steps": cfg_steps, "nu_f64": last["nu_f64"],
+            "f32dev_uniform_ref": last["f32dev"], "f32dev_conduction_ref": last["f32cond"],
+            "f64_perturbed_1e-7": last["f64pert"],
+            "bars": {"max_dT_over_DeltaT": 1e-4, "rel_dNu": 1e-3},
+        }
     if not a.no_extra and not a.no_adjoint:
         extra["adjoint_mixed2d_512_f32dev"] = adjoint_cost("mixed2d_512", 400, 100)
         extra["adjoint_rb3d_128_f32dev"] = adjoint_cost("rb3d_128", 64, 8)
