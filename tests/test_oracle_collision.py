@@ -203,3 +203,94 @@ def test_unit_rates_give_advection_diffusion_equilibrium(lat, c2):
         i = [j for j in range(lat.d) if lat.vectors[a][j] != 0][0]
         s = lat.vectors[a][i]
         assert torch.allclose(gt[:, a], T * (c2 + u[:, i] ** 2 + s * u[:, i]) / 2, atol=1e-15)
+
+
+# --- the Maxwellian comparator (MCM) and the thermal lattices of the paper ---
+
+def _central(lat, pop, u):
+    """Central moments of populations pop (n, Q) at velocity u (n, d), from the
+    definition sum_a pop_a prod_d (e_ad - u_d)^m_d (written out here, not the
+    oracle's matrix)."""
+    out = {}
+    for m in lat.M:
+        acc = torch.zeros(pop.shape[0], dtype=DT)
+        for a, e in enumerate(lat.vectors):
+            t = pop[:, a].clone()
+            for i in range(lat.d):
+                for _ in range(m[i]):
+                    t = t * (e[i] - u[:, i])
+            acc = acc + t
+        out[m] = acc
+    return out
+
+
+def _maxwell_cm(m, dens, c2):
+    """Central moment of the continuous Maxwellian truncated to the lattice:
+    dens * prod_d c(m_d) with c(0) = 1, c(1) = 0, c(2) = c^2 (matching principle)."""
+    v = dens.clone()
+    for k in m:
+        v = v * (1.0 if k == 0 else (0.0 if k == 1 else c2))
+    return v
+
+
+@pytest.mark.parametrize("lat", [L.D2Q9, L.D3Q27])
+def test_mcm_fluid_high_orders_are_maxwellian(lat):
+    """MCM: with unit rates above second order and no force, every post-
+    collision central moment of order >= 3 equals the Maxwellian value, while
+    the second order keeps its own (viscous) rate.  The FP model differs there
+    (products of the post-collision second order), so the check discriminates."""
+    f = _rand_state(lat, 25, 71, amp=0.1)
+    w = [1.0] * lat.Q
+    nu_slots = (4, 5) if lat.d == 2 else (4, 5, 6, 8, 9)
+    for k in nu_slots:
+        w[k] = 1.7
+    F = torch.zeros(25, lat.d, dtype=DT)
+    ft, rho, u = fluid_collide(f, F, lat, w, model="MCM")
+    cm = _central(lat, ft, u)
+    for m in lat.M:
+        if sum(m) >= 3:
+            assert torch.allclose(cm[m], _maxwell_cm(m, rho, 1 / 3), atol=1e-15, rtol=0), m
+    ft_fp, _, _ = fluid_collide(f, F, lat, w, model="FP")
+    top = (2, 2) if lat.d == 2 else (2, 2, 0)
+    assert float((_central(lat, ft_fp, u)[top] - _maxwell_cm(top, rho, 1 / 3)).abs().max()) > 1e-6
+
+
+@pytest.mark.parametrize("lat", [L.D2Q9_T, L.D3Q15_T])
+def test_mcm_thermal_high_orders_are_maxwellian(lat):
+    """MCM on the paper's thermal lattices: orders >= 3 relax (rate 1) to the
+    Maxwellian moments T prod c(m_d) with c^2 = c^_s^2."""
+    g = torch.Generator().manual_seed(81)
+    gp = torch.rand(25, lat.Q, generator=g, dtype=DT) + 0.2
+    u = (torch.rand(25, lat.d, generator=g, dtype=DT) - 0.5) * 0.2
+    w = [1.0] * lat.Q
+    for k in range(1, lat.d + 1):
+        w[k] = 1.4
+    c2 = 1 / 3
+    gt, T = thermal_collide(gp, u, lat, w, c2, model="MCM")
+    cm = _central(lat, gt, u)
+    for m in lat.M:
+        if sum(m) >= 3:
+            assert torch.allclose(cm[m], _maxwell_cm(m, T, c2), atol=1e-14, rtol=0), m
+
+
+@pytest.mark.parametrize("lat", [L.D2Q9_T, L.D3Q15_T])
+def test_thermal_option_a_third_order_closed_form(lat):
+    """FP option A (Eq. Dij2D_goptionA): with unit rates above first order the
+    third-order moments of the form (1,2,0) relax to (2/3) c^_s^2 times the
+    post-collision first-order moment (1 - w) eta_(1,0,0), evaluated here from
+    the input by the definition of the central moments."""
+    g = torch.Generator().manual_seed(91)
+    gp = torch.rand(25, lat.Q, generator=g, dtype=DT) + 0.2
+    u = (torch.rand(25, lat.d, generator=g, dtype=DT) - 0.5) * 0.2
+    wa = 1.35
+    w = [1.0] * lat.Q
+    for k in range(1, lat.d + 1):
+        w[k] = wa
+    c2 = 1 / 3
+    gt, T = thermal_collide(gp, u, lat, w, c2, option="A")
+    pre = _central(lat, gp, u)
+    post = _central(lat, gt, u)
+    pairs = [((2, 1), (0, 1)), ((1, 2), (1, 0))] if lat.d == 2 else \
+        [((1, 2, 0), (1, 0, 0)), ((0, 1, 2), (0, 1, 0)), ((2, 0, 1), (0, 0, 1))]
+    for m, low in pairs:
+        assert torch.allclose(post[m], 2 / 3 * c2 * (1 - wa) * pre[low], atol=1e-13, rtol=0), m

@@ -68,7 +68,8 @@ def _equilibrium_fluid(lf, u):
     return ft.T.reshape((lf.Q,) + tuple(shp))
 
 
-@pytest.mark.parametrize("pair,shape", [("D2Q9-D2Q5", (8, 6, 1)), ("D3Q27-D3Q7", (4, 5, 3))])
+@pytest.mark.parametrize("pair,shape", [("D2Q9-D2Q5", (8, 6, 1)), ("D3Q27-D3Q7", (4, 5, 3)),
+                                        ("D2Q9-D2Q9", (7, 6, 1)), ("D3Q27-D3Q15", (4, 3, 5))])
 def test_periodic_conservation(pair, shape):
     prm = _params(pair, shape, [P] * 6)
     f, g = _random_state(prm, 1)
@@ -93,7 +94,8 @@ def test_periodic_momentum_gain_equals_force():
         assert abs(float(j1[1] - j0[1] - Fy)) < 1e-14
 
 
-@pytest.mark.parametrize("pair,shape", [("D2Q9-D2Q5", (7, 6, 1)), ("D3Q27-D3Q7", (4, 4, 3))])
+@pytest.mark.parametrize("pair,shape", [("D2Q9-D2Q5", (7, 6, 1)), ("D3Q27-D3Q7", (4, 4, 3)),
+                                        ("D2Q9-D2Q9", (6, 7, 1)), ("D3Q27-D3Q15", (4, 3, 4))])
 def test_closed_box_conservation(pair, shape):
     wall = Face("noslip", "adiabatic")
     faces = [wall] * 4 + ([P, P] if shape[2] == 1 else [wall, wall])
@@ -149,7 +151,8 @@ def test_shear_wave_decay(diagonal):
     assert abs(rate / (nu * k2) - 1) < 1e-2
 
 
-@pytest.mark.parametrize("pair,shape,axis", [("D2Q9-D2Q5", (64, 1, 1), 0), ("D3Q27-D3Q7", (1, 1, 48), 2)])
+@pytest.mark.parametrize("pair,shape,axis", [("D2Q9-D2Q5", (64, 1, 1), 0), ("D3Q27-D3Q7", (1, 1, 48), 2),
+                                             ("D2Q9-D2Q9", (1, 64, 1), 1), ("D3Q27-D3Q15", (48, 1, 1), 0)])
 @pytest.mark.parametrize("u0", [0.0, 0.05])
 def test_thermal_mode_decay_and_advection(pair, shape, axis, u0):
     wa = 1.3
@@ -194,7 +197,8 @@ def test_couette_lid_linear_profile():
     assert mac["u"][1].abs().max() < 1e-13
 
 
-@pytest.mark.parametrize("pair,shape,axis", [("D2Q9-D2Q5", (1, 6, 1), 1), ("D3Q27-D3Q7", (1, 1, 6), 2)])
+@pytest.mark.parametrize("pair,shape,axis", [("D2Q9-D2Q5", (1, 6, 1), 1), ("D3Q27-D3Q7", (1, 1, 6), 2),
+                                             ("D2Q9-D2Q9", (1, 6, 1), 1), ("D3Q27-D3Q15", (1, 1, 6), 2)])
 def test_conduction_profile_and_nusselt(pair, shape, axis):
     faces = [P] * 6
     faces[2 * axis] = Face("noslip", "dirichlet", T=0.5)
