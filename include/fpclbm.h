@@ -47,8 +47,18 @@ extern "C" {
 #define FPC_ERR_STATE (-5)    /* the call does not fit the simulation's configuration */
 
 /* Lattice pairs (fluid + thermal). */
-#define FPC_D2Q9_D2Q5 1  /* D2Q9 fluid (Eqs. ex, ey) + D2Q5 thermal (axis subset of D2Q9) */
-#define FPC_D3Q27_D3Q7 2 /* D3Q27 fluid (Sec. 5.2) + D3Q7 thermal (axis subset of D3Q27) */
+#define FPC_D2Q9_D2Q5 1   /* D2Q9 fluid (Eqs. ex, ey) + D2Q5 thermal (axis subset of D2Q9) */
+#define FPC_D3Q27_D3Q7 2  /* D3Q27 fluid (Sec. 5.2) + D3Q7 thermal (axis subset of D3Q27) */
+#define FPC_D2Q9_D2Q9 3   /* D2Q9 fluid + the paper's D2Q9 thermal lattice (Sec. 4.4, App. B); FP64 only */
+#define FPC_D3Q27_D3Q15 4 /* D3Q27 fluid + the paper's D3Q15 thermal lattice (Sec. 5.4, App. C); FP64 only */
+
+/* Collision models (fpc_params.model). */
+#define FPC_MODEL_FP 0  /* Fokker-Planck central-moment attractors (the method) */
+#define FPC_MODEL_MCM 1 /* Maxwellian central-moment attractors: the comparator of Sec. 7 */
+
+/* Thermal attractors above second order (fpc_params.thermal_option; D2Q9 / D3Q15 thermal only). */
+#define FPC_THERMAL_OPTION_A 0 /* diffusion tensor c^_s^2 I at every order (Eq. Dij2D_goptionA) */
+#define FPC_THERMAL_OPTION_B 1 /* renormalised by the post-collision second order over T (Eq. Dij2D_g) */
 
 /* Storage precision of the populations. */
 #define FPC_FP64 0     /* populations f, g stored and collided in FP64 */
@@ -80,16 +90,19 @@ extern "C" {
  *        122, 212, 221, 222)  (moment order of Sec. 5.2).
  *   Slot 0 has no effect (mass is conserved).
  * omega_g: thermal rates.  D2Q5 (App. B Step 3): (00, 10, 01, 20+02, 20-02);
- *   D3Q7 (App. C Step 3): (000, 100, 010, 001, 200, 020, 002).
+ *   D3Q7 (App. C Step 3): (000, 100, 010, 001, 200, 020, 002);
+ *   D2Q9 (App. B Step 3): (00, 10, 01, 20+02, 20-02, 11, 21, 12, 22);
+ *   D3Q15 (App. C Step 3): (000, 100, 010, 001, 110, 101, 011, 200, 020, 002,
+ *          120, 012, 201, 111, 220).
  * Every rate in use must lie in (0, 2).
  */
 typedef struct fpc_params {
-  int lattice;   /* FPC_D2Q9_D2Q5 or FPC_D3Q27_D3Q7 */
+  int lattice;   /* FPC_D2Q9_D2Q5, FPC_D3Q27_D3Q7, FPC_D2Q9_D2Q9 or FPC_D3Q27_D3Q15 */
   int precision; /* FPC_FP64 or FPC_FP32_DEV */
   int nx, ny, nz;
   double omega_f[27];
-  double omega_g[7];
-  double cs2_T;  /* thermal diffusion parameter c^_s^2 (option A); default 1/3 (D2Q5), 1/4 (D3Q7) */
+  double omega_g[15];
+  double cs2_T;  /* thermal diffusion parameter c^_s^2; default 1/3 (D2Q5, D2Q9, D3Q15), 1/4 (D3Q7) */
   double g_beta; /* buoyancy per unit temperature: F = g_beta (T - T0) along up_axis */
   double T0;     /* Boussinesq reference temperature; also the FP32-deviation offset of g */
   double rho0;   /* reference density: initial density, moving-wall density, FP32-deviation offset of f */
@@ -112,9 +125,21 @@ typedef struct fpc_params {
    * periodic; s must be finite.  Defaults: s = 0, k = -1. */
   double T_ref_slope;
   int T_ref_axis;
+  /* Collision model, FPC_MODEL_FP (default) or FPC_MODEL_MCM.  The MCM
+   * comparator replaces every attractor by the Maxwellian central moment
+   * (rho or T times prod c(m_d), c(0) = 1, c(1) = 0, c(2) = c_s^2 or c^_s^2):
+   * on D2Q5 / D3Q7 thermal it differs from FP in the fluid orders >= 4 only. */
+  int model;
+  /* FPC_THERMAL_OPTION_A (default) or _B; only the D2Q9 / D3Q15 thermal
+   * lattices have moments above second order for it to act on. */
+  int thermal_option;
 } fpc_params;
 
 typedef struct fpc_sim fpc_sim;
+
+/* sizeof(fpc_params) as compiled into the library: lets a binding check its
+ * copy of the struct layout before the first call. */
+size_t fpc_params_bytes(void);
 
 /* Library version (major*10000 + minor*100 + patch). */
 int fpc_version(void);
@@ -239,6 +264,8 @@ int fpc_current_buffer(const fpc_sim* s, void** ptr);
  * FP32), holding adjoints of the stored values; every element of lam_out that
  * belongs to a node is written (padding is not).  The method is not part of
  * the paper: this is the exact adjoint of the discrete update above.
+ * Available for the FP model on FPC_D2Q9_D2Q5 / FPC_D3Q27_D3Q7; other
+ * configurations return FPC_ERR_STATE (as does fpc_adjoint_init).
  */
 int fpc_adjoint_step(fpc_sim* s, const void* S_prev, const void* lam_in, void* lam_out, const double* dJdT,
                      double ke_weight, double* const* dJdtheta);

@@ -27,6 +27,12 @@ FPC_ERR_STATE = -5
 
 FPC_D2Q9_D2Q5 = 1
 FPC_D3Q27_D3Q7 = 2
+FPC_D2Q9_D2Q9 = 3
+FPC_D3Q27_D3Q15 = 4
+FPC_MODEL_FP = 0
+FPC_MODEL_MCM = 1
+FPC_THERMAL_OPTION_A = 0
+FPC_THERMAL_OPTION_B = 1
 FPC_FP64 = 0
 FPC_FP32_DEV = 1
 
@@ -37,7 +43,7 @@ FPC_BC_LID_ADIABATIC = 3
 FPC_BC_LID_DIRICHLET = 4
 
 EXPORTED = (
-    "fpc_version", "fpc_last_error", "fpc_params_default", "fpc_params_natural", "fpc_params_mixed",
+    "fpc_version", "fpc_last_error", "fpc_params_bytes", "fpc_params_default", "fpc_params_natural", "fpc_params_mixed",
     "fpc_state_bytes", "fpc_create", "fpc_destroy", "fpc_set_stream", "fpc_init", "fpc_step", "fpc_step_from",
     "fpc_get_step", "fpc_macros", "fpc_diagnostics", "fpc_save", "fpc_load", "fpc_export_fp64",
     "fpc_import_fp64", "fpc_current_buffer", "fpc_adjoint_step", "fpc_adjoint_init",
@@ -58,7 +64,7 @@ class fpc_params(ctypes.Structure):
         ("ny", ctypes.c_int),
         ("nz", ctypes.c_int),
         ("omega_f", ctypes.c_double * 27),
-        ("omega_g", ctypes.c_double * 7),
+        ("omega_g", ctypes.c_double * 15),
         ("cs2_T", ctypes.c_double),
         ("g_beta", ctypes.c_double),
         ("T0", ctypes.c_double),
@@ -71,6 +77,8 @@ class fpc_params(ctypes.Structure):
         ("wall_T_profile", ctypes.c_void_p * 6),
         ("T_ref_slope", ctypes.c_double),
         ("T_ref_axis", ctypes.c_int),
+        ("model", ctypes.c_int),
+        ("thermal_option", ctypes.c_int),
     ]
 
 
@@ -107,6 +115,7 @@ def load():
         "fpc_init": (i, [vp, vp]),
         "fpc_step": (i, [vp, i]),
         "fpc_step_from": (i, [vp, vp, vp]),
+        "fpc_params_bytes": (ctypes.c_size_t, []),
         "fpc_get_step": (i, [vp, ctypes.POINTER(ll)]),
         "fpc_macros": (i, [vp, vp, vp, vp]),
         "fpc_diagnostics": (i, [vp, i, dp, dp, dp, dp]),
@@ -122,6 +131,9 @@ def load():
         fn = getattr(lib, name)
         fn.restype = res
         fn.argtypes = args
+    if lib.fpc_params_bytes() != ctypes.sizeof(fpc_params):
+        raise ImportError(f"{LIB_PATH}: fpc_params is {lib.fpc_params_bytes()} bytes in the library but "
+                          f"{ctypes.sizeof(fpc_params)} in this binding (rebuild the library)")
     _lib = lib
     return lib
 

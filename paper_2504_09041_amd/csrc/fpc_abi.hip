@@ -48,6 +48,12 @@ int hipfail(hipError_t e, const char* what) {
 
 size_t elem_size(int precision) { return precision == FPC_FP64 ? 8 : 4; }
 
+// the paper's own thermal lattices (D2Q9 / D3Q15)
+bool paper_thermal(int lattice) { return lattice == FPC_D2Q9_D2Q9 || lattice == FPC_D3Q27_D3Q15; }
+
+// the hand-written adjoint covers the FP model on the D2Q5 / D3Q7 thermal lattices
+bool adjoint_supported(const fpc_params& p) { return !paper_thermal(p.lattice) && p.model == FPC_MODEL_FP; }
+
 int lattice_dims(int lattice, int* Qf, int* Qg, int* dim) {
   if (lattice == FPC_D2Q9_D2Q5) {
     *Qf = 9; *Qg = 5; *dim = 2;
@@ -55,6 +61,14 @@ int lattice_dims(int lattice, int* Qf, int* Qg, int* dim) {
   }
   if (lattice == FPC_D3Q27_D3Q7) {
     *Qf = 27; *Qg = 7; *dim = 3;
+    return FPC_OK;
+  }
+  if (lattice == FPC_D2Q9_D2Q9) {
+    *Qf = 9; *Qg = 9; *dim = 2;
+    return FPC_OK;
+  }
+  if (lattice == FPC_D3Q27_D3Q15) {
+    *Qf = 27; *Qg = 15; *dim = 3;
     return FPC_OK;
   }
   return fail(FPC_ERR_ARG, "unknown lattice %d", lattice);
@@ -80,6 +94,11 @@ int validate(const fpc_params* p) {
   if (rc) return rc;
   if (p->precision != FPC_FP64 && p->precision != FPC_FP32_DEV)
     return fail(FPC_ERR_ARG, "unknown precision %d", p->precision);
+  if (p->precision == FPC_FP32_DEV && paper_thermal(p->lattice))
+    return fail(FPC_ERR_ARG, "the D2Q9 / D3Q15 thermal lattices run in FP64 only");
+  if (p->model != FPC_MODEL_FP && p->model != FPC_MODEL_MCM) return fail(FPC_ERR_ARG, "unknown model %d", p->model);
+  if (p->thermal_option != FPC_THERMAL_OPTION_A && p->thermal_option != FPC_THERMAL_OPTION_B)
+    return fail(FPC_ERR_ARG, "unknown thermal option %d", p->thermal_option);
   if (p->nx <= 0 || p->ny <= 0 || p->nz <= 0) return fail(FPC_ERR_SIZE, "grid sizes must be positive");
   if (dim == 2 && p->nz != 1) return fail(FPC_ERR_SIZE, "2D lattice needs nz == 1");
   const double N = (double)p->nx * p->ny * p->nz;
@@ -151,7 +170,9 @@ StepArgs<R> make_args(const fpc_sim* s, const void* src, void* dst) {
   for (int k = 0; k < 3; ++k) a.per[k] = p.bc[2 * k] == FPC_BC_PERIODIC;
   a.plane = s->plane;
   for (int k = 0; k < 27; ++k) a.c.om[k] = (R)p.omega_f[k];
-  for (int k = 0; k < 7; ++k) a.c.omg[k] = (R)p.omega_g[k];
+  for (int k = 0; k < 15; ++k) a.c.omg[k] = (R)p.omega_g[k];
+  a.c.model = p.model;
+  a.c.topt = p.thermal_option;
   a.c.cs2T = (R)p.cs2_T;
   a.c.gbeta = (R)p.g_beta;
   a.c.T0 = (R)p.T0;
@@ -180,14 +201,15 @@ StepArgs<R> make_args(const fpc_sim* s, const void* src, void* dst) {
 int launch_update(fpc_sim* s, const void* src, void* dst, const double* T_init, int mode) {
   hipError_t e;
   const int up = s->p.up_axis;
+  const int tk = paper_thermal(s->p.lattice) ? 1 : 0;
   if (s->p.precision == FPC_FP64) {
     const StepArgs<double> a = make_args<double>(s, src, dst);
-    e = s->dim == 2 ? launch_step2d<double>(a, up, T_init, mode, s->stream)
-                    : launch_step3d<double>(a, up, T_init, mode, s->stream);
+    e = s->dim == 2 ? launch_step2d<double>(a, up, tk, T_init, mode, s->stream)
+                    : launch_step3d<double>(a, up, tk, T_init, mode, s->stream);
   } else {
     const StepArgs<float> a = make_args<float>(s, src, dst);
-    e = s->dim == 2 ? launch_step2d<float>(a, up, T_init, mode, s->stream)
-                    : launch_step3d<float>(a, up, T_init, mode, s->stream);
+    e = s->dim == 2 ? launch_step2d<float>(a, up, tk, T_init, mode, s->stream)
+                    : launch_step3d<float>(a, up, tk, T_init, mode, s->stream);
   }
   if (e != hipSuccess) return hipfail(e, "kernel launch");
   return FPC_OK;
@@ -222,8 +244,8 @@ void set_rates(fpc_params* p, double nu, double alpha) {
   const double wn = rate_from(nu, 1.0 / 3.0);
   const double wa = rate_from(alpha, p->cs2_T);
   for (int k = 0; k < 27; ++k) p->omega_f[k] = 1.0;
-  for (int k = 0; k < 7; ++k) p->omega_g[k] = 1.0;
-  if (p->lattice == FPC_D2Q9_D2Q5) {
+  for (int k = 0; k < 15; ++k) p->omega_g[k] = 1.0;
+  if (p->lattice == FPC_D2Q9_D2Q5 || p->lattice == FPC_D2Q9_D2Q9) {
     p->omega_f[4] = wn;  // 20 - 02
     p->omega_f[5] = wn;  // 11
     p->omega_g[1] = p->omega_g[2] = wa;
@@ -238,7 +260,9 @@ void set_rates(fpc_params* p, double nu, double alpha) {
 
 extern "C" {
 
-int fpc_version(void) { return 10000; }
+int fpc_version(void) { return 10100; }
+
+size_t fpc_params_bytes(void) { return sizeof(fpc_params); }
 
 const char* fpc_last_error(void) { return g_err.c_str(); }
 
@@ -256,8 +280,8 @@ int fpc_params_default(fpc_params* p, int lattice, int precision, int nx, int ny
   p->ny = ny;
   p->nz = nz;
   for (int k = 0; k < 27; ++k) p->omega_f[k] = 1.0;
-  for (int k = 0; k < 7; ++k) p->omega_g[k] = 1.0;
-  p->cs2_T = dim == 2 ? 1.0 / 3.0 : 0.25;
+  for (int k = 0; k < 15; ++k) p->omega_g[k] = 1.0;
+  p->cs2_T = lattice == FPC_D3Q27_D3Q7 ? 0.25 : 1.0 / 3.0;
   p->rho0 = 1.0;
   p->dT_ref = 1.0;
   p->up_axis = dim == 2 ? 1 : 2;
@@ -346,7 +370,7 @@ int fpc_create(const fpc_params* p, void* bufA, void* bufB, void* hip_stream, fp
   }
   e = hipHostMalloc(&s->result_host, 8 * sizeof(double), hipHostMallocDefault);
   if (e != hipSuccess) {
-    hipFree(s->scratch);
+    (void)hipFree(s->scratch);
     delete s;
     return hipfail(e, "hipHostMalloc(result)");
   }
@@ -487,6 +511,7 @@ int fpc_import_fp64(fpc_sim* s, const double* src, long long step) {
 int fpc_adjoint_step(fpc_sim* s, const void* S_prev, const void* lam_in, void* lam_out, const double* dJdT,
                      double ke_weight, double* const* dJdtheta) {
   if (!s || !S_prev || !lam_in || !lam_out) return fail(FPC_ERR_ARG, "NULL argument");
+  if (!adjoint_supported(s->p)) return fail(FPC_ERR_STATE, "adjoint: FP model with D2Q5 / D3Q7 thermal only");
   if (lam_in == lam_out || lam_out == S_prev) return fail(FPC_ERR_ARG, "lam_out must not alias lam_in or S_prev");
   if (!std::isfinite(ke_weight)) return fail(FPC_ERR_ARG, "ke_weight not finite");
   double* dth[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
@@ -510,6 +535,7 @@ int fpc_adjoint_step(fpc_sim* s, const void* S_prev, const void* lam_in, void* l
 int fpc_adjoint_init(fpc_sim* s, const double* T_init, const void* lam0, const double* dJdT, double ke_weight,
                      double* dJdT_init) {
   if (!s || !T_init || !lam0 || !dJdT_init) return fail(FPC_ERR_ARG, "NULL argument");
+  if (!adjoint_supported(s->p)) return fail(FPC_ERR_STATE, "adjoint: FP model with D2Q5 / D3Q7 thermal only");
   if (!std::isfinite(ke_weight)) return fail(FPC_ERR_ARG, "ke_weight not finite");
   hipError_t e;
   if (s->p.precision == FPC_FP64) {

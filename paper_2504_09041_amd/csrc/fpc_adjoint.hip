@@ -89,21 +89,22 @@ struct Scatter {
 
   template <int Q, int QBASE>
   __device__ __forceinline__ void push(R v) const {
-    const long long sh = e.template shift<Q>();
-    if (!E::template checked<Q>()) {
+    constexpr bool TH = QBASE != 0;
+    const long long sh = e.template shift<Q, TH>();
+    if (!E::template checked<Q, TH>()) {
       m.store_at(QBASE + Q, sh, e.node, v);
       return;
     }
     bool wx = false, wy = false, wz = false;
-    const unsigned idx = e.template source<Q>(wx, wy, wz);
-    if (E::template wrap_only<Q>()) {
+    const unsigned idx = e.template source<Q, TH>(wx, wy, wz);
+    if (E::template wrap_only<Q, TH>()) {
       m.store_at(QBASE + Q, sh, idx, v);
       return;
     }
     const bool wall = wx || wy || wz;
     R out = v;
     if (QBASE != 0 && Q != 0) {
-      constexpr int ex = L::ex(Q), ey = L::ey(Q), ez = L::ez(Q);
+      constexpr int ex = lex<L, TH>(Q), ey = ley<L, TH>(Q), ez = lez<L, TH>(Q);
       constexpr int F = ex > 0 ? 0 : (ex < 0 ? 1 : (ey > 0 ? 2 : (ey < 0 ? 3 : (ez > 0 ? 4 : 5))));
       constexpr int k = F >> 1;
       const StepArgs<R>& a = A.s;
@@ -115,7 +116,7 @@ struct Scatter {
         }
       }
     }
-    m.store_sel(wall, QBASE + L::opp(Q), e.node, QBASE + Q, sh, idx, out);
+    m.store_sel(wall, QBASE + lopp<L, TH>(Q), e.node, QBASE + Q, sh, idx, out);
   }
 };
 
@@ -175,7 +176,7 @@ __global__ void __launch_bounds__(256) adjoint_step_kernel(AdjArgs<R> A, unsigne
 #pragma unroll
     for (int q = 0; q < L::Qf; ++q) f[q] += R(L::w(q)) * a.c.rho_r;
 #pragma unroll
-    for (int q = 0; q < L::Qg; ++q) g[q] += (q == 0 ? R(1) - R(D) * a.c.cs2T : R(0.5) * a.c.cs2T) * Tr;
+    for (int q = 0; q < L::Qg; ++q) g[q] += L::template wT<R>(q, a.c.cs2T) * Tr;
   }
   adj::Tape<R, D> t;
   adj::forward<R, D, UP>(f, g, a.c, t);

@@ -38,12 +38,14 @@ namespace fpc {
 template <class R>
 struct CollParams {
   R om[27];   // fluid rates in the paper's slot order (see fpclbm.h)
-  R omg[7];   // thermal rates
+  R omg[15];  // thermal rates (moment order of the thermal lattice)
   R cs2T;     // thermal diffusion parameter c^_s^2
   R gbeta;    // buoyancy per unit temperature along the up axis
   R T0;       // Boussinesq reference temperature
   R rho_r;    // storage offset of f (0: plain populations)
   R T_r;      // storage offset of g at the box centre (0: plain populations)
+  int model;  // 0: FP attractors; 1: Maxwellian central moments (MCM comparator, Sec. 7)
+  int topt;   // thermal higher-order attractors: 0 option A, 1 option B (Sec. 4.3)
 };
 
 // Macros of the time level, produced by the collision for diagnostics.
@@ -105,20 +107,237 @@ __device__ __forceinline__ R rho_ref(const CollParams<R>& c) {
   return R(0);
 }
 
+
+// ---------------------------------------------------------------------------
+// The paper's thermal lattices, on plain populations (FP64 storage):
+// D2Q9 (Sec. 4.3-4.4, App. B) and D3Q15 (Sec. 5.3-5.4, App. C).
+// Higher-order attractors (Eq. Mvcmattractor2D_g with Eq. Dij2D_goptionA /
+// Dij2D_g, and their 3D forms): option A uses c^_s^2 I at every order, option
+// B the post-collision second-order moments over T above second order; the
+// MCM comparator uses the Maxwellian moments T prod c(m_d).  The first- and
+// second-order rules are common to all three.
+// ---------------------------------------------------------------------------
+
+// D2Q9 thermal: central moments by 1D shifts (x per row, then y), as for f.
+template <class R, bool STD>
+__device__ __forceinline__ void thermal_d2q9(R (&g)[kQ2], R ux, R uy, R T, const CollParams<R>& c) {
+  R x0m, x1m, x2m, x0z, x1z, x2z, x0p, x1p, x2p;
+  shift_fwd(g[7], g[4], g[8], ux, x0m, x1m, x2m);  // ey = -1
+  shift_fwd(g[3], g[0], g[1], ux, x0z, x1z, x2z);  // ey =  0
+  shift_fwd(g[6], g[2], g[5], ux, x0p, x1p, x2p);  // ey = +1
+  R e00, e01, e02, e10, e11, e12, e20, e21, e22;
+  shift_fwd(x0m, x0z, x0p, uy, e00, e01, e02);
+  shift_fwd(x1m, x1z, x1p, uy, e10, e11, e12);
+  shift_fwd(x2m, x2z, x2p, uy, e20, e21, e22);
+  (void)e00;  // equals T
+  auto og = [&](int k) -> R { return rate_g<2, STD>(c, k); };
+  const R cT = c.cs2T;
+  // orders 1-2 (App. B Step 3): first order and 11 toward 0; 2s toward 2 c^2 T, 2d toward 0
+  const R t10 = (R(1) - og(1)) * e10, t01 = (R(1) - og(2)) * e01;
+  const R s2 = e20 + e02, d2 = e20 - e02;
+  const R ts = s2 + og(3) * (R(2) * cT * T - s2), td = (R(1) - og(4)) * d2;
+  const R t20 = R(0.5) * (ts + td), t02 = R(0.5) * (ts - td);
+  const R t11 = (R(1) - og(5)) * e11;
+  R m21, m12, m22;
+  if (c.model != 0) {  // MCM
+    m21 = R(0);
+    m12 = R(0);
+    m22 = cT * cT * T;
+  } else if (c.topt != 0) {  // option B (Eq. MvT2DoptionB)
+    const R iT = R(1) / T;
+    m21 = R(2) / R(3) * iT * (t20 * t01 + R(2) * t11 * t10);
+    m12 = R(2) / R(3) * iT * (t02 * t10 + R(2) * t11 * t01);
+    m22 = iT * (t20 * t02 + R(2) * t11 * t11);
+  } else {  // option A (Eq. MvT2D)
+    m21 = R(2) / R(3) * cT * t01;
+    m12 = R(2) / R(3) * cT * t10;
+    m22 = R(0.5) * cT * (t20 + t02);
+  }
+  const R t21 = e21 + og(6) * (m21 - e21);
+  const R t12 = e12 + og(7) * (m12 - e12);
+  const R t22 = e22 + og(8) * (m22 - e22);
+  shift_inv(T, t01, t02, uy, x0m, x0z, x0p);
+  shift_inv(t10, t11, t12, uy, x1m, x1z, x1p);
+  shift_inv(t20, t21, t22, uy, x2m, x2z, x2p);
+  shift_inv(x0m, x1m, x2m, ux, g[7], g[4], g[8]);
+  shift_inv(x0z, x1z, x2z, ux, g[3], g[0], g[1]);
+  shift_inv(x0p, x1p, x2p, ux, g[6], g[2], g[5]);
+}
+
+// D3Q15 moment set in the paper's order (Sec. 5.4):
+// 000 100 010 001 110 101 011 200 020 002 120 012 201 111 220.
+namespace t15 {
+constexpr int kM[kQ15][3] = {{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {1, 1, 0}, {1, 0, 1}, {0, 1, 1}, {2, 0, 0},
+                             {0, 2, 0}, {0, 0, 2}, {1, 2, 0}, {0, 1, 2}, {2, 0, 1}, {1, 1, 1}, {2, 2, 0}};
+// On D3Q15 every raw moment with exponents <= 2 equals one of the set: with
+// at most one non-zero exponent it is in the set itself; with two or more
+// only the corners contribute, and a corner moment depends only on the
+// exponent parities (s^2 = 1).  Index of that set member.
+constexpr int alias(int a, int b, int c) {
+  const int nz = (a > 0) + (b > 0) + (c > 0);
+  if (nz <= 1) {
+    if (a + b + c == 0) return 0;
+    if (a) return a == 1 ? 1 : 7;
+    if (b) return b == 1 ? 2 : 8;
+    return c == 1 ? 3 : 9;
+  }
+  const int p = (a & 1) + 2 * (b & 1) + 4 * (c & 1);
+  constexpr int byp[8] = {14, 10, 11, 4, 12, 5, 6, 13};  // parity x + 2y + 4z -> set index
+  return byp[p];
+}
+constexpr int binom(int m, int i) { return (m == 2 && i == 1) ? 2 : 1; }
+}  // namespace t15
+
+// sum over i <= m (componentwise) of prod_d binom(m_d, i_d) (-u_d)^(m_d - i_d) r[alias(i)],
+// leaving out i == m when SKIP_SELF
+template <class R, int K, bool SKIP_SELF>
+__device__ __forceinline__ R t15_shift(const R (&r)[kQ15], const R (&nux)[3], const R (&nuy)[3], const R (&nuz)[3]) {
+  constexpr int mx = t15::kM[K][0], my = t15::kM[K][1], mz = t15::kM[K][2];
+  R acc = R(0);
+#pragma unroll
+  for (int i = 0; i <= mx; ++i)
+#pragma unroll
+    for (int j = 0; j <= my; ++j)
+#pragma unroll
+      for (int k = 0; k <= mz; ++k) {
+        if (SKIP_SELF && i == mx && j == my && k == mz) continue;
+        const R cf = R(t15::binom(mx, i) * t15::binom(my, j) * t15::binom(mz, k)) * nux[mx - i] * nuy[my - j] *
+                     nuz[mz - k];
+        acc += cf * r[t15::alias(i, j, k)];
+      }
+  return acc;
+}
+
+template <class R, bool STD>
+__device__ __forceinline__ void thermal_d3q15(R (&g)[kQ15], R ux, R uy, R uz, R T, const CollParams<R>& c) {
+  // raw moments: corner Walsh-Hadamard transform h[px + 2py + 4pz] =
+  // sum_corners g s_x^px s_y^py s_z^pz, plus the axis pairs and the rest
+  R h[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) h[j] = g[7 + j];  // corner j: s_x = -1 if j&1, s_y if j&2, s_z if j&4
+#pragma unroll
+  for (int bit = 1; bit < 8; bit <<= 1)
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if (!(j & bit)) {
+        const R p = h[j], q = h[j | bit];
+        h[j] = p + q;
+        h[j | bit] = p - q;
+      }
+  const R Sx = g[1] + g[2], Dx = g[1] - g[2], Sy = g[3] + g[4], Dy = g[3] - g[4];
+  const R Sz = g[5] + g[6], Dz = g[5] - g[6];
+  R r[kQ15];
+  r[0] = g[0] + Sx + Sy + Sz + h[0];
+  r[1] = Dx + h[1];
+  r[2] = Dy + h[2];
+  r[3] = Dz + h[4];
+  r[4] = h[3];   // 110
+  r[5] = h[5];   // 101
+  r[6] = h[6];   // 011
+  r[7] = Sx + h[0];
+  r[8] = Sy + h[0];
+  r[9] = Sz + h[0];
+  r[10] = h[1];  // 120
+  r[11] = h[2];  // 012
+  r[12] = h[4];  // 201
+  r[13] = h[7];  // 111
+  r[14] = h[0];  // 220
+  // central moments (App. C Step 2): binomial expansion about u
+  const R nux[3] = {R(1), -ux, ux * ux}, nuy[3] = {R(1), -uy, uy * uy}, nuz[3] = {R(1), -uz, uz * uz};
+  R e[kQ15];
+#define FPC_T15(K) e[K] = t15_shift<R, K, false>(r, nux, nuy, nuz);
+  FPC_T15(1) FPC_T15(2) FPC_T15(3) FPC_T15(4) FPC_T15(5) FPC_T15(6) FPC_T15(7) FPC_T15(8) FPC_T15(9)
+  FPC_T15(10) FPC_T15(11) FPC_T15(12) FPC_T15(13) FPC_T15(14)
+#undef FPC_T15
+  // relaxation (App. C Step 3), moment by moment
+  auto og = [&](int k) -> R { return rate_g<3, STD>(c, k); };
+  const R cT = c.cs2T;
+  R t[kQ15];
+  t[0] = T;
+#pragma unroll
+  for (int k = 1; k <= 6; ++k) t[k] = (R(1) - og(k)) * e[k];  // first order, off-diagonal second order
+#pragma unroll
+  for (int k = 7; k <= 9; ++k) t[k] = e[k] + og(k) * (cT * T - e[k]);
+  R m120, m012, m201, m111, m220;
+  if (c.model != 0) {  // MCM
+    m120 = m012 = m201 = m111 = R(0);
+    m220 = cT * cT * T;
+  } else if (c.topt != 0) {  // option B
+    const R f = R(2) / (R(3) * T);
+    m120 = f * (t[8] * t[1] + R(2) * t[4] * t[2]);
+    m012 = f * (t[9] * t[2] + R(2) * t[6] * t[3]);
+    m201 = f * (t[7] * t[3] + R(2) * t[5] * t[1]);
+    m111 = f * (t[4] * t[3] + t[5] * t[2] + t[6] * t[1]);
+    m220 = (t[7] * t[8] + R(2) * t[4] * t[4]) / T;
+  } else {  // option A
+    m120 = R(2) / R(3) * cT * t[1];
+    m012 = R(2) / R(3) * cT * t[2];
+    m201 = R(2) / R(3) * cT * t[3];
+    m111 = R(0);
+    m220 = R(0.5) * cT * (t[7] + t[8]);
+  }
+  t[10] = e[10] + og(10) * (m120 - e[10]);
+  t[11] = e[11] + og(11) * (m012 - e[11]);
+  t[12] = e[12] + og(12) * (m201 - e[12]);
+  t[13] = e[13] + og(13) * (m111 - e[13]);
+  t[14] = e[14] + og(14) * (m220 - e[14]);
+  // raw moments back: the central map is unit lower triangular in this order,
+  // so r_m = t_m - (terms of lower members), member by member
+  r[0] = T;
+#define FPC_T15I(K) r[K] = t[K] - t15_shift<R, K, true>(r, nux, nuy, nuz);
+  FPC_T15I(1) FPC_T15I(2) FPC_T15I(3) FPC_T15I(4) FPC_T15I(5) FPC_T15I(6) FPC_T15I(7) FPC_T15I(8) FPC_T15I(9)
+  FPC_T15I(10) FPC_T15I(11) FPC_T15I(12) FPC_T15I(13) FPC_T15I(14)
+#undef FPC_T15I
+  // populations: corners by the inverse Hadamard transform of
+  // (220, 120, 012, 110, 201, 101, 011, 111); axis pairs and rest from the rest
+  h[0] = r[14];
+  h[1] = r[10];
+  h[2] = r[11];
+  h[3] = r[4];
+  h[4] = r[12];
+  h[5] = r[5];
+  h[6] = r[6];
+  h[7] = r[13];
+#pragma unroll
+  for (int bit = 1; bit < 8; bit <<= 1)
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if (!(j & bit)) {
+        const R p = h[j], q = h[j | bit];
+        h[j] = p + q;
+        h[j | bit] = p - q;
+      }
+#pragma unroll
+  for (int j = 0; j < 8; ++j) g[7 + j] = R(0.125) * h[j];
+  g[1] = R(0.5) * ((r[7] - r[14]) + (r[1] - r[10]));
+  g[2] = R(0.5) * ((r[7] - r[14]) - (r[1] - r[10]));
+  g[3] = R(0.5) * ((r[8] - r[14]) + (r[2] - r[11]));
+  g[4] = R(0.5) * ((r[8] - r[14]) - (r[2] - r[11]));
+  g[5] = R(0.5) * ((r[9] - r[14]) + (r[3] - r[12]));
+  g[6] = R(0.5) * ((r[9] - r[14]) - (r[3] - r[12]));
+  g[0] = r[0] - r[7] - r[8] - r[9] + R(2) * r[14];
+}
+
 // ---------------------------------------------------------------------------
 // 2D: D2Q9 fluid + D2Q5 thermal.  f, g hold the pulled (pre-collision) stored
 // values on entry and the post-collision stored values on exit.
 // ---------------------------------------------------------------------------
 // Tr: storage reference of g at this node (g is stored as g - w^T Tr).
-template <class R, int UP, bool STD = false>
-__device__ __forceinline__ void collide2d(R (&f)[kQ2], R (&g)[kQ2T], const CollParams<R>& c, R Tr,
+// QG: thermal lattice, D2Q5 (5, deviation form) or D2Q9 (9, plain populations).
+template <class R, int UP, bool STD = false, int QG = kQ2T>
+__device__ __forceinline__ void collide2d(R (&f)[kQ2], R (&g)[QG], const CollParams<R>& c, R Tr,
                                           Macros<R>* mac) {
   constexpr R cs2 = R(1) / R(3);
   const R rr = rho_ref(c);
   const R drho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
   const R jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
   const R jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
-  const R dT = ((g[0] + g[1]) + (g[2] + g[3])) + g[4];
+  R dT;
+  if constexpr (QG == kQ2T) {
+    dT = ((g[0] + g[1]) + (g[2] + g[3])) + g[4];
+  } else {
+    dT = ((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + (g[6] + g[7])) + g[8];
+  }
   const R T = Tr + dT;
   const R rho = rr + drho;
   const R Fb = c.gbeta * (T - c.T0);
@@ -172,9 +391,13 @@ __device__ __forceinline__ void collide2d(R (&f)[kQ2], R (&g)[kQ2T], const CollP
   const R t02 = R(0.5) * (t2s - t2d);
   const R t21 = k21 + om(6) * (rr * A * uy - k21) + (R(1) - R(0.5) * om(6)) * s21;
   const R t12 = k12 + om(7) * (rr * ux * B - k12) + (R(1) - R(0.5) * om(7)) * s12;
-  // kappa^Mv_22 = (kappa~20 kappa~02 + 2 kappa~11^2) / rho
-  const R mv22 = (dprod(rr, A, t20, B, t02) + R(2) * dprod(rr, uxy, t11, uxy, t11) +
-                  rr * rr * (R(2) * uxx * uyy) - rr * A * B * drho) * irho;
+  // kappa^Mv_22 = (kappa~20 kappa~02 + 2 kappa~11^2) / rho (FP); rho c_s^4 (MCM)
+  R mv22;
+  if (c.model != 0)
+    mv22 = drho * (cs2 * cs2) - rr * (cs2 * (uxx + uyy) + uxx * uyy);
+  else
+    mv22 = (dprod(rr, A, t20, B, t02) + R(2) * dprod(rr, uxy, t11, uxy, t11) + rr * rr * (R(2) * uxx * uyy) -
+            rr * A * B * drho) * irho;
   const R t22 = k22 + om(8) * (mv22 - k22) + (R(1) - R(0.5) * om(8)) * s22;
 
   // central -> populations: y shifts per mx, then x shifts per row ey
@@ -185,6 +408,10 @@ __device__ __forceinline__ void collide2d(R (&f)[kQ2], R (&g)[kQ2T], const CollP
   shift_inv(x0z, x1z, x2z, ux, f[3], f[0], f[1]);
   shift_inv(x0p, x1p, x2p, ux, f[6], f[2], f[5]);
 
+  if constexpr (QG != kQ2T) {
+    thermal_d2q9<R, STD>(g, ux, uy, T, c);
+    return;
+  } else {
   // thermal D2Q5: raw moments (00, 10, 01, 20, 02) -> central -> relax -> back
   const R cT = c.cs2T;
   auto og = [&](int k) -> R { return rate_g<2, STD>(c, k); };
@@ -209,6 +436,7 @@ __device__ __forceinline__ void collide2d(R (&f)[kQ2], R (&g)[kQ2T], const CollP
   g[3] = R(0.5) * (m20 - m10);
   g[2] = R(0.5) * (m02 + m01);
   g[4] = R(0.5) * (m02 - m01);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -223,8 +451,9 @@ __device__ __forceinline__ R cpow(int m, R u, R cs2) {
   return m == 0 ? R(1) : (m == 1 ? -u : cs2 + u * u);
 }
 
-template <class R, int UP, bool STD = false>
-__device__ __forceinline__ void collide3d(R (&f)[kQ3], R (&g)[kQ3T], const CollParams<R>& c, R Tr,
+// QG: thermal lattice, D3Q7 (7, deviation form) or D3Q15 (15, plain populations).
+template <class R, int UP, bool STD = false, int QG = kQ3T>
+__device__ __forceinline__ void collide3d(R (&f)[kQ3], R (&g)[QG], const CollParams<R>& c, R Tr,
                                           Macros<R>* mac) {
   constexpr R cs2 = R(1) / R(3);
   const R rr = rho_ref(c);
@@ -238,7 +467,13 @@ __device__ __forceinline__ void collide3d(R (&f)[kQ3], R (&g)[kQ3T], const CollP
     if (D3_EY[a] != 0) jy += D3_EY[a] > 0 ? f[a] : -f[a];
     if (D3_EZ[a] != 0) jz += D3_EZ[a] > 0 ? f[a] : -f[a];
   }
-  const R dT = ((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + g[6]);
+  R dT = ((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + g[6]);
+  if constexpr (QG != kQ3T) {
+    R dc = R(0);
+#pragma unroll
+    for (int q = 7; q < QG; ++q) dc += g[q];
+    dT += dc;
+  }
   const R T = Tr + dT;
   const R rho = rr + drho;
   const R Fb = c.gbeta * (T - c.T0);
@@ -342,12 +577,24 @@ __device__ __forceinline__ void collide3d(R (&f)[kQ3], R (&g)[kQ3T], const CollP
     return dprod(rr, Rst(m1, n1, p1), w[I3(m1, n1, p1)], Rst(m2, n2, p2), w[I3(m2, n2, p2)]);
   };
   {
-    const R mv220 = (P(2, 0, 0, 0, 2, 0) + R(2) * P(1, 1, 0, 1, 1, 0) + rr2 * (R(2) * uxx * uyy) - rr * A * B * drho) * irho;
-    const R mv202 = (P(2, 0, 0, 0, 0, 2) + R(2) * P(1, 0, 1, 1, 0, 1) + rr2 * (R(2) * uxx * uzz) - rr * A * C * drho) * irho;
-    const R mv022 = (P(0, 2, 0, 0, 0, 2) + R(2) * P(0, 1, 1, 0, 1, 1) + rr2 * (R(2) * uyy * uzz) - rr * B * C * drho) * irho;
-    const R mv211 = (P(2, 0, 0, 0, 1, 1) + R(2) * P(1, 1, 0, 1, 0, 1) + rr2 * (R(2) * uxx * uyz) - rr * A * uyz * drho) * irho;
-    const R mv121 = (P(0, 2, 0, 1, 0, 1) + R(2) * P(1, 1, 0, 0, 1, 1) + rr2 * (R(2) * uyy * uxz) - rr * B * uxz * drho) * irho;
-    const R mv112 = (P(0, 0, 2, 1, 1, 0) + R(2) * P(0, 1, 1, 1, 0, 1) + rr2 * (R(2) * uzz * uxy) - rr * C * uxy * drho) * irho;
+    // FP: products of post-collision second-order moments; MCM: rho c_s^4 or 0
+    R mv220, mv202, mv022, mv211, mv121, mv112;
+    if (c.model != 0) {
+      constexpr R cs4 = cs2 * cs2;
+      mv220 = drho * cs4 - rr * (cs2 * (uxx + uyy) + uxx * uyy);
+      mv202 = drho * cs4 - rr * (cs2 * (uxx + uzz) + uxx * uzz);
+      mv022 = drho * cs4 - rr * (cs2 * (uyy + uzz) + uyy * uzz);
+      mv211 = -rr * A * uyz;
+      mv121 = -rr * B * uxz;
+      mv112 = -rr * C * uxy;
+    } else {
+      mv220 = (P(2, 0, 0, 0, 2, 0) + R(2) * P(1, 1, 0, 1, 1, 0) + rr2 * (R(2) * uxx * uyy) - rr * A * B * drho) * irho;
+      mv202 = (P(2, 0, 0, 0, 0, 2) + R(2) * P(1, 0, 1, 1, 0, 1) + rr2 * (R(2) * uxx * uzz) - rr * A * C * drho) * irho;
+      mv022 = (P(0, 2, 0, 0, 0, 2) + R(2) * P(0, 1, 1, 0, 1, 1) + rr2 * (R(2) * uyy * uzz) - rr * B * C * drho) * irho;
+      mv211 = (P(2, 0, 0, 0, 1, 1) + R(2) * P(1, 1, 0, 1, 0, 1) + rr2 * (R(2) * uxx * uyz) - rr * A * uyz * drho) * irho;
+      mv121 = (P(0, 2, 0, 1, 0, 1) + R(2) * P(1, 1, 0, 0, 1, 1) + rr2 * (R(2) * uyy * uxz) - rr * B * uxz * drho) * irho;
+      mv112 = (P(0, 0, 2, 1, 1, 0) + R(2) * P(0, 1, 1, 1, 0, 1) + rr2 * (R(2) * uzz * uxy) - rr * C * uxy * drho) * irho;
+    }
     w[I3(2, 2, 0)] = relax(w[I3(2, 2, 0)], mv220, om(17), s220);
     w[I3(2, 0, 2)] = relax(w[I3(2, 0, 2)], mv202, om(18), s202);
     w[I3(0, 2, 2)] = relax(w[I3(0, 2, 2)], mv022, om(19), s022);
@@ -355,35 +602,51 @@ __device__ __forceinline__ void collide3d(R (&f)[kQ3], R (&g)[kQ3T], const CollP
     w[I3(1, 2, 1)] = relax(w[I3(1, 2, 1)], mv121, om(21), s121);
     w[I3(1, 1, 2)] = relax(w[I3(1, 1, 2)], mv112, om(22), s112);
   }
-  // order 5: (2 / 5 rho) [...] from post-collision second x third order
+  // order 5: (2 / 5 rho) [...] from post-collision second x third order (FP);
+  // zero for MCM (deviation -rho_r kappa_rest)
   {
-    const R f25 = R(2) / R(5);
-    const R r122 = f25 * (Rst(0, 2, 0) * Rst(1, 0, 2) + Rst(0, 0, 2) * Rst(1, 2, 0) + R(4) * Rst(0, 1, 1) * Rst(1, 1, 1) +
-                          R(2) * (Rst(1, 0, 1) * Rst(0, 2, 1) + Rst(1, 1, 0) * Rst(0, 1, 2))) - Rst(1, 2, 2);
-    const R r212 = f25 * (Rst(2, 0, 0) * Rst(0, 1, 2) + Rst(0, 0, 2) * Rst(2, 1, 0) + R(4) * Rst(1, 0, 1) * Rst(1, 1, 1) +
-                          R(2) * (Rst(1, 1, 0) * Rst(1, 0, 2) + Rst(0, 1, 1) * Rst(2, 0, 1))) - Rst(2, 1, 2);
-    const R r221 = f25 * (Rst(2, 0, 0) * Rst(0, 2, 1) + Rst(0, 2, 0) * Rst(2, 0, 1) + R(4) * Rst(1, 1, 0) * Rst(1, 1, 1) +
-                          R(2) * (Rst(0, 1, 1) * Rst(2, 1, 0) + Rst(1, 0, 1) * Rst(1, 2, 0))) - Rst(2, 2, 1);
-    const R mv122 = (f25 * (P(0, 2, 0, 1, 0, 2) + P(0, 0, 2, 1, 2, 0) + R(4) * P(0, 1, 1, 1, 1, 1) +
-                            R(2) * (P(1, 0, 1, 0, 2, 1) + P(1, 1, 0, 0, 1, 2))) +
-                     rr2 * r122 - rr * Rst(1, 2, 2) * drho) * irho;
-    const R mv212 = (f25 * (P(2, 0, 0, 0, 1, 2) + P(0, 0, 2, 2, 1, 0) + R(4) * P(1, 0, 1, 1, 1, 1) +
-                            R(2) * (P(1, 1, 0, 1, 0, 2) + P(0, 1, 1, 2, 0, 1))) +
-                     rr2 * r212 - rr * Rst(2, 1, 2) * drho) * irho;
-    const R mv221 = (f25 * (P(2, 0, 0, 0, 2, 1) + P(0, 2, 0, 2, 0, 1) + R(4) * P(1, 1, 0, 1, 1, 1) +
-                            R(2) * (P(0, 1, 1, 2, 1, 0) + P(1, 0, 1, 1, 2, 0))) +
-                     rr2 * r221 - rr * Rst(2, 2, 1) * drho) * irho;
+    R mv122, mv212, mv221;
+    if (c.model != 0) {
+      mv122 = -rr * Rst(1, 2, 2);
+      mv212 = -rr * Rst(2, 1, 2);
+      mv221 = -rr * Rst(2, 2, 1);
+    } else {
+      const R f25 = R(2) / R(5);
+      const R r122 = f25 * (Rst(0, 2, 0) * Rst(1, 0, 2) + Rst(0, 0, 2) * Rst(1, 2, 0) + R(4) * Rst(0, 1, 1) * Rst(1, 1, 1) +
+                            R(2) * (Rst(1, 0, 1) * Rst(0, 2, 1) + Rst(1, 1, 0) * Rst(0, 1, 2))) - Rst(1, 2, 2);
+      const R r212 = f25 * (Rst(2, 0, 0) * Rst(0, 1, 2) + Rst(0, 0, 2) * Rst(2, 1, 0) + R(4) * Rst(1, 0, 1) * Rst(1, 1, 1) +
+                            R(2) * (Rst(1, 1, 0) * Rst(1, 0, 2) + Rst(0, 1, 1) * Rst(2, 0, 1))) - Rst(2, 1, 2);
+      const R r221 = f25 * (Rst(2, 0, 0) * Rst(0, 2, 1) + Rst(0, 2, 0) * Rst(2, 0, 1) + R(4) * Rst(1, 1, 0) * Rst(1, 1, 1) +
+                            R(2) * (Rst(0, 1, 1) * Rst(2, 1, 0) + Rst(1, 0, 1) * Rst(1, 2, 0))) - Rst(2, 2, 1);
+      mv122 = (f25 * (P(0, 2, 0, 1, 0, 2) + P(0, 0, 2, 1, 2, 0) + R(4) * P(0, 1, 1, 1, 1, 1) +
+                       R(2) * (P(1, 0, 1, 0, 2, 1) + P(1, 1, 0, 0, 1, 2))) +
+               rr2 * r122 - rr * Rst(1, 2, 2) * drho) * irho;
+      mv212 = (f25 * (P(2, 0, 0, 0, 1, 2) + P(0, 0, 2, 2, 1, 0) + R(4) * P(1, 0, 1, 1, 1, 1) +
+                       R(2) * (P(1, 1, 0, 1, 0, 2) + P(0, 1, 1, 2, 0, 1))) +
+               rr2 * r212 - rr * Rst(2, 1, 2) * drho) * irho;
+      mv221 = (f25 * (P(2, 0, 0, 0, 2, 1) + P(0, 2, 0, 2, 0, 1) + R(4) * P(1, 1, 0, 1, 1, 1) +
+                       R(2) * (P(0, 1, 1, 2, 1, 0) + P(1, 0, 1, 1, 2, 0))) +
+               rr2 * r221 - rr * Rst(2, 2, 1) * drho) * irho;
+    }
     w[I3(1, 2, 2)] = relax(w[I3(1, 2, 2)], mv122, om(23), s122);
     w[I3(2, 1, 2)] = relax(w[I3(2, 1, 2)], mv212, om(24), s212);
     w[I3(2, 2, 1)] = relax(w[I3(2, 2, 1)], mv221, om(25), s221);
   }
-  // order 6: (1 / 3 rho) [...] from post-collision second x fourth order
+  // order 6: (1 / 3 rho) [...] from post-collision second x fourth order (FP);
+  // rho c_s^6 for MCM
   {
-    const R f13 = R(1) / R(3);
-    const R mv222 = (f13 * (P(2, 0, 0, 0, 2, 2) + P(0, 2, 0, 2, 0, 2) + P(0, 0, 2, 2, 2, 0) +
-                            R(4) * (P(1, 1, 0, 1, 1, 2) + P(1, 0, 1, 1, 2, 1) + P(0, 1, 1, 2, 1, 1))) +
-                     rr2 * (R(4) / R(3)) * (uxx * uyy * C + uxx * uzz * B + uyy * uzz * A) -
-                     rr * A * B * C * drho) * irho;
+    R mv222;
+    if (c.model != 0) {
+      constexpr R cs4 = cs2 * cs2;
+      mv222 = drho * (cs4 * cs2) -
+              rr * (cs4 * (uxx + uyy + uzz) + cs2 * (uxx * uyy + uxx * uzz + uyy * uzz) + uxx * uyy * uzz);
+    } else {
+      const R f13 = R(1) / R(3);
+      mv222 = (f13 * (P(2, 0, 0, 0, 2, 2) + P(0, 2, 0, 2, 0, 2) + P(0, 0, 2, 2, 2, 0) +
+                      R(4) * (P(1, 1, 0, 1, 1, 2) + P(1, 0, 1, 1, 2, 1) + P(0, 1, 1, 2, 1, 1))) +
+               rr2 * (R(4) / R(3)) * (uxx * uyy * C + uxx * uzz * B + uyy * uzz * A) - rr * A * B * C * drho) *
+              irho;
+    }
     w[I3(2, 2, 2)] = relax(w[I3(2, 2, 2)], mv222, om(26), s222);
   }
 
@@ -409,6 +672,10 @@ __device__ __forceinline__ void collide3d(R (&f)[kQ3], R (&g)[kQ3T], const CollP
       shift_inv(w[I3(0, ey + 1, ez + 1)], w[I3(1, ey + 1, ez + 1)], w[I3(2, ey + 1, ez + 1)], ux,
                 f[d3_index(-1, ey, ez)], f[d3_index(0, ey, ez)], f[d3_index(1, ey, ez)]);
 
+  if constexpr (QG != kQ3T) {
+    thermal_d3q15<R, STD>(g, ux, uy, uz, T, c);
+    return;
+  } else {
   // thermal D3Q7: links 1/2 = +-x, 3/4 = +-y, 5/6 = +-z
   const R cT = c.cs2T;
   auto og = [&](int k) -> R { return rate_g<3, STD>(c, k); };
@@ -435,6 +702,7 @@ __device__ __forceinline__ void collide3d(R (&f)[kQ3], R (&g)[kQ3T], const CollP
   g[4] = R(0.5) * (m020 - m010);
   g[5] = R(0.5) * (m002 + m001);
   g[6] = R(0.5) * (m002 - m001);
+  }
 }
 
 }  // namespace fpc

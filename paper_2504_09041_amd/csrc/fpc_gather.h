@@ -27,23 +27,68 @@
 namespace fpc {
 namespace stream {
 
-struct Lat2 {
+// Lattice pairs: fluid links (ex, ey, ez, opp, w) and thermal links (tex,
+// tey, tez, topp, wT with the runtime diffusion parameter c = c^_s^2).
+struct Lat2 {  // D2Q9 + D2Q5
   static constexpr int D = 2, Qf = kQ2, Qg = kQ2T;
   static constexpr int ex(int a) { return D2_EX[a]; }
   static constexpr int ey(int a) { return D2_EY[a]; }
   static constexpr int ez(int) { return 0; }
   static constexpr int opp(int a) { return D2_OPP[a]; }
   static constexpr double w(int a) { return w2(a); }
+  static constexpr int tex(int a) { return D2_EX[a]; }
+  static constexpr int tey(int a) { return D2_EY[a]; }
+  static constexpr int tez(int) { return 0; }
+  static constexpr int topp(int a) { return D2_OPP[a]; }
+  template <class R>
+  static __device__ __forceinline__ R wT(int a, R c) { return a == 0 ? R(1) - R(2) * c : R(0.5) * c; }
 };
 
-struct Lat3 {
+struct Lat2T9 : Lat2 {  // D2Q9 + D2Q9
+  static constexpr int Qg = kQ2;
+  template <class R>
+  static __device__ __forceinline__ R wT(int a, R c) {
+    const R w0 = R(1) - c, w1 = R(0.5) * c;
+    return (D2_EX[a] == 0 ? w0 : w1) * (D2_EY[a] == 0 ? w0 : w1);
+  }
+};
+
+struct Lat3 {  // D3Q27 + D3Q7
   static constexpr int D = 3, Qf = kQ3, Qg = kQ3T;
   static constexpr int ex(int a) { return D3_EX[a]; }
   static constexpr int ey(int a) { return D3_EY[a]; }
   static constexpr int ez(int a) { return D3_EZ[a]; }
   static constexpr int opp(int a) { return d3_opp(a); }
   static constexpr double w(int a) { return w3(a); }
+  static constexpr int tex(int a) { return D3_EX[a]; }
+  static constexpr int tey(int a) { return D3_EY[a]; }
+  static constexpr int tez(int a) { return D3_EZ[a]; }
+  static constexpr int topp(int a) { return d3_opp(a); }
+  template <class R>
+  static __device__ __forceinline__ R wT(int a, R c) { return a == 0 ? R(1) - R(3) * c : R(0.5) * c; }
 };
+
+struct Lat3T15 : Lat3 {  // D3Q27 + D3Q15
+  static constexpr int Qg = kQ15;
+  static constexpr int tex(int a) { return T15_EX[a]; }
+  static constexpr int tey(int a) { return T15_EY[a]; }
+  static constexpr int tez(int a) { return T15_EZ[a]; }
+  static constexpr int topp(int a) { return t15_opp(a); }
+  template <class R>
+  static __device__ __forceinline__ R wT(int a, R c) {
+    return a == 0 ? R(1) - R(3) * c + R(2) * c * c : (a <= 6 ? R(0.5) * (c - c * c) : R(0.125) * c * c);
+  }
+};
+
+// link components of the fluid (TH = false) or thermal (TH = true) lattice
+template <class L, bool TH>
+constexpr int lex(int a) { return TH ? L::tex(a) : L::ex(a); }
+template <class L, bool TH>
+constexpr int ley(int a) { return TH ? L::tey(a) : L::ey(a); }
+template <class L, bool TH>
+constexpr int lez(int a) { return TH ? L::tez(a) : L::ez(a); }
+template <class L, bool TH>
+constexpr int lopp(int a) { return TH ? L::topp(a) : L::opp(a); }
 
 __device__ __forceinline__ unsigned node_of(int x, int y, int z, int nx, int ny) {
   return ((unsigned)z * (unsigned)ny + (unsigned)y) * (unsigned)nx + (unsigned)x;
@@ -212,19 +257,19 @@ struct Edges {
     }
   }
 
-  template <int A>
+  template <int A, bool TH>
   static constexpr bool checked() {
-    return (CX && L::ex(A) != 0) || (CY && L::ey(A) != 0) || (CZ && L::ez(A) != 0);
+    return (CX && lex<L, TH>(A) != 0) || (CY && ley<L, TH>(A) != 0) || (CZ && lez<L, TH>(A) != 0);
   }
-  template <int A>
+  template <int A, bool TH>
   __device__ __forceinline__ long long shift() const {
-    return (long long)L::ex(A) + (long long)L::ey(A) * a.nx + (long long)L::ez(A) * a.nx * a.ny;
+    return (long long)lex<L, TH>(A) + (long long)ley<L, TH>(A) * a.nx + (long long)lez<L, TH>(A) * a.nx * a.ny;
   }
   // Checked link A: the wrapped source index (used with shift()) and the
   // axes on which the link meets a wall.
-  template <int A>
+  template <int A, bool TH>
   __device__ __forceinline__ unsigned source(bool& wx, bool& wy, bool& wz) const {
-    constexpr int ex = L::ex(A), ey = L::ey(A), ez = L::ez(A);
+    constexpr int ex = lex<L, TH>(A), ey = ley<L, TH>(A), ez = lez<L, TH>(A);
     constexpr bool cx = CX && ex != 0, cy = CY && ey != 0, cz = CZ && ez != 0;
     const bool ox = cx && (ex > 0 ? xlo : xhi);
     const bool oy = cy && (ey > 0 ? ylo : yhi);
@@ -238,9 +283,9 @@ struct Edges {
     return idx;
   }
   // only periodic wraps are possible on this link (no wall test needed)
-  template <int A>
+  template <int A, bool TH>
   static constexpr bool wrap_only() {
-    return PX && !(CY && L::ey(A) != 0) && !(CZ && L::ez(A) != 0);
+    return PX && !(CY && ley<L, TH>(A) != 0) && !(CZ && lez<L, TH>(A) != 0);
   }
 };
 
@@ -260,17 +305,18 @@ struct Gather {
   __device__ __forceinline__ Gather(const StepArgs<R>& a_, const M& m_, int x_, int y_, int z_, unsigned node_, R Tr_)
       : a(a_), m(m_), e(a_, x_, y_, z_, node_), x(x_), y(y_), z(z_), Tr(Tr_) {}
 
-  // Incoming population of link A of one distribution whose planes start at
-  // QBASE (fluid: 0, thermal: Qf), pulled or bounced; reports per axis
-  // whether the link met a wall there.
-  template <int A, int QBASE>
+  // Incoming population of link A of the fluid (TH = false, planes from 0)
+  // or thermal (TH = true, planes from Qf) distribution, pulled or bounced;
+  // reports per axis whether the link met a wall there.
+  template <int A, bool TH>
   __device__ __forceinline__ R pull(bool& wx, bool& wy, bool& wz) const {
-    const long long sh = e.template shift<A>();
-    if (!E::template checked<A>()) return m.load(QBASE + A, sh, e.node);
-    const unsigned idx = e.template source<A>(wx, wy, wz);
-    if (E::template wrap_only<A>()) return m.load(QBASE + A, sh, idx);
+    constexpr int QBASE = TH ? L::Qf : 0;
+    const long long sh = e.template shift<A, TH>();
+    if (!E::template checked<A, TH>()) return m.load(QBASE + A, sh, e.node);
+    const unsigned idx = e.template source<A, TH>(wx, wy, wz);
+    if (E::template wrap_only<A, TH>()) return m.load(QBASE + A, sh, idx);
     const bool wall = wx || wy || wz;
-    return m.load_sel(wall, QBASE + L::opp(A), e.node, QBASE + A, sh, idx);
+    return m.load_sel(wall, QBASE + lopp<L, TH>(A), e.node, QBASE + A, sh, idx);
   }
 
   template <int F>
@@ -283,9 +329,9 @@ struct Gather {
   template <int A>
   __device__ __forceinline__ R f() const {
     bool wx = false, wy = false, wz = false;
-    R v = pull<A, 0>(wx, wy, wz);
+    R v = pull<A, false>(wx, wy, wz);
     constexpr int ex = L::ex(A), ey = L::ey(A), ez = L::ez(A);
-    if (E::template checked<A>()) {
+    if (E::template checked<A, false>()) {
       // moving wall: only when exactly one face is crossed
       constexpr int FX = ex > 0 ? 0 : 1, FY = ey > 0 ? 2 : 3, FZ = ez > 0 ? 4 : 5;
       const int nc = (int)wx + (int)wy + (int)wz;
@@ -298,29 +344,54 @@ struct Gather {
     return v;
   }
 
-  // Thermal link A (axis links: at most one face can be crossed).
+  // Dirichlet temperature of face F at this node (uniform or per-node profile)
+  template <int F>
+  __device__ __forceinline__ double wall_T() const {
+    constexpr int k = F >> 1;
+    double Tw = a.face[F].Tw;
+    if (a.face[F].Tprof) {
+      const size_t t = k == 0 ? (size_t)z * a.ny + y : (k == 1 ? (size_t)z * a.nx + x : (size_t)y * a.nx + x);
+      Tw = a.face[F].Tprof[t];
+    }
+    return Tw;
+  }
+
+  // Thermal link A.  A wall link is bounced back; if any face it crosses is a
+  // Dirichlet face it is anti-bounced toward the mean of those faces'
+  // temperatures (axis links cross one face; diagonal links of D2Q9 / D3Q15
+  // can cross two or three at edges and corners).
   template <int A>
   __device__ __forceinline__ R g() const {
     bool wx = false, wy = false, wz = false;
-    R v = pull<A, L::Qf>(wx, wy, wz);
+    R v = pull<A, true>(wx, wy, wz);
     if (A == 0) return v;
-    constexpr int ex = L::ex(A), ey = L::ey(A), ez = L::ez(A);
-    constexpr int F = ex > 0 ? 0 : (ex < 0 ? 1 : (ey > 0 ? 2 : (ey < 0 ? 3 : (ez > 0 ? 4 : 5))));
-    constexpr int k = F >> 1;
-    constexpr int ea = ex + ey + ez;  // axis link: the one non-zero component
-    const bool wall = E::template checked<A>() && (wx || wy || wz);
+    constexpr int ex = L::tex(A), ey = L::tey(A), ez = L::tez(A);
+    constexpr int FX = ex > 0 ? 0 : 1, FY = ey > 0 ? 2 : 3, FZ = ez > 0 ? 4 : 5;
+    constexpr int nax = (ex != 0) + (ey != 0) + (ez != 0);
+    const R wa = L::template wT<R>(A, a.c.cs2T);
+    const bool wall = E::template checked<A, true>() && (wx || wy || wz);
     if (wall) {
-      if (a.face[F].dirichlet) {
-        double Tw = a.face[F].Tw;
-        if (a.face[F].Tprof) {
-          const size_t t = k == 0 ? (size_t)z * a.ny + y : (k == 1 ? (size_t)z * a.nx + x : (size_t)y * a.nx + x);
-          Tw = a.face[F].Tprof[t];
-        }
-        v = -v + a.c.cs2T * (R(Tw) - Tr);  // 2 w^T_a = c^_s^2 on axis links
+      double tsum = 0.0;
+      int nd = 0;
+      if (ex != 0 && wx && a.face[FX].dirichlet) {
+        tsum += wall_T<FX>();
+        ++nd;
+      }
+      if (ey != 0 && wy && a.face[FY].dirichlet) {
+        tsum += wall_T<FY>();
+        ++nd;
+      }
+      if (ez != 0 && wz && a.face[FZ].dirichlet) {
+        tsum += wall_T<FZ>();
+        ++nd;
+      }
+      if (nd > 0) {
+        const double Tw = nax == 1 ? tsum : tsum / nd;
+        v = -v + R(2) * wa * (R(Tw) - Tr);  // 2 w^T_a T_w, in storage form
       }
     } else if constexpr (kDeviations<R>) {
       // the value was stored against the source node's reference Tr(x - e_A)
-      v -= R(0.5) * a.c.cs2T * (R(ea) * a.Tg[k]);
+      v -= wa * (R(ex) * a.Tg[0] + R(ey) * a.Tg[1] + R(ez) * a.Tg[2]);
     }
     return v;
   }
@@ -334,18 +405,17 @@ __device__ __forceinline__ void gather(const StepArgs<R>& a, const M& m, int x, 
     f[0] = p.template f<0>(); f[1] = p.template f<1>(); f[2] = p.template f<2>();
     f[3] = p.template f<3>(); f[4] = p.template f<4>(); f[5] = p.template f<5>();
     f[6] = p.template f<6>(); f[7] = p.template f<7>(); f[8] = p.template f<8>();
-    g[0] = p.template g<0>(); g[1] = p.template g<1>(); g[2] = p.template g<2>();
-    g[3] = p.template g<3>(); g[4] = p.template g<4>();
   } else {
 #define FPC_F(A) f[A] = p.template f<A>();
     FPC_F(0) FPC_F(1) FPC_F(2) FPC_F(3) FPC_F(4) FPC_F(5) FPC_F(6) FPC_F(7) FPC_F(8)
     FPC_F(9) FPC_F(10) FPC_F(11) FPC_F(12) FPC_F(13) FPC_F(14) FPC_F(15) FPC_F(16) FPC_F(17)
     FPC_F(18) FPC_F(19) FPC_F(20) FPC_F(21) FPC_F(22) FPC_F(23) FPC_F(24) FPC_F(25) FPC_F(26)
 #undef FPC_F
-    g[0] = p.template g<0>(); g[1] = p.template g<1>(); g[2] = p.template g<2>();
-    g[3] = p.template g<3>(); g[4] = p.template g<4>(); g[5] = p.template g<5>();
-    g[6] = p.template g<6>();
   }
+#define FPC_G(A) if constexpr (A < L::Qg) g[A] = p.template g<A>();
+  FPC_G(0) FPC_G(1) FPC_G(2) FPC_G(3) FPC_G(4) FPC_G(5) FPC_G(6) FPC_G(7)
+  FPC_G(8) FPC_G(9) FPC_G(10) FPC_G(11) FPC_G(12) FPC_G(13) FPC_G(14)
+#undef FPC_G
 }
 
 }  // namespace stream

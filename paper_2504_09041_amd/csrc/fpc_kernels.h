@@ -48,11 +48,12 @@ __device__ __forceinline__ R tref(const StepArgs<R>& a, int x, int y, int z) {
   return a.T_o + (a.Tg[0] * R(x) + a.Tg[1] * R(y) + a.Tg[2] * R(z));
 }
 // Launchers of the fused step (defined in fpc_step.hip).
+// tk: thermal lattice, 0 = D2Q5 / D3Q7, 1 = D2Q9 / D3Q15 (FP64 only).
 // mode: 0 = step (pull from args.src), 1 = init (equilibrium from T_init).
 template <class R>
-hipError_t launch_step2d(const StepArgs<R>& a, int up, const double* T_init, int mode, hipStream_t s);
+hipError_t launch_step2d(const StepArgs<R>& a, int up, int tk, const double* T_init, int mode, hipStream_t s);
 template <class R>
-hipError_t launch_step3d(const StepArgs<R>& a, int up, const double* T_init, int mode, hipStream_t s);
+hipError_t launch_step3d(const StepArgs<R>& a, int up, int tk, const double* T_init, int mode, hipStream_t s);
 
 // Adjoint kernels (fpc_adjoint.hip).  `a.src` is S_{n-1} (adjoint step) or
 // unused (adjoint of the initial collision).

@@ -17,15 +17,29 @@ namespace {
 
 constexpr int kBlock = 256;
 
-__device__ __forceinline__ double wfluid(int lattice, int q) { return lattice == 1 ? w2(q) : w3(q); }
-
-__device__ __forceinline__ double wtherm(int d, double cs2T, int q) {
-  return q == 0 ? 1.0 - d * cs2T : 0.5 * cs2T;
+// lattice pair codes: 1 D2Q9+D2Q5, 2 D3Q27+D3Q7, 3 D2Q9+D2Q9, 4 D3Q27+D3Q15
+__device__ __forceinline__ bool is2d(int lattice) { return lattice == 1 || lattice == 3; }
+__device__ __forceinline__ int qf_of(int lattice) { return is2d(lattice) ? kQ2 : kQ3; }
+__device__ __forceinline__ int qg_of(int lattice) {
+  return lattice == 1 ? kQ2T : (lattice == 2 ? kQ3T : (lattice == 3 ? kQ2 : kQ15));
 }
 
-__device__ __forceinline__ int ex_of(int lattice, int q) { return lattice == 1 ? D2_EX[q] : D3_EX[q]; }
-__device__ __forceinline__ int ey_of(int lattice, int q) { return lattice == 1 ? D2_EY[q] : D3_EY[q]; }
-__device__ __forceinline__ int ez_of(int lattice, int q) { return lattice == 1 ? 0 : D3_EZ[q]; }
+__device__ __forceinline__ double wfluid(int lattice, int q) { return is2d(lattice) ? w2(q) : w3(q); }
+
+// thermal rest weight of link q (c = c^_s^2)
+__device__ __forceinline__ double wtherm(int lattice, double c, int q) {
+  if (lattice == 1) return q == 0 ? 1.0 - 2.0 * c : 0.5 * c;
+  if (lattice == 2) return q == 0 ? 1.0 - 3.0 * c : 0.5 * c;
+  if (lattice == 3) {
+    const double w0 = 1.0 - c, w1 = 0.5 * c;
+    return (D2_EX[q] == 0 ? w0 : w1) * (D2_EY[q] == 0 ? w0 : w1);
+  }
+  return q == 0 ? 1.0 - 3.0 * c + 2.0 * c * c : (q <= 6 ? 0.5 * (c - c * c) : 0.125 * c * c);
+}
+
+__device__ __forceinline__ int ex_of(int lattice, int q) { return is2d(lattice) ? D2_EX[q] : D3_EX[q]; }
+__device__ __forceinline__ int ey_of(int lattice, int q) { return is2d(lattice) ? D2_EY[q] : D3_EY[q]; }
+__device__ __forceinline__ int ez_of(int lattice, int q) { return is2d(lattice) ? 0 : D3_EZ[q]; }
 
 // thermal storage reference at a node
 __device__ __forceinline__ double tref_node(const StateDesc& d, size_t node) {
@@ -41,8 +55,8 @@ __device__ __forceinline__ double ld(const StateDesc& d, int q, size_t node) {
 // FP64 macros of one node (rho, u[3], T).
 template <class R>
 __device__ void node_macros(const StateDesc& d, size_t node, double& rho, double u[3], double& T) {
-  const int Qf = d.lattice == 1 ? kQ2 : kQ3;
-  const int Qg = d.lattice == 1 ? kQ2T : kQ3T;
+  const int Qf = qf_of(d.lattice);
+  const int Qg = qg_of(d.lattice);
   double s = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
   for (int q = 0; q < Qf; ++q) {
     const double v = ld<R>(d, q, node);
@@ -72,7 +86,7 @@ __global__ void __launch_bounds__(kBlock) macros_kernel(StateDesc d, double* rho
   if (rho) rho[node] = r;
   if (T) T[node] = t;
   if (u) {
-    const int dim = d.lattice == 1 ? 2 : 3;
+    const int dim = is2d(d.lattice) ? 2 : 3;
     for (int i = 0; i < dim; ++i) u[i * N + node] = uu[i];
   }
 }
@@ -82,13 +96,12 @@ __global__ void __launch_bounds__(kBlock) export_kernel(StateDesc d, double* dst
   const size_t N = (size_t)d.nx * d.ny * d.nz;
   const size_t node = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (node >= N) return;
-  const int Qf = d.lattice == 1 ? kQ2 : kQ3;
-  const int Qg = d.lattice == 1 ? kQ2T : kQ3T;
-  const int dim = d.lattice == 1 ? 2 : 3;
+  const int Qf = qf_of(d.lattice);
+  const int Qg = qg_of(d.lattice);
   for (int q = 0; q < Qf; ++q) dst[q * N + node] = ld<R>(d, q, node) + wfluid(d.lattice, q) * d.rho_r;
   const double tr = tref_node(d, node);
   for (int q = 0; q < Qg; ++q)
-    dst[(Qf + q) * N + node] = ld<R>(d, Qf + q, node) + wtherm(dim, d.cs2T, q) * tr;
+    dst[(Qf + q) * N + node] = ld<R>(d, Qf + q, node) + wtherm(d.lattice, d.cs2T, q) * tr;
 }
 
 template <class R>
@@ -96,13 +109,12 @@ __global__ void __launch_bounds__(kBlock) import_kernel(StateDesc d, R* out, con
   const size_t N = (size_t)d.nx * d.ny * d.nz;
   const size_t node = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (node >= N) return;
-  const int Qf = d.lattice == 1 ? kQ2 : kQ3;
-  const int Qg = d.lattice == 1 ? kQ2T : kQ3T;
-  const int dim = d.lattice == 1 ? 2 : 3;
+  const int Qf = qf_of(d.lattice);
+  const int Qg = qg_of(d.lattice);
   for (int q = 0; q < Qf; ++q) out[q * d.plane + node] = (R)(src[q * N + node] - wfluid(d.lattice, q) * d.rho_r);
   const double tr = tref_node(d, node);
   for (int q = 0; q < Qg; ++q)
-    out[(Qf + q) * d.plane + node] = (R)(src[(Qf + q) * N + node] - wtherm(dim, d.cs2T, q) * tr);
+    out[(Qf + q) * d.plane + node] = (R)(src[(Qf + q) * N + node] - wtherm(d.lattice, d.cs2T, q) * tr);
 }
 
 // Deterministic block reduction: sum (op 0) or max (op 1) over kBlock values.
@@ -169,8 +181,8 @@ __global__ void __launch_bounds__(kBlock) diag_face_kernel(StateDesc d, int face
     c[t1] = (int)(i % n[t1]);
     c[t2] = (int)(i / n[t1]);
     const int L = n[k];
-    const int Qf = d.lattice == 1 ? kQ2 : kQ3;
-    const int Qg = d.lattice == 1 ? kQ2T : kQ3T;
+    const int Qf = qf_of(d.lattice);
+    const int Qg = qg_of(d.lattice);
     double Tl[2];
     for (int layer = 0; layer < 2; ++layer) {
       c[k] = (face & 1) ? L - 1 - layer : layer;

@@ -1,13 +1,17 @@
 // Lattice tables of the GPU path (compile-time constants).
 //
 // Population order follows the paper: D2Q9 as in Eqs. (ex), (ey) of Sec. 4.2,
-// D3Q27 as in Sec. 5.2.  The thermal lattices D2Q5 / D3Q7 are the first five /
-// seven vectors of those sets (rest, then the axis links).
+// D3Q27 as in Sec. 5.2, D3Q15 as in Sec. 5.4.  The thermal lattices D2Q5 /
+// D3Q7 are the first five / seven vectors of D2Q9 / D3Q27 (rest, then the
+// axis links); the paper's own thermal lattices are D2Q9 and D3Q15.
 //
 // Weights are those of the rest state (central moments equal to their
-// attractors at rho = 1, u = 0): the product of the 1D weights {2/3, 1/6, 1/6}
-// for D2Q9 / D3Q27, and {1 - d c^2, c^2 / 2} for the thermal lattices, with
-// c^2 the runtime diffusion parameter.
+// attractors at rho = 1 or T = 1, u = 0): the product of the 1D weights
+// {2/3, 1/6, 1/6} for D2Q9 / D3Q27; for the thermal lattices, with c the
+// runtime diffusion parameter c^_s^2,
+//   D2Q5 / D3Q7: {1 - d c, c / 2},
+//   D2Q9:        product of the 1D weights {1 - c, c / 2, c / 2},
+//   D3Q15:       rest 1 - 3c + 2c^2, axis (c - c^2) / 2, corner c^2 / 8.
 #pragma once
 
 namespace fpc {
@@ -37,6 +41,19 @@ constexpr int d3_index(int ex, int ey, int ez) {
 }
 constexpr int d3_opp(int a) { return d3_index(-D3_EX[a], -D3_EY[a], -D3_EZ[a]); }
 constexpr int kQ3T = 7;  // D3Q7: first seven D3Q27 links
+
+// D3Q15 in the paper's order: rest, +-x, +-y, +-z, then the eight corners
+// (x sign fastest, then y, then z from +1 to -1).
+constexpr int kQ15 = 15;
+constexpr int T15_EX[kQ15] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1};
+constexpr int T15_EY[kQ15] = {0, 0, 0, 1, -1, 0, 0, 1, 1, -1, -1, 1, 1, -1, -1};
+constexpr int T15_EZ[kQ15] = {0, 0, 0, 0, 0, 1, -1, 1, 1, 1, 1, -1, -1, -1, -1};
+constexpr int t15_index(int ex, int ey, int ez) {
+  for (int a = 0; a < kQ15; ++a)
+    if (T15_EX[a] == ex && T15_EY[a] == ey && T15_EZ[a] == ez) return a;
+  return -1;
+}
+constexpr int t15_opp(int a) { return t15_index(-T15_EX[a], -T15_EY[a], -T15_EZ[a]); }
 
 // 1D weight of a link component e in {-1, 0, 1} (c_s^2 = 1/3).
 constexpr double w1d(int e) { return e == 0 ? 2.0 / 3.0 : 1.0 / 6.0; }

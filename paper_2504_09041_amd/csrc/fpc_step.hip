@@ -39,9 +39,9 @@ template <class L, class R, class M, int UP, bool NT, bool STD>
 __device__ __forceinline__ void collide_store(const StepArgs<R>& a, const M& m, unsigned node, R Tr, R (&f)[L::Qf],
                                               R (&g)[L::Qg]) {
   if constexpr (L::D == 2)
-    collide2d<R, UP, STD>(f, g, a.c, Tr, (Macros<R>*)nullptr);
+    collide2d<R, UP, STD, L::Qg>(f, g, a.c, Tr, (Macros<R>*)nullptr);
   else
-    collide3d<R, UP, STD>(f, g, a.c, Tr, (Macros<R>*)nullptr);
+    collide3d<R, UP, STD, L::Qg>(f, g, a.c, Tr, (Macros<R>*)nullptr);
   auto cur = m.cursor(node);
 #pragma unroll
   for (int q = 0; q < L::Qf; ++q) m.template store_next<NT>(cur, f[q]);
@@ -94,9 +94,8 @@ __global__ void __launch_bounds__(256) init_kernel(StepArgs<R> a, const double* 
   for (int q = 0; q < L::Qf; ++q) f[q] = R(L::w(q)) * drw;
   const R Tr = tref(a, x, y, z);
   const R dT = R(T_init[node]) - Tr;
-  g[0] = (R(1) - R(L::D) * a.c.cs2T) * dT;
 #pragma unroll
-  for (int q = 1; q < L::Qg; ++q) g[q] = R(0.5) * a.c.cs2T * dT;
+  for (int q = 0; q < L::Qg; ++q) g[q] = L::template wT<R>(q, a.c.cs2T) * dT;
   collide_store<L, R, Glob64<R>, UP, false, false>(a, m, node, Tr, f, g);
 }
 
@@ -104,13 +103,12 @@ __global__ void __launch_bounds__(256) init_kernel(StepArgs<R> a, const double* 
 // slots share one rate, the thermal first-order slots share one rate, and
 // every other slot in use relaxes at exactly 1.
 template <class R>
-bool standard_rates(const StepArgs<R>& a, int D) {
+bool standard_rates(const StepArgs<R>& a, int D, int Qg) {
   const int Qf = D == 2 ? kQ2 : kQ3;
   for (int k = 1; k < Qf; ++k) {
     const bool nu = D == 2 ? (k == 4 || k == 5) : (k == 4 || k == 5 || k == 6 || k == 8 || k == 9);
     if (nu ? a.c.om[k] != a.c.om[4] : a.c.om[k] != R(1)) return false;
   }
-  const int Qg = D == 2 ? kQ2T : kQ3T;
   for (int k = 1; k < Qg; ++k) {
     const bool first = k <= D;
     if (first ? a.c.omg[k] != a.c.omg[1] : a.c.omg[k] != R(1)) return false;
@@ -130,7 +128,7 @@ hipError_t launch_up(const StepArgs<R>& a, const double* T_init, int mode, hipSt
   }
   const double state_bytes = (double)a.plane * (L::Qf + L::Qg) * sizeof(R);
   const bool nt = state_bytes > FPC_NT_MIB * 1024.0 * 1024.0;
-  const bool std_rates = standard_rates(a, L::D);
+  const bool std_rates = standard_rates(a, L::D, L::Qg);
   if (state_bytes < 4294967296.0) {
     const unsigned tb = (unsigned)state_bytes;
     if (nt) {
@@ -155,23 +153,38 @@ hipError_t launch_up(const StepArgs<R>& a, const double* T_init, int mode, hipSt
 
 }  // namespace
 
+// tk: thermal lattice, 0 = D2Q5 / D3Q7, 1 = the paper's D2Q9 / D3Q15 (FP64 only)
 template <class R>
-hipError_t launch_step2d(const StepArgs<R>& a, int up, const double* T_init, int mode, hipStream_t s) {
-  return up == 0 ? launch_up<Lat2, R, 0>(a, T_init, mode, s) : launch_up<Lat2, R, 1>(a, T_init, mode, s);
+hipError_t launch_step2d(const StepArgs<R>& a, int up, int tk, const double* T_init, int mode, hipStream_t s) {
+  if (tk == 0)
+    return up == 0 ? launch_up<Lat2, R, 0>(a, T_init, mode, s) : launch_up<Lat2, R, 1>(a, T_init, mode, s);
+  if constexpr (sizeof(R) == 8)
+    return up == 0 ? launch_up<Lat2T9, R, 0>(a, T_init, mode, s) : launch_up<Lat2T9, R, 1>(a, T_init, mode, s);
+  return hipErrorInvalidValue;
 }
 
 template <class R>
-hipError_t launch_step3d(const StepArgs<R>& a, int up, const double* T_init, int mode, hipStream_t s) {
-  switch (up) {
-    case 0: return launch_up<Lat3, R, 0>(a, T_init, mode, s);
-    case 1: return launch_up<Lat3, R, 1>(a, T_init, mode, s);
-    default: return launch_up<Lat3, R, 2>(a, T_init, mode, s);
+hipError_t launch_step3d(const StepArgs<R>& a, int up, int tk, const double* T_init, int mode, hipStream_t s) {
+  if (tk == 0) {
+    switch (up) {
+      case 0: return launch_up<Lat3, R, 0>(a, T_init, mode, s);
+      case 1: return launch_up<Lat3, R, 1>(a, T_init, mode, s);
+      default: return launch_up<Lat3, R, 2>(a, T_init, mode, s);
+    }
   }
+  if constexpr (sizeof(R) == 8) {
+    switch (up) {
+      case 0: return launch_up<Lat3T15, R, 0>(a, T_init, mode, s);
+      case 1: return launch_up<Lat3T15, R, 1>(a, T_init, mode, s);
+      default: return launch_up<Lat3T15, R, 2>(a, T_init, mode, s);
+    }
+  }
+  return hipErrorInvalidValue;
 }
 
-template hipError_t launch_step2d<double>(const StepArgs<double>&, int, const double*, int, hipStream_t);
-template hipError_t launch_step2d<float>(const StepArgs<float>&, int, const double*, int, hipStream_t);
-template hipError_t launch_step3d<double>(const StepArgs<double>&, int, const double*, int, hipStream_t);
-template hipError_t launch_step3d<float>(const StepArgs<float>&, int, const double*, int, hipStream_t);
+template hipError_t launch_step2d<double>(const StepArgs<double>&, int, int, const double*, int, hipStream_t);
+template hipError_t launch_step2d<float>(const StepArgs<float>&, int, int, const double*, int, hipStream_t);
+template hipError_t launch_step3d<double>(const StepArgs<double>&, int, int, const double*, int, hipStream_t);
+template hipError_t launch_step3d<float>(const StepArgs<float>&, int, int, const double*, int, hipStream_t);
 
 }  // namespace fpc

@@ -14,9 +14,13 @@ import torch
 from . import _abi as A
 
 FACE_INDEX = {"-x": 0, "+x": 1, "-y": 2, "+y": 3, "-z": 4, "+z": 5}
-LATTICES = {"D2Q9-D2Q5": A.FPC_D2Q9_D2Q5, "D3Q27-D3Q7": A.FPC_D3Q27_D3Q7}
+LATTICES = {"D2Q9-D2Q5": A.FPC_D2Q9_D2Q5, "D3Q27-D3Q7": A.FPC_D3Q27_D3Q7,
+            "D2Q9-D2Q9": A.FPC_D2Q9_D2Q9, "D3Q27-D3Q15": A.FPC_D3Q27_D3Q15}
 PRECISIONS = {"f64": A.FPC_FP64, "f32dev": A.FPC_FP32_DEV}
-Q = {A.FPC_D2Q9_D2Q5: (9, 5, 2), A.FPC_D3Q27_D3Q7: (27, 7, 3)}
+MODELS = {"FP": A.FPC_MODEL_FP, "MCM": A.FPC_MODEL_MCM}
+THERMAL_OPTIONS = {"A": A.FPC_THERMAL_OPTION_A, "B": A.FPC_THERMAL_OPTION_B}
+Q = {A.FPC_D2Q9_D2Q5: (9, 5, 2), A.FPC_D3Q27_D3Q7: (27, 7, 3), A.FPC_D2Q9_D2Q9: (9, 9, 2),
+     A.FPC_D3Q27_D3Q15: (27, 15, 3)}
 
 
 def face_code(fluid, thermal):
@@ -68,15 +72,20 @@ def conduction_reference(p, axis):
     return p
 
 
-def params_from_workload(cfg, precision="f64", shape=None, cs2_T=None, T_reference="uniform"):
+def params_from_workload(cfg, precision="f64", shape=None, cs2_T=None, T_reference="uniform", model="FP",
+                         thermal_option="A"):
     """C parameters of a workload description (``workloads.CONFIGS`` entry).
 
     The physical -> lattice mapping runs in the library
     (fpc_params_natural / fpc_params_mixed).  ``T_reference`` picks the
     FP32-deviation storage reference of g: "uniform" (T0) or "conduction"
-    (affine between the Dirichlet walls normal to the workload's L axis)."""
+    (affine between the Dirichlet walls normal to the workload's L axis).
+    ``model``: "FP" or "MCM" (the Maxwellian comparator); ``thermal_option``:
+    "A" or "B" (acts on the D2Q9 / D3Q15 thermal lattices)."""
     shape = tuple(cfg["shape"]) if shape is None else tuple(shape)
     p = default_params(cfg["pair"], precision, shape)
+    p.model = MODELS[model]
+    p.thermal_option = THERMAL_OPTIONS[thermal_option]
     if cs2_T is not None:
         p.cs2_T = float(cs2_T)
     if cfg["flow"] == "natural":

@@ -27,6 +27,25 @@ SMALL_CASES = {
 }
 
 
+def shift_temperature(cfg, dT0):
+    """The same set-up with every temperature raised by dT0 (walls, hot/cold
+    levels, hence T0): keeps T away from 0 where an attractor divides by T."""
+    cfg["T_hot"] += dT0
+    cfg["T_cold"] += dT0
+    for fd in cfg["faces"]:
+        if fd["thermal"] == "dirichlet":
+            fd["T"] = float(fd["T"]) + dT0
+    return cfg
+
+
+def with_pair(cfg, paper_thermal):
+    """The same set-up on the paper's thermal lattice (D2Q9 / D3Q15) when
+    paper_thermal, else unchanged."""
+    if paper_thermal:
+        cfg["pair"] = "D2Q9-D2Q9" if cfg["pair"].startswith("D2Q9") else "D3Q27-D3Q15"
+    return cfg
+
+
 def need_gpu():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
@@ -49,10 +68,10 @@ def initial_T(cfg, seed=None):
     return torch.tensor(workloads.initial_temperature(cfg, seed=seed))
 
 
-def perturbed_state(cfg, seed, amp=1e-2):
+def perturbed_state(cfg, seed, amp=1e-2, **prm_kw):
     """Oracle initial state of a set-up, each population multiplied by
     (1 + amp * U(-1, 1)) with seeded noise.  Returns (f, g) FP64 CPU."""
-    prm = params_from_config(cfg)
+    prm = params_from_config(cfg, **prm_kw)
     T = initial_T(cfg)
     # a non-trivial temperature field as well
     T = T + 0.2 * torch.tensor(workloads.uniform_field(T.shape, seed + 7))
@@ -62,21 +81,22 @@ def perturbed_state(cfg, seed, amp=1e-2):
     return f * (1 + amp * pf), g * (1 + amp * pg)
 
 
-def workload_params(cfg, precision):
+def workload_params(cfg, precision, model="FP", thermal_option="A"):
     """C parameters; precision "f64", "f32dev" (uniform thermal storage
     reference T0) or "f32cond" (FP32 deviations from the conduction profile
     between the Dirichlet walls of the workload's L axis)."""
     from paper_2504_09041_amd.sim import params_from_workload
 
+    kw = dict(model=model, thermal_option=thermal_option)
     if precision == "f32cond":
-        return params_from_workload(cfg, "f32dev", T_reference="conduction")
-    return params_from_workload(cfg, precision)
+        return params_from_workload(cfg, "f32dev", T_reference="conduction", **kw)
+    return params_from_workload(cfg, precision, **kw)
 
 
-def make_sim(cfg, precision, wall_profiles=None):
+def make_sim(cfg, precision, wall_profiles=None, model="FP", thermal_option="A"):
     from paper_2504_09041_amd.sim import Simulation
 
-    return Simulation(workload_params(cfg, precision), wall_profiles=wall_profiles)
+    return Simulation(workload_params(cfg, precision, model, thermal_option), wall_profiles=wall_profiles)
 
 
 def load_state(sim, f, g, step=0):
@@ -94,8 +114,8 @@ def rel_err(a, b):
     return float((a - b).abs().max()) / (scale if scale > 0 else 1.0)
 
 
-def oracle_run(cfg, f, g, nsteps, wall_T=None):
-    prm = params_from_config(cfg)
+def oracle_run(cfg, f, g, nsteps, wall_T=None, model="FP", thermal_option="A"):
+    prm = params_from_config(cfg, model=model, thermal_option=thermal_option)
     mac = None
     for _ in range(nsteps):
         f, g, mac = osim.step(prm, f, g, wall_T)

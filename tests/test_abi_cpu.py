@@ -46,7 +46,14 @@ def test_params_struct_layout_matches_header():
     assert p.omega_f.offset == 20 + 4  # 5 ints, padded to 8
     assert p.T_ref_slope.offset == p.wall_T_profile.offset + 6 * 8
     assert p.T_ref_axis.offset == p.T_ref_slope.offset + 8
-    assert ctypes.sizeof(p) == p.T_ref_axis.offset + 8  # int padded to the struct's 8-byte alignment
+    assert p.model.offset == p.T_ref_axis.offset + 4
+    assert p.thermal_option.offset == p.model.offset + 4
+    assert ctypes.sizeof(p) == p.thermal_option.offset + 4 + 4  # padded to the struct's 8-byte alignment
+
+
+def test_params_size_matches_library():
+    lib = _lib()
+    assert lib.fpc_params_bytes() == ctypes.sizeof(A.fpc_params)
 
 
 def test_validation_errors():

@@ -1,0 +1,123 @@
+"""Parity of the HIP path with the FP64 oracle beyond the hot path's lattices.
+
+The rows checked here:
+- the paper's own thermal lattices, D2Q9 (Sec. 4.4, App. B) and D3Q15
+  (Sec. 5.4, App. C), with option A and option B for the thermal attractors
+  above second order (Eq. Dij2D_goptionA, Eq. Dij2D_g);
+- the Maxwellian central-moment comparator (MCM, Sec. 7), on the paper's
+  thermal lattices and on the hot path's D2Q5 / D3Q7 pairs.
+
+Bars as for the hot path: FP64 within 1e-13 relative after one step and
+1e-12 after 50 steps; FP32 deviations within 1e-5 on the populations.
+Temperatures are raised by 1.5 so that option B's division by T stays away
+from zero (the paper's cavity runs use walls at 1 and 2).
+"""
+
+import pytest
+import torch
+
+import workloads
+from oracle import sim as osim
+from oracle.collision import rest_weights
+from oracle.params import params_from_config
+from tests import gpu_common as G
+
+pytestmark = pytest.mark.gpu
+
+CASES = list(G.SMALL_CASES)
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    G.need_gpu()
+
+
+def _run_and_compare(cfg, precision, kw, seed, tol1, tol50):
+    f0, g0 = G.perturbed_state(cfg, seed=seed, **kw)
+    sim = G.make_sim(cfg, precision, **kw)
+    G.load_state(sim, f0, g0)
+    sim.step(1)
+    f, g = G.read_state(sim)
+    fo, go, mac, prm = G.oracle_run(cfg, f0, g0, 1, **kw)
+    e1 = (G.rel_err(f, fo), G.rel_err(g, go))
+    sim.step(49)
+    f, g = G.read_state(sim)
+    fo, go, mac, prm = G.oracle_run(cfg, fo, go, 49, **kw)
+    e50 = (G.rel_err(f, fo), G.rel_err(g, go))
+    print(f"  1 step {e1[0]:.2e} {e1[1]:.2e}; 50 steps {e50[0]:.2e} {e50[1]:.2e}")
+    assert max(e1) < tol1
+    assert max(e50) < tol50
+    # diagnostics of the time level
+    m = sim.macros()
+    assert G.rel_err(m["T"].cpu(), mac["T"]) < tol50
+    d = sim.diagnostics(cfg["nu_face"])
+    nu_o = float(osim.nusselt(prm, mac["T"], cfg["nu_face"]))
+    tol_nu = tol50 if precision == "f64" else 1e-3
+    assert abs(d["nu"] - nu_o) <= tol_nu * max(1.0, abs(nu_o))
+    sim.close()
+
+
+@pytest.mark.parametrize("case", CASES)
+@pytest.mark.parametrize("model,opt", [("FP", "A"), ("FP", "B"), ("MCM", "A")])
+def test_paper_thermal_lattice_steps_match_oracle(case, model, opt):
+    print(f"case={case} model={model} option={opt}", flush=True)
+    cfg = G.with_pair(G.shift_temperature(G.small_config(case), 1.5), True)
+    _run_and_compare(cfg, "f64", dict(model=model, thermal_option=opt), 51, 1e-13, 1e-12)
+
+
+@pytest.mark.parametrize("case", CASES)
+@pytest.mark.parametrize("precision,tol1,tol50", [("f64", 1e-13, 1e-12), ("f32cond", 1e-5, 1e-5)])
+def test_mcm_on_hot_path_lattices_matches_oracle(case, precision, tol1, tol50):
+    print(f"case={case} precision={precision}", flush=True)
+    cfg = G.small_config(case)
+    _run_and_compare(cfg, precision, dict(model="MCM", thermal_option="A"), 52, tol1, tol50)
+
+
+def test_paper_thermal_lattices_reject_fp32():
+    from paper_2504_09041_amd import _abi as A
+
+    cfg = G.with_pair(G.small_config("dhc2d"), True)
+    with pytest.raises(A.FpcError):
+        G.make_sim(cfg, "f32dev")
+
+
+def test_adjoint_rejects_unsupported_models():
+    import ctypes
+
+    from paper_2504_09041_amd import _abi as A
+
+    cfg = G.small_config("dhc2d")
+    sim = G.make_sim(cfg, "f64", model="MCM")
+    S = sim.save()
+    lam = torch.zeros_like(S)
+    lam2 = torch.zeros_like(S)
+    rc = A.load().fpc_adjoint_step(sim.handle, ctypes.c_void_p(S.data_ptr()), ctypes.c_void_p(lam.data_ptr()),
+                                   ctypes.c_void_p(lam2.data_ptr()), None, ctypes.c_double(0.0), None)
+    assert rc == A.FPC_ERR_STATE
+
+
+@pytest.mark.parametrize("workload,pair", [("rb2d_1024x512", "D2Q9-D2Q9"), ("dhc3d_256", "D3Q27-D3Q15")])
+def test_paper_thermal_full_size_step_on_sampled_nodes(workload, pair):
+    """One FP64 step at the full workload size (the 256^3 D3Q27 + D3Q15 state,
+    5.6 GB per buffer, takes the 64-bit addressing path) against the oracle
+    at ~2000 sampled nodes."""
+    print(f"workload={workload} pair={pair}", flush=True)
+    cfg = workloads.config(workload, pair=pair)
+    prm = params_from_config(cfg)
+    lf, lg = prm.lattices
+    wf = rest_weights(lf)
+    wg = rest_weights(lg, thermal=True, cs2=prm.cs2T)
+    sim = G.make_sim(cfg, "f64")
+    S = G.full_hashed_state(cfg["shape"], lf.Q, lg.Q, wf, wg, seed=23, device="cuda")
+    sim.import_fp64(S)
+    del S
+    sim.step(1)
+    out = sim.export_fp64()
+    x, y, z = G.sample_nodes(cfg["shape"], 2000, seed=24)
+    got = out[:, z.cuda(), y.cuda(), x.cuda()].cpu()
+    del out
+    gf, gg = G.hashed_state_getters(cfg["shape"], lf.Q, lg.Q, wf, wg, seed=23)
+    fo, go, _ = osim.step_at(prm, gf, gg, (x, y, z))
+    assert G.rel_err(got[: lf.Q], fo) < 1e-13
+    assert G.rel_err(got[lf.Q:], go) < 1e-13
+    sim.close()
