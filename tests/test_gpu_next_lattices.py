@@ -121,3 +121,17 @@ def test_paper_thermal_full_size_step_on_sampled_nodes(workload, pair):
     assert G.rel_err(got[: lf.Q], fo) < 1e-13
     assert G.rel_err(got[lf.Q:], go) < 1e-13
     sim.close()
+
+
+def test_fp_outlasts_mcm_in_the_sheared_cube():
+    """The stability claim of Sec. 7 at one point of the Ma = 0.25, Pr = 0.71
+    sweep on a 32^3 grid (D3Q27 + D3Q15, FP64): at Pe = 900 the FP model runs
+    20,000 steps with the watchdog quiet, the MCM comparator trips it.  (The
+    full sweep, ``python -m paper_2504_09041_amd.stability``, finds the largest
+    stable Pe there at ~1,180 for FP and ~690 for MCM over 200,000 steps.)"""
+    from paper_2504_09041_amd.stability import survives
+
+    ok_fp, n_fp = survives("FP", 32, 0.25, 0.71, 900.0, 20000)
+    ok_mcm, n_mcm = survives("MCM", 32, 0.25, 0.71, 900.0, 20000)
+    print(f"FP: {ok_fp} ({n_fp} steps), MCM: {ok_mcm} ({n_mcm} steps)")
+    assert ok_fp and not ok_mcm

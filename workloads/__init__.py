@@ -15,6 +15,8 @@ Rayleigh-Benard):
 * ``dhc3d_256``     - 3D differentially heated cube, 256^3, Ra 1e6
 * ``mixed2d_512``   - 2D lid-driven mixed convection, 512^2, Re 1e3, Ri 1
 * ``rb3d_128``      - 3D Rayleigh-Benard, 128^3, periodic in x and y, Ra 1e5
+* ``mixed3d_64``    - 3D lid-driven mixed convection, 64^3, D3Q15 thermal: the
+                      set-up of the stability comparison of Sec. 7
 
 Faces are listed in the order -x, +x, -y, +y, -z, +z.  In 2D the z faces are
 periodic with nz = 1.
@@ -69,6 +71,19 @@ CONFIGS = {
                   _P, _P],
         "steps": 10000, "nu_face": 3, "init": "conduction_noise_uniform", "seed": 2508,
         "J_window": (5000, 10000), "checkpoint_every": 100, "grad_face": 2,
+    },
+    # Stability comparison of Sec. 7: lid-driven cube, hot moving top, cold
+    # bottom, adiabatic sides; the paper's own thermal lattice (D3Q15).  Ma
+    # and Pe are swept (Re = Pe / Pr); the buoyancy strength is not given in
+    # the paper and is set by Ri = 1.
+    "mixed3d_64": {
+        "pair": "D3Q27-D3Q15", "shape": (64, 64, 64), "precision": "f64",
+        "flow": "mixed", "Re": 710.0, "Ri": 1.0, "Pe": 1e3, "U_lid": 0.25 / 3 ** 0.5, "Pr": 0.71,
+        "L_axis": 2, "up_axis": 2, "T_hot": 2.0, "T_cold": 1.0,
+        "faces": [_face("noslip", "adiabatic"), _face("noslip", "adiabatic"),
+                  _face("noslip", "adiabatic"), _face("noslip", "adiabatic"),
+                  _face("noslip", "dirichlet", 1.0), _face("lid", "dirichlet", 2.0, (0.25 / 3 ** 0.5, 0.0, 0.0))],
+        "steps": 1_000_000, "nu_face": 4, "init": "conduction_noise_uniform", "seed": 2510,
     },
     "rb3d_128": {
         "pair": "D3Q27-D3Q7", "shape": (128, 128, 128), "precision": "f32dev",
