@@ -150,7 +150,7 @@ def pmc_summary(a):
     return rec
 
 
-def time_workload(name, precision, steps, warmup, shape=None):
+def time_workload(name, precision, steps, warmup, shape=None, pair=None, model="FP", thermal_option="A"):
     import torch
 
     import workloads
@@ -159,10 +159,13 @@ def time_workload(name, precision, steps, warmup, shape=None):
     cfg = workloads.config(name)
     if shape is not None:
         cfg["shape"] = tuple(shape)
+    if pair is not None:
+        cfg["pair"] = pair
+    kw = dict(model=model, thermal_option=thermal_option)
     if precision == "f32cond":
-        p = params_from_workload(cfg, "f32dev", T_reference="conduction")
+        p = params_from_workload(cfg, "f32dev", T_reference="conduction", **kw)
     else:
-        p = params_from_workload(cfg, precision)
+        p = params_from_workload(cfg, precision, **kw)
     sim = Simulation(p)
     T = torch.tensor(workloads.initial_temperature(cfg), device="cuda")
     sim.init(T)
@@ -186,6 +189,8 @@ def time_workload(name, precision, steps, warmup, shape=None):
     per_launch_s = ms * 1e-3 / steps
     out = {
         "workload": name,
+        "pair": cfg["pair"],
+        "model": model,
         "precision": precision,
         "shape": list(cfg["shape"]),
         "nodes": N,
@@ -240,8 +245,8 @@ def adjoint_cost(name, nsteps, every, reps=20):
     t_fwd = e0.elapsed_time(e1) / reps
     # adjoint step alone
     S = sim.save()
-    lam = torch.zeros((sim.Qf + sim.Qg, sim.plane), dtype=torch.float32, device="cuda")
-    lam2 = torch.empty_like(lam)
+    lam = sim.new_adjoint()
+    lam2 = sim.new_adjoint()
     lib = A.load()
     vp = lambda t: ctypes.c_void_p(t.data_ptr())  # noqa: E731
     for _ in range(3):
@@ -408,6 +413,13 @@ def main():
         # the 64 x 64 cavity: launch-bound (4096 nodes per launch)
         extra["dhc2d_64_f64"] = time_workload("dhc2d_64", "f64", a.steps, a.warmup)
         extra["copy_4GiB"] = copy_bandwidth(4096, 20)
+        # the paper's own thermal lattices (FP64), and the MCM comparator on the
+        # headline workload: same step structure, more (or the same) bytes
+        extra["rb2d_1024x512_f64_D2Q9thermal"] = time_workload("rb2d_1024x512", "f64", a.steps, a.warmup,
+                                                               pair="D2Q9-D2Q9")
+        extra["rb3d_128_f64_D3Q15thermal"] = time_workload("rb3d_128", "f64", a.steps3d, max(5, a.warmup // 10),
+                                                           pair="D3Q27-D3Q15")
+        extra["rb2d_1024x512_f64_MCM"] = time_workload("rb2d_1024x512", "f64", a.steps, a.warmup, model="MCM")
         # FP32 against FP64 over the workload's full run (the precision half of
         # the metric): errors of T and of the bottom-wall Nu at the end
         cfg_steps = 50000

@@ -170,11 +170,16 @@ int fpc_params_natural(fpc_params* p, double Ra, double Pr, double U0, int L_axi
 int fpc_params_mixed(fpc_params* p, double Re, double Ri, double Pe, double U_lid, int L_axis,
                      double T_hot, double T_cold);
 
-/* Bytes each of the two state buffers must hold, and the element stride
- * between population planes (elements, not bytes).  State layout: plane q
- * (fluid planes 0..Qf-1, then thermal planes) holds N values [z][y][x] of
- * FP64 (FPC_FP64) or FP32 (FPC_FP32_DEV), starting at q * plane_stride. */
-int fpc_state_bytes(const fpc_params* p, size_t* bytes_per_buffer, size_t* plane_stride);
+/* Bytes each of the two state buffers must hold, and the padded row length
+ * nxp (nx rounded up to a multiple of 64).  State layout (elements of FP64
+ * for FPC_FP64, FP32 for FPC_FP32_DEV): node (x, y, z) has the padded index
+ * n = (z ny + y) nxp + x; nodes form tiles of 64 consecutive padded indices,
+ * and tile t = n / 64 stores its Q = Qf + Qg populations (fluid 0..Qf-1, then
+ * thermal) one after the other as runs of 64 values, so population q of node
+ * n is element (t Q + q) 64 + n % 64.  Elements of padding nodes
+ * (x >= nx) are never read or written by the step kernels.
+ * bytes_per_buffer = nxp ny nz Q sizeof(element). */
+int fpc_state_bytes(const fpc_params* p, size_t* bytes_per_buffer, size_t* row_stride);
 
 /*
  * Create a simulation that borrows two device buffers of at least

@@ -137,15 +137,12 @@ class AdjointSolver:
                 self.ckpt.append(sim.save())
         return J
 
-    def _lam(self):
-        return torch.empty((self.sim.Qf + self.sim.Qg, self.sim.plane), dtype=self.dt, device=self.device)
-
     def backward(self):
         """Returns (dJ/dtheta or None, dJ/dT_init)."""
         sim = self.sim
         lib = A.load()
-        lam = self._lam().zero_()
-        lam2 = self._lam()
+        lam = sim.new_adjoint()
+        lam2 = sim.new_adjoint()
         dth = None
         ptrs = None
         if self.theta_face is not None:

@@ -19,7 +19,7 @@ struct fpc_sim {
   int cur;  // index of the buffer holding the current state
   hipStream_t stream;
   long long step;
-  size_t plane;
+  int nxp;  // padded row length of the storage layout
   size_t bytes;
   int Qf, Qg, dim;
   double* scratch;  // reduction partials, then 8 doubles of results
@@ -74,16 +74,10 @@ int lattice_dims(int lattice, int* Qf, int* Qg, int* dim) {
   return fail(FPC_ERR_ARG, "unknown lattice %d", lattice);
 }
 
-// Element stride between population planes: N rounded up to 64 elements
-// (256 B in FP32), plus FPC_PLANE_PAD elements so that the planes of one
-// node do not all start at the same offset modulo a large power of two.
-#ifndef FPC_PLANE_PAD
-#define FPC_PLANE_PAD 320
-#endif
-size_t plane_of(const fpc_params* p) {
-  const size_t N = (size_t)p->nx * p->ny * p->nz;
-  return (N + 63) / 64 * 64 + FPC_PLANE_PAD;
-}
+// Storage layout: rows padded to whole 64-node tiles; each tile holds its
+// Q populations as consecutive runs of 64 values.
+int nxp_of(const fpc_params* p) { return (p->nx + 63) / 64 * 64; }
+size_t padded_nodes(const fpc_params* p) { return (size_t)nxp_of(p) * p->ny * p->nz; }
 
 bool rate_ok(double w) { return std::isfinite(w) && w > 0.0 && w < 2.0; }
 
@@ -103,9 +97,9 @@ int validate(const fpc_params* p) {
   if (dim == 2 && p->nz != 1) return fail(FPC_ERR_SIZE, "2D lattice needs nz == 1");
   const double N = (double)p->nx * p->ny * p->nz;
   if (N * (Qf + Qg) > 4.0e10) return fail(FPC_ERR_SIZE, "grid too large");
-  // kernels address a population plane with 32-bit byte offsets
-  if (N * (double)elem_size(p->precision) >= 4294967296.0)
-    return fail(FPC_ERR_SIZE, "grid too large for 32-bit plane offsets (N * sizeof(real) must be < 4 GiB)");
+  // kernels index padded nodes with 32-bit integers
+  if ((double)((p->nx + 63) / 64 * 64) * p->ny * p->nz >= 2147483648.0)
+    return fail(FPC_ERR_SIZE, "grid too large (padded node count must be < 2^31)");
   if (p->nx > (1 << 24) || p->ny > (1 << 24) || p->nz > 65535) return fail(FPC_ERR_SIZE, "axis too long");
   for (int k = 1; k < Qf; ++k)
     if (!rate_ok(p->omega_f[k])) return fail(FPC_ERR_ARG, "omega_f[%d] = %g outside (0, 2)", k, p->omega_f[k]);
@@ -168,7 +162,7 @@ StepArgs<R> make_args(const fpc_sim* s, const void* src, void* dst) {
   a.ny = p.ny;
   a.nz = p.nz;
   for (int k = 0; k < 3; ++k) a.per[k] = p.bc[2 * k] == FPC_BC_PERIODIC;
-  a.plane = s->plane;
+  a.nxp = s->nxp;
   for (int k = 0; k < 27; ++k) a.c.om[k] = (R)p.omega_f[k];
   for (int k = 0; k < 15; ++k) a.c.omg[k] = (R)p.omega_g[k];
   a.c.model = p.model;
@@ -224,7 +218,7 @@ StateDesc desc_of(const fpc_sim* s) {
   d.nx = p.nx;
   d.ny = p.ny;
   d.nz = p.nz;
-  d.plane = s->plane;
+  d.nxp = s->nxp;
   const bool dev = p.precision == FPC_FP32_DEV;
   d.rho_r = dev ? p.rho0 : 0.0;
   d.T_r = dev ? p.T0 : 0.0;
@@ -328,14 +322,13 @@ int fpc_params_mixed(fpc_params* p, double Re, double Ri, double Pe, double U_li
   return FPC_OK;
 }
 
-int fpc_state_bytes(const fpc_params* p, size_t* bytes_per_buffer, size_t* plane_stride) {
+int fpc_state_bytes(const fpc_params* p, size_t* bytes_per_buffer, size_t* row_stride) {
   int rc = validate(p);
   if (rc) return rc;
   int Qf, Qg, dim;
   lattice_dims(p->lattice, &Qf, &Qg, &dim);
-  const size_t plane = plane_of(p);
-  if (bytes_per_buffer) *bytes_per_buffer = plane * (Qf + Qg) * elem_size(p->precision);
-  if (plane_stride) *plane_stride = plane;
+  if (bytes_per_buffer) *bytes_per_buffer = padded_nodes(p) * (Qf + Qg) * elem_size(p->precision);
+  if (row_stride) *row_stride = (size_t)nxp_of(p);
   return FPC_OK;
 }
 
@@ -355,8 +348,8 @@ int fpc_create(const fpc_params* p, void* bufA, void* bufB, void* hip_stream, fp
   s->cur = 0;
   s->stream = static_cast<hipStream_t>(hip_stream);
   lattice_dims(p->lattice, &s->Qf, &s->Qg, &s->dim);
-  s->plane = plane_of(p);
-  s->bytes = s->plane * (s->Qf + s->Qg) * elem_size(p->precision);
+  s->nxp = nxp_of(p);
+  s->bytes = padded_nodes(p) * (s->Qf + s->Qg) * elem_size(p->precision);
   hipError_t e = hipGetDevice(&s->device);
   if (e != hipSuccess) {
     delete s;

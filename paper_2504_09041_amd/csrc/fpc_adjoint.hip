@@ -90,11 +90,12 @@ struct Scatter {
   template <int Q, int QBASE>
   __device__ __forceinline__ void push(R v) const {
     constexpr bool TH = QBASE != 0;
-    const long long sh = e.template shift<Q, TH>();
+    constexpr int ex = lex<L, TH>(Q);
     if (!E::template checked<Q, TH>()) {
-      m.store_at(QBASE + Q, sh, e.node, v);
+      m.store_tile(QBASE + Q, e.tl.template base<ex>(e.template dtile<Q, TH>()), e.tl.template lane<ex>(), v);
       return;
     }
+    const long long sh = e.template shift<Q, TH>();
     bool wx = false, wy = false, wz = false;
     const unsigned idx = e.template source<Q, TH>(wx, wy, wz);
     if (E::template wrap_only<Q, TH>()) {
@@ -104,7 +105,7 @@ struct Scatter {
     const bool wall = wx || wy || wz;
     R out = v;
     if (QBASE != 0 && Q != 0) {
-      constexpr int ex = lex<L, TH>(Q), ey = ley<L, TH>(Q), ez = lez<L, TH>(Q);
+      constexpr int ey = ley<L, TH>(Q), ez = lez<L, TH>(Q);
       constexpr int F = ex > 0 ? 0 : (ex < 0 ? 1 : (ey > 0 ? 2 : (ey < 0 ? 3 : (ez > 0 ? 4 : 5))));
       constexpr int k = F >> 1;
       const StepArgs<R>& a = A.s;
@@ -154,9 +155,9 @@ __global__ void __launch_bounds__(256) adjoint_step_kernel(AdjArgs<R> A, unsigne
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
   const int z = blockIdx.z;
   if (x >= a.nx || y >= a.ny) return;
-  const M mS(a.src, nullptr, a.plane, total_bytes);
-  const M mL(A.lam_in, A.lam_out, a.plane, total_bytes);
-  const unsigned node = node_of(x, y, z, a.nx, a.ny);
+  const M mS(a.src, nullptr, total_bytes);
+  const M mL(A.lam_in, A.lam_out, total_bytes);
+  const unsigned node = node_of(x, y, z, a.nxp, a.ny);
   // which axes have an edge node in this wavefront (wave-uniform)
   const bool needx = __any(x == 0 || x == a.nx - 1);
   const bool needyz = __any(y == 0 || y == a.ny - 1) || (D == 3 && __any(z == 0 || z == a.nz - 1));
@@ -185,7 +186,8 @@ __global__ void __launch_bounds__(256) adjoint_step_kernel(AdjArgs<R> A, unsigne
   for (int q = 0; q < L::Qf; ++q) fb[q] = mL.load(q, 0, node);
 #pragma unroll
   for (int q = 0; q < L::Qg; ++q) gb[q] = mL.load(L::Qf + q, 0, node);
-  add_seed<R, D, UP>(t, a.c, A.dJdT ? A.dJdT[node] : 0.0, A.ke, fb, gb);
+  const size_t cell = ((size_t)z * a.ny + y) * a.nx + x;  // index of the unpadded node fields
+  add_seed<R, D, UP>(t, a.c, A.dJdT ? A.dJdT[cell] : 0.0, A.ke, fb, gb);
   adj::reverse<R, D, UP>(t, a.c, fb, gb);
   if (variant == 0)
     scatter<L, R, M, false, false, false>(A, mL, x, y, z, node, fb, gb);
@@ -215,7 +217,9 @@ __global__ void __launch_bounds__(256) adjoint_init_kernel(AdjInitArgs<R> A) {
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
   const int z = blockIdx.z;
   if (x >= a.nx || y >= a.ny) return;
-  const unsigned node = ((unsigned)z * (unsigned)a.ny + (unsigned)y) * (unsigned)a.nx + (unsigned)x;
+  constexpr int Q = Lk::Qf + Lk::Qg;
+  const size_t node = ((size_t)z * a.ny + y) * a.nx + x;  // unpadded node fields
+  const unsigned n = node_of(x, y, z, a.nxp, a.ny);         // storage layout
   R f[Lk::Qf], g[Lk::Qg], wg[Lk::Qg];
 #pragma unroll
   for (int q = 0; q < Lk::Qf; ++q) f[q] = R(Lk::w(q)) * a.rho_w;
@@ -229,9 +233,9 @@ __global__ void __launch_bounds__(256) adjoint_init_kernel(AdjInitArgs<R> A) {
   adj::forward<R, D, UP>(f, g, a.c, t);
   R fb[Lk::Qf], gb[Lk::Qg];
 #pragma unroll
-  for (int q = 0; q < Lk::Qf; ++q) fb[q] = A.lam0[(size_t)q * a.plane + node];
+  for (int q = 0; q < Lk::Qf; ++q) fb[q] = A.lam0[elem64<Q>(q, n)];
 #pragma unroll
-  for (int q = 0; q < Lk::Qg; ++q) gb[q] = A.lam0[(size_t)(Lk::Qf + q) * a.plane + node];
+  for (int q = 0; q < Lk::Qg; ++q) gb[q] = A.lam0[elem64<Q>(Lk::Qf + q, n)];
   add_seed<R, D, UP>(t, a.c, A.dJdT ? A.dJdT[node] : 0.0, A.ke, fb, gb);
   adj::reverse<R, D, UP>(t, a.c, fb, gb);
   double s = 0.0;
@@ -249,11 +253,12 @@ hipError_t launch_adj(const AdjArgs<R>* step, const AdjInitArgs<R>* init, hipStr
   const dim3 block(bx, by, 1);
   const dim3 grid((a.nx + bx - 1) / bx, (a.ny + by - 1) / by, a.nz);
   if (step) {
-    const double bytes = (double)a.plane * (L::Qf + L::Qg) * sizeof(R);
+    constexpr int Q = L::Qf + L::Qg;
+    const double bytes = (double)a.nxp * a.ny * a.nz * Q * sizeof(R);
     if (bytes < 4294967296.0)
-      adjoint_step_kernel<L, R, Buf32<R>, UP><<<grid, block, 0, st>>>(*step, (unsigned)bytes);
+      adjoint_step_kernel<L, R, Buf32<R, Q>, UP><<<grid, block, 0, st>>>(*step, (unsigned)bytes);
     else
-      adjoint_step_kernel<L, R, Glob64<R>, UP><<<grid, block, 0, st>>>(*step, 0u);
+      adjoint_step_kernel<L, R, Glob64<R, Q>, UP><<<grid, block, 0, st>>>(*step, 0u);
   } else {
     adjoint_init_kernel<D, R, UP><<<grid, block, 0, st>>>(*init);
   }

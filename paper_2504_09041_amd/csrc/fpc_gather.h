@@ -11,9 +11,9 @@
 // adjoint of an incoming link back to the slot it was read from, so every
 // slot of the output is written exactly once.
 //
-// Layout: SoA planes, plane q holds the N node values [z][y][x]; a wavefront
-// covers 64 consecutive x of one row, so every access is a contiguous run of
-// one plane (shifted by at most one element).
+// Layout: tiles of 64 nodes (below); a wavefront owns one tile, so every
+// access is a contiguous run of 64 values of one population of one tile
+// (shifted by at most one element into the neighbouring tile).
 //
 // Boundary handling is resolved per wavefront by the caller (a ballot over
 // the edge tests) and compiled in: CX / CY / CZ enable the range checks of an
@@ -90,139 +90,158 @@ constexpr int lez(int a) { return TH ? L::tez(a) : L::ez(a); }
 template <class L, bool TH>
 constexpr int lopp(int a) { return TH ? L::topp(a) : L::opp(a); }
 
-__device__ __forceinline__ unsigned node_of(int x, int y, int z, int nx, int ny) {
-  return ((unsigned)z * (unsigned)ny + (unsigned)y) * (unsigned)nx + (unsigned)x;
+// Padded node index: rows hold nxp = nx rounded up to 64 nodes.
+__device__ __forceinline__ unsigned node_of(int x, int y, int z, int nxp, int ny) {
+  return ((unsigned)z * (unsigned)ny + (unsigned)y) * (unsigned)nxp + (unsigned)x;
 }
 
 // ---------------------------------------------------------------------------
-// Addressing of a pair of state-layout buffers (read side `src`, write side
-// `dst`).  Two policies with the same interface:
-//   load(q, shift, idx)                  plane q at lane index idx - shift
-//   load_sel(w, qw, iw, q, shift, idx)   per lane: plane qw at iw if w, else as load
-//   store<NT>(q, idx, v)                 plane q at idx
-//   store_at(q, shift, idx, v)           plane q at idx - shift
-//   store_sel(w, qw, iw, q, shift, idx, v)
-// (shift is wave-uniform.)
-// Buf32: each buffer through one raw buffer descriptor; the lane supplies a
-//   32-bit byte offset, the plane offset of loads is a wave-uniform scalar
-//   (usable while a buffer is below 4 GiB).  Keeps the address arithmetic off
-//   the vector ALU and the scalar register file small.
-// Glob64: 64-bit plane base pointers plus a 32-bit lane offset (any size).
+// Storage layout of a state buffer (and of an adjoint state): nodes are
+// grouped in tiles of 64 consecutive padded node indices (64 consecutive x of
+// one row; rows are padded to whole tiles).  A tile stores its Q = Qf + Qg
+// populations one after the other, each as a run of 64 values, so population
+// q of node n is element
+//     elem(q, n) = (tile(n) Q + q) 64 + lane(n),  tile = n / 64, lane = n % 64.
+// A wavefront owns exactly one tile: its stores fill Q * 64 contiguous values,
+// and each pulled population is a run of 64 values of one source tile
+// (straddling two tiles by one element for e_x != 0).
+// ---------------------------------------------------------------------------
+template <int Q>
+__device__ __forceinline__ unsigned elem(int q, unsigned n) {
+  return ((n >> 6) * (unsigned)Q + (unsigned)q) * 64u + (n & 63u);
+}
+template <int Q>
+__device__ __forceinline__ size_t elem64(int q, unsigned n) {
+  return ((size_t)(n >> 6) * (unsigned)Q + (unsigned)q) * 64u + (n & 63u);
+}
+
+// Interior fast path of a pull along e = (ex, ey, ez): the source of lane l
+// lies in tile t - dt (dt = ey nxp/64 + ez ny nxp/64, wave-uniform) at lane
+// l - ex, or across the tile border for the first / last lane.  Relative to a
+// base tile that is wave-uniform, the lane's element offset is a per-lane
+// constant, precomputed once:
+//   ex =  0: base t - dt,     lane offset l
+//   ex = +1: base t - dt - 1, lane offset 63 (l = 0) or Q 64 + l - 1
+//   ex = -1: base t - dt,     lane offset Q 64 (l = 63) or l + 1
+// (all non-negative; used only for waves with no x-edge lane, so the border
+// tiles exist in the same row).
+template <int Q>
+struct TileLanes {
+  unsigned t;       // tile of the wave (wave-uniform)
+  unsigned o0, op, om;  // lane element offsets for ex = 0, +1, -1
+  __device__ __forceinline__ explicit TileLanes(unsigned node) {
+    t = __builtin_amdgcn_readfirstlane(node >> 6);
+    const unsigned l = node & 63u;
+    o0 = l;
+    op = l == 0 ? 63u : (unsigned)Q * 64u + l - 1u;
+    om = l == 63 ? (unsigned)Q * 64u : l + 1u;
+  }
+  template <int EX>
+  __device__ __forceinline__ unsigned base(int dt) const { return t - (unsigned)dt - (EX > 0 ? 1u : 0u); }
+  template <int EX>
+  __device__ __forceinline__ unsigned lane() const { return EX == 0 ? o0 : (EX > 0 ? op : om); }
+};
+
+// ---------------------------------------------------------------------------
+// Addressing of a pair of buffers in the storage layout (read side `src`,
+// write side `dst`).  Two policies with the same interface:
+//   load(q, shift, idx)               population q of padded node idx - shift
+//   load_sel(w, qw, iw, q, shift, idx)  per lane: (qw, iw) if w, else as load
+//   load_tile(q, tb, lane)            interior fast path (TileLanes)
+//   cursor(n) / store_next<NT>(cur, v)  the Q populations of node n in order
+//   store_at(q, shift, idx, v), store_sel(...), store_tile(q, tb, lane, v)
+// Buf32: each buffer through one raw buffer descriptor (below 4 GiB); the
+//   interior path passes the lane offset in a vector register and the tile
+//   offset as a wave-uniform scalar, so it costs no vector ALU.
+// Glob64: 64-bit element offsets (any size).
 // ---------------------------------------------------------------------------
 constexpr int kBufDword3 = 0x00020000;  // raw (untyped) buffer, gfx9 family
 typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
 
-template <class R>
+template <class R, int Q>
 struct Buf32 {
   __amdgpu_buffer_rsrc_t rsrc_s, rsrc_d;
-  unsigned pb;  // plane stride in bytes
   static constexpr unsigned S = sizeof(R);
 
-  __device__ __forceinline__ Buf32(const R* s, R* d, size_t plane, unsigned total_bytes)
+  __device__ __forceinline__ Buf32(const R* s, R* d, unsigned total_bytes)
       : rsrc_s(__builtin_amdgcn_make_buffer_rsrc(const_cast<R*>(s), 0, (int)total_bytes, kBufDword3)),
-        rsrc_d(__builtin_amdgcn_make_buffer_rsrc(d, 0, (int)total_bytes, kBufDword3)),
-        pb((unsigned)plane * S) {}
+        rsrc_d(__builtin_amdgcn_make_buffer_rsrc(d, 0, (int)total_bytes, kBufDword3)) {}
 
-  __device__ __forceinline__ __amdgpu_buffer_rsrc_t rs_src() const { return rsrc_s; }
-  __device__ __forceinline__ __amdgpu_buffer_rsrc_t rs_dst() const { return rsrc_d; }
   __device__ __forceinline__ R raw(unsigned voff, unsigned soff) const {
     if constexpr (sizeof(R) == 4)
-      return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b32(rs_src(), (int)voff, (int)soff, 0));
+      return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b32(rsrc_s, (int)voff, (int)soff, 0));
     else
-      return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b64(rs_src(), (int)voff, (int)soff, 0));
+      return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b64(rsrc_s, (int)voff, (int)soff, 0));
   }
   template <bool NT>
-  __device__ __forceinline__ void raw_store(unsigned voff, R v) const {
+  __device__ __forceinline__ void raw_store(unsigned voff, unsigned soff, R v) const {
     constexpr int aux = NT ? 2 : 0;  // cache policy: non-temporal
     if constexpr (sizeof(R) == 4)
-      __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), rs_dst(), (int)voff, 0, aux);
+      __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), rsrc_d, (int)voff, (int)soff, aux);
     else
-      __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), rs_dst(), (int)voff, 0, aux);
-  }
-  // byte offset of plane q minus the streaming shift (non-negative for q >= 1
-  // or shift == 0, as every plane is longer than any shift)
-  __device__ __forceinline__ unsigned base(int q, long long shift) const {
-    return (unsigned)q * pb - (unsigned)(shift * (long long)S);
+      __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), rsrc_d, (int)voff, (int)soff, aux);
   }
   __device__ __forceinline__ R load(int q, long long shift, unsigned idx) const {
-    return raw(idx * S, base(q, shift));
+    return raw(elem<Q>(q, idx - (unsigned)shift) * S, 0u);
   }
   __device__ __forceinline__ R load_sel(bool w, int qw, unsigned iw, int q, long long shift, unsigned idx) const {
-    const unsigned vs = idx * S + base(q, shift);
-    const unsigned vw = iw * S + (unsigned)qw * pb;
-    return raw(w ? vw : vs, 0u);
+    return raw((w ? elem<Q>(qw, iw) : elem<Q>(q, idx - (unsigned)shift)) * S, 0u);
   }
-  // stores take the plane offset on the lane side: one add per store and no
-  // scalar register per plane held across the collision
-  template <bool NT>
-  __device__ __forceinline__ void store(int q, unsigned idx, R v) const {
-    raw_store<NT>(idx * S + (unsigned)q * pb, v);
+  __device__ __forceinline__ R load_tile(int q, unsigned tb, unsigned lane) const {
+    return raw(lane * S, (tb * (unsigned)Q + (unsigned)q) * 64u * S);
   }
-  // store the planes of one node in order: cursor starts at cursor(idx) and
-  // advances by one plane per store
-  __device__ __forceinline__ unsigned cursor(unsigned idx) const { return idx * S; }
+  __device__ __forceinline__ unsigned cursor(unsigned n) const { return elem<Q>(0, n) * S; }
   template <bool NT>
   __device__ __forceinline__ void store_next(unsigned& cur, R v) const {
-    raw_store<NT>(cur, v);
-    cur += pb;
+    raw_store<NT>(cur, 0u, v);
+    cur += 64u * S;
   }
   __device__ __forceinline__ void store_at(int q, long long shift, unsigned idx, R v) const {
-    raw_store<false>(idx * S + base(q, shift), v);
+    raw_store<false>(elem<Q>(q, idx - (unsigned)shift) * S, 0u, v);
   }
   __device__ __forceinline__ void store_sel(bool w, int qw, unsigned iw, int q, long long shift, unsigned idx,
                                             R v) const {
-    const unsigned vs = idx * S + base(q, shift);
-    const unsigned vw = iw * S + (unsigned)qw * pb;
-    raw_store<false>(w ? vw : vs, v);
+    raw_store<false>((w ? elem<Q>(qw, iw) : elem<Q>(q, idx - (unsigned)shift)) * S, 0u, v);
+  }
+  __device__ __forceinline__ void store_tile(int q, unsigned tb, unsigned lane, R v) const {
+    raw_store<false>(lane * S, (tb * (unsigned)Q + (unsigned)q) * 64u * S, v);
   }
 };
 
-template <class R>
+template <class R, int Q>
 struct Glob64 {
   const R* src;
   R* dst;
-  size_t plane;
 
-  __device__ __forceinline__ Glob64(const R* s, R* d, size_t plane_, unsigned) : src(s), dst(d), plane(plane_) {}
+  __device__ __forceinline__ Glob64(const R* s, R* d, unsigned) : src(s), dst(d) {}
 
-  // p[idx] with a 32-bit byte offset (uniform base + lane offset)
-  template <class P>
-  static __device__ __forceinline__ P* at(P* p, unsigned idx) {
-    return reinterpret_cast<P*>(reinterpret_cast<char*>(const_cast<R*>(p)) + idx * (unsigned)sizeof(R));
-  }
   __device__ __forceinline__ R load(int q, long long shift, unsigned idx) const {
-    return *at(src + (size_t)q * plane - shift, idx);
+    return src[elem64<Q>(q, idx - (unsigned)shift)];
   }
   __device__ __forceinline__ R load_sel(bool w, int qw, unsigned iw, int q, long long shift, unsigned idx) const {
-    const R* pw = src + (size_t)qw * plane;
-    const R* ps = src + (size_t)q * plane - shift;
-    return *at(w ? pw : ps, w ? iw : idx);
+    return src[w ? elem64<Q>(qw, iw) : elem64<Q>(q, idx - (unsigned)shift)];
   }
-  template <bool NT>
-  __device__ __forceinline__ void store(int q, unsigned idx, R v) const {
-    R* p = at(dst + (size_t)q * plane, idx);
-    if constexpr (NT)
-      __builtin_nontemporal_store(v, p);
-    else
-      *p = v;
+  __device__ __forceinline__ R load_tile(int q, unsigned tb, unsigned lane) const {
+    return src[((size_t)tb * (unsigned)Q + (unsigned)q) * 64u + lane];
   }
-  __device__ __forceinline__ void store_at(int q, long long shift, unsigned idx, R v) const {
-    *at(dst + (size_t)q * plane - shift, idx) = v;
-  }
-  __device__ __forceinline__ R* cursor(unsigned idx) const { return at(dst, idx); }
+  __device__ __forceinline__ R* cursor(unsigned n) const { return dst + elem64<Q>(0, n); }
   template <bool NT>
   __device__ __forceinline__ void store_next(R*& cur, R v) const {
     if constexpr (NT)
       __builtin_nontemporal_store(v, cur);
     else
       *cur = v;
-    cur += plane;
+    cur += 64;
+  }
+  __device__ __forceinline__ void store_at(int q, long long shift, unsigned idx, R v) const {
+    dst[elem64<Q>(q, idx - (unsigned)shift)] = v;
   }
   __device__ __forceinline__ void store_sel(bool w, int qw, unsigned iw, int q, long long shift, unsigned idx,
                                             R v) const {
-    R* pw = dst + (size_t)qw * plane;
-    R* ps = dst + (size_t)q * plane - shift;
-    *at(w ? pw : ps, w ? iw : idx) = v;
+    dst[w ? elem64<Q>(qw, iw) : elem64<Q>(q, idx - (unsigned)shift)] = v;
+  }
+  __device__ __forceinline__ void store_tile(int q, unsigned tb, unsigned lane, R v) const {
+    dst[((size_t)tb * (unsigned)Q + (unsigned)q) * 64u + lane] = v;
   }
 };
 
@@ -238,14 +257,16 @@ struct Edges {
   // (periodic axis: the source index moves by +-n_k times the axis stride) or
   // meets a wall.  PX: x is known to be periodic.
   bool xlo = false, xhi = false, ylo = false, yhi = false, zlo = false, zhi = false;
-  unsigned nxm = 0, nxp = 0;  // node index with the x wrap of an e_x = -1 / +1 link applied
+  unsigned wxm = 0, wxp = 0;  // node index with the x wrap of an e_x = -1 / +1 link applied
+  TileLanes<L::Qf + L::Qg> tl;  // interior fast path
 
-  __device__ __forceinline__ Edges(const StepArgs<R>& a_, int x, int y, int z, unsigned node_) : a(a_), node(node_) {
+  __device__ __forceinline__ Edges(const StepArgs<R>& a_, int x, int y, int z, unsigned node_)
+      : a(a_), node(node_), tl(node_) {
     if (CX) {
       xlo = x == 0;
       xhi = x == a.nx - 1;
-      nxp = node + (xlo ? (unsigned)a.nx : 0u);
-      nxm = node - (xhi ? (unsigned)a.nx : 0u);
+      wxp = node + (xlo ? (unsigned)a.nx : 0u);
+      wxm = node - (xhi ? (unsigned)a.nx : 0u);
     }
     if (CY) {
       ylo = y == 0;
@@ -261,9 +282,16 @@ struct Edges {
   static constexpr bool checked() {
     return (CX && lex<L, TH>(A) != 0) || (CY && ley<L, TH>(A) != 0) || (CZ && lez<L, TH>(A) != 0);
   }
+  // padded-index offset of the source of link A (strides 1, nxp, nxp ny)
   template <int A, bool TH>
   __device__ __forceinline__ long long shift() const {
-    return (long long)lex<L, TH>(A) + (long long)ley<L, TH>(A) * a.nx + (long long)lez<L, TH>(A) * a.nx * a.ny;
+    return (long long)lex<L, TH>(A) + (long long)ley<L, TH>(A) * a.nxp + (long long)lez<L, TH>(A) * a.nxp * a.ny;
+  }
+  // the same in whole tiles, without the x component (wave-uniform)
+  template <int A, bool TH>
+  __device__ __forceinline__ int dtile() const {
+    const int rt = a.nxp >> 6;  // tiles per row
+    return ley<L, TH>(A) * rt + lez<L, TH>(A) * rt * a.ny;
   }
   // Checked link A: the wrapped source index (used with shift()) and the
   // axes on which the link meets a wall.
@@ -274,9 +302,9 @@ struct Edges {
     const bool ox = cx && (ex > 0 ? xlo : xhi);
     const bool oy = cy && (ey > 0 ? ylo : yhi);
     const bool oz = cz && (ez > 0 ? zlo : zhi);
-    unsigned idx = cx ? (ex > 0 ? nxp : nxm) : node;
-    if (cy) idx += oy ? (unsigned)(ey * a.ny) * (unsigned)a.nx : 0u;
-    if (cz) idx += oz ? (unsigned)(ez * a.nz) * (unsigned)a.nx * (unsigned)a.ny : 0u;
+    unsigned idx = cx ? (ex > 0 ? wxp : wxm) : node;
+    if (cy) idx += oy ? (unsigned)(ey * a.ny) * (unsigned)a.nxp : 0u;
+    if (cz) idx += oz ? (unsigned)(ez * a.nz) * (unsigned)a.nxp * (unsigned)a.ny : 0u;
     wx = ox && !PX && !a.per[0];
     wy = oy && !a.per[1];
     wz = oz && !a.per[2];
@@ -305,14 +333,16 @@ struct Gather {
   __device__ __forceinline__ Gather(const StepArgs<R>& a_, const M& m_, int x_, int y_, int z_, unsigned node_, R Tr_)
       : a(a_), m(m_), e(a_, x_, y_, z_, node_), x(x_), y(y_), z(z_), Tr(Tr_) {}
 
-  // Incoming population of link A of the fluid (TH = false, planes from 0)
-  // or thermal (TH = true, planes from Qf) distribution, pulled or bounced;
+  // Incoming population of link A of the fluid (TH = false, populations from
+  // 0) or thermal (TH = true, from Qf) distribution, pulled or bounced;
   // reports per axis whether the link met a wall there.
   template <int A, bool TH>
   __device__ __forceinline__ R pull(bool& wx, bool& wy, bool& wz) const {
     constexpr int QBASE = TH ? L::Qf : 0;
+    constexpr int ex = lex<L, TH>(A);
+    if (!E::template checked<A, TH>())
+      return m.load_tile(QBASE + A, e.tl.template base<ex>(e.template dtile<A, TH>()), e.tl.template lane<ex>());
     const long long sh = e.template shift<A, TH>();
-    if (!E::template checked<A, TH>()) return m.load(QBASE + A, sh, e.node);
     const unsigned idx = e.template source<A, TH>(wx, wy, wz);
     if (E::template wrap_only<A, TH>()) return m.load(QBASE + A, sh, idx);
     const bool wall = wx || wy || wz;

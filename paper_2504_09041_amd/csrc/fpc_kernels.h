@@ -25,8 +25,8 @@ struct StepArgs {
   const R* __restrict__ src;  // S_{n-1}
   R* __restrict__ dst;        // S_n
   int nx, ny, nz;
+  int nxp;                    // row length of the storage layout (nx rounded up to 64)
   int per[3];                 // axis periodic flags
-  size_t plane;               // element stride between population planes
   CollParams<R> c;
   R rho_w;                    // moving-wall density
   // storage reference of g: Tr(x, y, z) = T_o + Tg . (x, y, z)
@@ -70,7 +70,7 @@ struct StateDesc {
   int precision;  // 0 FP64, 1 FP32 deviations
   int lattice;    // 1 = 2D, 2 = 3D
   int nx, ny, nz;
-  size_t plane;
+  int nxp;  // row length of the storage layout (nx rounded up to 64)
   double rho_r, T_r;  // storage offsets (T_r at the box centre)
   double T_o, Tg[3];  // thermal storage reference Tr(x, y, z) = T_o + Tg . (x, y, z)
   double cs2T;

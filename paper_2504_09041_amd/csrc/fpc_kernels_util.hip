@@ -47,9 +47,19 @@ __device__ __forceinline__ double tref_node(const StateDesc& d, size_t node) {
   return d.T_o + (d.Tg[0] * (double)x + d.Tg[1] * (double)y + d.Tg[2] * (double)z);
 }
 
+// Element of population q of (unpadded) node `node` in the storage layout:
+// rows padded to nxp nodes, tiles of 64 padded nodes each holding its Q
+// populations as runs of 64 values.
+__device__ __forceinline__ size_t slot(const StateDesc& d, int q, size_t node) {
+  const size_t x = node % d.nx, row = node / d.nx;  // row = z ny + y
+  const size_t n = row * (size_t)d.nxp + x;
+  const size_t Q = (size_t)(qf_of(d.lattice) + qg_of(d.lattice));
+  return ((n >> 6) * Q + (size_t)q) * 64 + (n & 63);
+}
+
 template <class R>
 __device__ __forceinline__ double ld(const StateDesc& d, int q, size_t node) {
-  return (double)static_cast<const R*>(d.src)[q * d.plane + node];
+  return (double)static_cast<const R*>(d.src)[slot(d, q, node)];
 }
 
 // FP64 macros of one node (rho, u[3], T).
@@ -111,10 +121,10 @@ __global__ void __launch_bounds__(kBlock) import_kernel(StateDesc d, R* out, con
   if (node >= N) return;
   const int Qf = qf_of(d.lattice);
   const int Qg = qg_of(d.lattice);
-  for (int q = 0; q < Qf; ++q) out[q * d.plane + node] = (R)(src[q * N + node] - wfluid(d.lattice, q) * d.rho_r);
+  for (int q = 0; q < Qf; ++q) out[slot(d, q, node)] = (R)(src[q * N + node] - wfluid(d.lattice, q) * d.rho_r);
   const double tr = tref_node(d, node);
   for (int q = 0; q < Qg; ++q)
-    out[(Qf + q) * d.plane + node] = (R)(src[(Qf + q) * N + node] - wtherm(d.lattice, d.cs2T, q) * tr);
+    out[slot(d, Qf + q, node)] = (R)(src[(Qf + q) * N + node] - wtherm(d.lattice, d.cs2T, q) * tr);
 }
 
 // Deterministic block reduction: sum (op 0) or max (op 1) over kBlock values.

@@ -4,12 +4,13 @@
 // S_{n-1} with the wall rules applied at its own node (fpc_gather.h), collides
 // in registers (fpc_collide.h) and stores its own values to S_n.
 //
-// Boundary handling is resolved per wavefront: a ballot tells whether any lane
-// of the wave sits on an x, y or z edge of the box, and the gather is
-// instantiated with range checks only on those axes.  Interior wavefronts (the
-// vast majority) load every population from a wave-uniform plane offset with a
-// 32-bit lane offset and no checks at all; x-edge wavefronts of a periodic x
-// axis only wrap.
+// A wavefront owns one 64-node tile of the storage layout (blocks are whole
+// multiples of 64 along x, rows are padded to whole tiles).  Boundary handling
+// is resolved per wavefront: a ballot tells whether any lane of the wave sits
+// on an x, y or z edge of the box, and the gather is instantiated with range
+// checks only on those axes.  Interior wavefronts (the vast majority) load
+// every population from a wave-uniform tile offset plus a per-lane constant
+// and no checks at all; x-edge wavefronts of a periodic x axis only wrap.
 //
 // Stores are non-temporal when the state is too large to stay in the
 // last-level cache (it then streams through HBM anyway); smaller states keep
@@ -29,6 +30,8 @@
 #ifndef FPC_STEP_ATTR
 #define FPC_STEP_ATTR
 #endif
+
+static_assert(FPC_BLOCK_X_MAX % 64 == 0, "a wavefront must cover one whole 64-node tile");
 
 namespace fpc {
 namespace {
@@ -58,8 +61,8 @@ __global__ void __launch_bounds__(256) FPC_STEP_ATTR step_kernel(StepArgs<R> a, 
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
   const int z = blockIdx.z;
   if (x >= a.nx || y >= a.ny) return;
-  const M m(a.src, a.dst, a.plane, total_bytes);
-  const unsigned node = node_of(x, y, z, a.nx, a.ny);
+  const M m(a.src, a.dst, total_bytes);
+  const unsigned node = node_of(x, y, z, a.nxp, a.ny);
   const R Tr = tref(a, x, y, z);
   R f[L::Qf], g[L::Qg];
   // which axes have an edge node in this wavefront (wave-uniform)
@@ -86,17 +89,18 @@ __global__ void __launch_bounds__(256) init_kernel(StepArgs<R> a, const double* 
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
   const int z = blockIdx.z;
   if (x >= a.nx || y >= a.ny) return;
-  const Glob64<R> m(a.src, a.dst, a.plane, 0u);
-  const unsigned node = node_of(x, y, z, a.nx, a.ny);
+  using M = Glob64<R, L::Qf + L::Qg>;
+  const M m(a.src, a.dst, 0u);
+  const unsigned node = node_of(x, y, z, a.nxp, a.ny);
   R f[L::Qf], g[L::Qg];
   const R drw = a.rho_w - a.c.rho_r;
 #pragma unroll
   for (int q = 0; q < L::Qf; ++q) f[q] = R(L::w(q)) * drw;
   const R Tr = tref(a, x, y, z);
-  const R dT = R(T_init[node]) - Tr;
+  const R dT = R(T_init[((size_t)z * a.ny + y) * a.nx + x]) - Tr;
 #pragma unroll
   for (int q = 0; q < L::Qg; ++q) g[q] = L::template wT<R>(q, a.c.cs2T) * dT;
-  collide_store<L, R, Glob64<R>, UP, false, false>(a, m, node, Tr, f, g);
+  collide_store<L, R, M, UP, false, false>(a, m, node, Tr, f, g);
 }
 
 // Whether the rates form the standard set of rate_f / rate_g: the viscous
@@ -126,27 +130,29 @@ hipError_t launch_up(const StepArgs<R>& a, const double* T_init, int mode, hipSt
     init_kernel<L, R, UP><<<grid, block, 0, s>>>(a, T_init);
     return hipGetLastError();
   }
-  const double state_bytes = (double)a.plane * (L::Qf + L::Qg) * sizeof(R);
+  const double state_bytes = (double)a.nxp * a.ny * a.nz * (L::Qf + L::Qg) * sizeof(R);
+  using B32 = Buf32<R, L::Qf + L::Qg>;
+  using G64 = Glob64<R, L::Qf + L::Qg>;
   const bool nt = state_bytes > FPC_NT_MIB * 1024.0 * 1024.0;
   const bool std_rates = standard_rates(a, L::D, L::Qg);
   if (state_bytes < 4294967296.0) {
     const unsigned tb = (unsigned)state_bytes;
     if (nt) {
       if (std_rates)
-        step_kernel<L, R, Buf32<R>, UP, true, true><<<grid, block, 0, s>>>(a, tb);
+        step_kernel<L, R, B32, UP, true, true><<<grid, block, 0, s>>>(a, tb);
       else
-        step_kernel<L, R, Buf32<R>, UP, true, false><<<grid, block, 0, s>>>(a, tb);
+        step_kernel<L, R, B32, UP, true, false><<<grid, block, 0, s>>>(a, tb);
     } else {
       if (std_rates)
-        step_kernel<L, R, Buf32<R>, UP, false, true><<<grid, block, 0, s>>>(a, tb);
+        step_kernel<L, R, B32, UP, false, true><<<grid, block, 0, s>>>(a, tb);
       else
-        step_kernel<L, R, Buf32<R>, UP, false, false><<<grid, block, 0, s>>>(a, tb);
+        step_kernel<L, R, B32, UP, false, false><<<grid, block, 0, s>>>(a, tb);
     }
   } else {
     if (std_rates)
-      step_kernel<L, R, Glob64<R>, UP, true, true><<<grid, block, 0, s>>>(a, 0u);
+      step_kernel<L, R, G64, UP, true, true><<<grid, block, 0, s>>>(a, 0u);
     else
-      step_kernel<L, R, Glob64<R>, UP, true, false><<<grid, block, 0, s>>>(a, 0u);
+      step_kernel<L, R, G64, UP, true, false><<<grid, block, 0, s>>>(a, 0u);
   }
   return hipGetLastError();
 }

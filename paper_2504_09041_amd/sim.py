@@ -104,10 +104,11 @@ def params_from_workload(cfg, precision="f64", shape=None, cs2_T=None, T_referen
 
 
 def state_bytes(p):
+    """(bytes per state buffer, padded row length nxp) of the storage layout."""
     nb = ctypes.c_size_t()
-    ps = ctypes.c_size_t()
-    A.call("fpc_state_bytes", ctypes.byref(p), ctypes.byref(nb), ctypes.byref(ps))
-    return nb.value, ps.value
+    rs = ctypes.c_size_t()
+    A.call("fpc_state_bytes", ctypes.byref(p), ctypes.byref(nb), ctypes.byref(rs))
+    return nb.value, rs.value
 
 
 class Simulation:
@@ -126,10 +127,12 @@ class Simulation:
             t = t.to(self.device, torch.float64).contiguous()
             self._profiles[fi] = t
             self.params.wall_T_profile[fi] = t.data_ptr()
-        self.nbytes, self.plane = state_bytes(self.params)
+        self.nbytes, self.nxp = state_bytes(self.params)
         self.Qf, self.Qg, self.dim = Q[self.params.lattice]
         self.shape = (self.params.nx, self.params.ny, self.params.nz)
         self.N = self.params.nx * self.params.ny * self.params.nz
+        self.Np = self.nxp * self.params.ny * self.params.nz  # padded node count
+        self.dtype = torch.float64 if self.params.precision == A.FPC_FP64 else torch.float32
         with torch.cuda.device(self.device):
             self.buffers = [torch.empty(self.nbytes, dtype=torch.uint8, device=self.device) for _ in range(2)]
             self.stream = torch.cuda.current_stream(self.device)
@@ -234,9 +237,38 @@ class Simulation:
         A.call("fpc_current_buffer", self._h, ctypes.byref(p))
         return p.value
 
-    def state_view(self):
-        """The current state buffer viewed in storage format, shape (Qf+Qg, plane)."""
+    # -- storage layout ----------------------------------------------------
+    # Rows are padded to nxp = nx rounded up to 64; tiles of 64 padded nodes
+    # hold their Q populations as consecutive runs of 64 values (see
+    # fpc_state_bytes in include/fpclbm.h).  These helpers only move values
+    # between that layout and (Q, nz, ny, nx) arrays; padding is zero.
+    def to_storage(self, values, dtype=None):
+        """(Qf+Qg, nz, ny, nx) values -> flat tensor in the storage layout."""
+        nx, ny, nz = self.shape
+        Qt = self.Qf + self.Qg
+        dt = self.dtype if dtype is None else dtype
+        v = torch.as_tensor(values).to(self.device, dt).reshape(Qt, nz, ny, nx)
+        pad = torch.zeros((Qt, nz, ny, self.nxp), dtype=dt, device=self.device)
+        pad[..., :nx] = v
+        return pad.reshape(Qt, self.Np // 64, 64).permute(1, 0, 2).contiguous().reshape(-1)
+
+    def from_storage(self, buf):
+        """Flat storage-layout tensor (elements, or the raw bytes of a state
+        buffer) -> (Qf+Qg, nz, ny, nx) copy in its element type."""
+        nx, ny, nz = self.shape
+        Qt = self.Qf + self.Qg
+        if buf.dtype == torch.uint8:
+            buf = buf.view(self.dtype)
+        t = buf.reshape(self.Np // 64, Qt, 64).permute(1, 0, 2).reshape(Qt, nz, ny, self.nxp)
+        return t[..., :nx].contiguous()
+
+    def new_adjoint(self):
+        """A zeroed adjoint state (storage layout, the state's element type)."""
+        return torch.zeros(self.Np * (self.Qf + self.Qg), dtype=self.dtype, device=self.device)
+
+    def state_populations(self):
+        """The current state in storage form (deviations in FP32_DEV mode),
+        shape (Qf+Qg, nz, ny, nx)."""
         ptr = self.current_buffer()
         buf = self.buffers[0] if ptr == self.buffers[0].data_ptr() else self.buffers[1]
-        dt = torch.float64 if self.params.precision == A.FPC_FP64 else torch.float32
-        return buf.view(dt).view(self.Qf + self.Qg, self.plane)
+        return self.from_storage(buf)

@@ -62,9 +62,14 @@ def test_validation_errors():
     assert lib.fpc_params_default(ctypes.byref(p), 7, 0, 8, 8, 1) == A.FPC_ERR_ARG
     assert lib.fpc_params_default(ctypes.byref(p), A.FPC_D2Q9_D2Q5, 0, 8, 8, 2) == A.FPC_ERR_SIZE
     assert lib.fpc_params_default(ctypes.byref(p), A.FPC_D2Q9_D2Q5, 0, 8, 8, 1) == A.FPC_OK
-    nb, ps = ctypes.c_size_t(), ctypes.c_size_t()
-    assert lib.fpc_state_bytes(ctypes.byref(p), ctypes.byref(nb), ctypes.byref(ps)) == A.FPC_OK
-    assert ps.value >= 64 and ps.value % 64 == 0 and nb.value == ps.value * 14 * 8
+    nb, rs = ctypes.c_size_t(), ctypes.c_size_t()
+    assert lib.fpc_state_bytes(ctypes.byref(p), ctypes.byref(nb), ctypes.byref(rs)) == A.FPC_OK
+    # rows padded to whole 64-node tiles: nxp = 64, 8 rows, Q = 14 FP64 values per node
+    assert rs.value == 64 and nb.value == 64 * 8 * 14 * 8
+    q = A.fpc_params()
+    assert lib.fpc_params_default(ctypes.byref(q), A.FPC_D3Q27_D3Q7, A.FPC_FP32_DEV, 130, 3, 5) == A.FPC_OK
+    assert lib.fpc_state_bytes(ctypes.byref(q), ctypes.byref(nb), ctypes.byref(rs)) == A.FPC_OK
+    assert rs.value == 192 and nb.value == 192 * 3 * 5 * 34 * 4
     p.omega_f[4] = 2.0
     assert lib.fpc_state_bytes(ctypes.byref(p), ctypes.byref(nb), None) == A.FPC_ERR_ARG
     assert "omega_f[4]" in A.last_error()
@@ -117,3 +122,31 @@ def test_parameter_mapping_matches_oracle(name):
         assert math.isclose(p.g_beta, o.g_beta, rel_tol=1e-14)
         assert math.isclose(p.cs2_T, o.cs2T, rel_tol=1e-15)
         assert p.T0 == o.T0 and p.up_axis == o.up_axis
+
+
+def test_storage_layout_helpers_match_the_documented_layout():
+    """Simulation.to_storage / from_storage place population q of node
+    (x, y, z) at element (t Q + q) 64 + n % 64, n = (z ny + y) nxp + x,
+    t = n // 64 (the layout fpc_state_bytes documents), and round-trip."""
+    import types
+
+    import torch
+
+    from paper_2504_09041_amd.sim import Simulation
+
+    nx, ny, nz, Qf, Qg = 70, 3, 2, 9, 5
+    nxp = 128
+    m = types.SimpleNamespace(shape=(nx, ny, nz), Qf=Qf, Qg=Qg, nxp=nxp, Np=nxp * ny * nz,
+                              dtype=torch.float64, device=torch.device("cpu"))
+    Q = Qf + Qg
+    vals = torch.arange(Q * nz * ny * nx, dtype=torch.float64).reshape(Q, nz, ny, nx) + 1.0
+    flat = Simulation.to_storage(m, vals)
+    assert flat.numel() == m.Np * Q
+    for q, z, y, x in [(0, 0, 0, 0), (3, 1, 2, 69), (13, 0, 1, 64), (7, 1, 0, 63), (Qf, 1, 2, 5)]:
+        n = (z * ny + y) * nxp + x
+        assert flat[(n // 64 * Q + q) * 64 + n % 64] == vals[q, z, y, x]
+    # padding nodes (x >= nx) are zero
+    n = (1 * ny + 2) * nxp + 100
+    assert flat[(n // 64 * Q + 2) * 64 + n % 64] == 0
+    assert torch.equal(Simulation.from_storage(m, flat), vals)
+    assert torch.equal(Simulation.from_storage(m, flat.view(torch.uint8)), vals)

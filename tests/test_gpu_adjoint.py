@@ -41,14 +41,11 @@ def _profile_shape(cfg, face):
 
 
 def _lam_buffer(sim, values, dtype):
-    out = torch.zeros((sim.Qf + sim.Qg, sim.plane), dtype=dtype, device="cuda")
-    out[:, : sim.N] = values.reshape(sim.Qf + sim.Qg, sim.N).to("cuda", dtype)
-    return out
+    return sim.to_storage(values, dtype)
 
 
 def _from_lam(sim, lam):
-    nx, ny, nz = sim.shape
-    return lam[:, : sim.N].double().cpu().reshape(sim.Qf + sim.Qg, nz, ny, nx)
+    return sim.from_storage(lam).double().cpu()
 
 
 def _ptr(t):
