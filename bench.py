@@ -87,14 +87,15 @@ def copy_bandwidth(mib, reps):
 
 
 def kernel_fingerprint():
-    """sha256 over the sources of the forward step kernel: counters recorded
-    for other sources do not describe the kernel that runs."""
+    """sha256 over the sources of the step and adjoint kernels: counters
+    recorded for other sources do not describe the kernels that run."""
     import hashlib
 
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2504_09041_amd", "csrc")
-    # the forward step kernel and everything it includes
-    for name in ("fpc_step.hip", "fpc_collide.h", "fpc_kernels.h", "fpc_lattice.h"):
+    # the step and adjoint kernels and everything they include
+    for name in ("fpc_step.hip", "fpc_adjoint.hip", "fpc_adjoint.h", "fpc_gather.h", "fpc_collide.h",
+                 "fpc_kernels.h", "fpc_lattice.h"):
         with open(os.path.join(csrc, name), "rb") as fh:
             h.update(name.encode() + b"\0" + fh.read())
     return h.hexdigest()[:16]

@@ -24,6 +24,10 @@ SMALL_CASES = {
     "dhc3d": ("dhc3d_256", (6, 5, 4)),
     "rb3d": ("rb3d_128", (5, 4, 6)),
     "lid3d": ("rb3d_128", (4, 5, 6)),  # faces replaced below: moving +z lid, Dirichlet +-z
+    # rows of several 64-node storage tiles with a ragged last tile: interior
+    # waves (fast path), periodic-x edge waves, x-wall edge waves
+    "rb2d_tiles": ("rb2d_1024x512", (200, 5, 1)),
+    "dhc3d_tiles": ("dhc3d_256", (130, 4, 3)),
 }
 
 
