@@ -86,16 +86,17 @@ def copy_bandwidth(mib, reps):
             "GBs": nbytes / (ms * 1e-3) / 1e9}
 
 
-def kernel_fingerprint():
-    """sha256 over the sources of the step and adjoint kernels: counters
-    recorded for other sources do not describe the kernels that run."""
+def kernel_fingerprint(kind="step"):
+    """sha256 over the sources of the step kernel (kind "step") or of the
+    adjoint step kernel (kind "adjoint"), everything they include: counters
+    recorded for other sources do not describe the kernel that runs."""
     import hashlib
 
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2504_09041_amd", "csrc")
-    # the step and adjoint kernels and everything they include
-    for name in ("fpc_step.hip", "fpc_adjoint.hip", "fpc_adjoint.h", "fpc_gather.h", "fpc_collide.h",
-                 "fpc_kernels.h", "fpc_lattice.h"):
+    common = ("fpc_gather.h", "fpc_collide.h", "fpc_kernels.h", "fpc_lattice.h")
+    own = ("fpc_step.hip",) if kind == "step" else ("fpc_adjoint.hip", "fpc_adjoint.h")
+    for name in own + common:
         with open(os.path.join(csrc, name), "rb") as fh:
             h.update(name.encode() + b"\0" + fh.read())
     return h.hexdigest()[:16]
@@ -142,7 +143,7 @@ def pmc_summary(a):
         "fetch_scale": sf, "write_scale": sw, "dispatches": [nf, nw],
     }
     rec["traffic_bytes"] = rec["fetch_bytes"] + rec["write_bytes"]
-    rec["sources"] = kernel_fingerprint()
+    rec["sources"] = kernel_fingerprint("adjoint" if "adjoint" in a.kernel_regex else "step")
     path = os.path.join(ROOT, "profiles", "traffic.json")
     allrec = _traffic_record()
     allrec[a.key] = rec

@@ -22,6 +22,12 @@
 #include "fpc_adjoint.h"
 #include "fpc_gather.h"
 
+// Extra attributes of the 3D FP32 adjoint step kernel: its natural register
+// count sits just above the 168 VGPRs that allow 3 waves per SIMD.
+#ifndef FPC_ADJ3F_ATTR
+#define FPC_ADJ3F_ATTR __attribute__((amdgpu_waves_per_eu(3)))
+#endif
+
 namespace fpc {
 namespace {
 
@@ -148,7 +154,7 @@ __device__ __forceinline__ void scatter(const AdjArgs<R>& A, const M& mL, int x,
 // The edge variant is chosen per wavefront (ballot) for the gather and again
 // for the scatter; the collision and its adjoint in between are shared.
 template <class L, class R, class M, int UP>
-__global__ void __launch_bounds__(256) adjoint_step_kernel(AdjArgs<R> A, unsigned total_bytes) {
+__device__ __forceinline__ void adjoint_step(const AdjArgs<R>& A, unsigned total_bytes) {
   constexpr int D = L::D;
   const StepArgs<R>& a = A.s;
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
@@ -197,6 +203,15 @@ __global__ void __launch_bounds__(256) adjoint_step_kernel(AdjArgs<R> A, unsigne
     scatter<L, R, M, true, false, false>(A, mL, x, y, z, node, fb, gb);
   else
     scatter<L, R, M, true, true, D == 3>(A, mL, x, y, z, node, fb, gb);
+}
+
+template <class L, class R, class M, int UP>
+__global__ void __launch_bounds__(256) adjoint_step_kernel(AdjArgs<R> A, unsigned total_bytes) {
+  adjoint_step<L, R, M, UP>(A, total_bytes);
+}
+template <class L, class M, int UP>
+__global__ void __launch_bounds__(256) FPC_ADJ3F_ATTR adjoint_step_kernel_3f(AdjArgs<float> A, unsigned total_bytes) {
+  adjoint_step<L, float, M, UP>(A, total_bytes);
 }
 
 template <class R>
@@ -255,10 +270,17 @@ hipError_t launch_adj(const AdjArgs<R>* step, const AdjInitArgs<R>* init, hipStr
   if (step) {
     constexpr int Q = L::Qf + L::Qg;
     const double bytes = (double)a.nxp * a.ny * a.nz * Q * sizeof(R);
-    if (bytes < 4294967296.0)
-      adjoint_step_kernel<L, R, Buf32<R, Q>, UP><<<grid, block, 0, st>>>(*step, (unsigned)bytes);
-    else
-      adjoint_step_kernel<L, R, Glob64<R, Q>, UP><<<grid, block, 0, st>>>(*step, 0u);
+    if constexpr (D == 3 && sizeof(R) == 4) {
+      if (bytes < 4294967296.0)
+        adjoint_step_kernel_3f<L, Buf32<R, Q>, UP><<<grid, block, 0, st>>>(*step, (unsigned)bytes);
+      else
+        adjoint_step_kernel_3f<L, Glob64<R, Q>, UP><<<grid, block, 0, st>>>(*step, 0u);
+    } else {
+      if (bytes < 4294967296.0)
+        adjoint_step_kernel<L, R, Buf32<R, Q>, UP><<<grid, block, 0, st>>>(*step, (unsigned)bytes);
+      else
+        adjoint_step_kernel<L, R, Glob64<R, Q>, UP><<<grid, block, 0, st>>>(*step, 0u);
+    }
   } else {
     adjoint_init_kernel<D, R, UP><<<grid, block, 0, st>>>(*init);
   }
