@@ -150,3 +150,19 @@ def test_storage_layout_helpers_match_the_documented_layout():
     assert flat[(n // 64 * Q + 2) * 64 + n % 64] == 0
     assert torch.equal(Simulation.from_storage(m, flat), vals)
     assert torch.equal(Simulation.from_storage(m, flat.view(torch.uint8)), vals)
+
+
+@pytest.mark.parametrize("wl,shape", [("dhc2d_64", (1, 5, 1)), ("mixed2d_512", (5, 1, 1)),
+                                      ("dhc3d_256", (4, 3, 1))])
+def test_walled_axis_of_one_node_is_rejected(wl, shape):
+    """A walled axis needs two nodes (the wall Nusselt stencil reads two
+    layers): the library refuses one before any launch; a periodic axis of
+    one node is accepted."""
+    import workloads
+    from paper_2504_09041_amd.sim import params_from_workload, state_bytes
+
+    with pytest.raises(A.FpcError) as e:
+        state_bytes(params_from_workload(workloads.config(wl, shape=shape), "f64"))
+    assert e.value.code == A.FPC_ERR_SIZE
+    nb, nxp = state_bytes(params_from_workload(workloads.config("rb2d_1024x512", shape=(1, 6, 1)), "f64"))
+    assert nxp == 64 and nb == 64 * 6 * 14 * 8
