@@ -178,7 +178,12 @@ int fpc_params_mixed(fpc_params* p, double Re, double Ri, double Pe, double U_li
  * thermal) one after the other as runs of 64 values, so population q of node
  * n is element (t Q + q) 64 + n % 64.  Elements of padding nodes
  * (x >= nx) are never read or written by the step kernels.
- * bytes_per_buffer = nxp ny nz Q sizeof(element). */
+ * bytes_per_buffer = nxp ny nz Q sizeof(element).
+ * Validates the parameters first: FPC_ERR_ARG for invalid rates, faces, lid
+ * velocities, references or codes; FPC_ERR_SIZE when an axis length is not
+ * positive, a walled axis has fewer than 2 nodes, the padded node count
+ * nxp ny nz reaches 2^31, or a state would hold more than 4e10 populations.
+ * Either output pointer may be NULL. */
 int fpc_state_bytes(const fpc_params* p, size_t* bytes_per_buffer, size_t* row_stride);
 
 /*

@@ -166,3 +166,29 @@ def test_walled_axis_of_one_node_is_rejected(wl, shape):
     assert e.value.code == A.FPC_ERR_SIZE
     nb, nxp = state_bytes(params_from_workload(workloads.config("rb2d_1024x512", shape=(1, 6, 1)), "f64"))
     assert nxp == 64 and nb == 64 * 6 * 14 * 8
+
+
+def test_size_limits():
+    """Largest grids: the padded node count nxp ny nz must stay below 2^31
+    (32-bit node indices in the kernels) and a state below 4e10 populations;
+    just below the limits is accepted."""
+    lib = _lib()
+    nb = ctypes.c_size_t()
+
+    def state_rc(lattice, nx, ny, nz):
+        p = A.fpc_params()
+        assert lib.fpc_params_default(ctypes.byref(p), lattice, A.FPC_FP32_DEV, nx, ny, nz) == A.FPC_OK
+        return lib.fpc_state_bytes(ctypes.byref(p), ctypes.byref(nb), None)
+
+    # 2D: 65536 x 32767 padded nodes < 2^31
+    assert state_rc(A.FPC_D2Q9_D2Q5, 65536, 32767, 1) == A.FPC_OK
+    assert nb.value == 65536 * 32767 * 14 * 4
+    # 65536 x 32768 = 2^31 padded nodes: rejected
+    assert state_rc(A.FPC_D2Q9_D2Q5, 65536, 32768, 1) == A.FPC_ERR_SIZE
+    # padding counts: nx = 65473 pads to 65536
+    assert state_rc(A.FPC_D2Q9_D2Q5, 65473, 32768, 1) == A.FPC_ERR_SIZE
+    # 3D: 1290^3 padded to 1344 x 1290 x 1290 > 2^31
+    assert state_rc(A.FPC_D3Q27_D3Q7, 1290, 1290, 1290) == A.FPC_ERR_SIZE
+    assert state_rc(A.FPC_D3Q27_D3Q7, 1024, 1024, 1024) == A.FPC_OK
+    # more than 4e10 populations per state (1280^3 x 34) is rejected as well
+    assert state_rc(A.FPC_D3Q27_D3Q7, 1280, 1280, 1280) == A.FPC_ERR_SIZE
