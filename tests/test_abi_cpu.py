@@ -192,3 +192,50 @@ def test_size_limits():
     assert state_rc(A.FPC_D3Q27_D3Q7, 1024, 1024, 1024) == A.FPC_OK
     # more than 4e10 populations per state (1280^3 x 34) is rejected as well
     assert state_rc(A.FPC_D3Q27_D3Q7, 1280, 1280, 1280) == A.FPC_ERR_SIZE
+
+
+def test_null_and_invalid_arguments_fail_before_any_launch():
+    """Argument errors are caught on the host and reported through the status
+    code and fpc_last_error, without touching a device."""
+    lib = _lib()
+    vp = ctypes.c_void_p
+    p = A.fpc_params()
+    assert lib.fpc_params_default(ctypes.byref(p), A.FPC_D2Q9_D2Q5, A.FPC_FP64, 8, 8, 1) == A.FPC_OK
+    h = vp()
+    # NULL parameters / output handle
+    assert lib.fpc_create(None, vp(256), vp(512), None, ctypes.byref(h)) == A.FPC_ERR_ARG
+    assert lib.fpc_create(ctypes.byref(p), vp(256), vp(512), None, None) == A.FPC_ERR_ARG
+    # missing, identical or unaligned state buffers (never dereferenced)
+    assert lib.fpc_create(ctypes.byref(p), None, vp(512), None, ctypes.byref(h)) == A.FPC_ERR_ARG
+    assert lib.fpc_create(ctypes.byref(p), vp(256), vp(256), None, ctypes.byref(h)) == A.FPC_ERR_ARG
+    assert lib.fpc_create(ctypes.byref(p), vp(256), vp(520), None, ctypes.byref(h)) == A.FPC_ERR_ARG
+    assert "aligned" in A.last_error()
+    assert h.value is None
+    # invalid parameters are rejected by fpc_create as by fpc_state_bytes
+    p.omega_f[4] = 0.0
+    assert lib.fpc_create(ctypes.byref(p), vp(256), vp(512), None, ctypes.byref(h)) == A.FPC_ERR_ARG
+    # NULL simulation handle on every call that takes one
+    ll = ctypes.c_longlong()
+    d = ctypes.c_double()
+    assert lib.fpc_destroy(None) == A.FPC_ERR_ARG
+    assert lib.fpc_set_stream(None, None) == A.FPC_ERR_ARG
+    assert lib.fpc_init(None, vp(256)) == A.FPC_ERR_ARG
+    assert lib.fpc_step(None, 1) == A.FPC_ERR_ARG
+    assert lib.fpc_step_from(None, vp(256), vp(512)) == A.FPC_ERR_ARG
+    assert lib.fpc_get_step(None, ctypes.byref(ll)) == A.FPC_ERR_ARG
+    assert lib.fpc_macros(None, None, None, None) == A.FPC_ERR_ARG
+    assert lib.fpc_diagnostics(None, 0, ctypes.byref(d), ctypes.byref(d), ctypes.byref(d),
+                               ctypes.byref(d)) == A.FPC_ERR_ARG
+    assert lib.fpc_save(None, vp(256)) == A.FPC_ERR_ARG
+    assert lib.fpc_load(None, vp(256), 0) == A.FPC_ERR_ARG
+    assert lib.fpc_export_fp64(None, vp(256)) == A.FPC_ERR_ARG
+    assert lib.fpc_import_fp64(None, vp(256), 0) == A.FPC_ERR_ARG
+    assert lib.fpc_current_buffer(None, ctypes.byref(vp())) == A.FPC_ERR_ARG
+    assert lib.fpc_adjoint_step(None, vp(256), vp(512), vp(768), None, ctypes.c_double(0.0), None) == A.FPC_ERR_ARG
+    assert lib.fpc_adjoint_init(None, vp(256), vp(512), None, ctypes.c_double(0.0), vp(768)) == A.FPC_ERR_ARG
+    assert "NULL" in A.last_error()
+    # NULL parameter blocks of the helpers
+    assert lib.fpc_params_default(None, A.FPC_D2Q9_D2Q5, A.FPC_FP64, 8, 8, 1) == A.FPC_ERR_ARG
+    assert lib.fpc_params_natural(None, 1e6, 0.71, 0.05, 1, 0.5, -0.5) == A.FPC_ERR_ARG
+    assert lib.fpc_params_mixed(None, 100.0, 1.0, 71.0, 0.1, 1, 0.5, -0.5) == A.FPC_ERR_ARG
+    assert lib.fpc_state_bytes(None, None, None) == A.FPC_ERR_ARG

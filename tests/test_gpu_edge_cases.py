@@ -121,3 +121,47 @@ def test_state_above_4GiB_on_sampled_nodes(workload, precision, shape, tol):
     assert G.rel_err(got[lf.Q:], go) < tol
     sim.close()
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("wl,n", [("dhc3d_256", 8), ("rb3d_128", 8), ("dhc3d_256", 16), ("rb3d_128", 16)])
+def test_cubes_match_oracle(wl, n):
+    """8^3 and 16^3 boxes (walls on every face, or periodic x / y), 100 FP64
+    steps: every node against the oracle."""
+    print(f"workload={wl} n={n}", flush=True)
+    cfg = workloads.config(wl, shape=(n, n, n))
+    f0, g0 = G.perturbed_state(cfg, seed=49)
+    sim = G.make_sim(cfg, "f64")
+    G.load_state(sim, f0, g0)
+    sim.step(100)
+    f, g = G.read_state(sim)
+    fo, go, _, _ = G.oracle_run(cfg, f0, g0, 100)
+    assert G.rel_err(f, fo) < 1e-12
+    assert G.rel_err(g, go) < 1e-12
+    sim.close()
+
+
+@pytest.mark.parametrize("reference,max_dT,max_dNu", [("uniform", 1e-4, 2e-3), ("conduction", 1e-6, 1e-5)])
+def test_fp32_tracks_fp64_at_full_size(reference, max_dT, max_dNu):
+    """2D Rayleigh-Benard 1024x512 from the same initial field, 4000 steps:
+    the FP32 deviation form against the GPU FP64 run (itself pinned to the
+    oracle).  With the conduction reference FP32 stays two orders inside the
+    bars (1e-4 of the temperature difference on T, 1e-3 on the bottom-wall
+    Nusselt number); with the uniform reference T stays inside its bar but
+    the Nusselt error has already grown to about 1e-3 by this step."""
+    from paper_2504_09041_amd.sim import Simulation, params_from_workload
+
+    cfg = workloads.config("rb2d_1024x512")
+    T0 = torch.tensor(workloads.initial_temperature(cfg), device="cuda")
+    out = {}
+    for prec, ref in (("f64", "uniform"), ("f32dev", reference)):
+        sim = Simulation(params_from_workload(cfg, prec, T_reference=ref))
+        sim.init(T0)
+        sim.step(4000)
+        out[prec] = (sim.macros()["T"], sim.diagnostics(cfg["nu_face"])["nu"])
+        sim.close()
+    dT = cfg["T_hot"] - cfg["T_cold"]
+    eT = float((out["f32dev"][0] - out["f64"][0]).abs().max()) / dT
+    eNu = abs(out["f32dev"][1] - out["f64"][1]) / abs(out["f64"][1])
+    print(f"reference={reference}: max|dT|/DeltaT {eT:.2e}, rel dNu {eNu:.2e}")
+    assert eT < max_dT
+    assert eNu < max_dNu
