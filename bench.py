@@ -412,6 +412,11 @@ def main():
         # last-level cache: a pure-HBM figure for the FP64 kernel
         extra["rb2d_4096x4096_f64"] = time_workload("rb2d_1024x512", "f64", a.steps3d, max(5, a.warmup // 10),
                                                     shape=(4096, 4096, 1))
+        # the 3D cavity at 64^3 in FP64 and the 512^2 mixed-convection case in
+        # FP32 (forward step of the adjoint workload)
+        extra["dhc3d_64_f64"] = time_workload("dhc3d_256", "f64", 5 * a.steps3d, max(5, a.warmup // 10),
+                                              shape=(64, 64, 64))
+        extra["mixed2d_512_f32dev"] = time_workload("mixed2d_512", "f32dev", a.steps, a.warmup)
         # the 64 x 64 cavity: launch-bound (4096 nodes per launch)
         extra["dhc2d_64_f64"] = time_workload("dhc2d_64", "f64", a.steps, a.warmup)
         extra["copy_4GiB"] = copy_bandwidth(4096, 20)

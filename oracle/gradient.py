@@ -43,4 +43,4 @@ def gradient(prm, T_init, nsteps, kind, face=None, window=None, theta_face=None,
     gth = None
     if th is not None:
         gth = grads[1] if grads[1] is not None else torch.zeros_like(th)
-    return float(J), gth, gT
+    return float(J.detach()), gth, gT

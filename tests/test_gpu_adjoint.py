@@ -141,6 +141,9 @@ GRAD_CASES = {
     "mixed2d_nu_bottom_theta": ("mixed2d_512", (12, 10, 1), ("nu", 3, (20, 40)), 40, 7, 2),
     "dhc2d_nu_on_theta_face": ("dhc2d_64", (10, 8, 1), ("nu", 0, (10, 30)), 30, 8, 0),
     "rb3d_ke": ("rb3d_128", (6, 5, 6), ("ke", None, 20), 20, 6, 4),
+    # the sizes of the gradient workloads' small analogues: 32^2 and 16^3
+    "mixed2d_nu_32": ("mixed2d_512", (32, 32, 1), ("nu", 3, (20, 40)), 40, 7, 2),
+    "rb3d_ke_16": ("rb3d_128", (16, 16, 16), ("ke", None, 20), 20, 5, 4),
 }
 
 
