@@ -47,6 +47,20 @@ __device__ __forceinline__ R tref(const StepArgs<R>& a, int x, int y, int z) {
   if constexpr (!kDeviations<R>) return R(0);
   return a.T_o + (a.Tg[0] * R(x) + a.Tg[1] * R(y) + a.Tg[2] * R(z));
 }
+// XCD-aware block order.  Workgroups are dispatched to the 8 XCDs round-robin
+// by linear block index, and each XCD has its own L2.  The remap hands XCD k
+// the k-th contiguous range of logical blocks, so that neighbouring rows (and
+// z planes) are processed by the same XCD and their pulls can hit its L2.
+// Returns the logical block coordinates of this workgroup (a bijection).
+constexpr unsigned kXcds = 8;
+__device__ __forceinline__ dim3 xcd_block() {
+  const unsigned nb = gridDim.x * gridDim.y * gridDim.z;
+  const unsigned b = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+  const unsigned k = b % kXcds, q = nb / kXcds, r = nb % kXcds;
+  const unsigned l = k * q + (k < r ? k : r) + b / kXcds;  // start of XCD k's range + rank within it
+  return dim3(l % gridDim.x, (l / gridDim.x) % gridDim.y, l / (gridDim.x * gridDim.y));
+}
+
 // Launchers of the fused step (defined in fpc_step.hip).
 // tk: thermal lattice, 0 = D2Q5 / D3Q7, 1 = D2Q9 / D3Q15 (FP64 only).
 // mode: 0 = step (pull from args.src), 1 = init (equilibrium from T_init).

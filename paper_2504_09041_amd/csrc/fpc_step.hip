@@ -21,6 +21,12 @@
 
 // Launch tuning (compile-time): widest block along x, state size above which
 // stores are non-temporal, optional extra kernel attributes.
+#ifndef FPC_BLOCK_2D
+#define FPC_BLOCK_2D 256  // threads per block of the 2D kernels
+#endif
+#ifndef FPC_XCD_2D
+#define FPC_XCD_2D 1  // XCD-aware block order (xcd_block) for the 2D kernels
+#endif
 #ifndef FPC_BLOCK_X_MAX
 #define FPC_BLOCK_X_MAX 256
 #endif
@@ -56,10 +62,13 @@ __device__ __forceinline__ void collide_store(const StepArgs<R>& a, const M& m, 
 // M: addressing policy (Buf32 when the buffer is below 4 GiB, else Glob64).
 // STD: the standard rate set (see rate_f / rate_g).
 template <class L, class R, class M, int UP, bool NT, bool STD>
-__global__ void __launch_bounds__(256) FPC_STEP_ATTR step_kernel(StepArgs<R> a, unsigned total_bytes) {
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  const int y = blockIdx.y * blockDim.y + threadIdx.y;
-  const int z = blockIdx.z;
+__global__ void __launch_bounds__(L::D == 2 ? FPC_BLOCK_2D : 256) FPC_STEP_ATTR
+    step_kernel(StepArgs<R> a, unsigned total_bytes) {
+  // XCD-aware block order for the 2D kernels (3D measured 1-3% slower with it)
+  const dim3 bi = (L::D == 2 && FPC_XCD_2D) ? xcd_block() : dim3(blockIdx.x, blockIdx.y, blockIdx.z);
+  const int x = bi.x * blockDim.x + threadIdx.x;
+  const int y = bi.y * blockDim.y + threadIdx.y;
+  const int z = bi.z;
   if (x >= a.nx || y >= a.ny) return;
   const M m(a.src, a.dst, total_bytes);
   const unsigned node = node_of(x, y, z, a.nxp, a.ny);
@@ -123,7 +132,7 @@ bool standard_rates(const StepArgs<R>& a, int D, int Qg) {
 template <class L, class R, int UP>
 hipError_t launch_up(const StepArgs<R>& a, const double* T_init, int mode, hipStream_t s) {
   const int bx = a.nx >= FPC_BLOCK_X_MAX ? FPC_BLOCK_X_MAX : (a.nx >= 128 ? 128 : 64);
-  const int by = 256 / bx;
+  const int by = (mode == 0 && L::D == 2 ? FPC_BLOCK_2D : 256) / bx;
   const dim3 block(bx, by, 1);
   const dim3 grid((a.nx + bx - 1) / bx, (a.ny + by - 1) / by, a.nz);
   if (mode == 1) {
