@@ -22,10 +22,6 @@
 #include "fpc_adjoint.h"
 #include "fpc_gather.h"
 
-#ifndef FPC_XCD_2D
-#define FPC_XCD_2D 1  // XCD-aware block order (xcd_block) for the 2D kernels
-#endif
-
 // Extra attributes of the 3D FP32 adjoint step kernel: its natural register
 // count sits just above the 168 VGPRs that allow 3 waves per SIMD.
 #ifndef FPC_ADJ3F_ATTR
@@ -161,7 +157,8 @@ template <class L, class R, class M, int UP>
 __device__ __forceinline__ void adjoint_step(const AdjArgs<R>& A, unsigned total_bytes) {
   constexpr int D = L::D;
   const StepArgs<R>& a = A.s;
-  // XCD-aware block order for 2D, as in the forward step
+  // XCD-aware block order in 2D as in the forward step (the 3D in-plane order
+  // measured neutral for the adjoint)
   const dim3 bi = (D == 2 && FPC_XCD_2D) ? xcd_block() : dim3(blockIdx.x, blockIdx.y, blockIdx.z);
   const int x = bi.x * blockDim.x + threadIdx.x;
   const int y = bi.y * blockDim.y + threadIdx.y;

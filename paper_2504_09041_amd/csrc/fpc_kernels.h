@@ -61,6 +61,33 @@ __device__ __forceinline__ dim3 xcd_block() {
   return dim3(l % gridDim.x, (l / gridDim.x) % gridDim.y, l / (gridDim.x * gridDim.y));
 }
 
+// The same within each z plane of blocks: XCD k takes the k-th contiguous
+// range of the plane's blocks (identity when a plane's block count is not a
+// multiple of 8).
+__device__ __forceinline__ dim3 xcd_block_plane() {
+  const unsigned g = gridDim.x * gridDim.y;
+  if (g % kXcds != 0) return dim3(blockIdx.x, blockIdx.y, blockIdx.z);
+  const unsigned i = blockIdx.x + gridDim.x * blockIdx.y;  // in-plane index; XCD = i % 8 since g % 8 == 0
+  const unsigned l = (i % kXcds) * (g / kXcds) + i / kXcds;
+  return dim3(l % gridDim.x, l / gridDim.x, blockIdx.z);
+}
+
+// Block order of the step and adjoint kernels (launch tuning, measured):
+// contiguous ranges of rows per XCD in 2D; in 3D FP32, contiguous ranges of
+// rows per XCD within each z plane; launch order otherwise.
+#ifndef FPC_XCD_2D
+#define FPC_XCD_2D 1
+#endif
+#ifndef FPC_XCD_3DF
+#define FPC_XCD_3DF 1
+#endif
+template <int D, int S>
+__device__ __forceinline__ dim3 block_order() {
+  if (D == 2 && FPC_XCD_2D) return xcd_block();
+  if (D == 3 && S == 4 && FPC_XCD_3DF) return xcd_block_plane();
+  return dim3(blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
 // Launchers of the fused step (defined in fpc_step.hip).
 // tk: thermal lattice, 0 = D2Q5 / D3Q7, 1 = D2Q9 / D3Q15 (FP64 only).
 // mode: 0 = step (pull from args.src), 1 = init (equilibrium from T_init).

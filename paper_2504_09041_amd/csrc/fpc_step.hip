@@ -24,9 +24,7 @@
 #ifndef FPC_BLOCK_2D
 #define FPC_BLOCK_2D 256  // threads per block of the 2D kernels
 #endif
-#ifndef FPC_XCD_2D
-#define FPC_XCD_2D 1  // XCD-aware block order (xcd_block) for the 2D kernels
-#endif
+
 #ifndef FPC_BLOCK_X_MAX
 #define FPC_BLOCK_X_MAX 256
 #endif
@@ -64,8 +62,10 @@ __device__ __forceinline__ void collide_store(const StepArgs<R>& a, const M& m, 
 template <class L, class R, class M, int UP, bool NT, bool STD>
 __global__ void __launch_bounds__(L::D == 2 ? FPC_BLOCK_2D : 256) FPC_STEP_ATTR
     step_kernel(StepArgs<R> a, unsigned total_bytes) {
-  // XCD-aware block order for the 2D kernels (3D measured 1-3% slower with it)
-  const dim3 bi = (L::D == 2 && FPC_XCD_2D) ? xcd_block() : dim3(blockIdx.x, blockIdx.y, blockIdx.z);
+  // XCD-aware block order: contiguous ranges of rows per XCD in 2D; in 3D
+  // FP32, contiguous ranges of rows per XCD within each z plane (3D FP64
+  // measured 2% slower with it, and 3D with whole z slabs per XCD 1-3%)
+  const dim3 bi = block_order<L::D, sizeof(R)>();
   const int x = bi.x * blockDim.x + threadIdx.x;
   const int y = bi.y * blockDim.y + threadIdx.y;
   const int z = bi.z;
