@@ -11,9 +11,12 @@ fpc_diagnostics reports it (a non-finite value or |u| > 0.5), checked every
 ``check`` steps.  The largest surviving Pe is found by bisection in log Pe.
 
     python -m paper_2504_09041_amd.stability [--scenario ma|grid|pr] [--steps N]
+        [--hint previous.json]
 
 prints one JSON object per finished point (on stderr as it goes) and one
-summary object on stdout.
+summary object on stdout.  ``--hint`` takes the summary of an earlier run with
+fewer steps: a point that failed within fewer steps also fails within more,
+so its bracket starts at [pe_max / 8, pe_unstable] of that run.
 """
 
 from __future__ import annotations
@@ -60,17 +63,17 @@ def survives(model, L, Ma, Pr, Pe, steps, check=5000, option="A"):
     return ok, n
 
 
-def max_stable_pe(model, L, Ma, Pr, steps, lo=10.0, hi=1e6, iters=8, log=None):
+def max_stable_pe(model, L, Ma, Pr, steps, lo=10.0, hi=1e6, iters=8, log=None, check=5000):
     """Bisection in log Pe between a stable lower point and an unstable
     ``hi``.  The lower point starts at ``lo`` and is raised by factors of 3
     while the run fails there (at high Pr the small-Pe end has very large
     viscosities, which fail on their own)."""
-    ok_hi, _ = survives(model, L, Ma, Pr, hi, steps)
+    ok_hi, _ = survives(model, L, Ma, Pr, hi, steps, check)
     if ok_hi:
         return {"pe_max": hi, "bound": "lower (stable at the top of the range)"}
     start = lo
     while True:
-        ok_lo, n_lo = survives(model, L, Ma, Pr, start, steps)
+        ok_lo, n_lo = survives(model, L, Ma, Pr, start, steps, check)
         if log:
             print(f"  {model} L={L} Ma={Ma} Pr={Pr} Pe={start:.4g} -> {'stable' if ok_lo else f'unstable at {n_lo}'}",
                   file=log, flush=True)
@@ -82,7 +85,7 @@ def max_stable_pe(model, L, Ma, Pr, steps, lo=10.0, hi=1e6, iters=8, log=None):
     a, b = math.log(start), math.log(hi)
     for _ in range(iters):
         mid = 0.5 * (a + b)
-        ok, n = survives(model, L, Ma, Pr, math.exp(mid), steps)
+        ok, n = survives(model, L, Ma, Pr, math.exp(mid), steps, check)
         if log:
             print(f"  {model} L={L} Ma={Ma} Pr={Pr} Pe={math.exp(mid):.4g} -> {'stable' if ok else f'unstable at {n}'}",
                   file=log, flush=True)
@@ -109,7 +112,15 @@ def main(argv=None):
     ap.add_argument("--iters", type=int, default=7)
     ap.add_argument("--models", default="FP,MCM")
     ap.add_argument("--points", default="", help="comma list of indices into the scenario (default: all)")
+    ap.add_argument("--hint", help="summary JSON of an earlier run with fewer steps (narrows the brackets)")
+    ap.add_argument("--check", type=int, default=5000, help="steps between watchdog checks")
     a = ap.parse_args(argv)
+    hints = {}
+    if a.hint:
+        with open(a.hint) as fh:
+            for r in json.load(fh)["stability"]:
+                if r.get("pe_max") and r.get("pe_unstable") and r.get("steps", 0) <= a.steps:
+                    hints[(r["model"], r["L"], r["Ma"], r["Pr"])] = (r["pe_max"] / 8.0, r["pe_unstable"])
     if not torch.cuda.is_available():
         print("the stability study needs a GPU", file=sys.stderr)
         sys.exit(1)
@@ -121,7 +132,9 @@ def main(argv=None):
         for (L, Ma, Pr) in pts:
             for model in a.models.split(","):
                 t0 = time.perf_counter()
-                r = max_stable_pe(model, L, Ma, Pr, a.steps, iters=a.iters, log=sys.stderr)
+                lo, hi = hints.get((model, L, Ma, Pr), (10.0, 1e6))
+                r = max_stable_pe(model, L, Ma, Pr, a.steps, lo=lo, hi=hi, iters=a.iters, log=sys.stderr,
+                                  check=a.check)
                 r.update(scenario=sc, model=model, L=L, Ma=Ma, Pr=Pr, steps=a.steps,
                          seconds=time.perf_counter() - t0)
                 print(json.dumps(r), file=sys.stderr, flush=True)
