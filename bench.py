@@ -277,7 +277,7 @@ def adjoint_cost(name, nsteps, every, reps=20):
     }
 
 
-def precision_study(name, nsteps, every, noise=1e-7):
+def precision_study(name, nsteps, every, noise=1e-7, shape=None, **overrides):
     """FP32-deviation forms against FP64 on the same run, every `every` steps:
     max |T - T64| / dT and |Nu - Nu64| / |Nu64| for
       f32dev   FP32 deviations from the uniform reference T0,
@@ -285,13 +285,15 @@ def precision_study(name, nsteps, every, noise=1e-7):
       f64pert  FP64 from an initial temperature perturbed by `noise` dT
                (uniform noise): the divergence the flow itself produces from
                a perturbation of FP32 rounding size, the yardstick for the
-               other two."""
+               other two.
+    ``shape`` and ``overrides`` (e.g. Pe) change the workload's grid and
+    physical parameters."""
     import torch
 
     import workloads
     from paper_2504_09041_amd.sim import Simulation, params_from_workload
 
-    cfg = workloads.config(name)
+    cfg = workloads.config(name, **({"shape": tuple(shape)} if shape else {}), **overrides)
     dT = cfg["T_hot"] - cfg["T_cold"]
     T = torch.tensor(workloads.initial_temperature(cfg), device="cuda")
     Tp = T + noise * dT * torch.tensor(workloads.uniform_field(tuple(T.shape), 77), device="cuda")
@@ -320,7 +322,8 @@ def precision_study(name, nsteps, every, noise=1e-7):
         print(json.dumps(row), file=sys.stderr, flush=True)
     for s in sims.values():
         s.close()
-    return {"workload": name, "noise": noise, "rows": rows}
+    return {"workload": name, "shape": list(cfg["shape"]), "noise": noise, "rows": rows,
+            **{k: v for k, v in overrides.items()}}
 
 
 def _cpu_model():
@@ -438,6 +441,21 @@ def main():
             "f64_perturbed_1e-7": last["f64pert"],
             "bars": {"max_dT_over_DeltaT": 1e-4, "rel_dNu": 1e-3},
         }
+        # the 3D cavity's FP32 run against FP64 at 64^3 over its 20k steps
+        st = precision_study("dhc3d_256", 20000, 20000, shape=(64, 64, 64))
+        last = st["rows"][-1]
+        extra["fp32_vs_fp64_dhc3d_64"] = {
+            "steps": 20000, "nu_f64": last["nu_f64"], "f32dev_uniform_ref": last["f32dev"],
+            "f32dev_conduction_ref": last["f32cond"], "f64_perturbed_1e-7": last["f64pert"],
+        }
+        # the lid-driven mixed-convection cavity over its Pe range (10k steps)
+        for pe in (1e3, 1e4, 1e5):
+            st = precision_study("mixed2d_512", 10000, 10000, Pe=pe)
+            last = st["rows"][-1]
+            extra[f"fp32_vs_fp64_mixed2d_512_Pe{pe:.0e}"] = {
+                "steps": 10000, "Pe": pe, "nu_f64": last["nu_f64"], "f32dev_uniform_ref": last["f32dev"],
+                "f32dev_conduction_ref": last["f32cond"], "f64_perturbed_1e-7": last["f64pert"],
+            }
     if not a.no_extra and not a.no_adjoint:
         extra["adjoint_mixed2d_512_f32dev"] = adjoint_cost("mixed2d_512", 400, 100)
         extra["adjoint_rb3d_128_f32dev"] = adjoint_cost("rb3d_128", 64, 8)

@@ -246,3 +246,78 @@ def test_autograd_function_wrapper():
     gth, gT = s.backward()
     assert torch.allclose(th.grad, 2.0 * gth, rtol=1e-14, atol=0)
     assert torch.allclose(T0.grad, 2.0 * gT, rtol=1e-14, atol=0)
+
+
+def _fd_check(s, th0, T0, which, dirs, grad, hs=(1e-2, 1e-3, 1e-4, 1e-5, 1e-6)):
+    """Best relative error over h of central differences of the GPU forward
+    run against the directional derivatives of the adjoint gradient."""
+    worst = 0.0
+    for i in range(dirs.shape[0]):
+        d = dirs[i].reshape(grad.shape)
+        an = float((grad * d).sum())
+        best = float("inf")
+        for h in hs:
+            if which == "theta":
+                jp, jm = s.forward(th0 + h * d, T0), s.forward(th0 - h * d, T0)
+            else:
+                jp, jm = s.forward(th0, T0 + h * d), s.forward(th0, T0 - h * d)
+            best = min(best, abs((jp - jm) / (2 * h) - an) / max(abs(an), 1e-30))
+        worst = max(worst, best)
+    return worst
+
+
+def test_lid_cavity_gradient_at_full_size_matches_central_differences():
+    """The lid-driven mixed-convection workload at its full size (512^2, FP64,
+    Re 1e3, Ri 1, Pe 1e3): J = mean Nusselt number of the hot lid over steps
+    5000..10000, gradient with respect to the 512-value bottom-wall temperature
+    profile with checkpoints every 100 steps, against central differences
+    along 16 seeded unit directions (1e-6 relative at the best h).  The top
+    wall is 512 nodes from the bottom one, so a unit direction moves J by only
+    about 1e-6 (and not at all before step 512): the FP64 rounding of J
+    (about 1e-15) swamps differences at h <= 1e-4, and the plateau lies near
+    h = 1e-2."""
+    cfg = workloads.config("mixed2d_512")
+    n0, n1 = cfg["J_window"]
+    face, tf = cfg["nu_face"], cfg["grad_face"]
+    s = _solver(cfg, "f64", "nu", face, (n0, n1), n1, cfg["checkpoint_every"], tf)
+    th0 = _theta0(cfg, tf, 91).cuda()
+    T0 = G.initial_T(cfg).cuda()
+    J = s.forward(th0, T0)
+    gth, _ = s.backward()
+    dirs = torch.tensor(workloads.unit_directions(th0.numel(), 16, seed0=200)).cuda()
+    worst = _fd_check(s, th0, T0, "theta", dirs, gth, hs=(1e-1, 3e-2, 1e-2, 3e-3, 1e-3))
+    print(f"J {J:.12f}; worst directional relative error at the plateau {worst:.2e}")
+    assert worst < 1e-6
+
+
+def test_rb3d_gradient_at_full_size():
+    """3D Rayleigh-Benard at its full size (128^3): J = kinetic energy at step
+    3000, gradient with respect to the whole initial temperature field with
+    sqrt(N) checkpointing.  The FP64 gradient against central differences
+    along 4 seeded directions (1e-6 relative at the best h); the FP32 adjoint
+    against the FP64 one (the FP64 adjoint is pinned to the oracle at 16^3).
+    J is about 5e-3 and a unit direction of the 2M-value field moves it by
+    1e-8 to 1e-7, so the plateau of the differences lies at h = 1e-2 to 1e-1
+    (FP64 rounding of J dominates below 1e-3)."""
+    cfg = workloads.config("rb3d_128")
+    N = cfg["steps"]
+    K = int(round(N ** 0.5))
+    T0 = G.initial_T(cfg).cuda()
+    res = {}
+    for prec in ("f64", "f32dev"):
+        s = _solver(cfg, prec, "ke", None, N, N, K, None)
+        J = s.forward(None, T0)
+        _, gT = s.backward()
+        res[prec] = (J, gT)
+        if prec == "f64":
+            dirs = torch.tensor(workloads.unit_directions(T0.numel(), 4, seed0=300)).cuda()
+            worst = _fd_check(s, None, T0, "T_init", dirs, gT, hs=(1e-1, 3e-2, 1e-2))
+            print(f"FP64: J {J:.6e}; worst directional relative error {worst:.2e}")
+            assert worst < 1e-6
+        s.sim.close()
+        del s
+        torch.cuda.empty_cache()
+    e = G.rel_err(res["f32dev"][1].cpu(), res["f64"][1].cpu())
+    eJ = abs(res["f32dev"][0] - res["f64"][0]) / abs(res["f64"][0])
+    print(f"FP32 vs FP64 at 128^3: J {eJ:.2e}, dJ/dT_init {e:.2e}")
+    assert eJ < 1e-3 and e < 2e-3
