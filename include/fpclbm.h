@@ -9,8 +9,9 @@
  *   -> fluid collision: central moments, relaxation toward the Fokker-Planck
  *      attractors with renormalised diffusion tensor above second order and
  *      body-force sources                          (Sec. 4.1-4.2, 5.1-5.2, App. A)
- *   -> thermal collision with option-A attractors   (Sec. 4.3-4.4, 5.3, App. B/C)
- *   -> store the post-collision populations.
+ *   -> thermal collision with option-A attractors   (Sec. 4.3-4.4, 5.3, App. B/C;
+ *      option B and the Maxwellian comparator of Sec. 7 are selectable)
+ *   -> store the post-collision populations (64-node tiles, see fpc_state_bytes).
  *
  * Conventions shared by every call
  * --------------------------------
