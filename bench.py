@@ -46,7 +46,7 @@ def _args():
     ap.add_argument("--steps3d", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
-    ap.add_argument("--cpu-sample-steps", type=int, default=12)
+    ap.add_argument("--cpu-sample-steps", type=int, default=36)
     ap.add_argument("--mode", choices=("bench", "single", "copy", "pmc-summary", "precision", "adjoint"),
                     default="bench")
     ap.add_argument("--no-adjoint", action="store_true")
@@ -337,7 +337,7 @@ def _cpu_model():
     return "unknown"
 
 
-def cpu_baseline(name, nsteps, nsteps_1t=2):
+def cpu_baseline(name, nsteps, nsteps_1t=6):
     """The FP64 CPU oracle on the host cores, on a bounded sample of the same
     workload (nsteps steps of the full grid after its initial collision), with
     all threads and with one thread."""
