@@ -7,8 +7,10 @@ CompareNu3D (3D, 128^3).  This checks physics, not parity: the thermal
 lattice here is D2Q5 / D3Q7 (the paper's runs use D2Q9 / D3Q15), and the
 characteristic velocity U0 is a parameter (the paper uses 0.01), so agreement
 to a few tenths of a percent up to about one percent is the expectation.
+``--paper-lattices`` runs the paper's own thermal lattices instead (D2Q9 /
+D3Q15, FP64).
 
-    python -m paper_2504_09041_amd.validate [--quick]
+    python -m paper_2504_09041_amd.validate [--quick] [--paper-lattices]
 
 prints one JSON object.  The steady state is declared when the hot-wall mean
 Nusselt number changes by less than ``tol`` (relative) over one chunk of
@@ -54,12 +56,16 @@ def _wall_profile(T, L, Tw, dT):
     return -(L / dT) * (-8.0 / 3.0 * Tw + 3.0 * T1 - T2 / 3.0)
 
 
-def cavity(dim, Ra, n, U0=0.05, precision="f64", chunk=20000, tol=2e-6, max_steps=20_000_000, log=None):
+def cavity(dim, Ra, n, U0=0.05, precision="f64", chunk=20000, tol=2e-6, max_steps=20_000_000, log=None,
+           pair=None):
     """Run the heated cavity (hot x = 0 wall, cold x = n wall, adiabatic
-    elsewhere) from the conduction profile to a steady state."""
+    elsewhere) from the conduction profile to a steady state.  ``pair``
+    overrides the lattice pair (e.g. "D2Q9-D2Q9")."""
     name = "dhc2d_64" if dim == 2 else "dhc3d_256"
     shape = (n, n, 1) if dim == 2 else (n, n, n)
     cfg = workloads.config(name, shape=shape, Ra=float(Ra), U0=float(U0), init="conduction_noise_uniform")
+    if pair:
+        cfg["pair"] = pair
     ref = "conduction" if precision == "f32dev" else "uniform"
     p = params_from_workload(cfg, precision, T_reference=ref)
     sim = Simulation(p)
@@ -88,7 +94,7 @@ def cavity(dim, Ra, n, U0=0.05, precision="f64", chunk=20000, tol=2e-6, max_step
     u = m["u"]
     L = n
     alpha = _alpha(p, dim)
-    out = {"dim": dim, "Ra": Ra, "n": n, "U0": U0, "precision": precision, "steps": steps,
+    out = {"dim": dim, "Ra": Ra, "n": n, "U0": U0, "precision": precision, "pair": cfg["pair"], "steps": steps,
            "last_change": change, "seconds": time.perf_counter() - t0, "nu": nu}
     loc = _wall_profile(T, L, cfg["T_hot"], dT)
     if dim == 2:
@@ -122,6 +128,7 @@ def main(argv=None):
     ap.add_argument("--U0", type=float, default=0.05)
     ap.add_argument("--n2", type=int, default=512)
     ap.add_argument("--n3", type=int, default=128)
+    ap.add_argument("--paper-lattices", action="store_true", help="D2Q9 / D3Q15 thermal lattices (FP64)")
     a = ap.parse_args(argv)
     if not torch.cuda.is_available():
         print("validation needs a GPU", file=sys.stderr)
@@ -130,13 +137,15 @@ def main(argv=None):
     if a.quick:
         res.append(cavity(2, 1e4, 128, U0=0.1, log=sys.stderr))
     else:
+        pair2 = "D2Q9-D2Q9" if a.paper_lattices else None
+        pair3 = "D3Q27-D3Q15" if a.paper_lattices else None
         if a.dim in (0, 2):
             for Ra in (1e3, 1e4, 1e5, 1e6):
-                res.append(cavity(2, Ra, a.n2, U0=a.U0, log=sys.stderr))
+                res.append(cavity(2, Ra, a.n2, U0=a.U0, log=sys.stderr, pair=pair2))
         if a.dim in (0, 3):
             for Ra in (1e5, 1e6):
-                res.append(cavity(3, Ra, a.n3, U0=a.U0, precision="f32dev", chunk=5000, tol=5e-6,
-                                  log=sys.stderr))
+                res.append(cavity(3, Ra, a.n3, U0=a.U0, precision="f64" if a.paper_lattices else "f32dev",
+                                  chunk=5000, tol=5e-6, log=sys.stderr, pair=pair3))
     print(json.dumps({"validation": res}))
 
 
