@@ -156,6 +156,16 @@ struct TileLanes {
 // Glob64: 64-bit element offsets (any size).
 // ---------------------------------------------------------------------------
 constexpr int kBufDword3 = 0x00020000;  // raw (untyped) buffer, gfx9 family
+// Cache-policy bits of the ordinary (not non-temporal) state stores, per
+// element type (launch tuning, measured): FP64 states store with sc1 (2D FP64
+// step -2.3%, 3D FP64 64^3 step -10%), FP32 states with the default policy
+// (sc1 measured 1-5% slower there).
+#ifndef FPC_STORE_AUX_F64
+#define FPC_STORE_AUX_F64 16  // sc1
+#endif
+#ifndef FPC_STORE_AUX_F32
+#define FPC_STORE_AUX_F32 0
+#endif
 typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
 
 template <class R, int Q>
@@ -175,7 +185,8 @@ struct Buf32 {
   }
   template <bool NT>
   __device__ __forceinline__ void raw_store(unsigned voff, unsigned soff, R v) const {
-    constexpr int aux = NT ? 2 : 0;  // cache policy: non-temporal
+    // cache policy: non-temporal, else the element type's ordinary policy
+    constexpr int aux = NT ? 2 : (sizeof(R) == 8 ? FPC_STORE_AUX_F64 : FPC_STORE_AUX_F32);
     if constexpr (sizeof(R) == 4)
       __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), rsrc_d, (int)voff, (int)soff, aux);
     else
