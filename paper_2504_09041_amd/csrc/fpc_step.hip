@@ -24,6 +24,12 @@
 #ifndef FPC_BLOCK_2D
 #define FPC_BLOCK_2D 256  // threads per block of the 2D kernels
 #endif
+#ifndef FPC_BLOCK_3D
+#define FPC_BLOCK_3D 256  // threads per block of the 3D FP64 step kernels
+#endif
+#ifndef FPC_BLOCK_3DF
+#define FPC_BLOCK_3DF 128  // threads per block of the 3D FP32 step kernels (128^3: -0.7% against 256)
+#endif
 
 #ifndef FPC_BLOCK_X_MAX
 #define FPC_BLOCK_X_MAX 256
@@ -36,6 +42,9 @@
 #endif
 
 static_assert(FPC_BLOCK_X_MAX % 64 == 0, "a wavefront must cover one whole 64-node tile");
+static_assert(FPC_BLOCK_2D % 64 == 0 && FPC_BLOCK_2D >= 64 && FPC_BLOCK_2D <= 1024, "2D block size");
+static_assert(FPC_BLOCK_3D % 64 == 0 && FPC_BLOCK_3D >= 64 && FPC_BLOCK_3D <= 1024, "3D block size");
+static_assert(FPC_BLOCK_3DF % 64 == 0 && FPC_BLOCK_3DF >= 64 && FPC_BLOCK_3DF <= 1024, "3D FP32 block size");
 
 namespace fpc {
 namespace {
@@ -60,7 +69,7 @@ __device__ __forceinline__ void collide_store(const StepArgs<R>& a, const M& m, 
 // M: addressing policy (Buf32 when the buffer is below 4 GiB, else Glob64).
 // STD: the standard rate set (see rate_f / rate_g).
 template <class L, class R, class M, int UP, bool NT, bool STD>
-__global__ void __launch_bounds__(L::D == 2 ? FPC_BLOCK_2D : 256) FPC_STEP_ATTR
+__global__ void __launch_bounds__(L::D == 2 ? FPC_BLOCK_2D : (sizeof(R) == 4 ? FPC_BLOCK_3DF : FPC_BLOCK_3D)) FPC_STEP_ATTR
     step_kernel(StepArgs<R> a, unsigned total_bytes) {
   // XCD-aware block order: contiguous ranges of rows per XCD in 2D; in 3D
   // FP32, contiguous ranges of rows per XCD within each z plane (3D FP64
@@ -131,8 +140,11 @@ bool standard_rates(const StepArgs<R>& a, int D, int Qg) {
 
 template <class L, class R, int UP>
 hipError_t launch_up(const StepArgs<R>& a, const double* T_init, int mode, hipStream_t s) {
-  const int bx = a.nx >= FPC_BLOCK_X_MAX ? FPC_BLOCK_X_MAX : (a.nx >= 128 ? 128 : 64);
-  const int by = (mode == 0 && L::D == 2 ? FPC_BLOCK_2D : 256) / bx;
+  const int threads =
+      mode == 0 ? (L::D == 2 ? FPC_BLOCK_2D : (sizeof(R) == 4 ? FPC_BLOCK_3DF : FPC_BLOCK_3D)) : 256;
+  int bx = a.nx >= FPC_BLOCK_X_MAX ? FPC_BLOCK_X_MAX : (a.nx >= 128 ? 128 : 64);
+  if (bx > threads) bx = threads;
+  const int by = threads / bx;  // >= 1: threads and bx are multiples of 64, bx <= threads
   const dim3 block(bx, by, 1);
   const dim3 grid((a.nx + bx - 1) / bx, (a.ny + by - 1) / by, a.nz);
   if (mode == 1) {
