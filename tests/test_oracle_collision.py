@@ -1,7 +1,8 @@
 """Pins of the oracle's collision (CPU only).
 
-* the whole D2Q9 fluid / thermal collision against the paper's hand-expanded
-  App. A / App. B algorithm;
+* the whole D2Q9 fluid / thermal collision against a second route through it
+  (``tests/cm_binomial_2d.py``: binomial frame shifts, the printed P^-1, the
+  printed attractor and source lists);
 * the generic attractor recurrence against the attractor lists the paper
   prints for D2Q9 (Eq. D2Q9attractors, Eq. MvT2D, Eq. MvT2DoptionB), D3Q27
   (Sec. 5.2 list, with the printed kappa_122 term kappa~011 kappa~012 read as
@@ -19,7 +20,7 @@ import torch
 
 from oracle import lattices as L
 from oracle.collision import fluid_collide, recurrence, rest_weights, thermal_collide
-from tests import paper_appendix_2d as A
+from tests import cm_binomial_2d as B
 
 DT = torch.float64
 
@@ -37,20 +38,19 @@ def _rand_rates(q, seed, lo=0.6, hi=1.9):
 
 
 @pytest.mark.parametrize("seed", [0, 1, 2])
-def test_fluid_collision_matches_appendix_A(seed):
+def test_fluid_collision_matches_the_binomial_route(seed):
     f = _rand_state(L.D2Q9, 64, seed)
     g = torch.Generator().manual_seed(100 + seed)
     F = (torch.rand(64, 2, generator=g, dtype=DT) - 0.5) * 1e-2
     w = _rand_rates(9, seed)
     ft, rho, u = fluid_collide(f, F, L.D2Q9, w)
-    fa, rho_a, ux, uy = A.fluid_collide_appA([f[:, a] for a in range(9)], F[:, 0], F[:, 1], w)
-    fa = torch.stack(fa, 1)
-    assert torch.allclose(ft, fa, atol=2e-15, rtol=0)
-    assert torch.allclose(u[:, 0], ux, atol=1e-16, rtol=0)
+    fb, rho_b, ub = B.fluid_collide(f, F, w)
+    assert torch.allclose(ft, fb, atol=2e-15, rtol=0)
+    assert torch.allclose(u, ub, atol=1e-16, rtol=0)
 
 
 @pytest.mark.parametrize("seed", [0, 1])
-def test_thermal_collision_matches_appendix_B(seed):
+def test_thermal_collision_matches_the_binomial_route(seed):
     gen = torch.Generator().manual_seed(seed)
     T = (torch.rand(64, generator=gen, dtype=DT) - 0.5)
     w9 = rest_weights(L.D2Q9_T, thermal=True)
@@ -58,8 +58,8 @@ def test_thermal_collision_matches_appendix_B(seed):
     u = (torch.rand(64, 2, generator=gen, dtype=DT) - 0.5) * 0.2
     w = _rand_rates(9, 10 + seed)
     gt, _ = thermal_collide(g9, u, L.D2Q9_T, w, 1.0 / 3.0)
-    ga, _ = A.thermal_collide_appB([g9[:, a] for a in range(9)], u[:, 0], u[:, 1], w)
-    assert torch.allclose(gt, torch.stack(ga, 1), atol=2e-15, rtol=0)
+    gb, _ = B.thermal_collide(g9, u, w)
+    assert torch.allclose(gt, gb, atol=2e-15, rtol=0)
 
 
 def _lower_random(keys, seed):
@@ -294,3 +294,59 @@ def test_thermal_option_a_third_order_closed_form(lat):
         [((1, 2, 0), (1, 0, 0)), ((0, 1, 2), (0, 1, 0)), ((2, 0, 1), (0, 0, 1))]
     for m, low in pairs:
         assert torch.allclose(post[m], 2 / 3 * c2 * (1 - wa) * pre[low], atol=1e-13, rtol=0), m
+
+
+def _marginal(lat3, lat2, axis):
+    """(Q2, Q3) 0/1 matrix summing the 3D populations over the velocity
+    component along ``axis`` onto the 2D lattice of the other two axes."""
+    keep = [k for k in range(3) if k != axis]
+    M = torch.zeros(lat2.Q, lat3.Q, dtype=DT)
+    for a, v in enumerate(lat3.vectors):
+        M[lat2.vectors.index(tuple(v[k] for k in keep)), a] = 1.0
+    return M, keep
+
+
+def _exps3(m2, keep):
+    e = [0, 0, 0]
+    e[keep[0]], e[keep[1]] = m2
+    return tuple(e)
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+@pytest.mark.parametrize("model", ["FP", "MCM"])
+def test_3d_collision_of_a_marginal_is_the_2d_collision(axis, model):
+    """Summing the D3Q27 / D3Q7 populations over one velocity component gives a
+    D2Q9 / D2Q5 distribution whose raw and central moments are the (p, q, 0)
+    moments of the 3D one, whatever u and F along the summed axis.  Their
+    attractors (Eq. Mvcmattractor3D restricted to one plane), sources
+    (Eq. forcing:3D with one index zero) and relaxations are the 2D ones of
+    Sec. 4, as long as the diagonal second-order group relaxes at one rate in
+    both.  So the marginal of the 3D collision must equal the 2D collision of
+    the marginal: this ties every 3D term that touches a coordinate plane to
+    the 2D collision, which its own pins fix."""
+    n = 40
+    gen = torch.Generator().manual_seed(31 + axis)
+    f3 = _rand_state(L.D3Q27, n, 40 + axis)
+    F3 = (torch.rand(n, 3, generator=gen, dtype=DT) - 0.5) * 2e-2
+    w3 = _rand_rates(27, 50 + axis)
+    wd = 1.37
+    w3[7] = w3[8] = w3[9] = wd
+    M, keep = _marginal(L.D3Q27, L.D2Q9, axis)
+    w2 = [w3[L.D3Q27.index[_exps3(m, keep)]] for m in L.D2Q9.M]
+    w2[3] = w2[4] = wd
+    ft3, rho3, u3 = fluid_collide(f3, F3, L.D3Q27, w3, model=model)
+    ft2, rho2, u2 = fluid_collide(f3 @ M.T, F3[:, keep], L.D2Q9, w2, model=model)
+    assert torch.allclose(ft3 @ M.T, ft2, atol=2e-15, rtol=0)
+    assert torch.allclose(u3[:, keep], u2, atol=1e-16, rtol=0)
+    # thermal: D3Q7 onto D2Q5 with the same c^_s^2 and rates
+    c2 = 0.25
+    T = 0.3 + 0.1 * torch.rand(n, generator=gen, dtype=DT)
+    g3 = T[:, None] * rest_weights(L.D3Q7, thermal=True, cs2=c2)[None, :] + 0.01 * (
+        torch.rand(n, 7, generator=gen, dtype=DT) - 0.5)
+    wg3 = _rand_rates(7, 60 + axis)
+    wg3[4] = wg3[5] = wg3[6] = wd
+    Mg, _ = _marginal(L.D3Q7, L.D2Q5, axis)
+    wg2 = [1.0, wg3[1 + keep[0]], wg3[1 + keep[1]], wd, wd]
+    gt3, _ = thermal_collide(g3, u3, L.D3Q7, wg3, c2, model=model)
+    gt2, _ = thermal_collide(g3 @ Mg.T, u3[:, keep], L.D2Q5, wg2, c2, model=model)
+    assert torch.allclose(gt3 @ Mg.T, gt2, atol=2e-15, rtol=0)

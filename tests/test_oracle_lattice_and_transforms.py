@@ -1,8 +1,9 @@
 """Pins of the oracle's lattices, weights and moment transforms (CPU only).
 
 Each check compares the oracle with something it does not compute itself:
-textbook lattice weights, the complete {-1,0,1}^d velocity sets, and the
-paper's printed App. A transforms (P, F(u), F^-1(u), P^-1).
+textbook lattice weights, the complete {-1,0,1}^d velocity sets, the
+paper's printed App. A matrices P and P^-1 (golden fixture), and the frame
+transform F(u) written as the binomial expansion Sec. 4.2 describes.
 """
 
 import itertools
@@ -12,7 +13,7 @@ import torch
 
 from oracle import lattices as L
 from oracle.collision import cm_matrix, raw_matrix, rest_weights
-from tests import paper_appendix_2d as A
+from tests import cm_binomial_2d as B
 
 DT = torch.float64
 
@@ -55,35 +56,29 @@ def test_rest_weights_textbook(lat, thermal, cs2, expected):
 
 
 def test_raw_matrix_and_inverse_match_appendix_A():
-    """P (App. A Step 1) and P^-1 (App. A Step 5) for D2Q9."""
+    """P (App. A Step 1) and P^-1 (App. A Step 5) for D2Q9, as printed."""
     P = raw_matrix(L.D2Q9)
-    eye = torch.eye(9, dtype=DT)
-    f = [eye[:, a] for a in range(9)]
-    r = A.raw_d2q9(f)
-    Pp = torch.stack([r[k] for k in ("00", "10", "01", "20", "02", "11", "21", "12", "22")], 0)
+    Pp, Pinv = B.printed_matrices()
     assert torch.equal(P, Pp)
-    m = {k: eye[i] for i, k in enumerate(("00", "10", "01", "20", "02", "11", "21", "12", "22"))}
-    Pinv = torch.stack(A.pops_from_raw(m), 0)
-    assert torch.allclose(Pinv @ P, eye, atol=1e-15, rtol=0)
     assert torch.allclose(torch.linalg.inv(P), Pinv, atol=1e-15, rtol=0)
 
 
-def test_frame_transform_matches_appendix_A():
-    """C(u) = F(u) P with F(u) printed in App. A Step 2, and F^-1(u) of Step 4."""
+def test_frame_transform_is_the_binomial_shift():
+    """C(u) f equals the raw moments shifted by -u with binomial coefficients
+    (F(u) of Sec. 4.2), and the +u shift takes the central moments back."""
     g = torch.Generator().manual_seed(7)
     u = (torch.rand(50, 2, generator=g, dtype=DT) - 0.5) * 0.6
     f = torch.rand(50, 9, generator=g, dtype=DT)
     C = cm_matrix(L.D2Q9, u)
     kap = torch.einsum("nkq,nq->nk", C, f)
-    r = A.raw_d2q9([f[:, a] for a in range(9)])
-    kp = A.central_from_raw(r, u[:, 0], u[:, 1])
-    names = ("00", "10", "01", "20", "02", "11", "21", "12", "22")
-    kp = torch.stack([kp[k] for k in names], 1)
-    assert torch.allclose(kap, kp, atol=1e-14, rtol=0)
-    back = A.raw_from_central({k: kap[:, i] for i, k in enumerate(names)}, u[:, 0], u[:, 1])
-    back = torch.stack([back[k] for k in names], 1)
-    rr = torch.stack([r[k] for k in names], 1)
-    assert torch.allclose(back, rr, atol=1e-14, rtol=0)
+    raw = B.raw_moments(f)
+    kp = B.shift(raw, u[:, 0], u[:, 1], -1)
+    assert torch.allclose(kap, torch.stack([kp[m] for m in B.ORDER], 1), atol=1e-14, rtol=0)
+    back = B.shift({m: kap[:, i] for i, m in enumerate(B.ORDER)}, u[:, 0], u[:, 1], +1)
+    for m in B.ORDER:
+        assert torch.allclose(back[m], raw[m], atol=1e-14, rtol=0)
+    # and the printed P^-1 recovers the populations from the raw moments
+    assert torch.allclose(B.populations(raw), f, atol=1e-14, rtol=0)
 
 
 @pytest.mark.parametrize("lat", [L.D2Q9, L.D2Q5, L.D3Q27, L.D3Q7])
@@ -105,3 +100,23 @@ def test_d3q15_frame_is_not_negated_velocity():
     Fu = cm_matrix(L.D3Q15_T, u) @ torch.linalg.inv(P)
     Fm = cm_matrix(L.D3Q15_T, -u) @ torch.linalg.inv(P)
     assert (Fu @ Fm - torch.eye(15, dtype=DT)).abs().max() > 1e-3
+
+
+@pytest.mark.parametrize("name,lat", [("D2Q9", L.D2Q9), ("D3Q27", L.D3Q27), ("D3Q15", L.D3Q15_T)])
+def test_orderings_match_the_printed_ones(name, lat):
+    """Velocity and moment orders as printed (Sec. 4.2, 5.2, 5.4): the moment
+    order is the order of the relaxation-rate slots."""
+    import json
+    import os
+
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "paper_lattice_orderings.json")
+    with open(path) as fh:
+        ref = json.load(fh)[name]
+    comps = [ref[k] for k in ("ex", "ey", "ez") if k in ref]
+    assert lat.vectors == [tuple(c[a] for c in comps) for a in range(lat.Q)]
+    assert lat.M == [tuple(int(ch) for ch in m) for m in ref["moments"]]
+    # the thermal axis lattices are the leading vectors of the fluid ones
+    if name == "D2Q9":
+        assert L.D2Q5.vectors == lat.vectors[:5]
+    if name == "D3Q27":
+        assert L.D3Q7.vectors == lat.vectors[:7]
