@@ -1,19 +1,22 @@
 #!/usr/bin/env python3
 """Throughput of the fused FP central-moment stream-collide step on one MI355X.
 
-Workload: 2D Rayleigh-Benard, 1024 x 512 nodes, D2Q9 fluid + D2Q5 thermal,
-Ra 1e6, Pr 0.71 (periodic in x, hot bottom, cold top), synthetic seeded
-initial temperature; one step = one fused pull-stream-collide launch over the
-whole grid (fluid + thermal populations).  The headline line is the FP64
-form; the same workload in FP32-deviation storage, and the 3D 256^3
-D3Q27 + D3Q7 cavity (FP32 deviations, the HBM-bound case), are reported in
-the "extra" object.
+Headline workload: the 3D differentially heated cube, 256^3 nodes, D3Q27
+fluid + D3Q7 thermal, Ra 1e6, Pr 0.71 (hot and cold x walls, adiabatic
+no-slip elsewhere), FP32-deviation storage with the library's default
+storage reference, synthetic seeded initial temperature.  Its 4.56 GB of
+state streams through HBM on every step.  One step = one fused
+pull-stream-collide launch over the whole grid (fluid + thermal
+populations).  The other workloads (the 2D Rayleigh-Benard case whose state
+stays in the last-level cache, the FP64 forms, the paper's own thermal
+lattices, the precision and adjoint studies) are in the "extra" object.
 
 Timing: W warm-up steps, then K timed steps bracketed by a device
 synchronisation, with HIP events recorded on the stream the kernels are
 launched on (torch's current stream).  The roofline object uses the
 algorithmic bytes of one launch (every population read once and written
-once: 2 (Qf + Qg) sizeof(real) per node) over the average launch duration.
+once: 2 (Qf + Qg) sizeof(real) = 272 B per node) over the average launch
+duration.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 
@@ -41,13 +44,14 @@ sys.path.insert(0, ROOT)
 def _args():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
-    ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--steps3d", type=int, default=100)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps2d", type=int, default=2000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
-    ap.add_argument("--cpu-sample-steps", type=int, default=36)
-    ap.add_argument("--mode", choices=("bench", "single", "copy", "pmc-summary", "precision", "adjoint"),
+    ap.add_argument("--cpu-sample-steps", type=int, default=24)
+    ap.add_argument("--mode", choices=("bench", "single", "copy", "pmc-summary", "precision", "adjoint",
+                                       "objective"),
                     default="bench")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--fetch", help="rocprofv3 --pmc FETCH_SIZE output dir (kernel run)")
@@ -55,9 +59,9 @@ def _args():
     ap.add_argument("--copy-fetch", help="rocprofv3 --pmc FETCH_SIZE output dir (copy run)")
     ap.add_argument("--copy-write", help="rocprofv3 --pmc WRITE_SIZE output dir (copy run)")
     ap.add_argument("--kernel-regex", default="step_kernel")
-    ap.add_argument("--key", default="rb2d_1024x512_f64")
-    ap.add_argument("--workload", default="rb2d_1024x512")
-    ap.add_argument("--precision", default="f64")
+    ap.add_argument("--key", default="dhc3d_256_f32dev")
+    ap.add_argument("--workload", default="dhc3d_256")
+    ap.add_argument("--precision", default="f32dev")
     ap.add_argument("--mib", type=int, default=4096)
     ap.add_argument("--reps", type=int, default=10)
     return ap.parse_args()
@@ -152,22 +156,33 @@ def pmc_summary(a):
     return rec
 
 
+def workload_params(cfg, precision, **kw):
+    """C parameters of a workload in one of the forms: "f64"; "f32dev" (FP32
+    deviations, the library's default storage reference: the conduction
+    profile between a pair of Dirichlet walls); "f32uni" (FP32 deviations
+    from the uniform T0, the literal g - w^T T0 form); "f32cond" (the
+    conduction reference along the workload's L axis, set explicitly)."""
+    from paper_2504_09041_amd.sim import params_from_workload
+
+    if precision == "f32uni":
+        return params_from_workload(cfg, "f32dev", T_reference="uniform", **kw)
+    if precision == "f32cond":
+        return params_from_workload(cfg, "f32dev", T_reference="conduction", **kw)
+    return params_from_workload(cfg, precision, **kw)
+
+
 def time_workload(name, precision, steps, warmup, shape=None, pair=None, model="FP", thermal_option="A"):
     import torch
 
     import workloads
-    from paper_2504_09041_amd.sim import Simulation, params_from_workload
+    from paper_2504_09041_amd.sim import Simulation
 
     cfg = workloads.config(name)
     if shape is not None:
         cfg["shape"] = tuple(shape)
     if pair is not None:
         cfg["pair"] = pair
-    kw = dict(model=model, thermal_option=thermal_option)
-    if precision == "f32cond":
-        p = params_from_workload(cfg, "f32dev", T_reference="conduction", **kw)
-    else:
-        p = params_from_workload(cfg, precision, **kw)
+    p = workload_params(cfg, precision, model=model, thermal_option=thermal_option)
     sim = Simulation(p)
     T = torch.tensor(workloads.initial_temperature(cfg), device="cuda")
     sim.init(T)
@@ -277,11 +292,16 @@ def adjoint_cost(name, nsteps, every, reps=20):
     }
 
 
+BARS = {"max_dT_over_DeltaT": 1e-4, "rel_dNu": 1e-3}
+
+
 def precision_study(name, nsteps, every, noise=1e-7, shape=None, **overrides):
     """FP32-deviation forms against FP64 on the same run, every `every` steps:
     max |T - T64| / dT and |Nu - Nu64| / |Nu64| for
-      f32dev   FP32 deviations from the uniform reference T0,
-      f32cond  FP32 deviations from the conduction profile (affine reference),
+      f32dev   FP32 deviations with the library's default storage reference
+               (the conduction profile between the Dirichlet walls),
+      f32uni   FP32 deviations from the uniform reference T0 (the literal
+               g - w^T T0 form),
       f64pert  FP64 from an initial temperature perturbed by `noise` dT
                (uniform noise): the divergence the flow itself produces from
                a perturbation of FP32 rounding size, the yardstick for the
@@ -291,17 +311,17 @@ def precision_study(name, nsteps, every, noise=1e-7, shape=None, **overrides):
     import torch
 
     import workloads
-    from paper_2504_09041_amd.sim import Simulation, params_from_workload
+    from paper_2504_09041_amd.sim import Simulation
 
     cfg = workloads.config(name, **({"shape": tuple(shape)} if shape else {}), **overrides)
     dT = cfg["T_hot"] - cfg["T_cold"]
     T = torch.tensor(workloads.initial_temperature(cfg), device="cuda")
     Tp = T + noise * dT * torch.tensor(workloads.uniform_field(tuple(T.shape), 77), device="cuda")
     variants = {
-        "f64": (params_from_workload(cfg, "f64"), T),
-        "f32dev": (params_from_workload(cfg, "f32dev"), T),
-        "f32cond": (params_from_workload(cfg, "f32dev", T_reference="conduction"), T),
-        "f64pert": (params_from_workload(cfg, "f64"), Tp),
+        "f64": (workload_params(cfg, "f64"), T),
+        "f32dev": (workload_params(cfg, "f32dev"), T),
+        "f32uni": (workload_params(cfg, "f32uni"), T),
+        "f64pert": (workload_params(cfg, "f64"), Tp),
     }
     sims = {}
     for k, (p, T_init) in variants.items():
@@ -315,7 +335,7 @@ def precision_study(name, nsteps, every, noise=1e-7, shape=None, **overrides):
             s.step(every)
             out[k] = (s.diagnostics(cfg["nu_face"])["nu"], s.macros()["T"])
         row = {"step": n, "nu_f64": out["f64"][0]}
-        for k in ("f32dev", "f32cond", "f64pert"):
+        for k in ("f32dev", "f32uni", "f64pert"):
             row[k] = {"max_dT_over_DeltaT": float((out[k][1] - out["f64"][1]).abs().max()) / dT,
                       "rel_dNu": abs(out[k][0] - out["f64"][0]) / abs(out["f64"][0])}
         rows.append(row)
@@ -324,6 +344,54 @@ def precision_study(name, nsteps, every, noise=1e-7, shape=None, **overrides):
         s.close()
     return {"workload": name, "shape": list(cfg["shape"]), "noise": noise, "rows": rows,
             **{k: v for k, v in overrides.items()}}
+
+
+def precision_summary(st, steps, **extra):
+    """Worst errors of each form over the study's rows, with pass flags
+    against the bars (1e-4 dT on T, 1e-3 relative on Nu)."""
+    out = {"steps": steps, **extra, "nu_f64": st["rows"][-1]["nu_f64"], "bars": BARS}
+    for k, label in (("f32dev", "f32dev_default_ref"), ("f32uni", "f32dev_uniform_ref"),
+                     ("f64pert", "f64_perturbed_1e-7")):
+        worst = {m: max(r[k][m] for r in st["rows"]) for m in BARS}
+        rec = {"worst_over_run": worst, "last": st["rows"][-1][k]}
+        if k != "f64pert":
+            rec["pass"] = all(worst[m] <= BARS[m] for m in BARS)
+        out[label] = rec
+    return out
+
+
+def objective_cost(name, nsteps, reps=3):
+    """Cost of accumulating the wall-Nusselt objective during the forward run
+    (fpc_step_nusselt, fused into the step kernel) against plain steps: the
+    forward over the workload's J window, FP32 deviations."""
+    import torch
+
+    import workloads
+    from paper_2504_09041_amd.sim import Simulation
+
+    cfg = workloads.config(name)
+    sim = Simulation(workload_params(cfg, "f32dev"))
+    sim.init(torch.tensor(workloads.initial_temperature(cfg), device="cuda"))
+    acc = torch.zeros(1, dtype=torch.float64, device="cuda")
+    sim.step(100)
+    ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+    best = {}
+    for kind in ("plain", "nusselt") * reps:
+        e0, e1 = ev(), ev()
+        torch.cuda.synchronize()
+        e0.record()
+        if kind == "plain":
+            sim.step(nsteps)
+        else:
+            sim.step_nusselt(nsteps, cfg["nu_face"], 1.0 / nsteps, acc)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / nsteps
+        best[kind] = min(best.get(kind, float("inf")), ms)
+    sim.close()
+    return {"workload": name, "precision": "f32dev", "steps": nsteps, "plain_ms_per_step": best["plain"],
+            "objective_ms_per_step": best["nusselt"], "ratio": best["nusselt"] / best["plain"],
+            "target_ratio": 1.3}
 
 
 def _cpu_model():
@@ -337,45 +405,75 @@ def _cpu_model():
     return "unknown"
 
 
-def cpu_baseline(name, nsteps, nsteps_1t=6):
-    """The FP64 CPU oracle on the host cores, on a bounded sample of the same
-    workload (nsteps steps of the full grid after its initial collision), with
-    all threads and with one thread."""
+def cpu_baseline(nsteps3d, nsteps_1t=3, config1=True, gradients=True):
+    """The FP64 CPU oracle on the host cores, on bounded samples:
+    value: nsteps3d steps of the 3D cube at 32^3 (D3Q27 + D3Q7, the headline
+    lattice pair) after its initial collision, all threads; a few steps on
+    one thread; the 64 x 64 cavity over its full 2000 steps; and the
+    oracle's reference gradients (torch autograd through the FP64 oracle) at
+    16^3 (3D Rayleigh-Benard, KE objective) and 32 x 32 (lid-driven mixed
+    convection, windowed Nusselt objective)."""
     import torch
 
     import workloads
+    from oracle import gradient as ograd
     from oracle import sim as osim
     from oracle.params import params_from_config
 
-    cfg = workloads.config(name)
-    prm = params_from_config(cfg)
-    N = cfg["shape"][0] * cfg["shape"][1] * cfg["shape"][2]
-    T = torch.tensor(workloads.initial_temperature(cfg))
-    f0, g0 = osim.init_state(prm, T)
+    threads = os.cpu_count() or 1
 
-    def timed(threads, n):
-        torch.set_num_threads(threads)
-        f, g, _ = osim.step(prm, f0, g0)  # warm-up step (not timed)
+    def timed_run(name, shape, n, nthreads):
+        cfg = workloads.config(name, shape=shape)
+        prm = params_from_config(cfg)
+        T = torch.tensor(workloads.initial_temperature(cfg))
+        f, g = osim.init_state(prm, T)
+        torch.set_num_threads(nthreads)
+        f, g, _ = osim.step(prm, f, g)  # warm-up step (not timed)
         t0 = time.perf_counter()
         osim.run(prm, f, g, n)
-        return time.perf_counter() - t0
+        dt = time.perf_counter() - t0
+        torch.set_num_threads(threads)
+        N = shape[0] * shape[1] * shape[2]
+        return N * n / dt / 1e6, dt
 
-    threads = os.cpu_count() or 1
-    dt = timed(threads, nsteps)
-    dt1 = timed(1, nsteps_1t) if nsteps_1t > 0 else None
-    torch.set_num_threads(threads)
-    return {
-        "value": N * nsteps / dt / 1e6,
+    mlups, dt = timed_run("dhc3d_256", (32, 32, 32), nsteps3d, threads)
+    out = {
+        "value": mlups,
         "unit": "MLUPS",
         "cores": threads,
         "kind": "oracle",
-        "sample": f"{nsteps} FP64 oracle steps of the full {cfg['shape'][0]}x{cfg['shape'][1]} grid "
-                  f"({dt:.1f} s, {threads} threads)",
-        "value_1_thread": N * nsteps_1t / dt1 / 1e6 if dt1 else None,
-        "sample_1_thread": f"{nsteps_1t} steps ({dt1:.1f} s)" if dt1 else None,
+        "sample": f"{nsteps3d} FP64 oracle steps of the 3D cube at 32^3 (D3Q27+D3Q7, the headline lattice pair; "
+                  f"{dt:.1f} s, {threads} threads)",
         "cpu_model": _cpu_model(),
         "nproc": os.cpu_count(),
     }
+    if nsteps_1t > 0:
+        m1, d1 = timed_run("dhc3d_256", (32, 32, 32), nsteps_1t, 1)
+        out["value_1_thread"] = m1
+        out["sample_1_thread"] = f"{nsteps_1t} steps of the same 32^3 cube on 1 thread ({d1:.1f} s)"
+    if config1:
+        m, d = timed_run("dhc2d_64", (64, 64, 1), 2000, threads)
+        out["cavity_64x64_full_run"] = {"mlups": m, "seconds": d, "steps": 2000, "threads": threads}
+    if gradients:
+        cfg = workloads.config("rb3d_128", shape=(16, 16, 16))
+        prm = params_from_config(cfg)
+        T = torch.tensor(workloads.initial_temperature(cfg))
+        t0 = time.perf_counter()
+        ograd.gradient(prm, T, 20, "ke", at=20)
+        d3 = time.perf_counter() - t0
+        cfg = workloads.config("mixed2d_512", shape=(32, 32, 1))
+        prm = params_from_config(cfg)
+        T = torch.tensor(workloads.initial_temperature(cfg))
+        th = torch.full((1, 32), cfg["faces"][2]["T"], dtype=torch.float64)
+        t0 = time.perf_counter()
+        ograd.gradient(prm, T, 40, "nu", face=cfg["nu_face"], window=(20, 40), theta_face=2, theta=th)
+        d2 = time.perf_counter() - t0
+        out["reference_gradient"] = {
+            "rb3d_16^3_ke_20_steps": {"seconds": d3, "seconds_per_step": d3 / 20},
+            "mixed2d_32x32_nu_40_steps": {"seconds": d2, "seconds_per_step": d2 / 40},
+            "threads": threads,
+        }
+    return out
 
 
 def main():
@@ -404,62 +502,53 @@ def main():
     if a.mode == "adjoint":
         print(json.dumps(adjoint_cost(a.workload, a.steps, max(1, int(round(a.steps ** 0.5))))))
         return
-    head = time_workload("rb2d_1024x512", "f64", a.steps, a.warmup)
+    if a.mode == "objective":
+        print(json.dumps(objective_cost(a.workload, a.steps)))
+        return
+    head = time_workload("dhc3d_256", "f32dev", a.steps, a.warmup)
     extra = {}
     if not a.no_extra:
-        extra["rb2d_1024x512_f32dev"] = time_workload("rb2d_1024x512", "f32dev", a.steps, a.warmup)
-        extra["rb2d_1024x512_f32cond"] = time_workload("rb2d_1024x512", "f32cond", a.steps, a.warmup)
-        extra["dhc3d_256_f32dev"] = time_workload("dhc3d_256", "f32dev", a.steps3d, max(5, a.warmup // 10))
-        extra["rb3d_128_f32dev"] = time_workload("rb3d_128", "f32dev", 5 * a.steps3d, max(5, a.warmup // 10))
+        n2, w2 = a.steps2d, max(20, a.steps2d // 20)
+        n3, w3 = max(20, a.steps // 2), 10
+        # the 2D Rayleigh-Benard workload: its state (117 MB in FP64, 59 MB in
+        # FP32) stays in the 256 MB last-level cache, so it runs faster than
+        # a copy through HBM
+        extra["rb2d_1024x512_f64_llc_resident"] = time_workload("rb2d_1024x512", "f64", n2, w2)
+        extra["rb2d_1024x512_f32dev_llc_resident"] = time_workload("rb2d_1024x512", "f32dev", n2, w2)
+        extra["rb2d_1024x512_f32uni_llc_resident"] = time_workload("rb2d_1024x512", "f32uni", n2, w2)
+        extra["dhc3d_256_f32uni"] = time_workload("dhc3d_256", "f32uni", n3, w3)
+        extra["rb3d_128_f32dev"] = time_workload("rb3d_128", "f32dev", 5 * n3, w3)
         # the same 2D physics on a grid whose state (3.8 GB) does not fit the
         # last-level cache: a pure-HBM figure for the FP64 kernel
-        extra["rb2d_4096x4096_f64"] = time_workload("rb2d_1024x512", "f64", a.steps3d, max(5, a.warmup // 10),
-                                                    shape=(4096, 4096, 1))
+        extra["rb2d_4096x4096_f64"] = time_workload("rb2d_1024x512", "f64", n3, w3, shape=(4096, 4096, 1))
         # the 3D cavity at 64^3 in FP64 and the 512^2 mixed-convection case in
         # FP32 (forward step of the adjoint workload)
-        extra["dhc3d_64_f64"] = time_workload("dhc3d_256", "f64", 5 * a.steps3d, max(5, a.warmup // 10),
-                                              shape=(64, 64, 64))
-        extra["mixed2d_512_f32dev"] = time_workload("mixed2d_512", "f32dev", a.steps, a.warmup)
+        extra["dhc3d_64_f64"] = time_workload("dhc3d_256", "f64", 5 * n3, w3, shape=(64, 64, 64))
+        extra["mixed2d_512_f32dev"] = time_workload("mixed2d_512", "f32dev", n2, w2)
         # the 64 x 64 cavity: launch-bound (4096 nodes per launch)
-        extra["dhc2d_64_f64"] = time_workload("dhc2d_64", "f64", a.steps, a.warmup)
+        extra["dhc2d_64_f64"] = time_workload("dhc2d_64", "f64", n2, w2)
         extra["copy_4GiB"] = copy_bandwidth(4096, 20)
         # the paper's own thermal lattices (FP64), and the MCM comparator on the
-        # headline workload: same step structure, more (or the same) bytes
-        extra["rb2d_1024x512_f64_D2Q9thermal"] = time_workload("rb2d_1024x512", "f64", a.steps, a.warmup,
-                                                               pair="D2Q9-D2Q9")
-        extra["rb3d_128_f64_D3Q15thermal"] = time_workload("rb3d_128", "f64", a.steps3d, max(5, a.warmup // 10),
-                                                           pair="D3Q27-D3Q15")
-        extra["rb2d_1024x512_f64_MCM"] = time_workload("rb2d_1024x512", "f64", a.steps, a.warmup, model="MCM")
-        # FP32 against FP64 over the workload's full run (the precision half of
-        # the metric): errors of T and of the bottom-wall Nu at the end
-        cfg_steps = 50000
-        st = precision_study("rb2d_1024x512", cfg_steps, cfg_steps // 5)
-        last = st["rows"][-1]
-        extra["fp32_vs_fp64_rb2d_1024x512"] = {
-            "steps": cfg_steps, "nu_f64": last["nu_f64"],
-            "f32dev_uniform_ref": last["f32dev"], "f32dev_conduction_ref": last["f32cond"],
-            "f64_perturbed_1e-7": last["f64pert"],
-            "bars": {"max_dT_over_DeltaT": 1e-4, "rel_dNu": 1e-3},
-        }
-        # the 3D cavity's FP32 run against FP64 at 64^3 over its 20k steps
-        st = precision_study("dhc3d_256", 20000, 20000, shape=(64, 64, 64))
-        last = st["rows"][-1]
-        extra["fp32_vs_fp64_dhc3d_64"] = {
-            "steps": 20000, "nu_f64": last["nu_f64"], "f32dev_uniform_ref": last["f32dev"],
-            "f32dev_conduction_ref": last["f32cond"], "f64_perturbed_1e-7": last["f64pert"],
-        }
-        # the lid-driven mixed-convection cavity over its Pe range (10k steps)
+        # 2D workload: same step structure, more (or the same) bytes
+        extra["rb2d_1024x512_f64_D2Q9thermal"] = time_workload("rb2d_1024x512", "f64", n2, w2, pair="D2Q9-D2Q9")
+        extra["rb3d_128_f64_D3Q15thermal"] = time_workload("rb3d_128", "f64", n3, w3, pair="D3Q27-D3Q15")
+        extra["rb2d_1024x512_f64_MCM"] = time_workload("rb2d_1024x512", "f64", n2, w2, model="MCM")
+        # the wall-Nusselt objective accumulated during the forward run of the
+        # lid-driven cavity's J window (steps 5000-10000)
+        extra["objective_forward_mixed2d_512"] = objective_cost("mixed2d_512", 5001)
+        # FP32 against FP64 over the workloads' full runs (the precision half
+        # of the metric): worst errors of T and of the wall Nu, pass flags
+        st = precision_study("rb2d_1024x512", 50000, 5000)
+        extra["fp32_vs_fp64_rb2d_1024x512"] = precision_summary(st, 50000)
+        st = precision_study("dhc3d_256", 20000, 5000, shape=(64, 64, 64))
+        extra["fp32_vs_fp64_dhc3d_64"] = precision_summary(st, 20000)
         for pe in (1e3, 1e4, 1e5):
-            st = precision_study("mixed2d_512", 10000, 10000, Pe=pe)
-            last = st["rows"][-1]
-            extra[f"fp32_vs_fp64_mixed2d_512_Pe{pe:.0e}"] = {
-                "steps": 10000, "Pe": pe, "nu_f64": last["nu_f64"], "f32dev_uniform_ref": last["f32dev"],
-                "f32dev_conduction_ref": last["f32cond"], "f64_perturbed_1e-7": last["f64pert"],
-            }
+            st = precision_study("mixed2d_512", 10000, 5000, Pe=pe)
+            extra[f"fp32_vs_fp64_mixed2d_512_Pe{pe:.0e}"] = precision_summary(st, 10000, Pe=pe)
     if not a.no_extra and not a.no_adjoint:
         extra["adjoint_mixed2d_512_f32dev"] = adjoint_cost("mixed2d_512", 400, 100)
         extra["adjoint_rb3d_128_f32dev"] = adjoint_cost("rb3d_128", 64, 8)
-    tr = _traffic_record().get("rb2d_1024x512_f64")
+    tr = _traffic_record().get("dhc3d_256_f32dev")
     if tr and tr.get("sources") != kernel_fingerprint():
         tr = None  # the kernels changed since the counters were taken
     copy = extra.get("copy_4GiB")
@@ -472,12 +561,13 @@ def main():
         # HBM-side bytes per launch from the scaled FETCH_SIZE + WRITE_SIZE counters
         "traffic": tr["traffic_bytes"] if tr else None,
         "algorithmic_bytes": head["bytes_per_node"] * head["nodes"],
-        # fraction of what a plain elementwise copy attains on this device
+        "bytes_per_node": head["bytes_per_node"],
+        # fraction of what a plain elementwise copy of 4 GiB attains on this device
         "frac_of_copy": head["achieved_GBs"] / copy["GBs"] if copy else None,
     }
     cpu = None
     if not a.no_cpu_baseline:
-        cpu = cpu_baseline("rb2d_1024x512", a.cpu_sample_steps)
+        cpu = cpu_baseline(a.cpu_sample_steps)
     line = {
         "metric": "MLUPS (fluid+thermal) & % HBM roofline; FP32 vs FP64 at stated Nu error; adjoint/fwd",
         "value": head["mlups"],
@@ -489,14 +579,14 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": "rb2d_1024x512: 2D Rayleigh-Benard 1024x512, D2Q9+D2Q5 FP central-moment LBM, "
-                        "Ra=1e6, Pr=0.71, FP64",
-            "lattice": "D2Q9+D2Q5",
-            "grid": [1024, 512],
-            "precision": "f64",
+            "workload": "dhc3d_256: 3D differentially heated cube 256^3, D3Q27+D3Q7 FP central-moment LBM, "
+                        "Ra=1e6, Pr=0.71, FP32-deviation storage (default conduction reference)",
+            "lattice": "D3Q27+D3Q7",
+            "grid": [256, 256, 256],
+            "precision": "f32dev",
             "parallelism": "single GPU",
         },
         "roofline": roof,

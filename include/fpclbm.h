@@ -72,6 +72,9 @@ extern "C" {
 #define FPC_BC_LID_ADIABATIC 3     /* moving-wall bounce-back (lid_u) for f, bounce-back for g */
 #define FPC_BC_LID_DIRICHLET 4     /* moving-wall bounce-back for f, anti-bounce-back for g */
 
+/* fpc_params.T_ref_axis: pick the FP32 storage reference from the walls. */
+#define FPC_TREF_AUTO (-2)
+
 #define FPC_FACE_XM 0
 #define FPC_FACE_XP 1
 #define FPC_FACE_YM 2
@@ -117,13 +120,22 @@ typedef struct fpc_params {
    * in 2D a -y face profile has nx values).  Read on every step, so it can be changed
    * between steps; the library never frees it. */
   const double* wall_T_profile[6];
-  /* FP32-deviation storage reference of g (ignored for FPC_FP64).  With slope s
-   * and axis k >= 0, g is stored as g - w^T Tr(x) with
-   *   Tr(x) = T0 + s (x_k - (n_k - 1) / 2),
-   * an affine profile across the box (e.g. the conduction profile between two
-   * Dirichlet walls, so the stored deviations carry only the departure from
-   * it).  s = 0 or k < 0: the uniform reference T0.  Axis k must not be
-   * periodic; s must be finite.  Defaults: s = 0, k = -1. */
+  /* FP32-deviation storage reference of g (ignored for FPC_FP64).  The stored
+   * thermal values are g - w^T Tr(x), with Tr one of:
+   *   T_ref_axis = FPC_TREF_AUTO (the default of fpc_params_default): the
+   *     conduction profile between the pair of Dirichlet faces (FPC_BC_*_DIRICHLET
+   *     on both faces of an axis) with the largest wall-temperature difference,
+   *     Tr(x) = T0 + s (x_k - (n_k - 1) / 2) with s = (wall_T[+k] - wall_T[-k]) / n_k
+   *     (walls halfway outside the outermost nodes); the uniform T0 if there is
+   *     no such pair.  fpc_storage_reference() reports the choice.
+   *   T_ref_axis = k >= 0: the affine profile Tr(x) = T0 + T_ref_slope (x_k - (n_k - 1) / 2)
+   *     (fpc_params_conduction_reference() fills it for a chosen axis); axis k
+   *     must not be periodic and the slope must be finite.
+   *   T_ref_axis = -1: the uniform reference T0 (the literal g - w^T T0 form).
+   * An affine reference changes only what is stored: the algorithm computed is
+   * the same.  Between two Dirichlet walls it keeps the stored values to the
+   * departure from conduction, which keeps FP32 rounding in the wall layers
+   * (and the wall Nusselt number) far below that of the uniform form. */
   double T_ref_slope;
   int T_ref_axis;
   /* Collision model, FPC_MODEL_FP (default) or FPC_MODEL_MCM.  The MCM
@@ -150,7 +162,8 @@ const char* fpc_last_error(void);
 
 /* Zero *p, set lattice/precision/sizes, every rate to 1, cs2_T to the lattice
  * default, rho0 = 1, dT_ref = 1, T0 = 0, up_axis = 1 (2D) or 2 (3D), all faces
- * periodic.  Fails with FPC_ERR_ARG / FPC_ERR_SIZE on a bad lattice or size. */
+ * periodic, T_ref_axis = FPC_TREF_AUTO.  Fails with FPC_ERR_ARG / FPC_ERR_SIZE
+ * on a bad lattice or size. */
 int fpc_params_default(fpc_params* p, int lattice, int precision, int nx, int ny, int nz);
 
 /*
@@ -170,6 +183,20 @@ int fpc_params_natural(fpc_params* p, double Ra, double Pr, double U0, int L_axi
  * rates as in fpc_params_natural. */
 int fpc_params_mixed(fpc_params* p, double Re, double Ri, double Pe, double U_lid, int L_axis,
                      double T_hot, double T_cold);
+
+/* Set the FP32 storage reference to the conduction profile between the two
+ * Dirichlet faces of `axis` (T_ref_axis = axis, T_ref_slope =
+ * (wall_T[2 axis + 1] - wall_T[2 axis]) / n_axis, the linear profile through the
+ * wall temperatures with the walls halfway outside the outermost nodes,
+ * Sec. 6.1).  Call after the faces are set.  FPC_ERR_ARG if either face of the
+ * axis is not a Dirichlet face or the axis is out of range. */
+int fpc_params_conduction_reference(fpc_params* p, int axis);
+
+/* The FP32 storage reference the parameters select (after FPC_TREF_AUTO is
+ * resolved): *axis = k and *slope = s of Tr(x) = T0 + s (x_k - (n_k - 1) / 2),
+ * or *axis = -1, *slope = 0 for the uniform T0 (always so for FPC_FP64).
+ * Validates the parameters first (errors as fpc_state_bytes). */
+int fpc_storage_reference(const fpc_params* p, int* axis, double* slope);
 
 /* Bytes each of the two state buffers must hold, and the padded row length
  * nxp (nx rounded up to a multiple of 64).  State layout (elements of FP64
@@ -212,6 +239,22 @@ int fpc_init(fpc_sim* s, const double* T_init);
 int fpc_step(fpc_sim* s, int nsteps);
 
 /*
+ * Advance nsteps >= 0 time steps exactly as fpc_step, and after each step n
+ * add weight * <Nu>_face(n) to acc[0]: the mean wall Nusselt number of
+ * fpc_diagnostics on wall_face at the new time level n (Sec. 6.1 stencil
+ * dT/dn = -8/3 T_w + 3 T(1/2) - 1/3 T(3/2), Nu = -(L / dT_ref) dT/dn).
+ * acc: device pointer to one FP64 value, accumulated into (never
+ * overwritten), so a time-averaged objective sum_n w <Nu>(n) builds up over
+ * several calls without a host synchronisation.  The step kernel itself
+ * forms the sums from the two wall layers of the state it writes (per-tile
+ * partial sums in library-owned scratch, reduced in a fixed order into acc at
+ * the end of the call), so a step costs about what fpc_step costs.
+ * Asynchronous.  Errors: FPC_ERR_ARG (NULL, nsteps < 0, wall_face outside
+ * 0..5, weight not finite), FPC_ERR_STATE (periodic face, or a z face in 2D).
+ */
+int fpc_step_nusselt(fpc_sim* s, int nsteps, int wall_face, double weight, double* acc);
+
+/*
  * One time step from a caller-owned state into another caller-owned state:
  * S_dst = Phi(S_src) (the fused pull-stream-collide of fpc_step), with this
  * simulation's parameters.  src, dst: device pointers, 256-byte aligned, each
@@ -246,6 +289,15 @@ int fpc_macros(fpc_sim* s, double* rho, double* u, double* T);
  */
 int fpc_diagnostics(fpc_sim* s, int wall_face, double* nu_mean, double* ke, double* sumT, double* umax);
 
+/*
+ * Local wall Nusselt numbers of the current time level on wall_face (the
+ * stencil of fpc_diagnostics, Sec. 6.1, per wall node): nu[i] for wall node i
+ * in the profile layout of fpc_params.wall_T_profile (the face's two
+ * tangential axes, slower first); device pointer, M FP64 values.  Their mean
+ * is fpc_diagnostics' nu_mean.  Asynchronous.  Errors as fpc_step_nusselt.
+ */
+int fpc_nusselt_local(fpc_sim* s, int wall_face, double* nu);
+
 /* Copy the current state (fpc_state_bytes() bytes, storage format) to / from
  * device memory.  fpc_load resets the step counter to `step`. */
 int fpc_save(const fpc_sim* s, void* dst);
@@ -259,6 +311,21 @@ int fpc_import_fp64(fpc_sim* s, const double* src, long long step);
 
 /* Device pointer of the buffer that holds the current state. */
 int fpc_current_buffer(const fpc_sim* s, void** ptr);
+
+/*
+ * Adjoint seeds of the wall-Nusselt objective J = weight * <Nu>_face at one
+ * time level (the stencil of Sec. 6.1 as in fpc_diagnostics):
+ *   dJdT[x]  = dJ/dT(x): 3 s on the nodes next to the face, -s/3 on the second
+ *              layer, 0 elsewhere, s = -(L / dT_ref) weight / M (M nodes on the
+ *              face); device, N FP64 values [z][y][x], overwritten.  It is the
+ *              dJdT argument of fpc_adjoint_step / fpc_adjoint_init.
+ *   dJdTw[i] = dJ/dT_w(i) = -8/3 s, the direct dependence on the wall
+ *              temperature of wall node i (profile layout of
+ *              fpc_params.wall_T_profile); device, M FP64 values, overwritten;
+ *              may be NULL.
+ * Asynchronous.  Errors as fpc_step_nusselt.
+ */
+int fpc_nusselt_seed(fpc_sim* s, int wall_face, double weight, double* dJdT, double* dJdTw);
 
 /*
  * Adjoint (reverse mode) of one time step S_n = Phi(S_{n-1}), for an objective

@@ -41,12 +41,15 @@ FPC_BC_NOSLIP_ADIABATIC = 1
 FPC_BC_NOSLIP_DIRICHLET = 2
 FPC_BC_LID_ADIABATIC = 3
 FPC_BC_LID_DIRICHLET = 4
+FPC_TREF_AUTO = -2
 
 EXPORTED = (
     "fpc_version", "fpc_last_error", "fpc_params_bytes", "fpc_params_default", "fpc_params_natural", "fpc_params_mixed",
-    "fpc_state_bytes", "fpc_create", "fpc_destroy", "fpc_set_stream", "fpc_init", "fpc_step", "fpc_step_from",
-    "fpc_get_step", "fpc_macros", "fpc_diagnostics", "fpc_save", "fpc_load", "fpc_export_fp64",
-    "fpc_import_fp64", "fpc_current_buffer", "fpc_adjoint_step", "fpc_adjoint_init",
+    "fpc_params_conduction_reference", "fpc_storage_reference",
+    "fpc_state_bytes", "fpc_create", "fpc_destroy", "fpc_set_stream", "fpc_init", "fpc_step", "fpc_step_nusselt",
+    "fpc_step_from",
+    "fpc_get_step", "fpc_macros", "fpc_diagnostics", "fpc_nusselt_local", "fpc_save", "fpc_load", "fpc_export_fp64",
+    "fpc_import_fp64", "fpc_current_buffer", "fpc_nusselt_seed", "fpc_adjoint_step", "fpc_adjoint_init",
 )
 
 
@@ -108,22 +111,27 @@ def load():
         "fpc_params_default": (i, [P, i, i, i, i, i]),
         "fpc_params_natural": (i, [P, d, d, d, i, d, d]),
         "fpc_params_mixed": (i, [P, d, d, d, d, i, d, d]),
+        "fpc_params_conduction_reference": (i, [P, i]),
+        "fpc_storage_reference": (i, [P, ctypes.POINTER(i), dp]),
         "fpc_state_bytes": (i, [P, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]),
         "fpc_create": (i, [P, vp, vp, vp, ctypes.POINTER(vp)]),
         "fpc_destroy": (i, [vp]),
         "fpc_set_stream": (i, [vp, vp]),
         "fpc_init": (i, [vp, vp]),
         "fpc_step": (i, [vp, i]),
+        "fpc_step_nusselt": (i, [vp, i, i, d, vp]),
         "fpc_step_from": (i, [vp, vp, vp]),
         "fpc_params_bytes": (ctypes.c_size_t, []),
         "fpc_get_step": (i, [vp, ctypes.POINTER(ll)]),
         "fpc_macros": (i, [vp, vp, vp, vp]),
         "fpc_diagnostics": (i, [vp, i, dp, dp, dp, dp]),
+        "fpc_nusselt_local": (i, [vp, i, vp]),
         "fpc_save": (i, [vp, vp]),
         "fpc_load": (i, [vp, vp, ll]),
         "fpc_export_fp64": (i, [vp, vp]),
         "fpc_import_fp64": (i, [vp, vp, ll]),
         "fpc_current_buffer": (i, [vp, ctypes.POINTER(vp)]),
+        "fpc_nusselt_seed": (i, [vp, i, d, vp, vp]),
         "fpc_adjoint_step": (i, [vp, vp, vp, vp, vp, d, ctypes.POINTER(vp)]),
         "fpc_adjoint_init": (i, [vp, vp, vp, vp, d, vp]),
     }

@@ -15,8 +15,8 @@ Objectives are sums over time levels n of affine-in-T wall terms and kinetic
 energies of the time-n macros:
 
 * ``WallNusselt(face, n0, n1)``: mean over n in [n0, n1] of the wall Nusselt
-  number <Nu>_face(n), with Nu = -(L / dT_ref) (-8/3 T_w + 3 T(1/2) - 1/3 T(3/2))
-  (the one-sided stencil of Sec. 6.1);
+  number <Nu>_face(n) of the one-sided stencil of Sec. 6.1; the library
+  accumulates it during the forward steps and writes its adjoint seeds;
 * ``KineticEnergy(n)``: 1/2 sum rho |u|^2 at time level n.
 
 Gradients are with respect to a per-node Dirichlet wall-temperature profile
@@ -39,38 +39,44 @@ def _ptr(t):
 
 
 class WallNusselt:
-    """Mean wall Nusselt number on ``face`` over time levels n0..n1 (inclusive)."""
+    """Mean wall Nusselt number on ``face`` over time levels n0..n1 (inclusive).
+
+    Its value accumulates on the device during the forward run
+    (``fpc_step_nusselt``); its adjoint seeds come from ``fpc_nusselt_seed``."""
 
     def __init__(self, face, n0, n1):
         self.face = FACE_INDEX.get(face, face)
         self.n0, self.n1 = int(n0), int(n1)
         self._w = None
+        self.direct_wall = 0.0
 
     def bind(self, sim):
-        p = sim.params
-        nx, ny, nz = sim.shape
-        k = self.face // 2
-        n = (nx, ny, nz)[k]
-        M = sim.N // n
         W = self.n1 - self.n0 + 1
-        scale = -(n / p.dT_ref) / (M * W)
-        w = torch.zeros((nz, ny, nx), dtype=torch.float64, device=sim.device)
-        dim = 2 - k
-        l0, l1 = (0, 1) if self.face % 2 == 0 else (n - 1, n - 2)
-        w.select(dim, l0).fill_(3.0 * scale)
-        w.select(dim, l1).fill_(-scale / 3.0)
-        self._w = w.contiguous()
-        # d J / d T_w of the stencil's wall term, summed over the window
-        self.direct_wall = -(8.0 / 3.0) * scale * W
+        self._w, dTw = sim.nusselt_seed(self.face, 1.0 / W)
+        # the wall term enters each of the W levels with weight 1 / W
+        self.direct_wall = dTw * W
 
     def seed(self, n):
         if self.n0 <= n <= self.n1:
             return self._w, 0.0
         return None, 0.0
 
-    def value(self, sim, n):
-        if self.n0 <= n <= self.n1:
+    def start(self, sim):
+        """Term of time level 0 (host value)."""
+        if self.n0 <= 0 <= self.n1:
             return sim.diagnostics(self.face)["nu"] / (self.n1 - self.n0 + 1)
+        return 0.0
+
+    def advance(self, sim, n, m, acc):
+        """Step from level n to level m, adding the terms of levels n+1..m to
+        acc (device); returns the host part (none)."""
+        lo, hi = max(n + 1, self.n0), min(m, self.n1)
+        if lo > hi:
+            sim.step(m - n)
+            return 0.0
+        sim.step(lo - 1 - n)
+        sim.step_nusselt(hi - lo + 1, self.face, 1.0 / (self.n1 - self.n0 + 1), acc)
+        sim.step(m - hi)
         return 0.0
 
 
@@ -88,8 +94,17 @@ class KineticEnergy:
     def seed(self, n):
         return (None, 1.0) if n == self.n else (None, 0.0)
 
-    def value(self, sim, n):
-        return sim.diagnostics(-1)["ke"] if n == self.n else 0.0
+    def start(self, sim):
+        return sim.diagnostics(-1)["ke"] if self.n == 0 else 0.0
+
+    def advance(self, sim, n, m, acc):
+        if not n < self.n <= m:
+            sim.step(m - n)
+            return 0.0
+        sim.step(self.n - n)
+        v = sim.diagnostics(-1)["ke"]
+        sim.step(m - self.n)
+        return v
 
 
 class AdjointSolver:
@@ -129,13 +144,16 @@ class AdjointSolver:
         self.T_init = torch.as_tensor(T_init).to(self.device, torch.float64).contiguous().clone()
         sim.init(self.T_init)
         self.ckpt = [sim.save()]
-        J = self.obj.value(sim, 0)
-        for n in range(1, self.N + 1):
-            sim.step(1)
-            J += self.obj.value(sim, n)
+        acc = torch.zeros(1, dtype=torch.float64, device=self.device)
+        J = self.obj.start(sim)
+        n = 0
+        while n < self.N:
+            m = min(n + self.K, self.N)
+            J += self.obj.advance(sim, n, m, acc)
+            n = m
             if n % self.K == 0 and n < self.N:
                 self.ckpt.append(sim.save())
-        return J
+        return J + float(acc.item())
 
     def backward(self):
         """Returns (dJ/dtheta or None, dJ/dT_init)."""
@@ -171,7 +189,7 @@ class AdjointSolver:
         A.check(lib.fpc_adjoint_init(sim.handle, _ptr(self.T_init), _ptr(lam), _ptr(w0), ctypes.c_double(ke0),
                                      _ptr(dT)), "fpc_adjoint_init")
         if dth is not None and self.obj.face == self.theta_face:
-            dth += self.obj.direct_wall
+            dth += self.obj.direct_wall.reshape(dth.shape)
         torch.cuda.synchronize(self.device)
         return dth, dT
 

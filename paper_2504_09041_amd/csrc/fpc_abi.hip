@@ -25,6 +25,8 @@ struct fpc_sim {
   double* scratch;  // reduction partials, then 8 doubles of results
   size_t scratch_elems;
   double* result_host;  // pinned, 8 doubles
+  double* nu_slot;      // per-tile partial sums of the fused wall-Nusselt accumulation (kept zero between calls)
+  size_t nu_slot_elems;
   int device;
 };
 
@@ -129,25 +131,56 @@ int validate(const fpc_params* p) {
     }
   }
   if (!std::isfinite(p->T_ref_slope)) return fail(FPC_ERR_ARG, "T_ref_slope not finite");
-  if (p->T_ref_axis >= dim) return fail(FPC_ERR_ARG, "T_ref_axis %d invalid", p->T_ref_axis);
+  if (p->T_ref_axis >= dim || p->T_ref_axis < FPC_TREF_AUTO)
+    return fail(FPC_ERR_ARG, "T_ref_axis %d invalid", p->T_ref_axis);
   if (p->T_ref_axis >= 0 && p->bc[2 * p->T_ref_axis] == FPC_BC_PERIODIC && p->T_ref_slope != 0.0)
     return fail(FPC_ERR_ARG, "T_ref_axis %d is periodic", p->T_ref_axis);
   return FPC_OK;
 }
 
+bool dirichlet_face(int bc) { return bc == FPC_BC_NOSLIP_DIRICHLET || bc == FPC_BC_LID_DIRICHLET; }
+
+// The FP32 storage reference in use, as (axis, slope); axis -1: uniform T0.
+// FPC_TREF_AUTO takes the conduction profile between the pair of Dirichlet
+// faces with the largest temperature difference (the lower axis on a tie),
+// with the walls halfway outside the outermost nodes: slope = (T_+ - T_-) / n.
+void storage_reference(const fpc_params& p, int* axis, double* slope) {
+  *axis = -1;
+  *slope = 0.0;
+  if (p.T_ref_axis >= 0) {
+    *axis = p.T_ref_axis;
+    *slope = p.T_ref_slope;
+    return;
+  }
+  if (p.T_ref_axis != FPC_TREF_AUTO) return;
+  const int n[3] = {p.nx, p.ny, p.nz};
+  double best = 0.0;
+  for (int k = 0; k < 3; ++k) {
+    if (!dirichlet_face(p.bc[2 * k]) || !dirichlet_face(p.bc[2 * k + 1])) continue;
+    const double d = p.wall_T[2 * k + 1] - p.wall_T[2 * k];
+    if (std::fabs(d) > std::fabs(best)) {
+      best = d;
+      *axis = k;
+    }
+  }
+  if (*axis >= 0) *slope = best / n[*axis];
+}
+
 // Thermal storage reference Tr(x) = To + Tg . x of the stored g: T0 plus the
-// optional slope along T_ref_axis (centred on the box) for FP32 deviations,
-// zero for plain FP64 populations.
+// slope of storage_reference along its axis (centred on the box) for FP32
+// deviations, zero for plain FP64 populations.
 void thermal_reference(const fpc_params& p, double& To, double Tg[3]) {
   Tg[0] = Tg[1] = Tg[2] = 0.0;
   To = 0.0;
   if (p.precision != FPC_FP32_DEV) return;
   To = p.T0;
-  if (p.T_ref_axis >= 0 && p.T_ref_slope != 0.0) {
+  int k;
+  double slope;
+  storage_reference(p, &k, &slope);
+  if (k >= 0 && slope != 0.0) {
     const int n[3] = {p.nx, p.ny, p.nz};
-    const int k = p.T_ref_axis;
-    Tg[k] = p.T_ref_slope;
-    To -= p.T_ref_slope * 0.5 * (n[k] - 1);
+    Tg[k] = slope;
+    To -= slope * 0.5 * (n[k] - 1);
   }
 }
 
@@ -192,16 +225,19 @@ StepArgs<R> make_args(const fpc_sim* s, const void* src, void* dst) {
   return a;
 }
 
-int launch_update(fpc_sim* s, const void* src, void* dst, const double* T_init, int mode) {
+int launch_update(fpc_sim* s, const void* src, void* dst, const double* T_init, int mode,
+                  const NuAcc* obj = nullptr) {
   hipError_t e;
   const int up = s->p.up_axis;
   const int tk = paper_thermal(s->p.lattice) ? 1 : 0;
   if (s->p.precision == FPC_FP64) {
-    const StepArgs<double> a = make_args<double>(s, src, dst);
+    StepArgs<double> a = make_args<double>(s, src, dst);
+    if (obj) a.obj = *obj;
     e = s->dim == 2 ? launch_step2d<double>(a, up, tk, T_init, mode, s->stream)
                     : launch_step3d<double>(a, up, tk, T_init, mode, s->stream);
   } else {
-    const StepArgs<float> a = make_args<float>(s, src, dst);
+    StepArgs<float> a = make_args<float>(s, src, dst);
+    if (obj) a.obj = *obj;
     e = s->dim == 2 ? launch_step2d<float>(a, up, tk, T_init, mode, s->stream)
                     : launch_step3d<float>(a, up, tk, T_init, mode, s->stream);
   }
@@ -231,6 +267,24 @@ StateDesc desc_of(const fpc_sim* s) {
 }
 
 bool aligned256(const void* ptr) { return (reinterpret_cast<uintptr_t>(ptr) & 255u) == 0; }
+
+int check_wall_face(const fpc_sim* s, int wall_face) {
+  if (wall_face < -1 || wall_face > 5) return fail(FPC_ERR_ARG, "wall_face %d invalid", wall_face);
+  if (wall_face >= 4 && s->dim == 2) return fail(FPC_ERR_STATE, "2D has no z faces");
+  if (wall_face >= 0 && s->p.bc[wall_face] == FPC_BC_PERIODIC)
+    return fail(FPC_ERR_STATE, "face %d is periodic: no wall Nusselt number", wall_face);
+  return FPC_OK;
+}
+
+FaceDev face_of(const fpc_sim* s, int wall_face) {
+  FaceDev fd;
+  std::memset(&fd, 0, sizeof fd);
+  if (wall_face >= 0) {
+    fd.Tw = s->p.wall_T[wall_face];
+    fd.Tprof = s->p.wall_T_profile[wall_face];
+  }
+  return fd;
+}
 
 double rate_from(double D, double c2) { return 1.0 / (D / c2 + 0.5); }
 
@@ -281,7 +335,34 @@ int fpc_params_default(fpc_params* p, int lattice, int precision, int nx, int ny
   p->up_axis = dim == 2 ? 1 : 2;
   for (int f = 0; f < 6; ++f) p->bc[f] = FPC_BC_PERIODIC;
   p->T_ref_slope = 0.0;
-  p->T_ref_axis = -1;
+  p->T_ref_axis = FPC_TREF_AUTO;
+  return FPC_OK;
+}
+
+int fpc_params_conduction_reference(fpc_params* p, int axis) {
+  if (!p) return fail(FPC_ERR_ARG, "params is NULL");
+  int Qf, Qg, dim;
+  int rc = lattice_dims(p->lattice, &Qf, &Qg, &dim);
+  if (rc) return rc;
+  if (axis < 0 || axis >= dim) return fail(FPC_ERR_ARG, "axis %d invalid", axis);
+  if (!dirichlet_face(p->bc[2 * axis]) || !dirichlet_face(p->bc[2 * axis + 1]))
+    return fail(FPC_ERR_ARG, "conduction reference needs Dirichlet walls on both faces of axis %d", axis);
+  const int n[3] = {p->nx, p->ny, p->nz};
+  if (n[axis] <= 0) return fail(FPC_ERR_SIZE, "axis %d has no nodes", axis);
+  p->T_ref_axis = axis;
+  p->T_ref_slope = (p->wall_T[2 * axis + 1] - p->wall_T[2 * axis]) / n[axis];
+  return FPC_OK;
+}
+
+int fpc_storage_reference(const fpc_params* p, int* axis, double* slope) {
+  if (!p || !axis || !slope) return fail(FPC_ERR_ARG, "NULL argument");
+  int rc = validate(p);
+  if (rc) return rc;
+  storage_reference(*p, axis, slope);
+  if (p->precision != FPC_FP32_DEV) {
+    *axis = -1;
+    *slope = 0.0;
+  }
   return FPC_OK;
 }
 
@@ -355,7 +436,7 @@ int fpc_create(const fpc_params* p, void* bufA, void* bufB, void* hip_stream, fp
     delete s;
     return hipfail(e, "hipGetDevice");
   }
-  s->scratch_elems = diag_partials_needed(desc_of(s)) + 8;
+  s->scratch_elems = kDiagScratchDoubles;
   e = hipMalloc(&s->scratch, s->scratch_elems * sizeof(double));
   if (e != hipSuccess) {
     delete s;
@@ -367,6 +448,19 @@ int fpc_create(const fpc_params* p, void* bufA, void* bufB, void* hip_stream, fp
     delete s;
     return hipfail(e, "hipHostMalloc(result)");
   }
+  for (int f = 0; f < 2 * s->dim; ++f) {
+    const size_t c = nu_slot_count(p->nx, p->ny, p->nz, s->nxp, f);
+    if (c > s->nu_slot_elems) s->nu_slot_elems = c;
+  }
+  e = hipMalloc(&s->nu_slot, s->nu_slot_elems * sizeof(double));
+  if (e == hipSuccess) e = launch_fill_zero(s->nu_slot, s->nu_slot_elems, s->stream);
+  if (e != hipSuccess) {
+    if (s->nu_slot) (void)hipFree(s->nu_slot);
+    (void)hipFree(s->scratch);
+    (void)hipHostFree(s->result_host);
+    delete s;
+    return hipfail(e, "wall-Nusselt slots");
+  }
   *out = s;
   return FPC_OK;
 }
@@ -376,10 +470,12 @@ int fpc_destroy(fpc_sim* s) {
   hipError_t e1 = hipStreamSynchronize(s->stream);
   hipError_t e2 = hipFree(s->scratch);
   hipError_t e3 = hipHostFree(s->result_host);
+  hipError_t e4 = hipFree(s->nu_slot);
   delete s;
   if (e1 != hipSuccess) return hipfail(e1, "hipStreamSynchronize");
   if (e2 != hipSuccess) return hipfail(e2, "hipFree");
   if (e3 != hipSuccess) return hipfail(e3, "hipHostFree");
+  if (e4 != hipSuccess) return hipfail(e4, "hipFree");
   return FPC_OK;
 }
 
@@ -410,6 +506,51 @@ int fpc_step(fpc_sim* s, int nsteps) {
   return FPC_OK;
 }
 
+int fpc_step_nusselt(fpc_sim* s, int nsteps, int wall_face, double weight, double* acc) {
+  if (!s || !acc) return fail(FPC_ERR_ARG, "NULL argument");
+  if (nsteps < 0) return fail(FPC_ERR_ARG, "nsteps < 0");
+  if (wall_face < 0) return fail(FPC_ERR_ARG, "wall_face %d invalid", wall_face);
+  int rc = check_wall_face(s, wall_face);
+  if (rc) return rc;
+  if (!std::isfinite(weight)) return fail(FPC_ERR_ARG, "weight not finite");
+  const fpc_params& p = s->p;
+  const int n[3] = {p.nx, p.ny, p.nz};
+  const int k = wall_face >> 1;
+  const double M = (double)n[(k + 1) % 3] * n[(k + 2) % 3];
+  NuAcc o;
+  std::memset(&o, 0, sizeof o);
+  o.slot = s->nu_slot;
+  o.face = wall_face;
+  o.nk = n[k];
+  o.nt = n[k == 0 ? 1 : 0];  // faster tangential axis
+  o.ns = n[k == 2 ? 1 : 2];  // slower tangential axis
+  o.scale = -((double)n[k] / p.dT_ref) * weight / M;
+  o.Tw = p.wall_T[wall_face];
+  o.Tprof = p.wall_T_profile[wall_face];
+  thermal_reference(p, o.T_o, o.Tg);
+  for (int i = 0; i < nsteps; ++i) {
+    rc = launch_update(s, s->buf[s->cur], s->buf[s->cur ^ 1], nullptr, 0, &o);
+    if (rc) return rc;
+    s->cur ^= 1;
+    ++s->step;
+  }
+  const hipError_t e =
+      launch_nu_slots_reduce(s->nu_slot, nu_slot_count(p.nx, p.ny, p.nz, s->nxp, wall_face), acc, s->stream);
+  if (e != hipSuccess) return hipfail(e, "wall-Nusselt reduction");
+  return FPC_OK;
+}
+
+int fpc_nusselt_seed(fpc_sim* s, int wall_face, double weight, double* dJdT, double* dJdTw) {
+  if (!s || !dJdT) return fail(FPC_ERR_ARG, "NULL argument");
+  if (wall_face < 0) return fail(FPC_ERR_ARG, "wall_face %d invalid", wall_face);
+  int rc = check_wall_face(s, wall_face);
+  if (rc) return rc;
+  if (!std::isfinite(weight)) return fail(FPC_ERR_ARG, "weight not finite");
+  const hipError_t e = launch_nu_seed(desc_of(s), wall_face, s->p.dT_ref, weight, dJdT, dJdTw, s->stream);
+  if (e != hipSuccess) return hipfail(e, "wall-Nusselt seed kernels");
+  return FPC_OK;
+}
+
 int fpc_step_from(fpc_sim* s, const void* src, void* dst) {
   if (!s || !src || !dst) return fail(FPC_ERR_ARG, "NULL argument");
   if (!aligned256(src) || !aligned256(dst)) return fail(FPC_ERR_ARG, "state buffers must be 256-byte aligned");
@@ -435,39 +576,33 @@ int fpc_macros(fpc_sim* s, double* rho, double* u, double* T) {
 
 int fpc_diagnostics(fpc_sim* s, int wall_face, double* nu_mean, double* ke, double* sumT, double* umax) {
   if (!s) return fail(FPC_ERR_ARG, "sim is NULL");
-  if (wall_face < -1 || wall_face > 5) return fail(FPC_ERR_ARG, "wall_face %d invalid", wall_face);
-  if (wall_face >= 0 && s->p.bc[wall_face] == FPC_BC_PERIODIC)
-    return fail(FPC_ERR_STATE, "face %d is periodic: no wall Nusselt number", wall_face);
-  if (wall_face >= 4 && s->dim == 2) return fail(FPC_ERR_STATE, "2D has no z faces");
-  FaceDev fd;
-  std::memset(&fd, 0, sizeof fd);
-  if (wall_face >= 0) {
-    fd.Tw = s->p.wall_T[wall_face];
-    fd.Tprof = s->p.wall_T_profile[wall_face];
-  }
+  int rc = check_wall_face(s, wall_face);
+  if (rc) return rc;
   double* out = s->scratch + (s->scratch_elems - 8);
-  hipError_t e = launch_diagnostics(desc_of(s), wall_face, fd, s->p.dT_ref, s->scratch, out, s->stream);
+  hipError_t e = launch_diagnostics(desc_of(s), wall_face, face_of(s, wall_face), s->p.dT_ref, s->scratch, out,
+                                    s->stream);
   if (e != hipSuccess) return hipfail(e, "diagnostics kernels");
   e = hipMemcpyAsync(s->result_host, out, 5 * sizeof(double), hipMemcpyDeviceToHost, s->stream);
   if (e != hipSuccess) return hipfail(e, "hipMemcpyAsync");
   e = hipStreamSynchronize(s->stream);
   if (e != hipSuccess) return hipfail(e, "hipStreamSynchronize");
   const double* r = s->result_host;
-  if (nu_mean) {
-    if (wall_face >= 0) {
-      const int k = wall_face >> 1;
-      const int n[3] = {s->p.nx, s->p.ny, s->p.nz};
-      const double m = (double)n[(k + 1) % 3] * n[(k + 2) % 3];
-      *nu_mean = r[0] / m;
-    } else {
-      *nu_mean = 0.0;
-    }
-  }
+  if (nu_mean) *nu_mean = r[0];
   if (ke) *ke = r[1];
   if (sumT) *sumT = r[2];
   if (umax) *umax = r[3];
   if (r[4] != 0.0 || !std::isfinite(r[3]) || r[3] > 0.5)
     return fail(FPC_ERR_UNSTABLE, "unstable: %g non-finite nodes, max|u| = %g", r[4], r[3]);
+  return FPC_OK;
+}
+
+int fpc_nusselt_local(fpc_sim* s, int wall_face, double* nu) {
+  if (!s || !nu) return fail(FPC_ERR_ARG, "NULL argument");
+  if (wall_face < 0) return fail(FPC_ERR_ARG, "wall_face %d invalid", wall_face);
+  int rc = check_wall_face(s, wall_face);
+  if (rc) return rc;
+  const hipError_t e = launch_nu_local(desc_of(s), wall_face, face_of(s, wall_face), s->p.dT_ref, nu, s->stream);
+  if (e != hipSuccess) return hipfail(e, "local Nusselt kernel");
   return FPC_OK;
 }
 

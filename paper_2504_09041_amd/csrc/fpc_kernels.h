@@ -20,6 +20,24 @@ struct FaceDev {
   double uw[3];         // wall velocity
 };
 
+// Wall-Nusselt accumulation fused into the step (off when slot is NULL):
+// every node of the two layers next to `face` adds its share of
+// weight * <Nu>_face of the new time level (Sec. 6.1 stencil), summed per
+// wavefront into slot[] (one slot per 64-node tile of those layers, written
+// only by that tile's wavefront, so the per-slot sums over the steps of a run
+// are deterministic).
+struct NuAcc {
+  double* slot;
+  int face;
+  int nk;              // nodes along the face normal (L)
+  int nt;              // nodes along the faster tangential axis (profile row length)
+  int ns;              // nodes along the slower tangential axis
+  double scale;        // -(L / dT_ref) * weight / (nodes on the face)
+  double Tw;           // uniform wall temperature
+  const double* Tprof; // optional per-node wall temperature (profile layout)
+  double T_o, Tg[3];   // thermal storage reference in FP64 (zero for FP64 storage)
+};
+
 template <class R>
 struct StepArgs {
   const R* __restrict__ src;  // S_{n-1}
@@ -34,6 +52,7 @@ struct StepArgs {
   R T_o;
   R Tg[3];
   FaceDev face[6];
+  NuAcc obj;
 };
 
 // FP32 storage holds deviations from the references; FP64 storage holds the
@@ -122,10 +141,33 @@ struct StateDesc {
 hipError_t launch_macros(const StateDesc& d, double* rho, double* u, double* T, hipStream_t s);
 hipError_t launch_export(const StateDesc& d, double* dst, hipStream_t s);
 hipError_t launch_import(const StateDesc& d, void* dst, const double* src, hipStream_t s);
-// Writes out[0..4] = (sum Nu_local over the face or 0, KE, sum T, max|u|, #non-finite).
-// `partials` must hold at least diag_partials_needed(...) doubles.
-size_t diag_partials_needed(const StateDesc& d);
+// Diagnostics reductions.  Writes out[0..4] = (mean Nu over the face or 0,
+// KE, sum T, max|u|, number of non-finite nodes) with a fixed summation order
+// for a given grid.  `scratch` (device) must hold kDiagScratchDoubles doubles;
+// `out` (device, 5 doubles) must not overlap the first kDiagNodeBlocks * 4 +
+// kDiagFaceBlocks of them.
+constexpr unsigned kDiagNodeBlocks = 1024;  // stage-1 blocks over the nodes (at most)
+constexpr unsigned kDiagFaceBlocks = 64;    // stage-1 blocks over a face (at most)
+constexpr size_t kDiagScratchDoubles = (size_t)kDiagNodeBlocks * 4 + kDiagFaceBlocks + 8;
 hipError_t launch_diagnostics(const StateDesc& d, int face, const FaceDev& fd, double dT_ref,
-                              double* partials, double* out, hipStream_t s);
+                              double* scratch, double* out, hipStream_t s);
+
+// Local Nusselt number of every node of `face` (profile layout of
+// fpc_params.wall_T_profile) into out.
+hipError_t launch_nu_local(const StateDesc& d, int face, const FaceDev& fd, double dT_ref, double* out,
+                           hipStream_t s);
+
+// Slots of the fused wall-Nusselt accumulation for `face` (see NuAcc): one per
+// tile of the two wall layers.  nu_slot_count is the number a face needs.
+size_t nu_slot_count(int nx, int ny, int nz, int nxp, int face);
+// acc[0] += sum of slot[0..count) in a fixed order; the slots are zeroed.
+hipError_t launch_nu_slots_reduce(double* slot, size_t count, double* acc, hipStream_t s);
+// slot[0..count) = 0.
+hipError_t launch_fill_zero(double* p, size_t count, hipStream_t s);
+// Seeds of the adjoint of J = weight * <Nu>_face (Sec. 6.1 stencil):
+// dJdT[node] (N values, zero off the two wall layers) and, if dJdTw is not
+// NULL, dJdTw[i] = dJ / dT_w at wall node i (profile layout).
+hipError_t launch_nu_seed(const StateDesc& d, int face, double dT_ref, double weight, double* dJdT, double* dJdTw,
+                          hipStream_t s);
 
 }  // namespace fpc

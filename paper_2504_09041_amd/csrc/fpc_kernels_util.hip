@@ -141,25 +141,26 @@ __device__ double block_reduce(double v, double* sh, int op) {
   return r;
 }
 
-// Stage 1 over nodes: partials[b * 4 + (KE, sumT, umax, nonfinite)].
+// Stage 1 over nodes: partials[b * 4 + (KE, sumT, umax, nonfinite)].  A
+// fixed number of blocks (a function of N only) strides over the nodes, so
+// the partials fit a fixed scratch size for every grid and the summation
+// order is the same on every call.
 template <class R>
 __global__ void __launch_bounds__(kBlock) diag_nodes_kernel(StateDesc d, double* partials) {
   __shared__ double sh[kBlock];
   const size_t N = (size_t)d.nx * d.ny * d.nz;
-  const size_t node = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
   double ke = 0.0, st = 0.0, um = 0.0, bad = 0.0;
-  if (node < N) {
+  for (size_t node = (size_t)blockIdx.x * blockDim.x + threadIdx.x; node < N; node += stride) {
     double r, u[3], t;
     node_macros<R>(d, node, r, u, t);
     const double u2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-    ke = 0.5 * r * u2;
-    st = t;
-    um = sqrt(u2);
     if (!isfinite(r) || !isfinite(t) || !isfinite(u2)) {
-      bad = 1.0;
-      ke = 0.0;
-      st = 0.0;
-      um = 0.0;
+      bad += 1.0;
+    } else {
+      ke += 0.5 * r * u2;
+      st += t;
+      um = fmax(um, sqrt(u2));
     }
   }
   ke = block_reduce(ke, sh, 0);
@@ -174,43 +175,68 @@ __global__ void __launch_bounds__(kBlock) diag_nodes_kernel(StateDesc d, double*
   }
 }
 
-// Stage 1 over the nodes of one face: local Nusselt numbers.
+__device__ __forceinline__ size_t face_nodes_dev(const StateDesc& d, int face) {
+  const int k = face >> 1;
+  const size_t n[3] = {(size_t)d.nx, (size_t)d.ny, (size_t)d.nz};
+  return n[(k + 1) % 3] * n[(k + 2) % 3];
+}
+
+// Local Nusselt number at wall node i of `face` (i in the profile layout:
+// faster tangential axis first): the one-sided stencil of Sec. 6.1,
+// dT/dn = -8/3 T_w + 3 T(1/2) - 1/3 T(3/2) along the inward normal,
+// Nu = -(L / dT_ref) dT/dn with L the nodes along the normal.
 template <class R>
-__global__ void __launch_bounds__(kBlock) diag_face_kernel(StateDesc d, int face, FaceDev fd, double dT_ref,
-                                                           double* partials) {
-  __shared__ double sh[kBlock];
+__device__ double local_nusselt(const StateDesc& d, int face, const FaceDev& fd, double dT_ref, size_t i) {
   const int k = face >> 1;
   const int n[3] = {d.nx, d.ny, d.nz};
   const int t1 = k == 0 ? 1 : 0;  // faster tangential axis
   const int t2 = k == 2 ? 1 : 2;  // slower tangential axis
-  const size_t M = (size_t)n[t1] * n[t2];
-  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  double nu = 0.0;
-  if (i < M) {
-    int c[3];
-    c[t1] = (int)(i % n[t1]);
-    c[t2] = (int)(i / n[t1]);
-    const int L = n[k];
-    const int Qf = qf_of(d.lattice);
-    const int Qg = qg_of(d.lattice);
-    double Tl[2];
-    for (int layer = 0; layer < 2; ++layer) {
-      c[k] = (face & 1) ? L - 1 - layer : layer;
-      const size_t node = ((size_t)c[2] * d.ny + c[1]) * d.nx + c[0];
-      double t = 0.0;
-      for (int q = 0; q < Qg; ++q) t += ld<R>(d, Qf + q, node);
-      Tl[layer] = tref_node(d, node) + t;
-    }
-    const double Tw = fd.Tprof ? fd.Tprof[i] : fd.Tw;
-    const double dTdn = -8.0 / 3.0 * Tw + 3.0 * Tl[0] - Tl[1] / 3.0;
-    nu = -((double)L / dT_ref) * dTdn;
+  const int L = n[k];
+  const int Qf = qf_of(d.lattice);
+  const int Qg = qg_of(d.lattice);
+  int c[3];
+  c[t1] = (int)(i % n[t1]);
+  c[t2] = (int)(i / n[t1]);
+  double Tl[2];
+  for (int layer = 0; layer < 2; ++layer) {
+    c[k] = (face & 1) ? L - 1 - layer : layer;
+    const size_t node = ((size_t)c[2] * d.ny + c[1]) * d.nx + c[0];
+    double t = 0.0;
+    for (int q = 0; q < Qg; ++q) t += ld<R>(d, Qf + q, node);
+    Tl[layer] = tref_node(d, node) + t;
   }
+  const double Tw = fd.Tprof ? fd.Tprof[i] : fd.Tw;
+  const double dTdn = -8.0 / 3.0 * Tw + 3.0 * Tl[0] - Tl[1] / 3.0;
+  return -((double)L / dT_ref) * dTdn;
+}
+
+// Stage 1 over the nodes of one face: sums of the local Nusselt numbers
+// (fixed number of blocks striding over the face).
+template <class R>
+__global__ void __launch_bounds__(kBlock) diag_face_kernel(StateDesc d, int face, FaceDev fd, double dT_ref,
+                                                           double* partials) {
+  __shared__ double sh[kBlock];
+  const size_t M = face_nodes_dev(d, face);
+  double nu = 0.0;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < M; i += (size_t)gridDim.x * blockDim.x)
+    nu += local_nusselt<R>(d, face, fd, dT_ref, i);
   nu = block_reduce(nu, sh, 0);
   if (threadIdx.x == 0) partials[blockIdx.x] = nu;
 }
 
+// Local Nusselt number of every node of a face (profile layout).
+template <class R>
+__global__ void __launch_bounds__(kBlock) nu_local_kernel(StateDesc d, int face, FaceDev fd, double dT_ref,
+                                                          double* out) {
+  const size_t M = face_nodes_dev(d, face);
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < M; i += (size_t)gridDim.x * blockDim.x)
+    out[i] = local_nusselt<R>(d, face, fd, dT_ref, i);
+}
+
+// Final stage (one block): out = (mean Nu over the face or 0, KE, sum T,
+// max |u|, number of non-finite nodes).
 __global__ void __launch_bounds__(kBlock) diag_final_kernel(const double* pn, int nb, const double* pf, int nf,
-                                                            double* out) {
+                                                            double inv_face_nodes, double* out) {
   __shared__ double sh[kBlock];
   double ke = 0.0, st = 0.0, um = 0.0, bad = 0.0, nu = 0.0;
   for (int b = threadIdx.x; b < nb; b += kBlock) {
@@ -226,7 +252,7 @@ __global__ void __launch_bounds__(kBlock) diag_final_kernel(const double* pn, in
   um = block_reduce(um, sh, 1);
   bad = block_reduce(bad, sh, 0);
   if (threadIdx.x == 0) {
-    out[0] = nu;
+    out[0] = nu * inv_face_nodes;
     out[1] = ke;
     out[2] = st;
     out[3] = um;
@@ -234,15 +260,70 @@ __global__ void __launch_bounds__(kBlock) diag_final_kernel(const double* pn, in
   }
 }
 
-size_t node_blocks(const StateDesc& d) {
+// acc[0] += sum of the wall-Nusselt slots (fixed order); slots reset to 0.
+__global__ void __launch_bounds__(kBlock) nu_slots_reduce_kernel(double* slot, size_t count, double* acc) {
+  __shared__ double sh[kBlock];
+  double v = 0.0;
+  for (size_t i = threadIdx.x; i < count; i += kBlock) {
+    v += slot[i];
+    slot[i] = 0.0;
+  }
+  v = block_reduce(v, sh, 0);
+  if (threadIdx.x == 0) acc[0] += v;
+}
+
+__global__ void __launch_bounds__(kBlock) fill_zero_kernel(double* p, size_t count) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
+    p[i] = 0.0;
+}
+
+// Adjoint seeds of J = weight <Nu>_face with
+// <Nu> = (1/M) sum_wall -(L / dT_ref) (-8/3 T_w + 3 T(1/2) - 1/3 T(3/2)):
+// dJ/dT = 3 s on the first layer, -s/3 on the second, 0 elsewhere, and
+// dJ/dT_w = -8/3 s, with s = -(L / dT_ref) weight / M.
+__global__ void __launch_bounds__(kBlock) nu_seed_kernel(int nx, int ny, int nz, int face, double s, double* dJdT) {
+  const size_t N = (size_t)nx * ny * nz;
+  const int k = face >> 1;
+  const int n = k == 0 ? nx : (k == 1 ? ny : nz);
+  for (size_t node = (size_t)blockIdx.x * blockDim.x + threadIdx.x; node < N;
+       node += (size_t)gridDim.x * blockDim.x) {
+    const int c = k == 0 ? (int)(node % nx) : (k == 1 ? (int)((node / nx) % ny) : (int)(node / ((size_t)nx * ny)));
+    const int layer = (face & 1) ? n - 1 - c : c;
+    dJdT[node] = layer == 0 ? 3.0 * s : (layer == 1 ? -s / 3.0 : 0.0);
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) nu_seed_wall_kernel(size_t M, double s, double* dJdTw) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < M; i += (size_t)gridDim.x * blockDim.x)
+    dJdTw[i] = -8.0 / 3.0 * s;
+}
+
+unsigned grid_for(size_t count) {
+  const size_t b = (count + kBlock - 1) / kBlock;
+  return (unsigned)(b < 4096 ? (b > 0 ? b : 1) : 4096);
+}
+
+// Blocks of the two stage-1 kernels: one per kBlock nodes, capped.
+unsigned diag_node_blocks(const StateDesc& d) {
   const size_t N = (size_t)d.nx * d.ny * d.nz;
-  return (N + kBlock - 1) / kBlock;
+  const size_t b = (N + kBlock - 1) / kBlock;
+  return (unsigned)(b < kDiagNodeBlocks ? b : kDiagNodeBlocks);
 }
 
 size_t face_nodes(const StateDesc& d, int face) {
   const int k = face >> 1;
   const size_t n[3] = {(size_t)d.nx, (size_t)d.ny, (size_t)d.nz};
   return n[(k + 1) % 3] * n[(k + 2) % 3];
+}
+
+unsigned diag_face_blocks(const StateDesc& d, int face) {
+  const size_t b = (face_nodes(d, face) + kBlock - 1) / kBlock;
+  return (unsigned)(b < kDiagFaceBlocks ? b : kDiagFaceBlocks);
+}
+
+size_t node_blocks(const StateDesc& d) {
+  const size_t N = (size_t)d.nx * d.ny * d.nz;
+  return (N + kBlock - 1) / kBlock;
 }
 
 }  // namespace
@@ -274,29 +355,64 @@ hipError_t launch_import(const StateDesc& d, void* dst, const double* src, hipSt
   return hipGetLastError();
 }
 
-size_t diag_partials_needed(const StateDesc& d) {
-  size_t mf = 0;
-  for (int f = 0; f < 6; ++f) mf = face_nodes(d, f) > mf ? face_nodes(d, f) : mf;
-  return node_blocks(d) * 4 + (mf + kBlock - 1) / kBlock + 8;
-}
-
-hipError_t launch_diagnostics(const StateDesc& d, int face, const FaceDev& fd, double dT_ref, double* partials,
+hipError_t launch_diagnostics(const StateDesc& d, int face, const FaceDev& fd, double dT_ref, double* scratch,
                               double* out, hipStream_t s) {
-  const unsigned nb = (unsigned)node_blocks(d);
-  double* pf = partials + (size_t)nb * 4;
+  const unsigned nb = diag_node_blocks(d);
+  double* pf = scratch + (size_t)kDiagNodeBlocks * 4;
   unsigned nf = 0;
+  double inv_m = 0.0;
   if (d.precision == 0)
-    diag_nodes_kernel<double><<<nb, kBlock, 0, s>>>(d, partials);
+    diag_nodes_kernel<double><<<nb, kBlock, 0, s>>>(d, scratch);
   else
-    diag_nodes_kernel<float><<<nb, kBlock, 0, s>>>(d, partials);
+    diag_nodes_kernel<float><<<nb, kBlock, 0, s>>>(d, scratch);
   if (face >= 0) {
-    nf = (unsigned)((face_nodes(d, face) + kBlock - 1) / kBlock);
+    nf = diag_face_blocks(d, face);
+    inv_m = 1.0 / (double)face_nodes(d, face);
     if (d.precision == 0)
       diag_face_kernel<double><<<nf, kBlock, 0, s>>>(d, face, fd, dT_ref, pf);
     else
       diag_face_kernel<float><<<nf, kBlock, 0, s>>>(d, face, fd, dT_ref, pf);
   }
-  diag_final_kernel<<<1, kBlock, 0, s>>>(partials, (int)nb, pf, (int)nf, out);
+  diag_final_kernel<<<1, kBlock, 0, s>>>(scratch, (int)nb, pf, (int)nf, inv_m, out);
+  return hipGetLastError();
+}
+
+size_t nu_slot_count(int nx, int ny, int nz, int nxp, int face) {
+  const size_t nxt = (size_t)nxp / 64;
+  const int k = face >> 1;
+  if (k == 0) return 2 * (size_t)ny * nz;
+  if (k == 1) return 2 * (size_t)nz * nxt;
+  return 2 * (size_t)ny * nxt;
+}
+
+hipError_t launch_nu_slots_reduce(double* slot, size_t count, double* acc, hipStream_t s) {
+  nu_slots_reduce_kernel<<<1, kBlock, 0, s>>>(slot, count, acc);
+  return hipGetLastError();
+}
+
+hipError_t launch_nu_local(const StateDesc& d, int face, const FaceDev& fd, double dT_ref, double* out,
+                           hipStream_t s) {
+  const unsigned nb = grid_for(face_nodes(d, face));
+  if (d.precision == 0)
+    nu_local_kernel<double><<<nb, kBlock, 0, s>>>(d, face, fd, dT_ref, out);
+  else
+    nu_local_kernel<float><<<nb, kBlock, 0, s>>>(d, face, fd, dT_ref, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_zero(double* p, size_t count, hipStream_t s) {
+  fill_zero_kernel<<<grid_for(count), kBlock, 0, s>>>(p, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_nu_seed(const StateDesc& d, int face, double dT_ref, double weight, double* dJdT, double* dJdTw,
+                          hipStream_t s) {
+  const size_t N = (size_t)d.nx * d.ny * d.nz;
+  const size_t M = face_nodes(d, face);
+  const int n[3] = {d.nx, d.ny, d.nz};
+  const double sc = -((double)n[face >> 1] / dT_ref) * weight / (double)M;
+  nu_seed_kernel<<<grid_for(N), kBlock, 0, s>>>(d.nx, d.ny, d.nz, face, sc, dJdT);
+  if (dJdTw) nu_seed_wall_kernel<<<grid_for(M), kBlock, 0, s>>>(M, sc, dJdTw);
   return hipGetLastError();
 }
 

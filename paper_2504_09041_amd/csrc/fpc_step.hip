@@ -51,18 +51,94 @@ namespace {
 
 using namespace stream;
 
+// Lane l's value of a double (any lane, active or not).
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Fused wall-Nusselt accumulation (StepArgs::obj): a node in the layer next
+// to the face (the stencil's T(1/2)) adds scale (3 T - 8/3 T_w), a node in the
+// second layer (T(3/2)) adds scale (-T / 3), with T the time-level
+// temperature of the stored post-collision populations (Sec. 6.1 stencil,
+// Nu = -(L / dT) dT/dn).  The wavefront sums its lanes in a fixed order and
+// adds the sum to the slot of its tile.
+template <class L, class R>
+__device__ __forceinline__ void nu_accumulate(const StepArgs<R>& a, int x, int y, int z, double t) {
+  // (axis lengths come from NuAcc: a select between fields of the kernel
+  // argument would make the compiler keep a private copy of it)
+  const NuAcc& o = a.obj;
+  const int k = o.face >> 1;
+  const int c = k == 0 ? x : (k == 1 ? y : z);
+  const int layer = (o.face & 1) ? o.nk - 1 - c : c;
+  const bool in = layer <= 1;
+  if (!__any(in)) return;
+  double v = 0.0;
+  if (in) {
+    const double T = (o.T_o + (o.Tg[0] * (double)x + o.Tg[1] * (double)y + o.Tg[2] * (double)z)) + t;
+    if (layer == 0) {
+      const size_t i = (size_t)(k == 2 ? y : z) * o.nt + (k == 0 ? y : x);
+      const double Tw = o.Tprof ? o.Tprof[i] : o.Tw;
+      v = o.scale * (3.0 * T - (8.0 / 3.0) * Tw);
+    } else {
+      v = o.scale * (-T / 3.0);
+    }
+  }
+  // sum over the wavefront in a fixed order: a butterfly when every lane is
+  // active, else lane by lane over the active lanes (a ragged last tile)
+  const unsigned long long act = __ballot(1);
+  double sum = v;
+  if (act == ~0ull) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
+  } else {
+    sum = 0.0;
+    for (int l = 0; l < 64; ++l)
+      if ((act >> l) & 1ull) sum += readlane_f64(v, l);
+  }
+  // slot of this wavefront's tile (x >> 6, y, z and, on y / z faces, the
+  // layer are uniform over a wavefront)
+  const int xt = x >> 6;
+  const int nxt = a.nxp >> 6;
+  size_t idx;
+  if (k == 0) {
+    const int xlo = (o.face & 1) ? o.nk - 2 : 0;
+    idx = ((size_t)z * o.nt + y) * 2 + (size_t)(xt - (xlo >> 6));
+  } else if (k == 1) {
+    idx = ((size_t)z * 2 + layer) * nxt + xt;
+  } else {
+    idx = ((size_t)layer * o.ns + y) * nxt + xt;
+  }
+  // one add per slot and launch (the launches of a run are ordered on the
+  // stream, so the per-slot sum has a fixed order); an atomic add needs no
+  // return value, so the wavefront does not wait for the slot's old value
+  if (__lane_id() == (unsigned)(__ffsll((long long)act) - 1)) atomicAdd(&o.slot[idx], sum);
+}
+
 template <class L, class R, class M, int UP, bool NT, bool STD>
-__device__ __forceinline__ void collide_store(const StepArgs<R>& a, const M& m, unsigned node, R Tr, R (&f)[L::Qf],
-                                              R (&g)[L::Qg]) {
+__device__ __forceinline__ void collide_store(const StepArgs<R>& a, const M& m, int x, int y, int z, unsigned node,
+                                              R Tr, R (&f)[L::Qf], R (&g)[L::Qg]) {
   if constexpr (L::D == 2)
     collide2d<R, UP, STD, L::Qg>(f, g, a.c, Tr, (Macros<R>*)nullptr);
   else
     collide3d<R, UP, STD, L::Qg>(f, g, a.c, Tr, (Macros<R>*)nullptr);
+  // the fused wall-Nusselt accumulation needs only the sum of the stored
+  // thermal values; it runs after the stores so that the populations are no
+  // longer live
+  const bool obj = a.obj.slot != nullptr;
+  double t = 0.0;
+  if (obj) {
+#pragma unroll
+    for (int q = 0; q < L::Qg; ++q) t += (double)g[q];
+  }
   auto cur = m.cursor(node);
 #pragma unroll
   for (int q = 0; q < L::Qf; ++q) m.template store_next<NT>(cur, f[q]);
 #pragma unroll
   for (int q = 0; q < L::Qg; ++q) m.template store_next<NT>(cur, g[q]);
+  if (obj) nu_accumulate<L, R>(a, x, y, z, t);
 }
 
 
@@ -97,7 +173,7 @@ __global__ void __launch_bounds__(L::D == 2 ? FPC_BLOCK_2D : (sizeof(R) == 4 ? F
   } else {
     gather<L, R, M, true, true, L::D == 3>(a, m, x, y, z, node, Tr, f, g);
   }
-  collide_store<L, R, M, UP, NT, STD>(a, m, node, Tr, f, g);
+  collide_store<L, R, M, UP, NT, STD>(a, m, x, y, z, node, Tr, f, g);
 }
 
 // Initial state: the collision of f = w rho0, g = w^T T_init at every node.
@@ -118,7 +194,7 @@ __global__ void __launch_bounds__(256) init_kernel(StepArgs<R> a, const double* 
   const R dT = R(T_init[((size_t)z * a.ny + y) * a.nx + x]) - Tr;
 #pragma unroll
   for (int q = 0; q < L::Qg; ++q) g[q] = L::template wT<R>(q, a.c.cs2T) * dT;
-  collide_store<L, R, M, UP, false, false>(a, m, node, Tr, f, g);
+  collide_store<L, R, M, UP, false, false>(a, m, x, y, z, node, Tr, f, g);
 }
 
 // Whether the rates form the standard set of rate_f / rate_g: the viscous

@@ -57,29 +57,31 @@ def set_faces(p, faces):
 
 def conduction_reference(p, axis):
     """Set the FP32-deviation thermal storage reference to the conduction
-    profile between the two Dirichlet walls normal to ``axis`` (their wall
-    temperatures, walls halfway outside the outermost nodes)."""
-    lo, hi = 2 * axis, 2 * axis + 1
-    dirichlet = (A.FPC_BC_NOSLIP_DIRICHLET, A.FPC_BC_LID_DIRICHLET)
-    if p.bc[lo] not in dirichlet or p.bc[hi] not in dirichlet:
-        raise ValueError("conduction reference needs Dirichlet walls on both faces of axis %d" % axis)
-    n = (p.nx, p.ny, p.nz)[axis]
-    p.T_ref_axis = axis
-    # with T0 the mean of the two wall temperatures (as the natural and mixed
-    # helpers set it), Tr(x) = T0 + slope (x - (n-1)/2) meets the wall values
-    # at x = -1/2 and n - 1/2
-    p.T_ref_slope = (p.wall_T[hi] - p.wall_T[lo]) / n
+    profile between the two Dirichlet walls normal to ``axis`` (the library
+    computes it from their wall temperatures)."""
+    A.call("fpc_params_conduction_reference", ctypes.byref(p), int(axis))
     return p
 
 
-def params_from_workload(cfg, precision="f64", shape=None, cs2_T=None, T_reference="uniform", model="FP",
+def storage_reference(p):
+    """(axis, slope) of the FP32 storage reference the parameters select
+    (axis -1: the uniform T0)."""
+    k = ctypes.c_int()
+    s = ctypes.c_double()
+    A.call("fpc_storage_reference", ctypes.byref(p), ctypes.byref(k), ctypes.byref(s))
+    return k.value, s.value
+
+
+def params_from_workload(cfg, precision="f64", shape=None, cs2_T=None, T_reference="auto", model="FP",
                          thermal_option="A"):
     """C parameters of a workload description (``workloads.CONFIGS`` entry).
 
     The physical -> lattice mapping runs in the library
     (fpc_params_natural / fpc_params_mixed).  ``T_reference`` picks the
-    FP32-deviation storage reference of g: "uniform" (T0) or "conduction"
-    (affine between the Dirichlet walls normal to the workload's L axis).
+    FP32-deviation storage reference of g: "auto" (the library's default: the
+    conduction profile between the walls of a Dirichlet pair, else T0),
+    "uniform" (T0) or "conduction" (between the Dirichlet walls normal to the
+    workload's L axis).
     ``model``: "FP" or "MCM" (the Maxwellian comparator); ``thermal_option``:
     "A" or "B" (acts on the D2Q9 / D3Q15 thermal lattices)."""
     shape = tuple(cfg["shape"]) if shape is None else tuple(shape)
@@ -98,8 +100,11 @@ def params_from_workload(cfg, precision="f64", shape=None, cs2_T=None, T_referen
     set_faces(p, cfg["faces"])
     if T_reference == "conduction":
         conduction_reference(p, cfg["L_axis"])
-    elif T_reference != "uniform":
-        raise ValueError("T_reference must be 'uniform' or 'conduction'")
+    elif T_reference == "uniform":
+        p.T_ref_axis = -1
+        p.T_ref_slope = 0.0
+    elif T_reference != "auto":
+        raise ValueError("T_reference must be 'auto', 'uniform' or 'conduction'")
     return p
 
 
@@ -169,6 +174,26 @@ class Simulation:
     def step(self, n=1):
         A.call("fpc_step", self._h, int(n))
 
+    def step_nusselt(self, n, face, weight, acc):
+        """Advance n steps; after each, acc[0] += weight * <Nu>_face of the
+        new time level (acc: one-element FP64 device tensor)."""
+        if acc.dtype != torch.float64 or not acc.is_cuda or acc.numel() < 1:
+            raise ValueError("acc must be a FP64 device tensor")
+        A.call("fpc_step_nusselt", self._h, int(n), int(FACE_INDEX.get(face, face)), float(weight),
+               ctypes.c_void_p(acc.data_ptr()))
+
+    def nusselt_seed(self, face, weight=1.0):
+        """Adjoint seeds of weight * <Nu>_face: (dJ/dT as an (nz, ny, nx)
+        tensor, dJ/dT_w per wall node in the profile layout, flat)."""
+        fi = FACE_INDEX.get(face, face)
+        nx, ny, nz = self.shape
+        M = self.N // (nx, ny, nz)[fi // 2]
+        dT = torch.empty((nz, ny, nx), dtype=torch.float64, device=self.device)
+        dTw = torch.empty(M, dtype=torch.float64, device=self.device)
+        A.call("fpc_nusselt_seed", self._h, int(fi), float(weight), ctypes.c_void_p(dT.data_ptr()),
+               ctypes.c_void_p(dTw.data_ptr()))
+        return dT, dTw
+
     @property
     def step_count(self):
         v = ctypes.c_longlong()
@@ -194,6 +219,16 @@ class Simulation:
             A.check(rc, "fpc_diagnostics")
         return {"nu": vals[0].value, "ke": vals[1].value, "sumT": vals[2].value, "umax": vals[3].value,
                 "unstable": rc == A.FPC_ERR_UNSTABLE}
+
+    def nusselt_local(self, face):
+        """Local wall Nusselt numbers of the current time level on ``face``,
+        shaped like the face's profile (slower tangential axis first)."""
+        fi = FACE_INDEX.get(face, face)
+        nx, ny, nz = self.shape
+        shp = {0: (nz, ny), 1: (nz, nx), 2: (ny, nx)}[fi // 2]
+        out = torch.empty(shp, dtype=torch.float64, device=self.device)
+        A.call("fpc_nusselt_local", self._h, int(fi), ctypes.c_void_p(out.data_ptr()))
+        return out
 
     def export_fp64(self):
         """Current state as full FP64 populations, shape (Qf + Qg, nz, ny, nx)."""

@@ -86,14 +86,18 @@ def perturbed_state(cfg, seed, amp=1e-2, **prm_kw):
 
 
 def workload_params(cfg, precision, model="FP", thermal_option="A"):
-    """C parameters; precision "f64", "f32dev" (uniform thermal storage
-    reference T0) or "f32cond" (FP32 deviations from the conduction profile
-    between the Dirichlet walls of the workload's L axis)."""
+    """C parameters; precision "f64", "f32dev" (FP32 deviations with the
+    library's default storage reference: the conduction profile between a
+    pair of Dirichlet walls, else T0), "f32uni" (the uniform reference T0) or
+    "f32cond" (the conduction profile between the Dirichlet walls of the
+    workload's L axis, set explicitly)."""
     from paper_2504_09041_amd.sim import params_from_workload
 
     kw = dict(model=model, thermal_option=thermal_option)
     if precision == "f32cond":
         return params_from_workload(cfg, "f32dev", T_reference="conduction", **kw)
+    if precision == "f32uni":
+        return params_from_workload(cfg, "f32dev", T_reference="uniform", **kw)
     return params_from_workload(cfg, precision, **kw)
 
 

@@ -87,7 +87,7 @@ def test_validation_errors():
     assert lib.fpc_state_bytes(ctypes.byref(p), ctypes.byref(nb), None) == A.FPC_ERR_ARG
     p.bc[4] = p.bc[5] = A.FPC_BC_PERIODIC
     # thermal storage reference: axis in range, not periodic, finite slope
-    assert p.T_ref_axis == -1 and p.T_ref_slope == 0.0
+    assert p.T_ref_axis == A.FPC_TREF_AUTO and p.T_ref_slope == 0.0
     p.T_ref_slope = 0.01
     p.T_ref_axis = 2
     assert lib.fpc_state_bytes(ctypes.byref(p), ctypes.byref(nb), None) == A.FPC_ERR_ARG
@@ -239,3 +239,55 @@ def test_null_and_invalid_arguments_fail_before_any_launch():
     assert lib.fpc_params_natural(None, 1e6, 0.71, 0.05, 1, 0.5, -0.5) == A.FPC_ERR_ARG
     assert lib.fpc_params_mixed(None, 100.0, 1.0, 71.0, 0.1, 1, 0.5, -0.5) == A.FPC_ERR_ARG
     assert lib.fpc_state_bytes(None, None, None) == A.FPC_ERR_ARG
+
+
+@pytest.mark.parametrize("name", ["dhc2d_64", "rb2d_1024x512", "dhc3d_256", "mixed2d_512", "rb3d_128"])
+def test_default_storage_reference_is_the_conduction_profile(name):
+    """FPC_TREF_AUTO resolves to the conduction profile between the
+    workload's Dirichlet walls: axis L, slope (T_+ - T_-) / n_L, the line
+    through the two wall temperatures with the walls halfway outside the
+    outermost nodes (its values at x = -1/2 and n - 1/2 are the wall
+    temperatures)."""
+    from paper_2504_09041_amd.sim import params_from_workload, storage_reference
+
+    _lib()
+    cfg = workloads.config(name)
+    k = cfg["L_axis"]
+    n = cfg["shape"][k]
+    lo, hi = cfg["faces"][2 * k]["T"], cfg["faces"][2 * k + 1]["T"]
+    p = params_from_workload(cfg, "f32dev")
+    assert p.T_ref_axis == A.FPC_TREF_AUTO
+    axis, slope = storage_reference(p)
+    assert axis == k
+    T0 = p.T0
+    assert abs((T0 + slope * (-0.5 - (n - 1) / 2)) - lo) < 1e-15
+    assert abs((T0 + slope * (n - 0.5 - (n - 1) / 2)) - hi) < 1e-15
+    # the explicit conduction reference is the same; uniform and FP64 report none
+    assert storage_reference(params_from_workload(cfg, "f32dev", T_reference="conduction")) == (axis, slope)
+    assert storage_reference(params_from_workload(cfg, "f32dev", T_reference="uniform")) == (-1, 0.0)
+    assert storage_reference(params_from_workload(cfg, "f64")) == (-1, 0.0)
+
+
+def test_storage_reference_choices_and_errors():
+    from paper_2504_09041_amd.sim import params_from_workload, storage_reference
+
+    lib = _lib()
+    # no Dirichlet pair (adiabatic or periodic everywhere): the uniform reference
+    cfg = workloads.config("dhc2d_64")
+    cfg["faces"][0] = dict(cfg["faces"][2])
+    cfg["faces"][1] = dict(cfg["faces"][2])
+    p = params_from_workload(cfg, "f32dev")
+    assert storage_reference(p) == (-1, 0.0)
+    assert lib.fpc_params_conduction_reference(ctypes.byref(p), 0) == A.FPC_ERR_ARG
+    assert lib.fpc_params_conduction_reference(ctypes.byref(p), 2) == A.FPC_ERR_ARG
+    # two Dirichlet pairs: the larger wall-temperature difference wins
+    cfg = workloads.config("dhc3d_256", shape=(8, 6, 10))
+    cfg["faces"][4] = {"fluid": "noslip", "thermal": "dirichlet", "T": 2.0, "u_w": (0.0, 0.0, 0.0)}
+    cfg["faces"][5] = {"fluid": "noslip", "thermal": "dirichlet", "T": -1.0, "u_w": (0.0, 0.0, 0.0)}
+    p = params_from_workload(cfg, "f32dev")
+    assert storage_reference(p) == (2, -3.0 / 10)
+    assert lib.fpc_params_conduction_reference(ctypes.byref(p), 0) == A.FPC_OK
+    assert storage_reference(p) == (0, -1.0 / 8)
+    p.T_ref_axis = -3
+    nb = ctypes.c_size_t()
+    assert lib.fpc_state_bytes(ctypes.byref(p), ctypes.byref(nb), None) == A.FPC_ERR_ARG

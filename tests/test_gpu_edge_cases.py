@@ -140,28 +140,32 @@ def test_cubes_match_oracle(wl, n):
     sim.close()
 
 
-@pytest.mark.parametrize("reference,max_dT,max_dNu", [("uniform", 1e-4, 2e-3), ("conduction", 1e-6, 1e-5)])
-def test_fp32_tracks_fp64_at_full_size(reference, max_dT, max_dNu):
-    """2D Rayleigh-Benard 1024x512 from the same initial field, 4000 steps:
-    the FP32 deviation form against the GPU FP64 run (itself pinned to the
-    oracle).  With the conduction reference FP32 stays two orders inside the
-    bars (1e-4 of the temperature difference on T, 1e-3 on the bottom-wall
-    Nusselt number); with the uniform reference T stays inside its bar but
-    the Nusselt error has already grown to about 1e-3 by this step."""
-    from paper_2504_09041_amd.sim import Simulation, params_from_workload
-
+def test_fp32_default_meets_the_bars_over_the_full_run():
+    """2D Rayleigh-Benard 1024x512, Ra 1e6, from the same initial field over
+    the workload's full 50,000 steps: the FP32 deviation form with the
+    library's default storage reference against the GPU FP64 run (itself
+    pinned to the oracle), checked every 5,000 steps against the bars of
+    1e-4 of the temperature difference on T and 1e-3 relative on the
+    bottom-wall Nusselt number."""
     cfg = workloads.config("rb2d_1024x512")
     T0 = torch.tensor(workloads.initial_temperature(cfg), device="cuda")
-    out = {}
-    for prec, ref in (("f64", "uniform"), ("f32dev", reference)):
-        sim = Simulation(params_from_workload(cfg, prec, T_reference=ref))
-        sim.init(T0)
-        sim.step(4000)
-        out[prec] = (sim.macros()["T"], sim.diagnostics(cfg["nu_face"])["nu"])
-        sim.close()
+    sims = {}
+    for prec in ("f64", "f32dev"):
+        sims[prec] = G.make_sim(cfg, prec)
+        sims[prec].init(T0)
     dT = cfg["T_hot"] - cfg["T_cold"]
-    eT = float((out["f32dev"][0] - out["f64"][0]).abs().max()) / dT
-    eNu = abs(out["f32dev"][1] - out["f64"][1]) / abs(out["f64"][1])
-    print(f"reference={reference}: max|dT|/DeltaT {eT:.2e}, rel dNu {eNu:.2e}")
-    assert eT < max_dT
-    assert eNu < max_dNu
+    worst_T = worst_Nu = 0.0
+    for n in range(5000, 50001, 5000):
+        out = {}
+        for prec, sim in sims.items():
+            sim.step(5000)
+            out[prec] = (sim.macros()["T"], sim.diagnostics(cfg["nu_face"])["nu"])
+        eT = float((out["f32dev"][0] - out["f64"][0]).abs().max()) / dT
+        eNu = abs(out["f32dev"][1] - out["f64"][1]) / abs(out["f64"][1])
+        worst_T, worst_Nu = max(worst_T, eT), max(worst_Nu, eNu)
+        print(f"step {n}: max|dT|/DeltaT {eT:.2e}, rel dNu {eNu:.2e}", flush=True)
+        assert eT < 1e-4
+        assert eNu < 1e-3
+    for sim in sims.values():
+        sim.close()
+    print(f"worst over the run: {worst_T:.2e} / {worst_Nu:.2e}")
