@@ -298,6 +298,28 @@ int fpc_diagnostics(fpc_sim* s, int wall_face, double* nu_mean, double* ke, doub
  */
 int fpc_nusselt_local(fpc_sim* s, int wall_face, double* nu);
 
+/*
+ * The diagnostics of fpc_diagnostics without allocating, synchronising or
+ * copying to the host: for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Writes out[0..4] = (mean wall Nusselt number on wall_face, or 0 for
+ * wall_face = -1; KE; sum T; max |u|; number of nodes with a non-finite
+ * macro), exactly the values fpc_diagnostics returns (same kernels, same
+ * summation order), to `out` (device pointer, 5 FP64 values), asynchronously
+ * on the simulation's stream.  The watchdog is left to the caller (out[4] != 0
+ * or out[3] > 0.5).
+ * The reduction partials live in a library-owned device array of
+ * 1024 * 4 + 64 + 8 doubles (33 KiB) per GPU, held until the process ends;
+ * the reductions use at most 1024 + 64 blocks, so every grid the library
+ * accepts fits it (the call still returns FPC_ERR_SIZE if that bound were
+ * ever exceeded).  Every call on one GPU shares that array: calls that overlap
+ * on one GPU (other streams or host threads) race and must be serialised by
+ * the caller.  Nothing in it needs clearing between calls.  Errors:
+ * FPC_ERR_ARG (NULL sim or out, bad wall_face), FPC_ERR_STATE (periodic or
+ * missing face), FPC_ERR_HIP (launch failure).
+ */
+int fpc_diagnostics_noalloc(fpc_sim* s, int wall_face, double* out);
+
 /* Copy the current state (fpc_state_bytes() bytes, storage format) to / from
  * device memory.  fpc_load resets the step counter to `step`. */
 int fpc_save(const fpc_sim* s, void* dst);

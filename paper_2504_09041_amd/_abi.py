@@ -48,7 +48,7 @@ EXPORTED = (
     "fpc_params_conduction_reference", "fpc_storage_reference",
     "fpc_state_bytes", "fpc_create", "fpc_destroy", "fpc_set_stream", "fpc_init", "fpc_step", "fpc_step_nusselt",
     "fpc_step_from",
-    "fpc_get_step", "fpc_macros", "fpc_diagnostics", "fpc_nusselt_local", "fpc_save", "fpc_load", "fpc_export_fp64",
+    "fpc_get_step", "fpc_macros", "fpc_diagnostics", "fpc_nusselt_local", "fpc_diagnostics_noalloc", "fpc_save", "fpc_load", "fpc_export_fp64",
     "fpc_import_fp64", "fpc_current_buffer", "fpc_nusselt_seed", "fpc_adjoint_step", "fpc_adjoint_init",
 )
 
@@ -125,6 +125,7 @@ def load():
         "fpc_get_step": (i, [vp, ctypes.POINTER(ll)]),
         "fpc_macros": (i, [vp, vp, vp, vp]),
         "fpc_diagnostics": (i, [vp, i, dp, dp, dp, dp]),
+        "fpc_diagnostics_noalloc": (i, [vp, i, vp]),
         "fpc_nusselt_local": (i, [vp, i, vp]),
         "fpc_save": (i, [vp, vp]),
         "fpc_load": (i, [vp, vp, ll]),

@@ -6,12 +6,18 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "../../include/fpclbm.h"
 #include "fpc_kernels.h"
 
 using namespace fpc;
+
+// Device scratch of fpc_diagnostics_noalloc: the reduction partials, one copy
+// per GPU, held until the process ends.  Host code never uses this name as an
+// address: it takes the per-device address from hipGetSymbolAddress.
+static __device__ __align__(256) double scratch[kDiagScratchDoubles];
 
 struct fpc_sim {
   fpc_params p;
@@ -268,6 +274,30 @@ StateDesc desc_of(const fpc_sim* s) {
 
 bool aligned256(const void* ptr) { return (reinterpret_cast<uintptr_t>(ptr) & 255u) == 0; }
 
+// Per-device address of `scratch`, resolved once per device (with that device
+// current) by the first fpc_create on it.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kMaxDevices];
+
+int resolve_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return fail(FPC_ERR_STATE, "device %d out of range", device);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_dev[device]) return FPC_OK;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return hipfail(e, "hipGetSymbolAddress(scratch)");
+  if (!ptr) return fail(FPC_ERR_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+  g_scratch_dev[device] = static_cast<double*>(ptr);
+  return FPC_OK;
+}
+
+double* scratch_of(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch_dev[device];
+}
+
 int check_wall_face(const fpc_sim* s, int wall_face) {
   if (wall_face < -1 || wall_face > 5) return fail(FPC_ERR_ARG, "wall_face %d invalid", wall_face);
   if (wall_face >= 4 && s->dim == 2) return fail(FPC_ERR_STATE, "2D has no z faces");
@@ -436,6 +466,11 @@ int fpc_create(const fpc_params* p, void* bufA, void* bufB, void* hip_stream, fp
     delete s;
     return hipfail(e, "hipGetDevice");
   }
+  rc = resolve_scratch(s->device);
+  if (rc) {
+    delete s;
+    return rc;
+  }
   s->scratch_elems = kDiagScratchDoubles;
   e = hipMalloc(&s->scratch, s->scratch_elems * sizeof(double));
   if (e != hipSuccess) {
@@ -603,6 +638,22 @@ int fpc_nusselt_local(fpc_sim* s, int wall_face, double* nu) {
   if (rc) return rc;
   const hipError_t e = launch_nu_local(desc_of(s), wall_face, face_of(s, wall_face), s->p.dT_ref, nu, s->stream);
   if (e != hipSuccess) return hipfail(e, "local Nusselt kernel");
+  return FPC_OK;
+}
+
+int fpc_diagnostics_noalloc(fpc_sim* s, int wall_face, double* out) {
+  if (!s || !out) return fail(FPC_ERR_ARG, "NULL argument");
+  int rc = check_wall_face(s, wall_face);
+  if (rc) return rc;
+  double* part = scratch_of(s->device);
+  if (!part) return fail(FPC_ERR_STATE, "no scratch address for device %d", s->device);
+  // the reductions use at most kDiagNodeBlocks + kDiagFaceBlocks blocks for any
+  // grid, so their partials always fit; kept as a guard on that bound
+  if ((size_t)kDiagNodeBlocks * 4 + kDiagFaceBlocks > kDiagScratchDoubles)
+    return fail(FPC_ERR_SIZE, "diagnostics partials exceed the %zu-double scratch", kDiagScratchDoubles);
+  const hipError_t e =
+      launch_diagnostics(desc_of(s), wall_face, face_of(s, wall_face), s->p.dT_ref, part, out, s->stream);
+  if (e != hipSuccess) return hipfail(e, "diagnostics kernels");
   return FPC_OK;
 }
 
