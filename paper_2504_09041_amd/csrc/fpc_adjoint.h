@@ -62,6 +62,18 @@ struct MS {
   }
 };
 
+// Slots whose rate is the compile-time 1 of the standard rate set (STD): the
+// moment lands on its attractor (plus half its source), so its pre-collision
+// value drops out of the forward map and of its adjoint.
+template <int D, bool STD>
+__device__ __forceinline__ constexpr bool unit_f(int slot) {
+  return STD && !viscous_slot<D>(slot);
+}
+template <int D, bool STD>
+__device__ __forceinline__ constexpr bool unit_g(int k) {
+  return STD && !(k >= 1 && k <= D);
+}
+
 // Transposed 1D maps.  S(u): (a-, a0, a+) -> (k0, k1, k2) is shift_fwd.
 template <class R>
 __device__ __forceinline__ void shift_fwd_T(R k0, R k1, R k2, R u, R& am, R& a0, R& ap) {
@@ -171,7 +183,7 @@ __device__ constexpr int tlink(int ax, int sgn) {
   return D == 2 ? (sgn > 0 ? 1 + ax : 3 + ax) : (sgn > 0 ? 1 + 2 * ax : 2 + 2 * ax);
 }
 
-template <class R, int D, int UP>
+template <class R, int D, int UP, bool STD = false>
 __device__ __forceinline__ void forward(const R* f, const R* g, const CollParams<R>& c, Tape<R, D>& t) {
   using M = MS<D>;
   constexpr int NM = M::NM;
@@ -206,24 +218,31 @@ __device__ __forceinline__ void forward(const R* f, const R* g, const CollParams
     if (s == 0) t.kt[i] = rho;
     if (s == 1) {
       const int ax = M::ma(i) ? 0 : (M::mb(i) ? 1 : 2);
-      const R w = om[M::slot(i)];
-      t.kt[i] = t.k[i] - w * t.k[i] + (R(1) - R(0.5) * w) * (ax == UP ? Fb : R(0));
+      const R Fa = ax == UP ? Fb : R(0);
+      if (unit_f<D, STD>(M::slot(i))) {
+        t.kt[i] = R(0.5) * Fa;
+      } else {
+        const R w = om[M::slot(i)];
+        t.kt[i] = t.k[i] - w * t.k[i] + (R(1) - R(0.5) * w) * Fa;
+      }
     }
-    if (s == 2 && (M::ma(i) == 1 || M::mb(i) == 1 || M::mc(i) == 1)) t.kt[i] = (R(1) - om[M::slot(i)]) * t.k[i];
+    if (s == 2 && (M::ma(i) == 1 || M::mb(i) == 1 || M::mc(i) == 1))
+      t.kt[i] = unit_f<D, STD>(M::slot(i)) ? R(0) : (R(1) - om[M::slot(i)]) * t.k[i];
   }
   // diagonal second order as combinations (trace / deviators in 3D, 2s / 2d in 2D)
   if (D == 2) {
     const int a = M::at(2, 0, 0), b = M::at(0, 2, 0);
     const R s2 = t.k[a] + t.k[b], d2 = t.k[a] - t.k[b];
-    const R ts = s2 + om[3] * (R(2) * cs2 * rho - s2);
-    const R td = d2 - om[4] * d2;
+    const R ts = unit_f<D, STD>(3) ? R(2) * cs2 * rho : s2 + om[3] * (R(2) * cs2 * rho - s2);
+    const R td = unit_f<D, STD>(4) ? R(0) : d2 - om[4] * d2;
     t.kt[a] = R(0.5) * (ts + td);
     t.kt[b] = R(0.5) * (ts - td);
   } else {
     const int a = M::at(2, 0, 0), b = M::at(0, 2, 0), cc = M::at(0, 0, 2);
     const R tr = t.k[a] + t.k[b] + t.k[cc], d1 = t.k[a] - t.k[b], d2 = t.k[a] - t.k[cc];
-    const R ttr = tr + om[7] * (R(3) * cs2 * rho - tr);
-    const R t1 = d1 - om[8] * d1, t2 = d2 - om[9] * d2;
+    const R ttr = unit_f<D, STD>(7) ? R(3) * cs2 * rho : tr + om[7] * (R(3) * cs2 * rho - tr);
+    const R t1 = unit_f<D, STD>(8) ? R(0) : d1 - om[8] * d1;
+    const R t2 = unit_f<D, STD>(9) ? R(0) : d2 - om[9] * d2;
     const R t200 = (ttr + t1 + t2) * (R(1) / R(3));
     t.kt[a] = t200;
     t.kt[b] = t200 - t1;
@@ -243,8 +262,12 @@ __device__ __forceinline__ void forward(const R* f, const R* g, const CollParams
       R sig = R(0);
       const int mu = M::m(i, UP);
       if (mu > 0 && M::order(M::down(i, UP)) >= 2) sig = R(mu) * Fr * t.k[M::down(i, UP)];
-      const R w = om[M::slot(i)];
-      t.kt[i] = t.k[i] + w * (mv - t.k[i]) + (R(1) - R(0.5) * w) * sig;
+      if (unit_f<D, STD>(M::slot(i))) {
+        t.kt[i] = mv + R(0.5) * sig;
+      } else {
+        const R w = om[M::slot(i)];
+        t.kt[i] = t.k[i] + w * (mv - t.k[i]) + (R(1) - R(0.5) * w) * sig;
+      }
     }
   }
   // thermal: raw -> central
@@ -268,19 +291,20 @@ __device__ __forceinline__ void forward(const R* f, const R* g, const CollParams
   for (int ax = 0; ax < D; ++ax) t.et[1 + ax] = (R(1) - og[1 + ax]) * t.e[1 + ax];
   if (D == 2) {
     const R s2 = t.e[3] + t.e[4], d2 = t.e[3] - t.e[4];
-    const R ts = s2 + og[3] * (R(2) * c.cs2T * T - s2);
-    const R td = d2 - og[4] * d2;
+    const R ts = unit_g<D, STD>(3) ? R(2) * c.cs2T * T : s2 + og[3] * (R(2) * c.cs2T * T - s2);
+    const R td = unit_g<D, STD>(4) ? R(0) : d2 - og[4] * d2;
     t.et[3] = R(0.5) * (ts + td);
     t.et[4] = R(0.5) * (ts - td);
   } else {
 #pragma unroll
-    for (int ax = 0; ax < 3; ++ax) t.et[4 + ax] = t.e[4 + ax] + og[4 + ax] * (c.cs2T * T - t.e[4 + ax]);
+    for (int ax = 0; ax < 3; ++ax)
+      t.et[4 + ax] = unit_g<D, STD>(4 + ax) ? c.cs2T * T : t.e[4 + ax] + og[4 + ax] * (c.cs2T * T - t.e[4 + ax]);
   }
 }
 
 // Reverse of forward(): given fb (= f~bar) and gb (= g~bar) on the post-collision
 // populations, overwrite them with the adjoints of the pre-collision ones.
-template <class R, int D, int UP>
+template <class R, int D, int UP, bool STD = false>
 __device__ __forceinline__ void reverse(const Tape<R, D>& t, const CollParams<R>& c, R* fb, R* gb) {
   using M = MS<D>;
   constexpr int NM = M::NM;
@@ -318,15 +342,21 @@ __device__ __forceinline__ void reverse(const Tape<R, D>& t, const CollParams<R>
     for (int ax = 0; ax < D; ++ax) eb[1 + ax] = (R(1) - og[1 + ax]) * etb[1 + ax];
     if (D == 2) {
       const R tsb = R(0.5) * (etb[3] + etb[4]), tdb = R(0.5) * (etb[3] - etb[4]);
-      const R s2b = (R(1) - og[3]) * tsb, d2b = (R(1) - og[4]) * tdb;
-      Tb += og[3] * R(2) * c.cs2T * tsb;
+      const R s2b = unit_g<D, STD>(3) ? R(0) : (R(1) - og[3]) * tsb;
+      const R d2b = unit_g<D, STD>(4) ? R(0) : (R(1) - og[4]) * tdb;
+      Tb += (unit_g<D, STD>(3) ? R(2) * c.cs2T : og[3] * R(2) * c.cs2T) * tsb;
       eb[3] = s2b + d2b;
       eb[4] = s2b - d2b;
     } else {
 #pragma unroll
       for (int ax = 0; ax < 3; ++ax) {
-        eb[4 + ax] = (R(1) - og[4 + ax]) * etb[4 + ax];
-        Tb += og[4 + ax] * c.cs2T * etb[4 + ax];
+        if (unit_g<D, STD>(4 + ax)) {
+          eb[4 + ax] = R(0);
+          Tb += c.cs2T * etb[4 + ax];
+        } else {
+          eb[4 + ax] = (R(1) - og[4 + ax]) * etb[4 + ax];
+          Tb += og[4 + ax] * c.cs2T * etb[4 + ax];
+        }
       }
     }
     // e_ax = n_ax - u_ax T ; e_2ax = n_2ax - 2 u_ax n_ax + u_ax^2 T ; e_0 = T
@@ -372,11 +402,12 @@ __device__ __forceinline__ void reverse(const Tape<R, D>& t, const CollParams<R>
 #pragma unroll
     for (int i = 0; i < NM; ++i) {
       if (M::order(i) != s) continue;
-      const R w = om[M::slot(i)];
+      const bool unit = unit_f<D, STD>(M::slot(i));
+      const R w = unit ? R(1) : om[M::slot(i)];
       const R ktb = kb[i];
-      kp[i] += (R(1) - w) * ktb;
+      if (!unit) kp[i] += (R(1) - w) * ktb;
       // attractor
-      const R mvb = w * ktb;
+      const R mvb = unit ? ktb : w * ktb;
       R mv = R(0);
 #pragma unroll
       for (int p = 0; p < Terms<D>::npairs; ++p)
@@ -391,7 +422,7 @@ __device__ __forceinline__ void reverse(const Tape<R, D>& t, const CollParams<R>
       // source
       const int mu = M::m(i, UP);
       if (mu > 0 && M::order(M::down(i, UP)) >= 2) {
-        const R sb = (R(1) - R(0.5) * w) * ktb;
+        const R sb = unit ? R(0.5) * ktb : (R(1) - R(0.5) * w) * ktb;
         const int p = M::down(i, UP);
         const R sig = R(mu) * Fr * t.k[p];
         Fbb += sb * R(mu) * t.k[p] / t.rho;
@@ -403,14 +434,15 @@ __device__ __forceinline__ void reverse(const Tape<R, D>& t, const CollParams<R>
   // second order: off-diagonal
 #pragma unroll
   for (int i = 0; i < NM; ++i)
-    if (M::order(i) == 2 && (M::ma(i) == 1 || M::mb(i) == 1 || M::mc(i) == 1))
+    if (M::order(i) == 2 && (M::ma(i) == 1 || M::mb(i) == 1 || M::mc(i) == 1) && !unit_f<D, STD>(M::slot(i)))
       kp[i] += (R(1) - om[M::slot(i)]) * kb[i];
   // second order: diagonal combinations
   if (D == 2) {
     const int a = M::at(2, 0, 0), b = M::at(0, 2, 0);
     const R tsb = R(0.5) * (kb[a] + kb[b]), tdb = R(0.5) * (kb[a] - kb[b]);
-    const R s2b = (R(1) - om[3]) * tsb, d2b = (R(1) - om[4]) * tdb;
-    rhob += om[3] * R(2) * cs2 * tsb;
+    const R s2b = unit_f<D, STD>(3) ? R(0) : (R(1) - om[3]) * tsb;
+    const R d2b = unit_f<D, STD>(4) ? R(0) : (R(1) - om[4]) * tdb;
+    rhob += (unit_f<D, STD>(3) ? R(2) * cs2 : om[3] * R(2) * cs2) * tsb;
     kp[a] += s2b + d2b;
     kp[b] += s2b - d2b;
   } else {
@@ -419,8 +451,10 @@ __device__ __forceinline__ void reverse(const Tape<R, D>& t, const CollParams<R>
     const R ttrb = (kb[a] + kb[b] + kb[cc]) * third;
     const R t1b = (kb[a] - R(2) * kb[b] + kb[cc]) * third;
     const R t2b = (kb[a] + kb[b] - R(2) * kb[cc]) * third;
-    const R trb = (R(1) - om[7]) * ttrb, d1b = (R(1) - om[8]) * t1b, d2b = (R(1) - om[9]) * t2b;
-    rhob += om[7] * R(3) * cs2 * ttrb;
+    const R trb = unit_f<D, STD>(7) ? R(0) : (R(1) - om[7]) * ttrb;
+    const R d1b = unit_f<D, STD>(8) ? R(0) : (R(1) - om[8]) * t1b;
+    const R d2b = unit_f<D, STD>(9) ? R(0) : (R(1) - om[9]) * t2b;
+    rhob += (unit_f<D, STD>(7) ? R(3) * cs2 : om[7] * R(3) * cs2) * ttrb;
     kp[a] += trb + d1b + d2b;
     kp[b] += trb - d1b;
     kp[cc] += trb - d2b;
@@ -430,9 +464,13 @@ __device__ __forceinline__ void reverse(const Tape<R, D>& t, const CollParams<R>
   for (int i = 0; i < NM; ++i)
     if (M::order(i) == 1) {
       const int ax = M::ma(i) ? 0 : (M::mb(i) ? 1 : 2);
-      const R w = om[M::slot(i)];
-      kp[i] += (R(1) - w) * kb[i];
-      if (ax == UP) Fbb += (R(1) - R(0.5) * w) * kb[i];
+      if (unit_f<D, STD>(M::slot(i))) {
+        if (ax == UP) Fbb += R(0.5) * kb[i];
+      } else {
+        const R w = om[M::slot(i)];
+        kp[i] += (R(1) - w) * kb[i];
+        if (ax == UP) Fbb += (R(1) - R(0.5) * w) * kb[i];
+      }
     }
   // zeroth order: kt_0 = rho
   rhob += kb[M::at(0, 0, 0)];

@@ -153,7 +153,7 @@ __device__ __forceinline__ void scatter(const AdjArgs<R>& A, const M& mL, int x,
 // read, lam_out written); Buf32 below 4 GiB per buffer, else Glob64.
 // The edge variant is chosen per wavefront (ballot) for the gather and again
 // for the scatter; the collision and its adjoint in between are shared.
-template <class L, class R, class M, int UP>
+template <class L, class R, class M, int UP, bool STD>
 __device__ __forceinline__ void adjoint_step(const AdjArgs<R>& A, unsigned total_bytes) {
   constexpr int D = L::D;
   const StepArgs<R>& a = A.s;
@@ -189,7 +189,7 @@ __device__ __forceinline__ void adjoint_step(const AdjArgs<R>& A, unsigned total
     for (int q = 0; q < L::Qg; ++q) g[q] += L::template wT<R>(q, a.c.cs2T) * Tr;
   }
   adj::Tape<R, D> t;
-  adj::forward<R, D, UP>(f, g, a.c, t);
+  adj::forward<R, D, UP, STD>(f, g, a.c, t);
   R fb[L::Qf], gb[L::Qg];
 #pragma unroll
   for (int q = 0; q < L::Qf; ++q) fb[q] = mL.load(q, 0, node);
@@ -197,7 +197,7 @@ __device__ __forceinline__ void adjoint_step(const AdjArgs<R>& A, unsigned total
   for (int q = 0; q < L::Qg; ++q) gb[q] = mL.load(L::Qf + q, 0, node);
   const size_t cell = ((size_t)z * a.ny + y) * a.nx + x;  // index of the unpadded node fields
   add_seed<R, D, UP>(t, a.c, A.dJdT ? A.dJdT[cell] : 0.0, A.ke, fb, gb);
-  adj::reverse<R, D, UP>(t, a.c, fb, gb);
+  adj::reverse<R, D, UP, STD>(t, a.c, fb, gb);
   if (variant == 0)
     scatter<L, R, M, false, false, false>(A, mL, x, y, z, node, fb, gb);
   else if (variant == 1)
@@ -208,13 +208,15 @@ __device__ __forceinline__ void adjoint_step(const AdjArgs<R>& A, unsigned total
     scatter<L, R, M, true, true, D == 3>(A, mL, x, y, z, node, fb, gb);
 }
 
-template <class L, class R, class M, int UP>
+// STD: the standard rate set (fpc_kernels.h standard_rates), whose unit
+// rates fold at compile time.
+template <class L, class R, class M, int UP, bool STD>
 __global__ void __launch_bounds__(256) adjoint_step_kernel(AdjArgs<R> A, unsigned total_bytes) {
-  adjoint_step<L, R, M, UP>(A, total_bytes);
+  adjoint_step<L, R, M, UP, STD>(A, total_bytes);
 }
-template <class L, class M, int UP>
+template <class L, class M, int UP, bool STD>
 __global__ void __launch_bounds__(256) FPC_ADJ3F_ATTR adjoint_step_kernel_3f(AdjArgs<float> A, unsigned total_bytes) {
-  adjoint_step<L, float, M, UP>(A, total_bytes);
+  adjoint_step<L, float, M, UP, STD>(A, total_bytes);
 }
 
 template <class R>
@@ -273,16 +275,25 @@ hipError_t launch_adj(const AdjArgs<R>* step, const AdjInitArgs<R>* init, hipStr
   if (step) {
     constexpr int Q = L::Qf + L::Qg;
     const double bytes = (double)a.nxp * a.ny * a.nz * Q * sizeof(R);
+    const bool std_rates = standard_rates(a, D, L::Qg);
     if constexpr (D == 3 && sizeof(R) == 4) {
-      if (bytes < 4294967296.0)
-        adjoint_step_kernel_3f<L, Buf32<R, Q>, UP><<<grid, block, 0, st>>>(*step, (unsigned)bytes);
-      else
-        adjoint_step_kernel_3f<L, Glob64<R, Q>, UP><<<grid, block, 0, st>>>(*step, 0u);
+      if (bytes < 4294967296.0) {
+        if (std_rates)
+          adjoint_step_kernel_3f<L, Buf32<R, Q>, UP, true><<<grid, block, 0, st>>>(*step, (unsigned)bytes);
+        else
+          adjoint_step_kernel_3f<L, Buf32<R, Q>, UP, false><<<grid, block, 0, st>>>(*step, (unsigned)bytes);
+      } else {
+        adjoint_step_kernel_3f<L, Glob64<R, Q>, UP, false><<<grid, block, 0, st>>>(*step, 0u);
+      }
     } else {
-      if (bytes < 4294967296.0)
-        adjoint_step_kernel<L, R, Buf32<R, Q>, UP><<<grid, block, 0, st>>>(*step, (unsigned)bytes);
-      else
-        adjoint_step_kernel<L, R, Glob64<R, Q>, UP><<<grid, block, 0, st>>>(*step, 0u);
+      if (bytes < 4294967296.0) {
+        if (std_rates)
+          adjoint_step_kernel<L, R, Buf32<R, Q>, UP, true><<<grid, block, 0, st>>>(*step, (unsigned)bytes);
+        else
+          adjoint_step_kernel<L, R, Buf32<R, Q>, UP, false><<<grid, block, 0, st>>>(*step, (unsigned)bytes);
+      } else {
+        adjoint_step_kernel<L, R, Glob64<R, Q>, UP, false><<<grid, block, 0, st>>>(*step, 0u);
+      }
     }
   } else {
     adjoint_init_kernel<D, R, UP><<<grid, block, 0, st>>>(*init);

@@ -93,6 +93,24 @@ __device__ __forceinline__ R rate_f(const CollParams<R>& c, int k) {
   const bool nu = D == 2 ? (k == 4 || k == 5) : (k == 4 || k == 5 || k == 6 || k == 8 || k == 9);
   return nu ? c.om[4] : R(1);
 }
+// Relaxation of fluid slot K toward the attractor deviation dmv with source
+// s (App. A Step 3): k~ = k + w (dmv - k) + (1 - w/2) s.  A slot whose rate
+// is the compile-time 1 of the standard set lands on dmv + s/2 directly (the
+// same value, without keeping its pre-collision moment).
+template <int D>
+__device__ __forceinline__ constexpr bool viscous_slot(int k) {
+  return D == 2 ? (k == 4 || k == 5) : (k == 4 || k == 5 || k == 6 || k == 8 || k == 9);
+}
+template <int D, bool STD, int K, class R>
+__device__ __forceinline__ R relax_slot(const CollParams<R>& c, R k, R dmv, R s) {
+  if constexpr (STD && !viscous_slot<D>(K)) {
+    return dmv + R(0.5) * s;
+  } else {
+    const R w = rate_f<D, STD>(c, K);
+    return k + w * (dmv - k) + (R(1) - R(0.5) * w) * s;
+  }
+}
+
 template <int D, bool STD, class R>
 __device__ __forceinline__ R rate_g(const CollParams<R>& c, int k) {
   if (!STD) return c.omg[k];
@@ -380,17 +398,16 @@ __device__ __forceinline__ void collide2d(R (&f)[kQ2], R (&g)[QG], const CollPar
   }
 
   // relaxation (deviation form; attractor deviations dMv = Mv - rho_r kappa_rest)
-  auto om = [&](int k) -> R { return rate_f<2, STD>(c, k); };
-  const R t10 = k10 + om(1) * (rr * ux - k10) + (R(1) - R(0.5) * om(1)) * Fx;
-  const R t01 = k01 + om(2) * (rr * uy - k01) + (R(1) - R(0.5) * om(2)) * Fy;
+  const R t10 = relax_slot<2, STD, 1>(c, k10, rr * ux, Fx);
+  const R t01 = relax_slot<2, STD, 2>(c, k01, rr * uy, Fy);
   const R k2s = k20 + k02, k2d = k20 - k02;
-  const R t2s = k2s + om(3) * ((R(2) * cs2 * drho - rr * (uxx + uyy)) - k2s);
-  const R t2d = k2d + om(4) * (-rr * (uxx - uyy) - k2d);
-  const R t11 = k11 + om(5) * (-rr * uxy - k11);
+  const R t2s = relax_slot<2, STD, 3>(c, k2s, R(2) * cs2 * drho - rr * (uxx + uyy), R(0));
+  const R t2d = relax_slot<2, STD, 4>(c, k2d, -rr * (uxx - uyy), R(0));
+  const R t11 = relax_slot<2, STD, 5>(c, k11, -rr * uxy, R(0));
   const R t20 = R(0.5) * (t2s + t2d);
   const R t02 = R(0.5) * (t2s - t2d);
-  const R t21 = k21 + om(6) * (rr * A * uy - k21) + (R(1) - R(0.5) * om(6)) * s21;
-  const R t12 = k12 + om(7) * (rr * ux * B - k12) + (R(1) - R(0.5) * om(7)) * s12;
+  const R t21 = relax_slot<2, STD, 6>(c, k21, rr * A * uy, s21);
+  const R t12 = relax_slot<2, STD, 7>(c, k12, rr * ux * B, s12);
   // kappa^Mv_22 = (kappa~20 kappa~02 + 2 kappa~11^2) / rho (FP); rho c_s^4 (MCM)
   R mv22;
   if (c.model != 0)
@@ -398,7 +415,7 @@ __device__ __forceinline__ void collide2d(R (&f)[kQ2], R (&g)[QG], const CollPar
   else
     mv22 = (dprod(rr, A, t20, B, t02) + R(2) * dprod(rr, uxy, t11, uxy, t11) + rr * rr * (R(2) * uxx * uyy) -
             rr * A * B * drho) * irho;
-  const R t22 = k22 + om(8) * (mv22 - k22) + (R(1) - R(0.5) * om(8)) * s22;
+  const R t22 = relax_slot<2, STD, 8>(c, k22, mv22, s22);
 
   // central -> populations: y shifts per mx, then x shifts per row ey
   shift_inv(drho, t01, t02, uy, x0m, x0z, x0p);
@@ -533,8 +550,6 @@ __device__ __forceinline__ void collide3d(R (&f)[kQ3], R (&g)[QG], const CollPar
     if (m2 + n2 + p2 == 1) return R(0);
     return R(mu) * Fr * Kfull(m2, n2, p2);
   };
-  auto om = [&](int k) -> R { return rate_f<3, STD>(c, k); };
-  auto relax = [&](R k, R dmv, R w_, R s) -> R { return k + w_ * (dmv - k) + (R(1) - R(0.5) * w_) * s; };
 
   // sources of orders 3-6 from pre-collision moments, before anything is overwritten
   const R s120 = sig(1, 2, 0), s102 = sig(1, 0, 2), s210 = sig(2, 1, 0), s012 = sig(0, 1, 2);
@@ -545,31 +560,31 @@ __device__ __forceinline__ void collide3d(R (&f)[kQ3], R (&g)[QG], const CollPar
 
   // order 0 and 1
   w[I3(0, 0, 0)] = drho;
-  w[I3(1, 0, 0)] = relax(w[I3(1, 0, 0)], rr * ux, om(1), Fx);
-  w[I3(0, 1, 0)] = relax(w[I3(0, 1, 0)], rr * uy, om(2), Fy);
-  w[I3(0, 0, 1)] = relax(w[I3(0, 0, 1)], rr * uz, om(3), Fz);
+  w[I3(1, 0, 0)] = relax_slot<3, STD, 1>(c, w[I3(1, 0, 0)], rr * ux, Fx);
+  w[I3(0, 1, 0)] = relax_slot<3, STD, 2>(c, w[I3(0, 1, 0)], rr * uy, Fy);
+  w[I3(0, 0, 1)] = relax_slot<3, STD, 3>(c, w[I3(0, 0, 1)], rr * uz, Fz);
   // order 2: off-diagonal, then trace and the two deviators
-  w[I3(1, 1, 0)] = relax(w[I3(1, 1, 0)], -rr * uxy, om(4), R(0));
-  w[I3(1, 0, 1)] = relax(w[I3(1, 0, 1)], -rr * uxz, om(5), R(0));
-  w[I3(0, 1, 1)] = relax(w[I3(0, 1, 1)], -rr * uyz, om(6), R(0));
+  w[I3(1, 1, 0)] = relax_slot<3, STD, 4>(c, w[I3(1, 1, 0)], -rr * uxy, R(0));
+  w[I3(1, 0, 1)] = relax_slot<3, STD, 5>(c, w[I3(1, 0, 1)], -rr * uxz, R(0));
+  w[I3(0, 1, 1)] = relax_slot<3, STD, 6>(c, w[I3(0, 1, 1)], -rr * uyz, R(0));
   {
     const R a = w[I3(2, 0, 0)], b = w[I3(0, 2, 0)], d = w[I3(0, 0, 2)];
-    const R ts = relax(a + b + d, R(3) * cs2 * drho - rr * (uxx + uyy + uzz), om(7), R(0));
-    const R t1 = relax(a - b, -rr * (uxx - uyy), om(8), R(0));
-    const R t2 = relax(a - d, -rr * (uxx - uzz), om(9), R(0));
+    const R ts = relax_slot<3, STD, 7>(c, a + b + d, R(3) * cs2 * drho - rr * (uxx + uyy + uzz), R(0));
+    const R t1 = relax_slot<3, STD, 8>(c, a - b, -rr * (uxx - uyy), R(0));
+    const R t2 = relax_slot<3, STD, 9>(c, a - d, -rr * (uxx - uzz), R(0));
     const R t200 = (ts + t1 + t2) * (R(1) / R(3));
     w[I3(2, 0, 0)] = t200;
     w[I3(0, 2, 0)] = t200 - t1;
     w[I3(0, 0, 2)] = t200 - t2;
   }
   // order 3: attractors zero, deviation -rho_r kappa_rest
-  w[I3(1, 2, 0)] = relax(w[I3(1, 2, 0)], -rr * Rst(1, 2, 0), om(10), s120);
-  w[I3(1, 0, 2)] = relax(w[I3(1, 0, 2)], -rr * Rst(1, 0, 2), om(11), s102);
-  w[I3(2, 1, 0)] = relax(w[I3(2, 1, 0)], -rr * Rst(2, 1, 0), om(12), s210);
-  w[I3(0, 1, 2)] = relax(w[I3(0, 1, 2)], -rr * Rst(0, 1, 2), om(13), s012);
-  w[I3(2, 0, 1)] = relax(w[I3(2, 0, 1)], -rr * Rst(2, 0, 1), om(14), s201);
-  w[I3(0, 2, 1)] = relax(w[I3(0, 2, 1)], -rr * Rst(0, 2, 1), om(15), s021);
-  w[I3(1, 1, 1)] = relax(w[I3(1, 1, 1)], -rr * Rst(1, 1, 1), om(16), s111);
+  w[I3(1, 2, 0)] = relax_slot<3, STD, 10>(c, w[I3(1, 2, 0)], -rr * Rst(1, 2, 0), s120);
+  w[I3(1, 0, 2)] = relax_slot<3, STD, 11>(c, w[I3(1, 0, 2)], -rr * Rst(1, 0, 2), s102);
+  w[I3(2, 1, 0)] = relax_slot<3, STD, 12>(c, w[I3(2, 1, 0)], -rr * Rst(2, 1, 0), s210);
+  w[I3(0, 1, 2)] = relax_slot<3, STD, 13>(c, w[I3(0, 1, 2)], -rr * Rst(0, 1, 2), s012);
+  w[I3(2, 0, 1)] = relax_slot<3, STD, 14>(c, w[I3(2, 0, 1)], -rr * Rst(2, 0, 1), s201);
+  w[I3(0, 2, 1)] = relax_slot<3, STD, 15>(c, w[I3(0, 2, 1)], -rr * Rst(0, 2, 1), s021);
+  w[I3(1, 1, 1)] = relax_slot<3, STD, 16>(c, w[I3(1, 1, 1)], -rr * Rst(1, 1, 1), s111);
 
   // order 4: products of post-collision second-order moments
   const R rr2 = rr * rr;
@@ -595,12 +610,12 @@ __device__ __forceinline__ void collide3d(R (&f)[kQ3], R (&g)[QG], const CollPar
       mv121 = (P(0, 2, 0, 1, 0, 1) + R(2) * P(1, 1, 0, 0, 1, 1) + rr2 * (R(2) * uyy * uxz) - rr * B * uxz * drho) * irho;
       mv112 = (P(0, 0, 2, 1, 1, 0) + R(2) * P(0, 1, 1, 1, 0, 1) + rr2 * (R(2) * uzz * uxy) - rr * C * uxy * drho) * irho;
     }
-    w[I3(2, 2, 0)] = relax(w[I3(2, 2, 0)], mv220, om(17), s220);
-    w[I3(2, 0, 2)] = relax(w[I3(2, 0, 2)], mv202, om(18), s202);
-    w[I3(0, 2, 2)] = relax(w[I3(0, 2, 2)], mv022, om(19), s022);
-    w[I3(2, 1, 1)] = relax(w[I3(2, 1, 1)], mv211, om(20), s211);
-    w[I3(1, 2, 1)] = relax(w[I3(1, 2, 1)], mv121, om(21), s121);
-    w[I3(1, 1, 2)] = relax(w[I3(1, 1, 2)], mv112, om(22), s112);
+    w[I3(2, 2, 0)] = relax_slot<3, STD, 17>(c, w[I3(2, 2, 0)], mv220, s220);
+    w[I3(2, 0, 2)] = relax_slot<3, STD, 18>(c, w[I3(2, 0, 2)], mv202, s202);
+    w[I3(0, 2, 2)] = relax_slot<3, STD, 19>(c, w[I3(0, 2, 2)], mv022, s022);
+    w[I3(2, 1, 1)] = relax_slot<3, STD, 20>(c, w[I3(2, 1, 1)], mv211, s211);
+    w[I3(1, 2, 1)] = relax_slot<3, STD, 21>(c, w[I3(1, 2, 1)], mv121, s121);
+    w[I3(1, 1, 2)] = relax_slot<3, STD, 22>(c, w[I3(1, 1, 2)], mv112, s112);
   }
   // order 5: (2 / 5 rho) [...] from post-collision second x third order (FP);
   // zero for MCM (deviation -rho_r kappa_rest)
@@ -628,9 +643,9 @@ __device__ __forceinline__ void collide3d(R (&f)[kQ3], R (&g)[QG], const CollPar
                        R(2) * (P(0, 1, 1, 2, 1, 0) + P(1, 0, 1, 1, 2, 0))) +
                rr2 * r221 - rr * Rst(2, 2, 1) * drho) * irho;
     }
-    w[I3(1, 2, 2)] = relax(w[I3(1, 2, 2)], mv122, om(23), s122);
-    w[I3(2, 1, 2)] = relax(w[I3(2, 1, 2)], mv212, om(24), s212);
-    w[I3(2, 2, 1)] = relax(w[I3(2, 2, 1)], mv221, om(25), s221);
+    w[I3(1, 2, 2)] = relax_slot<3, STD, 23>(c, w[I3(1, 2, 2)], mv122, s122);
+    w[I3(2, 1, 2)] = relax_slot<3, STD, 24>(c, w[I3(2, 1, 2)], mv212, s212);
+    w[I3(2, 2, 1)] = relax_slot<3, STD, 25>(c, w[I3(2, 2, 1)], mv221, s221);
   }
   // order 6: (1 / 3 rho) [...] from post-collision second x fourth order (FP);
   // rho c_s^6 for MCM
@@ -647,7 +662,7 @@ __device__ __forceinline__ void collide3d(R (&f)[kQ3], R (&g)[QG], const CollPar
                rr2 * (R(4) / R(3)) * (uxx * uyy * C + uxx * uzz * B + uyy * uzz * A) - rr * A * B * C * drho) *
               irho;
     }
-    w[I3(2, 2, 2)] = relax(w[I3(2, 2, 2)], mv222, om(26), s222);
+    w[I3(2, 2, 2)] = relax_slot<3, STD, 26>(c, w[I3(2, 2, 2)], mv222, s222);
   }
 
   // central -> populations: z shifts, then y, then x

@@ -107,6 +107,24 @@ __device__ __forceinline__ dim3 block_order() {
   return dim3(blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
+// Whether the rates form the standard set of rate_f / rate_g: the viscous
+// slots share one rate, the thermal first-order slots share one rate, and
+// every other slot in use relaxes at exactly 1.  Kernels built for that set
+// (STD = true) take those rates as compile-time constants.
+template <class R>
+inline bool standard_rates(const StepArgs<R>& a, int D, int Qg) {
+  const int Qf = D == 2 ? kQ2 : kQ3;
+  for (int k = 1; k < Qf; ++k) {
+    const bool nu = D == 2 ? (k == 4 || k == 5) : (k == 4 || k == 5 || k == 6 || k == 8 || k == 9);
+    if (nu ? a.c.om[k] != a.c.om[4] : a.c.om[k] != R(1)) return false;
+  }
+  for (int k = 1; k < Qg; ++k) {
+    const bool first = k <= D;
+    if (first ? a.c.omg[k] != a.c.omg[1] : a.c.omg[k] != R(1)) return false;
+  }
+  return true;
+}
+
 // Launchers of the fused step (defined in fpc_step.hip).
 // tk: thermal lattice, 0 = D2Q5 / D3Q7, 1 = D2Q9 / D3Q15 (FP64 only).
 // mode: 0 = step (pull from args.src), 1 = init (equilibrium from T_init).

@@ -197,23 +197,6 @@ __global__ void __launch_bounds__(256) init_kernel(StepArgs<R> a, const double* 
   collide_store<L, R, M, UP, false, false>(a, m, x, y, z, node, Tr, f, g);
 }
 
-// Whether the rates form the standard set of rate_f / rate_g: the viscous
-// slots share one rate, the thermal first-order slots share one rate, and
-// every other slot in use relaxes at exactly 1.
-template <class R>
-bool standard_rates(const StepArgs<R>& a, int D, int Qg) {
-  const int Qf = D == 2 ? kQ2 : kQ3;
-  for (int k = 1; k < Qf; ++k) {
-    const bool nu = D == 2 ? (k == 4 || k == 5) : (k == 4 || k == 5 || k == 6 || k == 8 || k == 9);
-    if (nu ? a.c.om[k] != a.c.om[4] : a.c.om[k] != R(1)) return false;
-  }
-  for (int k = 1; k < Qg; ++k) {
-    const bool first = k <= D;
-    if (first ? a.c.omg[k] != a.c.omg[1] : a.c.omg[k] != R(1)) return false;
-  }
-  return true;
-}
-
 template <class L, class R, int UP>
 hipError_t launch_up(const StepArgs<R>& a, const double* T_init, int mode, hipStream_t s) {
   const int threads =
