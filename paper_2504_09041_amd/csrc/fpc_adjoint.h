@@ -167,7 +167,7 @@ template <class R, int D>
 struct Tape {
   static constexpr int NM = MS<D>::NM;
   static constexpr int NG = 2 * D + 1;
-  R rho, T, Fb, u[3];
+  R rho, ir, T, Fb, u[3];  // ir = 1 / rho
   R k[NM];   // pre-collision central moments
   R kt[NM];  // post-collision central moments
   R e[NG];   // thermal central moments (0, +-axis order 1, order 2 per axis)
@@ -201,17 +201,19 @@ __device__ __forceinline__ void forward(const R* f, const R* g, const CollParams
 #pragma unroll
   for (int q = 0; q < 2 * D + 1; ++q) T += g[q];
   const R Fb = c.gbeta * (T - c.T0);
+  const R ir = R(1) / rho;
   t.rho = rho;
+  t.ir = ir;
   t.T = T;
   t.Fb = Fb;
 #pragma unroll
-  for (int ax = 0; ax < 3; ++ax) t.u[ax] = ax < D ? (j[ax] + (ax == UP ? R(0.5) * Fb : R(0))) / rho : R(0);
+  for (int ax = 0; ax < 3; ++ax) t.u[ax] = ax < D ? (j[ax] + (ax == UP ? R(0.5) * Fb : R(0))) * ir : R(0);
 #pragma unroll
   for (int i = 0; i < NM; ++i) t.k[i] = f[M::pop(i)];
   apply<R, D, 0>(t.k, t.u);
   // relaxation, order by order
   const R* om = c.om;
-  const R Fr = Fb / rho;
+  const R Fr = Fb * ir;
 #pragma unroll
   for (int i = 0; i < NM; ++i) {
     const int s = M::order(i);
@@ -258,7 +260,7 @@ __device__ __forceinline__ void forward(const R* f, const R* g, const CollParams
 #pragma unroll
       for (int p = 0; p < Terms<D>::npairs; ++p)
         if (Terms<D>::valid(i, p)) mv += R(Terms<D>::coef(i, p)) * t.kt[Terms<D>::A(p)] * t.kt[Terms<D>::B(i, p)];
-      mv = mv / (R(s) * rho);
+      mv = mv * (ir * (R(1) / R(s)));
       R sig = R(0);
       const int mu = M::m(i, UP);
       if (mu > 0 && M::order(M::down(i, UP)) >= 2) sig = R(mu) * Fr * t.k[M::down(i, UP)];
@@ -396,7 +398,7 @@ __device__ __forceinline__ void reverse(const Tape<R, D>& t, const CollParams<R>
 #pragma unroll
   for (int i = 0; i < NM; ++i) kp[i] = R(0);
   const R* om = c.om;
-  const R Fr = t.Fb / t.rho;
+  const R Fr = t.Fb * t.ir;
 #pragma unroll
   for (int s = 2 * D; s >= 3; --s) {
 #pragma unroll
@@ -408,26 +410,27 @@ __device__ __forceinline__ void reverse(const Tape<R, D>& t, const CollParams<R>
       if (!unit) kp[i] += (R(1) - w) * ktb;
       // attractor
       const R mvb = unit ? ktb : w * ktb;
+      const R irs = t.ir * (R(1) / R(s));
       R mv = R(0);
 #pragma unroll
       for (int p = 0; p < Terms<D>::npairs; ++p)
         if (Terms<D>::valid(i, p)) {
           const int A = Terms<D>::A(p), B = Terms<D>::B(i, p);
-          const R cf = R(Terms<D>::coef(i, p)) / (R(s) * t.rho);
+          const R cf = R(Terms<D>::coef(i, p)) * irs;
           mv += cf * t.kt[A] * t.kt[B];
           kb[A] += mvb * cf * t.kt[B];
           kb[B] += mvb * cf * t.kt[A];
         }
-      rhob -= mvb * mv / t.rho;
+      rhob -= mvb * mv * t.ir;
       // source
       const int mu = M::m(i, UP);
       if (mu > 0 && M::order(M::down(i, UP)) >= 2) {
         const R sb = unit ? R(0.5) * ktb : (R(1) - R(0.5) * w) * ktb;
         const int p = M::down(i, UP);
         const R sig = R(mu) * Fr * t.k[p];
-        Fbb += sb * R(mu) * t.k[p] / t.rho;
+        Fbb += sb * R(mu) * t.k[p] * t.ir;
         kp[p] += sb * R(mu) * Fr;
-        rhob -= sb * sig / t.rho;
+        rhob -= sb * sig * t.ir;
       }
     }
   }
@@ -486,11 +489,11 @@ __device__ __forceinline__ void reverse(const Tape<R, D>& t, const CollParams<R>
   R udotub = R(0);
 #pragma unroll
   for (int ax = 0; ax < D; ++ax) {
-    jb[ax] = ub[ax] / t.rho;
+    jb[ax] = ub[ax] * t.ir;
     udotub += t.u[ax] * ub[ax];
   }
-  Fbb += ub[UP] / (R(2) * t.rho);
-  rhob -= udotub / t.rho;
+  Fbb += ub[UP] * (R(0.5) * t.ir);
+  rhob -= udotub * t.ir;
 #pragma unroll
   for (int i = 0; i < NM; ++i) {
     R v = kp[i] + rhob;
