@@ -49,8 +49,11 @@ def _args():
     ap.add_argument("--steps2d", type=int, default=2000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--shape", type=int, nargs=3, help="grid (nx ny nz) of --mode single instead of the workload's")
+    ap.add_argument("--no-multistep", action="store_true",
+                    help="forbid fpc_step's single-launch multi-step path (small grids)")
     ap.add_argument("--cpu-sample-steps", type=int, default=24)
-    ap.add_argument("--mode", choices=("bench", "single", "copy", "pmc-summary", "precision", "adjoint",
+    ap.add_argument("--mode", choices=("bench", "single", "copy", "pmc-summary", "trace-summary", "precision", "adjoint",
                                        "objective"),
                     default="bench")
     ap.add_argument("--no-adjoint", action="store_true")
@@ -59,6 +62,8 @@ def _args():
     ap.add_argument("--copy-fetch", help="rocprofv3 --pmc FETCH_SIZE output dir (copy run)")
     ap.add_argument("--copy-write", help="rocprofv3 --pmc WRITE_SIZE output dir (copy run)")
     ap.add_argument("--kernel-regex", default="step_kernel")
+    ap.add_argument("--trace", help="rocprofv3 --kernel-trace csv output dir (trace-summary)")
+    ap.add_argument("--top", type=int, default=45, help="rows of the trace summary")
     ap.add_argument("--key", default="dhc3d_256_f32dev")
     ap.add_argument("--workload", default="dhc3d_256")
     ap.add_argument("--precision", default="f32dev")
@@ -132,6 +137,30 @@ def _pmc_per_dispatch(d, regex):
     return sum(vals[len(vals) // 2:]) / len(vals[len(vals) // 2:]), len(vals)
 
 
+def trace_summary(a):
+    """Markdown table of a rocprofv3 kernel trace: dispatches grouped by kernel
+    and launch grid, with calls, average / median duration and total time."""
+    import csv
+    import glob
+    import statistics
+
+    path = glob.glob(os.path.join(a.trace, "**", "*kernel_trace.csv"), recursive=True)[0]
+    groups = {}
+    for r in csv.DictReader(open(path)):
+        name = r["Kernel_Name"]
+        grid = "x".join(r["Grid_Size_" + k] for k in "XYZ")
+        block = "x".join(r["Workgroup_Size_" + k] for k in "XY")
+        dur = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3  # us
+        groups.setdefault((name, grid, block), []).append(dur)
+    rows = sorted(groups.items(), key=lambda kv: -sum(kv[1]))[: a.top]
+    out = ["| kernel | grid | block | calls | avg us | median us | total ms |", "|---|---|---|---|---|---|---|"]
+    for (name, grid, block), d in rows:
+        short = name if len(name) <= 150 else name[:150] + "..."
+        out.append(f"| `{short}` | {grid} | {block} | {len(d)} | {sum(d) / len(d):.2f} | "
+                   f"{statistics.median(d):.2f} | {sum(d) * 1e-3:.1f} |")
+    return "\n".join(out)
+
+
 def pmc_summary(a):
     """Scale the TCC byte counters by what they read for a plain copy of
     known size and record bytes per launch in profiles/traffic.json."""
@@ -171,7 +200,8 @@ def workload_params(cfg, precision, **kw):
     return params_from_workload(cfg, precision, **kw)
 
 
-def time_workload(name, precision, steps, warmup, shape=None, pair=None, model="FP", thermal_option="A"):
+def time_workload(name, precision, steps, warmup, shape=None, pair=None, model="FP", thermal_option="A",
+                  multistep=True):
     import torch
 
     import workloads
@@ -184,6 +214,7 @@ def time_workload(name, precision, steps, warmup, shape=None, pair=None, model="
         cfg["pair"] = pair
     p = workload_params(cfg, precision, model=model, thermal_option=thermal_option)
     sim = Simulation(p)
+    sim.set_multistep(multistep)
     T = torch.tensor(workloads.initial_temperature(cfg), device="cuda")
     sim.init(T)
     del T
@@ -203,7 +234,8 @@ def time_workload(name, precision, steps, warmup, shape=None, pair=None, model="
     N = sim.N
     elem = 8 if precision == "f64" else 4
     bytes_per_node = 2 * (sim.Qf + sim.Qg) * elem
-    per_launch_s = ms * 1e-3 / steps
+    per_step_s = ms * 1e-3 / steps
+    launches = sim.multistep_launches
     out = {
         "workload": name,
         "pair": cfg["pair"],
@@ -216,7 +248,8 @@ def time_workload(name, precision, steps, warmup, shape=None, pair=None, model="
         "wall_s": wall,
         "mlups": N * steps / (ms * 1e-3) / 1e6,
         "bytes_per_node": bytes_per_node,
-        "achieved_GBs": bytes_per_node * N / per_launch_s / 1e9,
+        "achieved_GBs": bytes_per_node * N / per_step_s / 1e9,
+        "multistep_launches": launches,
         "nu": d["nu"],
         "unstable": d["unstable"],
     }
@@ -490,11 +523,15 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if a.mode == "trace-summary":
+        print(trace_summary(a))
+        return
     if a.mode == "copy":
         print(json.dumps(copy_bandwidth(a.mib, a.reps)))
         return
     if a.mode == "single":
-        print(json.dumps(time_workload(a.workload, a.precision, a.steps, a.warmup)))
+        print(json.dumps(time_workload(a.workload, a.precision, a.steps, a.warmup, shape=a.shape,
+                                       multistep=not a.no_multistep)))
         return
     if a.mode == "precision":
         print(json.dumps(precision_study(a.workload, a.steps, max(1, a.steps // 50))))

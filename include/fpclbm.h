@@ -235,8 +235,30 @@ int fpc_set_stream(fpc_sim* s, void* hip_stream);
  */
 int fpc_init(fpc_sim* s, const double* T_init);
 
-/* Advance nsteps >= 0 time steps (fused pull-stream-collide), asynchronously. */
+/*
+ * Advance nsteps >= 0 time steps (fused pull-stream-collide, Eq.
+ * LBMsteps-stream / LBMsteps-streamg with the collision of Sec. 4-5),
+ * asynchronously.  Small grids (at most 16 blocks of 256 nodes; the D2Q5 /
+ * D3Q7 thermal pair in 2D, or in 3D with FP32 storage; standard rate set)
+ * advance up to 1024 steps per cooperative launch, with a grid-wide barrier
+ * between steps, when the device supports cooperative launches; otherwise,
+ * and on every other grid, one launch per step.  Both paths compute the
+ * same step; they are compiled separately, so their states agree to rounding
+ * (multiply-adds may be fused differently), not bit for bit.  A barrier that
+ * times out (it cannot on a working device) leaves the state invalid and is
+ * reported by the next fpc_diagnostics as FPC_ERR_HIP, after which the sim
+ * uses per-step launches only.
+ */
 int fpc_step(fpc_sim* s, int nsteps);
+
+/*
+ * Allow (enable = 1, the default) or forbid (0) fpc_step's single-launch
+ * multi-step path on small grids.  Errors: FPC_ERR_ARG (NULL, enable not 0/1).
+ */
+int fpc_set_multistep(fpc_sim* s, int enable);
+
+/* Number of multi-step (cooperative) launches fpc_step has made on this sim. */
+int fpc_multistep_launches(const fpc_sim* s, long long* launches);
 
 /*
  * Advance nsteps >= 0 time steps exactly as fpc_step, and after each step n
@@ -350,32 +372,40 @@ int fpc_current_buffer(const fpc_sim* s, void** ptr);
 int fpc_nusselt_seed(fpc_sim* s, int wall_face, double weight, double* dJdT, double* dJdTw);
 
 /*
- * Adjoint (reverse mode) of one time step S_n = Phi(S_{n-1}), for an objective
- * J whose direct dependence on S_n is through the time-n macros.  Computes
- *   lam_out = (d S_n / d S_{n-1})^T (lam_in + dJ/dS_n)
+ * Adjoint (reverse mode) of one time step S_n = Phi(S_{n-1}) = collide_n(
+ * pull(S_{n-1})), for an objective J whose direct dependence on S_n is
+ * through the time-n macros.  The adjoint is carried as mu: mu_n is the
+ * adjoint of the pulled (pre-collision) populations entering the collision of
+ * step n + 1, so that the adjoint of the stored state S_n is
+ * lambda_n = pull^T mu_n.  Computes
+ *   mu_out = mu_{n-1} = collide_n^T (pull^T mu_in + dJ/dS_n),  mu_in = mu_n,
  * where dJ/dS_n is formed in the kernel from
  *   dJdT[x]    weight of T_n(x)  (device, N FP64 values, or NULL), and
  *   ke_weight  weight of the kinetic energy 1/2 sum rho |u|^2 of time n,
  * and accumulates (+=) the gradient with respect to the per-node Dirichlet
  * wall temperature of face f into dJdtheta[f] (device, FP64, profile layout
  * of fpc_params.wall_T_profile; dJdtheta may be NULL, or hold NULL entries).
- * S_prev: S_{n-1} in storage format (fpc_state_bytes()).  lam_in, lam_out:
- * adjoint states in the same layout and element type as the state (FP64 or
- * FP32), holding adjoints of the stored values; every element of lam_out that
- * belongs to a node is written (padding is not).  The method is not part of
- * the paper: this is the exact adjoint of the discrete update above.
- * Available for the FP model on FPC_D2Q9_D2Q5 / FPC_D3Q27_D3Q7; other
- * configurations return FPC_ERR_STATE (as does fpc_adjoint_init).
+ * A reverse sweep starts from mu_N = 0 and ends with fpc_adjoint_init on
+ * mu_0.  S_prev: S_{n-1} in storage format (fpc_state_bytes()).  mu_in,
+ * mu_out: adjoint states in the same layout and element type as the state
+ * (FP64 or FP32), distinct buffers; every element of mu_out that belongs to a
+ * node is written (padding is not).  Each node reads mu_in along the reversed
+ * links (the transpose of the pull, with the wall rules: -1 on Dirichlet
+ * links) and writes only its own slots.  The method is not part of the paper:
+ * this is the exact adjoint of the discrete update above.  Available for the
+ * FP model on FPC_D2Q9_D2Q5 / FPC_D3Q27_D3Q7; other configurations return
+ * FPC_ERR_STATE (as does fpc_adjoint_init).
  */
-int fpc_adjoint_step(fpc_sim* s, const void* S_prev, const void* lam_in, void* lam_out, const double* dJdT,
+int fpc_adjoint_step(fpc_sim* s, const void* S_prev, const void* mu_in, void* mu_out, const double* dJdT,
                      double ke_weight, double* const* dJdtheta);
 
 /*
- * Adjoint of the initial collision (fpc_init): given lam0 = dJ/dS_0 without
- * the level-0 seed, adds the seed (dJdT, ke_weight as in fpc_adjoint_step) and
- * writes dJ/dT_init[x] (device, N FP64 values).
+ * Adjoint of the initial collision (fpc_init): from mu0 (the adjoint of the
+ * pulled populations of step 1, as left by the last fpc_adjoint_step of a
+ * sweep) forms lambda_0 = pull^T mu0, adds the level-0 seed (dJdT, ke_weight
+ * as in fpc_adjoint_step) and writes dJ/dT_init[x] (device, N FP64 values).
  */
-int fpc_adjoint_init(fpc_sim* s, const double* T_init, const void* lam0, const double* dJdT, double ke_weight,
+int fpc_adjoint_init(fpc_sim* s, const double* T_init, const void* mu0, const double* dJdT, double ke_weight,
                      double* dJdT_init);
 
 #ifdef __cplusplus

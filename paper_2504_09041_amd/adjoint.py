@@ -11,6 +11,10 @@ checkpoints:
   from the segment's last step down to its first; finally the adjoint of the
   initial collision gives dJ/dT_init.  Memory: N/K checkpoints + K states.
 
+The adjoint travels between steps as mu_n, the adjoint of the pulled
+populations that enter the collision of step n + 1 (mu_N = 0); the kernels
+apply the transpose of the pull when they read it.
+
 Objectives are sums over time levels n of affine-in-T wall terms and kinetic
 energies of the time-n macros:
 
@@ -159,8 +163,8 @@ class AdjointSolver:
         """Returns (dJ/dtheta or None, dJ/dT_init)."""
         sim = self.sim
         lib = A.load()
-        lam = sim.new_adjoint()
-        lam2 = sim.new_adjoint()
+        mu = sim.new_adjoint()  # mu_N = 0
+        mu2 = sim.new_adjoint()
         dth = None
         ptrs = None
         if self.theta_face is not None:
@@ -179,14 +183,14 @@ class AdjointSolver:
                 states.append(seg[k])
             for n in range(s1, s0, -1):
                 w, ke = self.obj.seed(n)
-                A.check(lib.fpc_adjoint_step(sim.handle, _ptr(states[n - 1 - s0]), _ptr(lam), _ptr(lam2),
+                A.check(lib.fpc_adjoint_step(sim.handle, _ptr(states[n - 1 - s0]), _ptr(mu), _ptr(mu2),
                                              _ptr(w), ctypes.c_double(ke), ptrs), "fpc_adjoint_step")
-                lam, lam2 = lam2, lam
+                mu, mu2 = mu2, mu
             del states
         del seg
         w0, ke0 = self.obj.seed(0)
         dT = torch.empty_like(self.T_init)
-        A.check(lib.fpc_adjoint_init(sim.handle, _ptr(self.T_init), _ptr(lam), _ptr(w0), ctypes.c_double(ke0),
+        A.check(lib.fpc_adjoint_init(sim.handle, _ptr(self.T_init), _ptr(mu), _ptr(w0), ctypes.c_double(ke0),
                                      _ptr(dT)), "fpc_adjoint_init")
         if dth is not None and self.obj.face == self.theta_face:
             dth += self.obj.direct_wall.reshape(dth.shape)

@@ -34,6 +34,13 @@ struct fpc_sim {
   double* nu_slot;      // per-tile partial sums of the fused wall-Nusselt accumulation (kept zero between calls)
   size_t nu_slot_elems;
   int device;
+  // single-launch multi-step path (small grids)
+  unsigned* multi_ctl;  // device: [0] barrier word, [1] error flag, [2..3] placement words,
+                        // [4] release word, [8..8+kMultiMaxWork) arrival words
+  int multi_enabled;    // fpc_set_multistep
+  int multi_ok;         // the device supports cooperative launches
+  int multi_used;       // a multi-step launch has been made since the flag was last read
+  long long multi_launches;  // multi-step launches made by this sim
 };
 
 namespace {
@@ -249,6 +256,81 @@ int launch_update(fpc_sim* s, const void* src, void* dst, const double* T_init, 
   }
   if (e != hipSuccess) return hipfail(e, "kernel launch");
   return FPC_OK;
+}
+
+// Single-launch multi-step path (step_multi_kernel): grids of at most
+// kMultiMaxWork blocks of 256 threads, the D2Q5 / D3Q7 pairs in 2D (either
+// precision) and 3D FP32, the standard rate set and states below the
+// non-temporal threshold.  The working blocks share one XCD, so the limit is
+// low: at 64 blocks (a 128^2 grid) the single XCD made a step slower (5.1 us)
+// than one launch per step over the whole chip (3.7 us); at 16 blocks (the
+// 64^2 cavity) the path is 20% faster.
+constexpr unsigned kMultiMaxWork = 16;
+constexpr size_t kMultiCtlBytes = 4 * (8 + kMultiMaxWork);  // control words (see fpc_sim::multi_ctl)
+constexpr int kMultiMaxSteps = 1024;            // steps per launch (a few ms on the grids it serves)
+constexpr unsigned kMultiSpinLimit = 1u << 22;  // barrier polls before giving up (about a second)
+
+bool multi_eligible(const fpc_sim* s) {
+  const fpc_params& p = s->p;
+  if (!s->multi_enabled || !s->multi_ok || paper_thermal(p.lattice)) return false;
+  if (s->dim == 3 && p.precision == FPC_FP64) return false;
+  if (multi_work_blocks(p.nx, p.ny, p.nz) > kMultiMaxWork) return false;
+  if ((double)s->bytes > 128.0 * 1024.0 * 1024.0) return false;
+  if (p.precision == FPC_FP64) {
+    const StepArgs<double> a = make_args<double>(s, nullptr, nullptr);
+    return standard_rates(a, s->dim, s->Qg);
+  }
+  const StepArgs<float> a = make_args<float>(s, nullptr, nullptr);
+  return standard_rates(a, s->dim, s->Qg);
+}
+
+// 0: launched; 1: the runtime refused the cooperative launch (the caller
+// falls back to per-step launches and the path stays off for this sim);
+// < 0: error.
+int launch_multi(fpc_sim* s, int nsteps) {
+  MultiCtl c;
+  c.bar = s->multi_ctl;
+  c.err = reinterpret_cast<int*>(s->multi_ctl + 1);
+  c.place = s->multi_ctl + 2;
+  c.release = s->multi_ctl + 4;
+  c.arrive = s->multi_ctl + 8;  // kMultiMaxWork words
+  c.spin_limit = kMultiSpinLimit;
+  c.nwork = 0;
+  c.nsteps = nsteps;
+  c.seq = (int)(s->multi_launches & 1);
+  // light-barrier numbers: kMultiMaxSteps per launch, unique for 2^21 launches
+  c.gen = (unsigned)((s->multi_launches & 0x1fffff) * kMultiMaxSteps) + 1u;
+  const int up = s->p.up_axis;
+  hipError_t e;
+  if (s->p.precision == FPC_FP64)
+    e = launch_step_multi<double>(make_args<double>(s, s->buf[s->cur], s->buf[s->cur ^ 1]), s->dim, up, c, s->stream);
+  else
+    e = launch_step_multi<float>(make_args<float>(s, s->buf[s->cur], s->buf[s->cur ^ 1]), s->dim, up, c, s->stream);
+  if (e == hipErrorCooperativeLaunchTooLarge || e == hipErrorNotSupported) {
+    (void)hipGetLastError();
+    s->multi_ok = 0;
+    return 1;
+  }
+  if (e != hipSuccess) return hipfail(e, "cooperative kernel launch");
+  s->multi_used = 1;
+  ++s->multi_launches;
+  return FPC_OK;
+}
+
+// After the stream has drained: report (and clear) a barrier time-out of the
+// multi-step path.
+int multi_check(fpc_sim* s) {
+  if (!s->multi_used) return FPC_OK;
+  int flag = 0;
+  hipError_t e = hipMemcpy(&flag, s->multi_ctl + 1, sizeof flag, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hipfail(e, "hipMemcpy(multi-step flag)");
+  s->multi_used = 0;
+  if (!flag) return FPC_OK;
+  e = launch_fill_zero(reinterpret_cast<double*>(s->multi_ctl), kMultiCtlBytes / 8, s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) return hipfail(e, "multi-step flag reset");
+  s->multi_enabled = 0;
+  return fail(FPC_ERR_HIP, "multi-step launch: a grid barrier timed out, the state is invalid (path now off)");
 }
 
 StateDesc desc_of(const fpc_sim* s) {
@@ -489,13 +571,20 @@ int fpc_create(const fpc_params* p, void* bufA, void* bufB, void* hip_stream, fp
   }
   e = hipMalloc(&s->nu_slot, s->nu_slot_elems * sizeof(double));
   if (e == hipSuccess) e = launch_fill_zero(s->nu_slot, s->nu_slot_elems, s->stream);
+  if (e == hipSuccess) e = hipMalloc(&s->multi_ctl, kMultiCtlBytes);
+  if (e == hipSuccess) e = launch_fill_zero(reinterpret_cast<double*>(s->multi_ctl), kMultiCtlBytes / 8, s->stream);
   if (e != hipSuccess) {
+    if (s->multi_ctl) (void)hipFree(s->multi_ctl);
     if (s->nu_slot) (void)hipFree(s->nu_slot);
     (void)hipFree(s->scratch);
     (void)hipHostFree(s->result_host);
     delete s;
     return hipfail(e, "wall-Nusselt slots");
   }
+  int coop = 0;
+  if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, s->device) != hipSuccess) coop = 0;
+  s->multi_ok = coop != 0;
+  s->multi_enabled = 1;
   *out = s;
   return FPC_OK;
 }
@@ -506,11 +595,26 @@ int fpc_destroy(fpc_sim* s) {
   hipError_t e2 = hipFree(s->scratch);
   hipError_t e3 = hipHostFree(s->result_host);
   hipError_t e4 = hipFree(s->nu_slot);
+  hipError_t e5 = hipFree(s->multi_ctl);
+  if (e4 == hipSuccess) e4 = e5;
   delete s;
   if (e1 != hipSuccess) return hipfail(e1, "hipStreamSynchronize");
   if (e2 != hipSuccess) return hipfail(e2, "hipFree");
   if (e3 != hipSuccess) return hipfail(e3, "hipHostFree");
   if (e4 != hipSuccess) return hipfail(e4, "hipFree");
+  return FPC_OK;
+}
+
+int fpc_set_multistep(fpc_sim* s, int enable) {
+  if (!s) return fail(FPC_ERR_ARG, "sim is NULL");
+  if (enable != 0 && enable != 1) return fail(FPC_ERR_ARG, "enable must be 0 or 1");
+  s->multi_enabled = enable;
+  return FPC_OK;
+}
+
+int fpc_multistep_launches(const fpc_sim* s, long long* launches) {
+  if (!s || !launches) return fail(FPC_ERR_ARG, "NULL argument");
+  *launches = s->multi_launches;
   return FPC_OK;
 }
 
@@ -532,6 +636,15 @@ int fpc_init(fpc_sim* s, const double* T_init) {
 int fpc_step(fpc_sim* s, int nsteps) {
   if (!s) return fail(FPC_ERR_ARG, "sim is NULL");
   if (nsteps < 0) return fail(FPC_ERR_ARG, "nsteps < 0");
+  while (nsteps >= 2 && multi_eligible(s)) {
+    const int n = nsteps < kMultiMaxSteps ? nsteps : kMultiMaxSteps;
+    const int rc = launch_multi(s, n);
+    if (rc < 0) return rc;
+    if (rc > 0) break;  // not launched (cooperative launch refused): per-step launches from here on
+    s->cur ^= n & 1;
+    s->step += n;
+    nsteps -= n;
+  }
   for (int i = 0; i < nsteps; ++i) {
     int rc = launch_update(s, s->buf[s->cur], s->buf[s->cur ^ 1], nullptr, 0);
     if (rc) return rc;
@@ -621,6 +734,8 @@ int fpc_diagnostics(fpc_sim* s, int wall_face, double* nu_mean, double* ke, doub
   if (e != hipSuccess) return hipfail(e, "hipMemcpyAsync");
   e = hipStreamSynchronize(s->stream);
   if (e != hipSuccess) return hipfail(e, "hipStreamSynchronize");
+  rc = multi_check(s);
+  if (rc) return rc;
   const double* r = s->result_host;
   if (nu_mean) *nu_mean = r[0];
   if (ke) *ke = r[1];
@@ -687,11 +802,11 @@ int fpc_import_fp64(fpc_sim* s, const double* src, long long step) {
   return FPC_OK;
 }
 
-int fpc_adjoint_step(fpc_sim* s, const void* S_prev, const void* lam_in, void* lam_out, const double* dJdT,
+int fpc_adjoint_step(fpc_sim* s, const void* S_prev, const void* mu_in, void* mu_out, const double* dJdT,
                      double ke_weight, double* const* dJdtheta) {
-  if (!s || !S_prev || !lam_in || !lam_out) return fail(FPC_ERR_ARG, "NULL argument");
+  if (!s || !S_prev || !mu_in || !mu_out) return fail(FPC_ERR_ARG, "NULL argument");
   if (!adjoint_supported(s->p)) return fail(FPC_ERR_STATE, "adjoint: FP model with D2Q5 / D3Q7 thermal only");
-  if (lam_in == lam_out || lam_out == S_prev) return fail(FPC_ERR_ARG, "lam_out must not alias lam_in or S_prev");
+  if (mu_in == mu_out || mu_out == S_prev) return fail(FPC_ERR_ARG, "mu_out must not alias mu_in or S_prev");
   if (!std::isfinite(ke_weight)) return fail(FPC_ERR_ARG, "ke_weight not finite");
   double* dth[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   if (dJdtheta)
@@ -702,27 +817,27 @@ int fpc_adjoint_step(fpc_sim* s, const void* S_prev, const void* lam_in, void* l
   hipError_t e;
   if (s->p.precision == FPC_FP64) {
     const StepArgs<double> a = make_args<double>(s, S_prev, nullptr);
-    e = launch_adjoint_step<double>(a, s->dim, s->p.up_axis, lam_in, lam_out, dJdT, ke_weight, dth, s->stream);
+    e = launch_adjoint_step<double>(a, s->dim, s->p.up_axis, mu_in, mu_out, dJdT, ke_weight, dth, s->stream);
   } else {
     const StepArgs<float> a = make_args<float>(s, S_prev, nullptr);
-    e = launch_adjoint_step<float>(a, s->dim, s->p.up_axis, lam_in, lam_out, dJdT, ke_weight, dth, s->stream);
+    e = launch_adjoint_step<float>(a, s->dim, s->p.up_axis, mu_in, mu_out, dJdT, ke_weight, dth, s->stream);
   }
   if (e != hipSuccess) return hipfail(e, "adjoint step kernel");
   return FPC_OK;
 }
 
-int fpc_adjoint_init(fpc_sim* s, const double* T_init, const void* lam0, const double* dJdT, double ke_weight,
+int fpc_adjoint_init(fpc_sim* s, const double* T_init, const void* mu0, const double* dJdT, double ke_weight,
                      double* dJdT_init) {
-  if (!s || !T_init || !lam0 || !dJdT_init) return fail(FPC_ERR_ARG, "NULL argument");
+  if (!s || !T_init || !mu0 || !dJdT_init) return fail(FPC_ERR_ARG, "NULL argument");
   if (!adjoint_supported(s->p)) return fail(FPC_ERR_STATE, "adjoint: FP model with D2Q5 / D3Q7 thermal only");
   if (!std::isfinite(ke_weight)) return fail(FPC_ERR_ARG, "ke_weight not finite");
   hipError_t e;
   if (s->p.precision == FPC_FP64) {
     const StepArgs<double> a = make_args<double>(s, nullptr, nullptr);
-    e = launch_adjoint_init<double>(a, s->dim, s->p.up_axis, T_init, lam0, dJdT, ke_weight, dJdT_init, s->stream);
+    e = launch_adjoint_init<double>(a, s->dim, s->p.up_axis, T_init, mu0, dJdT, ke_weight, dJdT_init, s->stream);
   } else {
     const StepArgs<float> a = make_args<float>(s, nullptr, nullptr);
-    e = launch_adjoint_init<float>(a, s->dim, s->p.up_axis, T_init, lam0, dJdT, ke_weight, dJdT_init, s->stream);
+    e = launch_adjoint_init<float>(a, s->dim, s->p.up_axis, T_init, mu0, dJdT, ke_weight, dJdT_init, s->stream);
   }
   if (e != hipSuccess) return hipfail(e, "adjoint init kernel");
   return FPC_OK;

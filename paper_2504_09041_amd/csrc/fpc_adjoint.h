@@ -393,12 +393,31 @@ __device__ __forceinline__ void reverse(const Tape<R, D>& t, const CollParams<R>
     for (int ax = 0; ax < D; ++ax)
       if (M::m(i, ax) > 0) ub[ax] += kb[i] * R(M::m(i, ax)) * t.kt[M::down(i, ax)];
   // relaxation reverse, highest order first; kb holds kappa~bar, kp the
-  // adjoint of the pre-collision moments
+  // adjoint of the pre-collision moments.  kappa = C(u) f adds
+  // ubar_i -= kp_m m_i kappa_{m - e_i} once kp_m is final, i.e. right after
+  // its order is done (sources only feed kp one order down), so the
+  // pre-collision moments of each order die as soon as the next order up is
+  // through.  Orders 0 and 1 of kappa are fixed by the macros: kappa_0 = rho,
+  // kappa_{e_ax} = j_ax - rho u_ax = -F_ax / 2.
   R kp[NM];
 #pragma unroll
   for (int i = 0; i < NM; ++i) kp[i] = R(0);
   const R* om = c.om;
   const R Fr = t.Fb * t.ir;
+  auto kpre = [&](int j) -> R {
+    const int s = M::order(j);
+    if (s == 0) return t.rho;
+    if (s == 1) return (M::m(j, UP) == 1) ? R(-0.5) * t.Fb : R(0);
+    return t.k[j];
+  };
+  auto ub_from_kp = [&](int s) {
+#pragma unroll
+    for (int i = 0; i < NM; ++i)
+      if (M::order(i) == s)
+#pragma unroll
+        for (int ax = 0; ax < D; ++ax)
+          if (M::m(i, ax) > 0) ub[ax] -= kp[i] * R(M::m(i, ax)) * kpre(M::down(i, ax));
+  };
 #pragma unroll
   for (int s = 2 * D; s >= 3; --s) {
 #pragma unroll
@@ -433,6 +452,7 @@ __device__ __forceinline__ void reverse(const Tape<R, D>& t, const CollParams<R>
         rhob -= sb * sig * t.ir;
       }
     }
+    ub_from_kp(s);
   }
   // second order: off-diagonal
 #pragma unroll
@@ -462,6 +482,7 @@ __device__ __forceinline__ void reverse(const Tape<R, D>& t, const CollParams<R>
     kp[b] += trb - d1b;
     kp[cc] += trb - d2b;
   }
+  ub_from_kp(2);
   // first order: kt = (1 - w) k + (1 - w/2) F
 #pragma unroll
   for (int i = 0; i < NM; ++i)
@@ -475,14 +496,9 @@ __device__ __forceinline__ void reverse(const Tape<R, D>& t, const CollParams<R>
         if (ax == UP) Fbb += (R(1) - R(0.5) * w) * kb[i];
       }
     }
+  ub_from_kp(1);
   // zeroth order: kt_0 = rho
   rhob += kb[M::at(0, 0, 0)];
-  // kappa = C(u) f
-#pragma unroll
-  for (int i = 0; i < NM; ++i)
-#pragma unroll
-    for (int ax = 0; ax < D; ++ax)
-      if (M::m(i, ax) > 0) ub[ax] -= kp[i] * R(M::m(i, ax)) * t.k[M::down(i, ax)];
   apply<R, D, 2>(kp, t.u);  // C^T kappabar -> fbar (in work layout)
   // u = (j + F/2) / rho
   R jb[3];

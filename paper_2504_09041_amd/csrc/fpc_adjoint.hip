@@ -1,31 +1,38 @@
 // Adjoint stream-collide step and adjoint of the initial collision.
 //
 // One time step is S_n = Phi(S_{n-1}) = collide(pull(S_{n-1})) (see
-// fpc_step.hip).  For an objective J whose direct dependence on S_n comes
-// through the time-n macros (rho, u, T, recovered from S_n), the adjoint
-// recursion lambda_{n-1} = Phi^T (lambda_n + dJ/dS_n) is evaluated per node x:
+// fpc_step.hip).  The adjoint is carried between steps as mu_{n-1}, the
+// adjoint of the pulled (pre-collision) populations that enter the collision
+// of step n; the adjoint of the stored state S_{n-1} is lambda_{n-1} =
+// pull^T mu_{n-1}.  For an objective J whose direct dependence on S_n comes
+// through the time-n macros (rho, u, T, recovered from S_n), one adjoint step
+//   mu_{n-1} = collide_n^T (pull^T mu_n + dJ/dS_n)
+// is evaluated per node x:
 //   1. pull S_{n-1} at x exactly as the forward step (same wall rules),
 //   2. redo the collision on plain populations, keeping the tape,
-//   3. add the objective's seed on S_n(x) (weights on T_n(x) and/or the
-//      kinetic energy 1/2 rho |u|^2), take lambda_n(x),
-//   4. back-propagate through the collision (fpc_adjoint.h),
-//   5. push each incoming link's adjoint to the slot it was pulled from:
-//      the neighbour's slot (x - e_a, a) for streaming and periodic links, the
-//      node's own opposite slot for wall links (sign +1 for bounce-back and
-//      moving walls, -1 for the Dirichlet anti-bounce-back, whose wall
-//      temperature receives 2 w^T_a = c^_s^2 times the link adjoint).
-// Streaming plus the wall rules read every slot of S_{n-1} exactly once, so
-// every slot of lambda_{n-1} is written exactly once: no atomics, and each
-// wall-temperature gradient entry has a single owner thread per launch.
+//   3. form lambda_n(x) = (pull^T mu_n)(x): the transpose of the pull is a
+//      pull in the opposite direction (Rev in fpc_gather.h): slot (x, a)
+//      feeds the incoming link (x + e_a, a), or across a wall face the node's
+//      own link (x, abar), with the factor -1 of the Dirichlet rule,
+//   4. add the objective's seed on S_n(x) (weights on T_n(x) and/or the
+//      kinetic energy 1/2 rho |u|^2),
+//   5. back-propagate through the collision (fpc_adjoint.h): mu_{n-1}(x),
+//      stored in x's own tile, and the Dirichlet wall temperature of each of
+//      x's own Dirichlet links receives 2 w^T_a = c^_s^2 times its adjoint.
+// Every access of a node is a run of its own tile (stores) or a pulled run
+// (loads), as in the forward step; each wall-temperature gradient entry has a
+// single owner thread per launch.
 #include <type_traits>
+#include <utility>
 
 #include "fpc_adjoint.h"
 #include "fpc_gather.h"
 
-// Extra attributes of the 3D FP32 adjoint step kernel: its natural register
-// count sits just above the 168 VGPRs that allow 3 waves per SIMD.
+// Extra attributes of the 3D FP32 adjoint step kernel (launch tuning; none:
+// its 136 VGPRs give 3 waves per SIMD, and a 4-wave build, which spills,
+// measured no faster).
 #ifndef FPC_ADJ3F_ATTR
-#define FPC_ADJ3F_ATTR __attribute__((amdgpu_waves_per_eu(3)))
+#define FPC_ADJ3F_ATTR
 #endif
 
 namespace fpc {
@@ -70,89 +77,78 @@ __device__ __forceinline__ void add_seed(const adj::Tape<R, D>& t, const CollPar
 template <class R>
 struct AdjArgs {
   StepArgs<R> s;      // s.src = S_{n-1} (storage format); s.dst unused
-  const R* lam_in;    // adjoint of S_n (same layout as the state)
-  R* lam_out;         // adjoint of S_{n-1}
+  const R* lam_in;    // mu_n: adjoint of the pulled populations of step n + 1 (state layout)
+  R* lam_out;         // mu_{n-1}: the same for step n
   const double* dJdT; // per-node seed on T_n, or null
   double ke;          // weight of the kinetic-energy seed
   double* dtheta[6];  // per-face wall-temperature gradient (accumulated), or null
 };
 
-// Adjoint of the streaming step for one node: push the adjoint of each
-// incoming link to the slot it was read from (Edges: same classification as
-// the gather).  Thermal Dirichlet links carry the factor -1 of the
-// anti-bounce-back; their wall temperature receives 2 w^T_a = c^_s^2 times the
-// link adjoint.
-template <class L, class R, class M, bool CX, bool CY, bool CZ, bool PX>
-struct Scatter {
-  using E = Edges<L, R, CX, CY, CZ, PX>;
-  const AdjArgs<R>& A;
-  const M& m;
-  E e;
-  int x, y, z;
-
-  __device__ __forceinline__ Scatter(const AdjArgs<R>& A_, const M& m_, int x_, int y_, int z_, unsigned node)
-      : A(A_), m(m_), e(A_.s, x_, y_, z_, node), x(x_), y(y_), z(z_) {}
-
-  template <int Q, int QBASE>
-  __device__ __forceinline__ void push(R v) const {
-    constexpr bool TH = QBASE != 0;
-    constexpr int ex = lex<L, TH>(Q);
-    if (!E::template checked<Q, TH>()) {
-      m.store_tile(QBASE + Q, e.tl.template base<ex>(e.template dtile<Q, TH>()), e.tl.template lane<ex>(), v);
-      return;
-    }
-    const long long sh = e.template shift<Q, TH>();
-    bool wx = false, wy = false, wz = false;
-    const unsigned idx = e.template source<Q, TH>(wx, wy, wz);
-    if (E::template wrap_only<Q, TH>()) {
-      m.store_at(QBASE + Q, sh, idx, v);
-      return;
-    }
-    const bool wall = wx || wy || wz;
-    R out = v;
-    if (QBASE != 0 && Q != 0) {
-      constexpr int ey = ley<L, TH>(Q), ez = lez<L, TH>(Q);
-      constexpr int F = ex > 0 ? 0 : (ex < 0 ? 1 : (ey > 0 ? 2 : (ey < 0 ? 3 : (ez > 0 ? 4 : 5))));
-      constexpr int k = F >> 1;
-      const StepArgs<R>& a = A.s;
-      if (wall && a.face[F].dirichlet) {
-        out = -v;
-        if (A.dtheta[F]) {
-          const size_t t = k == 0 ? (size_t)z * a.ny + y : (k == 1 ? (size_t)z * a.nx + x : (size_t)y * a.nx + x);
-          A.dtheta[F][t] += (double)(a.c.cs2T * v);
-        }
-      }
-    }
-    m.store_sel(wall, QBASE + lopp<L, TH>(Q), e.node, QBASE + Q, sh, idx, out);
-  }
-};
-
+// lambda_n(x) = (pull^T mu_n)(x): the pull on the reversed lattice, with the
+// factor -1 on thermal links whose x + e_a lies beyond a Dirichlet face.
+template <class P, class R, size_t... I>
+__device__ __forceinline__ void tpull_f(const P& p, R* fb, std::index_sequence<I...>) {
+  bool wx, wy, wz;
+  ((wx = wy = wz = false, fb[I] = p.template pull<(int)I, false>(wx, wy, wz)), ...);
+}
+template <class RL, int A, class P, class R>
+__device__ __forceinline__ R tpull_g1(const P& p, const StepArgs<R>& a) {
+  bool wx = false, wy = false, wz = false;
+  const R v = p.template pull<A, true>(wx, wy, wz);
+  if (A == 0 || !P::E::template checked<A, true>()) return v;
+  constexpr int ex = RL::tex(A), ey = RL::tey(A), ez = RL::tez(A);
+  constexpr int FX = ex > 0 ? 0 : 1, FY = ey > 0 ? 2 : 3, FZ = ez > 0 ? 4 : 5;
+  const bool dir = (ex != 0 && wx && a.face[FX].dirichlet) || (ey != 0 && wy && a.face[FY].dirichlet) ||
+                   (ez != 0 && wz && a.face[FZ].dirichlet);
+  return dir ? -v : v;
+}
+template <class RL, class P, class R, size_t... I>
+__device__ __forceinline__ void tpull_g(const P& p, const StepArgs<R>& a, R* gb, std::index_sequence<I...>) {
+  ((gb[I] = tpull_g1<RL, (int)I>(p, a)), ...);
+}
 template <class L, class R, class M, bool CX, bool CY, bool CZ, bool PX = false>
-__device__ __forceinline__ void scatter(const AdjArgs<R>& A, const M& mL, int x, int y, int z, unsigned node,
-                                        const R (&fb)[L::Qf], const R (&gb)[L::Qg]) {
-  const Scatter<L, R, M, CX, CY, CZ, PX> sc(A, mL, x, y, z, node);
-  if constexpr (L::D == 2) {
-    sc.template push<0, 0>(fb[0]); sc.template push<1, 0>(fb[1]); sc.template push<2, 0>(fb[2]);
-    sc.template push<3, 0>(fb[3]); sc.template push<4, 0>(fb[4]); sc.template push<5, 0>(fb[5]);
-    sc.template push<6, 0>(fb[6]); sc.template push<7, 0>(fb[7]); sc.template push<8, 0>(fb[8]);
-    sc.template push<0, kQ2>(gb[0]); sc.template push<1, kQ2>(gb[1]); sc.template push<2, kQ2>(gb[2]);
-    sc.template push<3, kQ2>(gb[3]); sc.template push<4, kQ2>(gb[4]);
-  } else {
-#define FPC_P(Q) sc.template push<Q, 0>(fb[Q]);
-    FPC_P(0) FPC_P(1) FPC_P(2) FPC_P(3) FPC_P(4) FPC_P(5) FPC_P(6) FPC_P(7) FPC_P(8)
-    FPC_P(9) FPC_P(10) FPC_P(11) FPC_P(12) FPC_P(13) FPC_P(14) FPC_P(15) FPC_P(16) FPC_P(17)
-    FPC_P(18) FPC_P(19) FPC_P(20) FPC_P(21) FPC_P(22) FPC_P(23) FPC_P(24) FPC_P(25) FPC_P(26)
-#undef FPC_P
-    sc.template push<0, kQ3>(gb[0]); sc.template push<1, kQ3>(gb[1]); sc.template push<2, kQ3>(gb[2]);
-    sc.template push<3, kQ3>(gb[3]); sc.template push<4, kQ3>(gb[4]); sc.template push<5, kQ3>(gb[5]);
-    sc.template push<6, kQ3>(gb[6]);
-  }
+__device__ __forceinline__ void tgather(const StepArgs<R>& a, const M& m, int x, int y, int z, unsigned node,
+                                        R (&fb)[L::Qf], R (&gb)[L::Qg]) {
+  using RL = Rev<L>;
+  const Gather<RL, R, M, CX, CY, CZ, PX> p(a, m, x, y, z, node, R(0));
+  tpull_f(p, fb, std::make_index_sequence<L::Qf>{});
+  tpull_g<RL>(p, a, gb, std::make_index_sequence<L::Qg>{});
 }
 
-// M: addressing policy of S_{n-1} (read) and of the adjoint pair (lam_in
-// read, lam_out written); Buf32 below 4 GiB per buffer, else Glob64.
-// The edge variant is chosen per wavefront (ballot) for the gather and again
-// for the scatter; the collision and its adjoint in between are shared.
+// Wall-temperature gradient: each thermal link of x that met a Dirichlet face
+// in the forward pull (g_a = -g~_abar + 2 w^T_a T_w) adds 2 w^T_a = c^_s^2
+// times its adjoint mu(x, a) to the face's entry of x.
+template <class L, class R, bool CX, bool CY, bool CZ, bool PX, int A>
+__device__ __forceinline__ void theta_link(const AdjArgs<R>& AA, const Edges<L, R, CX, CY, CZ, PX>& e, int x, int y,
+                                           int z, R v) {
+  if constexpr (A == 0 || !Edges<L, R, CX, CY, CZ, PX>::template checked<A, true>()) {
+    return;
+  } else {
+    const StepArgs<R>& a = AA.s;
+    bool wx = false, wy = false, wz = false;
+    (void)e.template source<A, true>(wx, wy, wz);
+    constexpr int ex = L::tex(A), ey = L::tey(A), ez = L::tez(A);
+    constexpr int F = ex > 0 ? 0 : (ex < 0 ? 1 : (ey > 0 ? 2 : (ey < 0 ? 3 : (ez > 0 ? 4 : 5))));
+    constexpr int k = F >> 1;
+    if ((wx || wy || wz) && a.face[F].dirichlet && AA.dtheta[F]) {
+      const size_t t = k == 0 ? (size_t)z * a.ny + y : (k == 1 ? (size_t)z * a.nx + x : (size_t)y * a.nx + x);
+      AA.dtheta[F][t] += (double)(a.c.cs2T * v);
+    }
+  }
+}
+template <class L, class R, bool CX, bool CY, bool CZ, bool PX, size_t... I>
+__device__ __forceinline__ void theta_links(const AdjArgs<R>& AA, int x, int y, int z, unsigned node, const R* gb,
+                                            std::index_sequence<I...>) {
+  if (!(CX || CY || CZ)) return;
+  const Edges<L, R, CX, CY, CZ, PX> e(AA.s, x, y, z, node);
+  (theta_link<L, R, CX, CY, CZ, PX, (int)I>(AA, e, x, y, z, gb[I]), ...);
+}
+
+// M: addressing policy of S_{n-1} (read) and of the adjoint pair (mu_n
+// read, mu_{n-1} written); Buf32 below 4 GiB per buffer, else Glob64.  The
+// edge variant is chosen per wavefront (ballot) for the forward pull, again
+// for the transposed pull of mu_n and for the wall-temperature gradient; the
+// collision and its adjoint in between, and the stores, are shared.
 template <class L, class R, class M, int UP, bool STD>
 __device__ __forceinline__ void adjoint_step(const AdjArgs<R>& A, unsigned total_bytes) {
   constexpr int D = L::D;
@@ -191,21 +187,30 @@ __device__ __forceinline__ void adjoint_step(const AdjArgs<R>& A, unsigned total
   adj::Tape<R, D> t;
   adj::forward<R, D, UP, STD>(f, g, a.c, t);
   R fb[L::Qf], gb[L::Qg];
-#pragma unroll
-  for (int q = 0; q < L::Qf; ++q) fb[q] = mL.load(q, 0, node);
-#pragma unroll
-  for (int q = 0; q < L::Qg; ++q) gb[q] = mL.load(L::Qf + q, 0, node);
+  if (variant == 0)
+    tgather<L, R, M, false, false, false>(a, mL, x, y, z, node, fb, gb);
+  else if (variant == 1)
+    tgather<L, R, M, true, false, false, true>(a, mL, x, y, z, node, fb, gb);
+  else if (variant == 2)
+    tgather<L, R, M, true, false, false>(a, mL, x, y, z, node, fb, gb);
+  else
+    tgather<L, R, M, true, true, D == 3>(a, mL, x, y, z, node, fb, gb);
   const size_t cell = ((size_t)z * a.ny + y) * a.nx + x;  // index of the unpadded node fields
   add_seed<R, D, UP>(t, a.c, A.dJdT ? A.dJdT[cell] : 0.0, A.ke, fb, gb);
   adj::reverse<R, D, UP, STD>(t, a.c, fb, gb);
-  if (variant == 0)
-    scatter<L, R, M, false, false, false>(A, mL, x, y, z, node, fb, gb);
-  else if (variant == 1)
-    scatter<L, R, M, true, false, false, true>(A, mL, x, y, z, node, fb, gb);
+  auto cur = mL.cursor(node);
+#pragma unroll
+  for (int q = 0; q < L::Qf; ++q) mL.template store_next<false>(cur, fb[q]);
+#pragma unroll
+  for (int q = 0; q < L::Qg; ++q) mL.template store_next<false>(cur, gb[q]);
+  if (variant == 0) return;  // no wall links
+  constexpr auto qg = std::make_index_sequence<L::Qg>{};
+  if (variant == 1)
+    theta_links<L, R, true, false, false, true>(A, x, y, z, node, gb, qg);
   else if (variant == 2)
-    scatter<L, R, M, true, false, false>(A, mL, x, y, z, node, fb, gb);
+    theta_links<L, R, true, false, false, false>(A, x, y, z, node, gb, qg);
   else
-    scatter<L, R, M, true, true, D == 3>(A, mL, x, y, z, node, fb, gb);
+    theta_links<L, R, true, true, D == 3, false>(A, x, y, z, node, gb, qg);
 }
 
 // STD: the standard rate set (fpc_kernels.h standard_rates), whose unit
@@ -223,15 +228,19 @@ template <class R>
 struct AdjInitArgs {
   StepArgs<R> s;       // geometry and parameters
   const double* T_init;
-  const R* lam0;       // adjoint of S_0
+  const R* lam0;       // mu_0: adjoint of the pulled populations of step 1
   const double* dJdT;  // seed on T_0, or null
   double ke;
   double* dTinit;      // output: dJ/dT_init per node
 };
 
+// lambda_0 = pull^T mu_0 (mu_0: the adjoint of the pulled populations of step
+// 1), then the adjoint of the initial collision.  Blocks are whole multiples
+// of 64 along x, so a wavefront owns one tile as in the step kernels.
 template <int D, class R, int UP>
 __global__ void __launch_bounds__(256) adjoint_init_kernel(AdjInitArgs<R> A) {
   using Lk = LinkOf<D>;
+  using L = typename std::conditional<D == 2, Lat2, Lat3>::type;
   const StepArgs<R>& a = A.s;
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
@@ -240,6 +249,8 @@ __global__ void __launch_bounds__(256) adjoint_init_kernel(AdjInitArgs<R> A) {
   constexpr int Q = Lk::Qf + Lk::Qg;
   const size_t node = ((size_t)z * a.ny + y) * a.nx + x;  // unpadded node fields
   const unsigned n = node_of(x, y, z, a.nxp, a.ny);         // storage layout
+  const bool needx = __any(x == 0 || x == a.nx - 1);
+  const bool needyz = __any(y == 0 || y == a.ny - 1) || (D == 3 && __any(z == 0 || z == a.nz - 1));
   R f[Lk::Qf], g[Lk::Qg], wg[Lk::Qg];
 #pragma unroll
   for (int q = 0; q < Lk::Qf; ++q) f[q] = R(Lk::w(q)) * a.rho_w;
@@ -252,10 +263,18 @@ __global__ void __launch_bounds__(256) adjoint_init_kernel(AdjInitArgs<R> A) {
   adj::Tape<R, D> t;
   adj::forward<R, D, UP>(f, g, a.c, t);
   R fb[Lk::Qf], gb[Lk::Qg];
-#pragma unroll
-  for (int q = 0; q < Lk::Qf; ++q) fb[q] = A.lam0[elem64<Q>(q, n)];
-#pragma unroll
-  for (int q = 0; q < Lk::Qg; ++q) gb[q] = A.lam0[elem64<Q>(Lk::Qf + q, n)];
+  using M = Glob64<R, Q>;
+  const M m(A.lam0, nullptr, 0u);
+  if (!needyz) {
+    if (!needx)
+      tgather<L, R, M, false, false, false>(a, m, x, y, z, n, fb, gb);
+    else if (a.per[0])
+      tgather<L, R, M, true, false, false, true>(a, m, x, y, z, n, fb, gb);
+    else
+      tgather<L, R, M, true, false, false>(a, m, x, y, z, n, fb, gb);
+  } else {
+    tgather<L, R, M, true, true, D == 3>(a, m, x, y, z, n, fb, gb);
+  }
   add_seed<R, D, UP>(t, a.c, A.dJdT ? A.dJdT[node] : 0.0, A.ke, fb, gb);
   adj::reverse<R, D, UP>(t, a.c, fb, gb);
   double s = 0.0;

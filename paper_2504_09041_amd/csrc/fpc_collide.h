@@ -110,6 +110,43 @@ __device__ __forceinline__ R relax_slot(const CollParams<R>& c, R k, R dmv, R s)
     return k + w * (dmv - k) + (R(1) - R(0.5) * w) * s;
   }
 }
+// The same for a slot without a source (s = 0 written out: a zero source
+// would still cost instructions, as IEEE arithmetic cannot drop it).
+template <int D, bool STD, int K, class R>
+__device__ __forceinline__ R relax_slot(const CollParams<R>& c, R k, R dmv) {
+  if constexpr (STD && !viscous_slot<D>(K)) {
+    return dmv;
+  } else {
+    const R w = rate_f<D, STD>(c, K);
+    return k + w * (dmv - k);
+  }
+}
+// With the source only when HAS_S (a source known to vanish at compile time).
+template <int D, bool STD, int K, bool HAS_S, class R>
+__device__ __forceinline__ R relax_src(const CollParams<R>& c, R k, R dmv, R s) {
+  if constexpr (HAS_S)
+    return relax_slot<D, STD, K>(c, k, dmv, s);
+  else
+    return relax_slot<D, STD, K>(c, k, dmv);
+}
+// Whether the force source sigma_m = m_up (F / rho) kappa_{m - e_up} of
+// moment (m, n, p) can be non-zero: m_up > 0 and m - e_up not of order 1
+// (first-order central moments taken as zero).
+__device__ __forceinline__ constexpr bool has_sig(int up, int m, int n, int p) {
+  const int mu = up == 0 ? m : (up == 1 ? n : p);
+  return mu != 0 && (m + n + p - 1) != 1;
+}
+
+// The standard build (STD) also fixes the FP attractors and thermal option
+// A at compile time; the MCM comparator and option B run the general build.
+template <bool STD, class R>
+__device__ __forceinline__ bool mcm(const CollParams<R>& c) {
+  return !STD && c.model != 0;
+}
+template <bool STD, class R>
+__device__ __forceinline__ bool option_b(const CollParams<R>& c) {
+  return !STD && c.topt != 0;
+}
 
 template <int D, bool STD, class R>
 __device__ __forceinline__ R rate_g(const CollParams<R>& c, int k) {
@@ -157,11 +194,11 @@ __device__ __forceinline__ void thermal_d2q9(R (&g)[kQ2], R ux, R uy, R T, const
   const R t20 = R(0.5) * (ts + td), t02 = R(0.5) * (ts - td);
   const R t11 = (R(1) - og(5)) * e11;
   R m21, m12, m22;
-  if (c.model != 0) {  // MCM
+  if (mcm<STD>(c)) {  // MCM
     m21 = R(0);
     m12 = R(0);
     m22 = cT * cT * T;
-  } else if (c.topt != 0) {  // option B (Eq. MvT2DoptionB)
+  } else if (option_b<STD>(c)) {  // option B (Eq. MvT2DoptionB)
     const R iT = R(1) / T;
     m21 = R(2) / R(3) * iT * (t20 * t01 + R(2) * t11 * t10);
     m12 = R(2) / R(3) * iT * (t02 * t10 + R(2) * t11 * t01);
@@ -277,10 +314,10 @@ __device__ __forceinline__ void thermal_d3q15(R (&g)[kQ15], R ux, R uy, R uz, R 
 #pragma unroll
   for (int k = 7; k <= 9; ++k) t[k] = e[k] + og(k) * (cT * T - e[k]);
   R m120, m012, m201, m111, m220;
-  if (c.model != 0) {  // MCM
+  if (mcm<STD>(c)) {  // MCM
     m120 = m012 = m201 = m111 = R(0);
     m220 = cT * cT * T;
-  } else if (c.topt != 0) {  // option B
+  } else if (option_b<STD>(c)) {  // option B
     const R f = R(2) / (R(3) * T);
     m120 = f * (t[8] * t[1] + R(2) * t[4] * t[2]);
     m012 = f * (t[9] * t[2] + R(2) * t[6] * t[3]);
@@ -398,19 +435,19 @@ __device__ __forceinline__ void collide2d(R (&f)[kQ2], R (&g)[QG], const CollPar
   }
 
   // relaxation (deviation form; attractor deviations dMv = Mv - rho_r kappa_rest)
-  const R t10 = relax_slot<2, STD, 1>(c, k10, rr * ux, Fx);
-  const R t01 = relax_slot<2, STD, 2>(c, k01, rr * uy, Fy);
+  const R t10 = relax_src<2, STD, 1, UP == 0>(c, k10, rr * ux, Fx);
+  const R t01 = relax_src<2, STD, 2, UP == 1>(c, k01, rr * uy, Fy);
   const R k2s = k20 + k02, k2d = k20 - k02;
-  const R t2s = relax_slot<2, STD, 3>(c, k2s, R(2) * cs2 * drho - rr * (uxx + uyy), R(0));
-  const R t2d = relax_slot<2, STD, 4>(c, k2d, -rr * (uxx - uyy), R(0));
-  const R t11 = relax_slot<2, STD, 5>(c, k11, -rr * uxy, R(0));
+  const R t2s = relax_slot<2, STD, 3>(c, k2s, R(2) * cs2 * drho - rr * (uxx + uyy));
+  const R t2d = relax_slot<2, STD, 4>(c, k2d, -rr * (uxx - uyy));
+  const R t11 = relax_slot<2, STD, 5>(c, k11, -rr * uxy);
   const R t20 = R(0.5) * (t2s + t2d);
   const R t02 = R(0.5) * (t2s - t2d);
   const R t21 = relax_slot<2, STD, 6>(c, k21, rr * A * uy, s21);
   const R t12 = relax_slot<2, STD, 7>(c, k12, rr * ux * B, s12);
   // kappa^Mv_22 = (kappa~20 kappa~02 + 2 kappa~11^2) / rho (FP); rho c_s^4 (MCM)
   R mv22;
-  if (c.model != 0)
+  if (mcm<STD>(c))
     mv22 = drho * (cs2 * cs2) - rr * (cs2 * (uxx + uyy) + uxx * uyy);
   else
     mv22 = (dprod(rr, A, t20, B, t02) + R(2) * dprod(rr, uxy, t11, uxy, t11) + rr * rr * (R(2) * uxx * uyy) -
@@ -475,14 +512,25 @@ __device__ __forceinline__ void collide3d(R (&f)[kQ3], R (&g)[QG], const CollPar
   constexpr R cs2 = R(1) / R(3);
   const R rr = rho_ref(c);
 
-  // macros
-  R drho = R(0), jx = R(0), jy = R(0), jz = R(0);
+  // macros (each sum starts from its first term: an explicit 0 + x would
+  // cost an IEEE add)
+  R drho = f[0], jx = R(0), jy = R(0), jz = R(0);
+  bool hx = false, hy = false, hz = false;
 #pragma unroll
-  for (int a = 0; a < kQ3; ++a) {
+  for (int a = 1; a < kQ3; ++a) {
     drho += f[a];
-    if (D3_EX[a] != 0) jx += D3_EX[a] > 0 ? f[a] : -f[a];
-    if (D3_EY[a] != 0) jy += D3_EY[a] > 0 ? f[a] : -f[a];
-    if (D3_EZ[a] != 0) jz += D3_EZ[a] > 0 ? f[a] : -f[a];
+    if (D3_EX[a] != 0) {
+      jx = hx ? (D3_EX[a] > 0 ? jx + f[a] : jx - f[a]) : (D3_EX[a] > 0 ? f[a] : -f[a]);
+      hx = true;
+    }
+    if (D3_EY[a] != 0) {
+      jy = hy ? (D3_EY[a] > 0 ? jy + f[a] : jy - f[a]) : (D3_EY[a] > 0 ? f[a] : -f[a]);
+      hy = true;
+    }
+    if (D3_EZ[a] != 0) {
+      jz = hz ? (D3_EZ[a] > 0 ? jz + f[a] : jz - f[a]) : (D3_EZ[a] > 0 ? f[a] : -f[a]);
+      hz = true;
+    }
   }
   R dT = ((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + g[6]);
   if constexpr (QG != kQ3T) {
@@ -560,31 +608,31 @@ __device__ __forceinline__ void collide3d(R (&f)[kQ3], R (&g)[QG], const CollPar
 
   // order 0 and 1
   w[I3(0, 0, 0)] = drho;
-  w[I3(1, 0, 0)] = relax_slot<3, STD, 1>(c, w[I3(1, 0, 0)], rr * ux, Fx);
-  w[I3(0, 1, 0)] = relax_slot<3, STD, 2>(c, w[I3(0, 1, 0)], rr * uy, Fy);
-  w[I3(0, 0, 1)] = relax_slot<3, STD, 3>(c, w[I3(0, 0, 1)], rr * uz, Fz);
+  w[I3(1, 0, 0)] = relax_src<3, STD, 1, UP == 0>(c, w[I3(1, 0, 0)], rr * ux, Fx);
+  w[I3(0, 1, 0)] = relax_src<3, STD, 2, UP == 1>(c, w[I3(0, 1, 0)], rr * uy, Fy);
+  w[I3(0, 0, 1)] = relax_src<3, STD, 3, UP == 2>(c, w[I3(0, 0, 1)], rr * uz, Fz);
   // order 2: off-diagonal, then trace and the two deviators
-  w[I3(1, 1, 0)] = relax_slot<3, STD, 4>(c, w[I3(1, 1, 0)], -rr * uxy, R(0));
-  w[I3(1, 0, 1)] = relax_slot<3, STD, 5>(c, w[I3(1, 0, 1)], -rr * uxz, R(0));
-  w[I3(0, 1, 1)] = relax_slot<3, STD, 6>(c, w[I3(0, 1, 1)], -rr * uyz, R(0));
+  w[I3(1, 1, 0)] = relax_slot<3, STD, 4>(c, w[I3(1, 1, 0)], -rr * uxy);
+  w[I3(1, 0, 1)] = relax_slot<3, STD, 5>(c, w[I3(1, 0, 1)], -rr * uxz);
+  w[I3(0, 1, 1)] = relax_slot<3, STD, 6>(c, w[I3(0, 1, 1)], -rr * uyz);
   {
     const R a = w[I3(2, 0, 0)], b = w[I3(0, 2, 0)], d = w[I3(0, 0, 2)];
-    const R ts = relax_slot<3, STD, 7>(c, a + b + d, R(3) * cs2 * drho - rr * (uxx + uyy + uzz), R(0));
-    const R t1 = relax_slot<3, STD, 8>(c, a - b, -rr * (uxx - uyy), R(0));
-    const R t2 = relax_slot<3, STD, 9>(c, a - d, -rr * (uxx - uzz), R(0));
+    const R ts = relax_slot<3, STD, 7>(c, a + b + d, R(3) * cs2 * drho - rr * (uxx + uyy + uzz));
+    const R t1 = relax_slot<3, STD, 8>(c, a - b, -rr * (uxx - uyy));
+    const R t2 = relax_slot<3, STD, 9>(c, a - d, -rr * (uxx - uzz));
     const R t200 = (ts + t1 + t2) * (R(1) / R(3));
     w[I3(2, 0, 0)] = t200;
     w[I3(0, 2, 0)] = t200 - t1;
     w[I3(0, 0, 2)] = t200 - t2;
   }
   // order 3: attractors zero, deviation -rho_r kappa_rest
-  w[I3(1, 2, 0)] = relax_slot<3, STD, 10>(c, w[I3(1, 2, 0)], -rr * Rst(1, 2, 0), s120);
-  w[I3(1, 0, 2)] = relax_slot<3, STD, 11>(c, w[I3(1, 0, 2)], -rr * Rst(1, 0, 2), s102);
-  w[I3(2, 1, 0)] = relax_slot<3, STD, 12>(c, w[I3(2, 1, 0)], -rr * Rst(2, 1, 0), s210);
-  w[I3(0, 1, 2)] = relax_slot<3, STD, 13>(c, w[I3(0, 1, 2)], -rr * Rst(0, 1, 2), s012);
-  w[I3(2, 0, 1)] = relax_slot<3, STD, 14>(c, w[I3(2, 0, 1)], -rr * Rst(2, 0, 1), s201);
-  w[I3(0, 2, 1)] = relax_slot<3, STD, 15>(c, w[I3(0, 2, 1)], -rr * Rst(0, 2, 1), s021);
-  w[I3(1, 1, 1)] = relax_slot<3, STD, 16>(c, w[I3(1, 1, 1)], -rr * Rst(1, 1, 1), s111);
+  w[I3(1, 2, 0)] = relax_src<3, STD, 10, has_sig(UP, 1, 2, 0)>(c, w[I3(1, 2, 0)], -rr * Rst(1, 2, 0), s120);
+  w[I3(1, 0, 2)] = relax_src<3, STD, 11, has_sig(UP, 1, 0, 2)>(c, w[I3(1, 0, 2)], -rr * Rst(1, 0, 2), s102);
+  w[I3(2, 1, 0)] = relax_src<3, STD, 12, has_sig(UP, 2, 1, 0)>(c, w[I3(2, 1, 0)], -rr * Rst(2, 1, 0), s210);
+  w[I3(0, 1, 2)] = relax_src<3, STD, 13, has_sig(UP, 0, 1, 2)>(c, w[I3(0, 1, 2)], -rr * Rst(0, 1, 2), s012);
+  w[I3(2, 0, 1)] = relax_src<3, STD, 14, has_sig(UP, 2, 0, 1)>(c, w[I3(2, 0, 1)], -rr * Rst(2, 0, 1), s201);
+  w[I3(0, 2, 1)] = relax_src<3, STD, 15, has_sig(UP, 0, 2, 1)>(c, w[I3(0, 2, 1)], -rr * Rst(0, 2, 1), s021);
+  w[I3(1, 1, 1)] = relax_src<3, STD, 16, has_sig(UP, 1, 1, 1)>(c, w[I3(1, 1, 1)], -rr * Rst(1, 1, 1), s111);
 
   // order 4: products of post-collision second-order moments
   const R rr2 = rr * rr;
@@ -594,7 +642,7 @@ __device__ __forceinline__ void collide3d(R (&f)[kQ3], R (&g)[QG], const CollPar
   {
     // FP: products of post-collision second-order moments; MCM: rho c_s^4 or 0
     R mv220, mv202, mv022, mv211, mv121, mv112;
-    if (c.model != 0) {
+    if (mcm<STD>(c)) {
       constexpr R cs4 = cs2 * cs2;
       mv220 = drho * cs4 - rr * (cs2 * (uxx + uyy) + uxx * uyy);
       mv202 = drho * cs4 - rr * (cs2 * (uxx + uzz) + uxx * uzz);
@@ -610,18 +658,18 @@ __device__ __forceinline__ void collide3d(R (&f)[kQ3], R (&g)[QG], const CollPar
       mv121 = (P(0, 2, 0, 1, 0, 1) + R(2) * P(1, 1, 0, 0, 1, 1) + rr2 * (R(2) * uyy * uxz) - rr * B * uxz * drho) * irho;
       mv112 = (P(0, 0, 2, 1, 1, 0) + R(2) * P(0, 1, 1, 1, 0, 1) + rr2 * (R(2) * uzz * uxy) - rr * C * uxy * drho) * irho;
     }
-    w[I3(2, 2, 0)] = relax_slot<3, STD, 17>(c, w[I3(2, 2, 0)], mv220, s220);
-    w[I3(2, 0, 2)] = relax_slot<3, STD, 18>(c, w[I3(2, 0, 2)], mv202, s202);
-    w[I3(0, 2, 2)] = relax_slot<3, STD, 19>(c, w[I3(0, 2, 2)], mv022, s022);
-    w[I3(2, 1, 1)] = relax_slot<3, STD, 20>(c, w[I3(2, 1, 1)], mv211, s211);
-    w[I3(1, 2, 1)] = relax_slot<3, STD, 21>(c, w[I3(1, 2, 1)], mv121, s121);
-    w[I3(1, 1, 2)] = relax_slot<3, STD, 22>(c, w[I3(1, 1, 2)], mv112, s112);
+    w[I3(2, 2, 0)] = relax_src<3, STD, 17, has_sig(UP, 2, 2, 0)>(c, w[I3(2, 2, 0)], mv220, s220);
+    w[I3(2, 0, 2)] = relax_src<3, STD, 18, has_sig(UP, 2, 0, 2)>(c, w[I3(2, 0, 2)], mv202, s202);
+    w[I3(0, 2, 2)] = relax_src<3, STD, 19, has_sig(UP, 0, 2, 2)>(c, w[I3(0, 2, 2)], mv022, s022);
+    w[I3(2, 1, 1)] = relax_src<3, STD, 20, has_sig(UP, 2, 1, 1)>(c, w[I3(2, 1, 1)], mv211, s211);
+    w[I3(1, 2, 1)] = relax_src<3, STD, 21, has_sig(UP, 1, 2, 1)>(c, w[I3(1, 2, 1)], mv121, s121);
+    w[I3(1, 1, 2)] = relax_src<3, STD, 22, has_sig(UP, 1, 1, 2)>(c, w[I3(1, 1, 2)], mv112, s112);
   }
   // order 5: (2 / 5 rho) [...] from post-collision second x third order (FP);
   // zero for MCM (deviation -rho_r kappa_rest)
   {
     R mv122, mv212, mv221;
-    if (c.model != 0) {
+    if (mcm<STD>(c)) {
       mv122 = -rr * Rst(1, 2, 2);
       mv212 = -rr * Rst(2, 1, 2);
       mv221 = -rr * Rst(2, 2, 1);
@@ -643,15 +691,15 @@ __device__ __forceinline__ void collide3d(R (&f)[kQ3], R (&g)[QG], const CollPar
                        R(2) * (P(0, 1, 1, 2, 1, 0) + P(1, 0, 1, 1, 2, 0))) +
                rr2 * r221 - rr * Rst(2, 2, 1) * drho) * irho;
     }
-    w[I3(1, 2, 2)] = relax_slot<3, STD, 23>(c, w[I3(1, 2, 2)], mv122, s122);
-    w[I3(2, 1, 2)] = relax_slot<3, STD, 24>(c, w[I3(2, 1, 2)], mv212, s212);
-    w[I3(2, 2, 1)] = relax_slot<3, STD, 25>(c, w[I3(2, 2, 1)], mv221, s221);
+    w[I3(1, 2, 2)] = relax_src<3, STD, 23, has_sig(UP, 1, 2, 2)>(c, w[I3(1, 2, 2)], mv122, s122);
+    w[I3(2, 1, 2)] = relax_src<3, STD, 24, has_sig(UP, 2, 1, 2)>(c, w[I3(2, 1, 2)], mv212, s212);
+    w[I3(2, 2, 1)] = relax_src<3, STD, 25, has_sig(UP, 2, 2, 1)>(c, w[I3(2, 2, 1)], mv221, s221);
   }
   // order 6: (1 / 3 rho) [...] from post-collision second x fourth order (FP);
   // rho c_s^6 for MCM
   {
     R mv222;
-    if (c.model != 0) {
+    if (mcm<STD>(c)) {
       constexpr R cs4 = cs2 * cs2;
       mv222 = drho * (cs4 * cs2) -
               rr * (cs4 * (uxx + uyy + uzz) + cs2 * (uxx * uyy + uxx * uzz + uyy * uzz) + uxx * uyy * uzz);
@@ -662,7 +710,7 @@ __device__ __forceinline__ void collide3d(R (&f)[kQ3], R (&g)[QG], const CollPar
                rr2 * (R(4) / R(3)) * (uxx * uyy * C + uxx * uzz * B + uyy * uzz * A) - rr * A * B * C * drho) *
               irho;
     }
-    w[I3(2, 2, 2)] = relax_slot<3, STD, 26>(c, w[I3(2, 2, 2)], mv222, s222);
+    w[I3(2, 2, 2)] = relax_src<3, STD, 26, has_sig(UP, 2, 2, 2)>(c, w[I3(2, 2, 2)], mv222, s222);
   }
 
   // central -> populations: z shifts, then y, then x

@@ -7,9 +7,10 @@
 //   moving wall  f_a = f~_abar + 2 w_a rho_w (e_a . u_w) / c_s^2
 //   adiabatic    g_a = g~_abar
 //   Dirichlet    g_a = -g~_abar + 2 w^T_a T_w
-// Adjoint (scatter): the transpose of that selection; each node pushes the
-// adjoint of an incoming link back to the slot it was read from, so every
-// slot of the output is written exactly once.
+// Adjoint: the transpose of that selection, taken as a pull in the opposite
+// direction (Rev below): the adjoint of stored slot (x, a) is that of the
+// incoming link it feeds, (x + e_a, a), or across a wall face the node's own
+// (x, abar), with the factor -1 of the Dirichlet rule.
 //
 // Layout: tiles of 64 nodes (below); a wavefront owns one tile, so every
 // access is a contiguous run of 64 values of one population of one tile
@@ -78,6 +79,20 @@ struct Lat3T15 : Lat3 {  // D3Q27 + D3Q15
   static __device__ __forceinline__ R wT(int a, R c) {
     return a == 0 ? R(1) - R(3) * c + R(2) * c * c : (a <= 6 ? R(0.5) * (c - c * c) : R(0.125) * c * c);
   }
+};
+
+// The same lattice pair with every link reversed (e -> -e; slots, opposite
+// slots and weights unchanged).  A pull on Rev<L> reads x + e_a, and a link
+// whose x + e_a lies beyond a wall face takes the node's own opposite slot:
+// the transpose of the selection made by the pull on L.
+template <class L>
+struct Rev : L {
+  static constexpr int ex(int a) { return -L::ex(a); }
+  static constexpr int ey(int a) { return -L::ey(a); }
+  static constexpr int ez(int a) { return -L::ez(a); }
+  static constexpr int tex(int a) { return -L::tex(a); }
+  static constexpr int tey(int a) { return -L::tey(a); }
+  static constexpr int tez(int a) { return -L::tez(a); }
 };
 
 // link components of the fluid (TH = false) or thermal (TH = true) lattice
@@ -177,7 +192,10 @@ constexpr int kBufDword3 = 0x00020000;  // raw (untyped) buffer, gfx9 family
 #endif
 typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
 
-template <class R, int Q>
+// LAUX: cache policy of the loads (the multi-step kernel reads the previous
+// step with device-scope loads, which miss the per-CU L1: another CU of the
+// same XCD may have written the line since).
+template <class R, int Q, int LAUX = FPC_LOAD_AUX>
 struct Buf32 {
   __amdgpu_buffer_rsrc_t rsrc_s, rsrc_d;
   static constexpr unsigned S = sizeof(R);
@@ -188,9 +206,9 @@ struct Buf32 {
 
   __device__ __forceinline__ R raw(unsigned voff, unsigned soff) const {
     if constexpr (sizeof(R) == 4)
-      return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b32(rsrc_s, (int)voff, (int)soff, FPC_LOAD_AUX));
+      return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b32(rsrc_s, (int)voff, (int)soff, LAUX));
     else
-      return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b64(rsrc_s, (int)voff, (int)soff, FPC_LOAD_AUX));
+      return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b64(rsrc_s, (int)voff, (int)soff, LAUX));
   }
   template <bool NT>
   __device__ __forceinline__ void raw_store(unsigned voff, unsigned soff, R v) const {
@@ -341,6 +359,24 @@ struct Edges {
 // Gather: the incoming (pre-collision) populations of one node, in storage
 // form relative to this node's references.
 // ---------------------------------------------------------------------------
+// e . t for a compile-time link e, summing only its non-zero components
+// (a zero component times t would still cost an IEEE multiply-add).
+template <int EX, int EY, int EZ, class R>
+__device__ __forceinline__ R edot(const R (&t)[3]) {
+  R d = R(0);  // the rest link (never used for it)
+  bool any = false;
+  if constexpr (EX != 0) {
+    d = R(EX) * t[0];
+    any = true;
+  }
+  if constexpr (EY != 0) {
+    d = any ? d + R(EY) * t[1] : R(EY) * t[1];
+    any = true;
+  }
+  if constexpr (EZ != 0) d = any ? d + R(EZ) * t[2] : R(EZ) * t[2];
+  return d;
+}
+
 template <class L, class R, class M, bool CX, bool CY, bool CZ, bool PX>
 struct Gather {
   using E = Edges<L, R, CX, CY, CZ, PX>;
@@ -441,7 +477,7 @@ struct Gather {
       }
     } else if constexpr (kDeviations<R>) {
       // the value was stored against the source node's reference Tr(x - e_A)
-      v -= wa * (R(ex) * a.Tg[0] + R(ey) * a.Tg[1] + R(ez) * a.Tg[2]);
+      v -= wa * edot<ex, ey, ez>(a.Tg);
     }
     return v;
   }

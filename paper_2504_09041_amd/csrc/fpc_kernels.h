@@ -110,9 +110,13 @@ __device__ __forceinline__ dim3 block_order() {
 // Whether the rates form the standard set of rate_f / rate_g: the viscous
 // slots share one rate, the thermal first-order slots share one rate, and
 // every other slot in use relaxes at exactly 1.  Kernels built for that set
-// (STD = true) take those rates as compile-time constants.
+// (STD = true) take those rates as compile-time constants, and with them the
+// FP attractors and (on the paper's D2Q9 / D3Q15 thermal lattices, the only
+// ones where it differs) thermal option A.
 template <class R>
 inline bool standard_rates(const StepArgs<R>& a, int D, int Qg) {
+  if (a.c.model != 0) return false;
+  if (a.c.topt != 0 && Qg != (D == 2 ? 5 : 7)) return false;
   const int Qf = D == 2 ? kQ2 : kQ3;
   for (int k = 1; k < Qf; ++k) {
     const bool nu = D == 2 ? (k == 4 || k == 5) : (k == 4 || k == 5 || k == 6 || k == 8 || k == 9);
@@ -132,6 +136,31 @@ template <class R>
 hipError_t launch_step2d(const StepArgs<R>& a, int up, int tk, const double* T_init, int mode, hipStream_t s);
 template <class R>
 hipError_t launch_step3d(const StepArgs<R>& a, int up, int tk, const double* T_init, int mode, hipStream_t s);
+
+// Several steps in one cooperative launch (small grids, D2Q5 / D3Q7 pairs,
+// standard rate set, state below the non-temporal threshold): see
+// step_multi_kernel in fpc_step.hip.  The host fills everything but nwork,
+// which the launcher sets.
+struct MultiCtl {
+  unsigned* bar;        // full barrier's word (zero between launches)
+  int* err;             // sticky: a barrier wait ran out
+  unsigned* place;      // two XCD-placement words, used by alternate launches
+  unsigned* arrive;     // light barrier: one arrival word per working block
+  unsigned* release;    // light barrier: release word
+  unsigned spin_limit;  // polls before giving up
+  unsigned nwork;       // working blocks (the launch has nwork * kXcds), at most 64
+  int nsteps;
+  int seq;              // launch number (selects the placement word)
+  unsigned gen;         // light-barrier number of this launch's first step (unique per launch)
+};
+// Working blocks of 256 threads (64, 128 or 256 along x) that cover the grid.
+inline unsigned multi_work_blocks(int nx, int ny, int nz) {
+  const int bx = nx >= 256 ? 256 : (nx >= 128 ? 128 : 64);
+  const int by = 256 / bx;
+  return (unsigned)((nx + bx - 1) / bx) * (unsigned)((ny + by - 1) / by) * (unsigned)nz;
+}
+template <class R>
+hipError_t launch_step_multi(const StepArgs<R>& a, int dim, int up, const MultiCtl& c, hipStream_t s);
 
 // Adjoint kernels (fpc_adjoint.hip).  `a.src` is S_{n-1} (adjoint step) or
 // unused (adjoint of the initial collision).

@@ -124,38 +124,28 @@ __device__ __forceinline__ void collide_store(const StepArgs<R>& a, const M& m, 
     collide2d<R, UP, STD, L::Qg>(f, g, a.c, Tr, (Macros<R>*)nullptr);
   else
     collide3d<R, UP, STD, L::Qg>(f, g, a.c, Tr, (Macros<R>*)nullptr);
-  // the fused wall-Nusselt accumulation needs only the sum of the stored
-  // thermal values; it runs after the stores so that the populations are no
-  // longer live
-  const bool obj = a.obj.slot != nullptr;
-  double t = 0.0;
-  if (obj) {
-#pragma unroll
-    for (int q = 0; q < L::Qg; ++q) t += (double)g[q];
-  }
   auto cur = m.cursor(node);
 #pragma unroll
   for (int q = 0; q < L::Qf; ++q) m.template store_next<NT>(cur, f[q]);
 #pragma unroll
   for (int q = 0; q < L::Qg; ++q) m.template store_next<NT>(cur, g[q]);
-  if (obj) nu_accumulate<L, R>(a, x, y, z, t);
+  // the fused wall-Nusselt accumulation needs only the sum of the stored
+  // thermal values; it is formed after the stores, so that its branch does
+  // not split the collision (and its scheduling) in two
+  if (a.obj.slot != nullptr) {
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < L::Qg; ++q) t += (double)g[q];
+    nu_accumulate<L, R>(a, x, y, z, t);
+  }
 }
 
 
-// M: addressing policy (Buf32 when the buffer is below 4 GiB, else Glob64).
-// STD: the standard rate set (see rate_f / rate_g).
+// One node's update: pull S_{n-1} (m's source), collide, store S_n (m's
+// destination).  Lanes outside the box must not call it (the edge ballots
+// count the calling lanes only).
 template <class L, class R, class M, int UP, bool NT, bool STD>
-__global__ void __launch_bounds__(L::D == 2 ? FPC_BLOCK_2D : (sizeof(R) == 4 ? FPC_BLOCK_3DF : FPC_BLOCK_3D)) FPC_STEP_ATTR
-    step_kernel(StepArgs<R> a, unsigned total_bytes) {
-  // XCD-aware block order: contiguous ranges of rows per XCD in 2D; in 3D
-  // FP32, contiguous ranges of rows per XCD within each z plane (3D FP64
-  // measured 2% slower with it, and 3D with whole z slabs per XCD 1-3%)
-  const dim3 bi = block_order<L::D, sizeof(R)>();
-  const int x = bi.x * blockDim.x + threadIdx.x;
-  const int y = bi.y * blockDim.y + threadIdx.y;
-  const int z = bi.z;
-  if (x >= a.nx || y >= a.ny) return;
-  const M m(a.src, a.dst, total_bytes);
+__device__ __forceinline__ void step_node(const StepArgs<R>& a, const M& m, int x, int y, int z) {
   const unsigned node = node_of(x, y, z, a.nxp, a.ny);
   const R Tr = tref(a, x, y, z);
   R f[L::Qf], g[L::Qg];
@@ -174,6 +164,190 @@ __global__ void __launch_bounds__(L::D == 2 ? FPC_BLOCK_2D : (sizeof(R) == 4 ? F
     gather<L, R, M, true, true, L::D == 3>(a, m, x, y, z, node, Tr, f, g);
   }
   collide_store<L, R, M, UP, NT, STD>(a, m, x, y, z, node, Tr, f, g);
+}
+
+// M: addressing policy (Buf32 when the buffer is below 4 GiB, else Glob64).
+// STD: the standard rate set (see rate_f / rate_g).
+template <class L, class R, class M, int UP, bool NT, bool STD>
+__global__ void __launch_bounds__(L::D == 2 ? FPC_BLOCK_2D : (sizeof(R) == 4 ? FPC_BLOCK_3DF : FPC_BLOCK_3D)) FPC_STEP_ATTR
+    step_kernel(StepArgs<R> a, unsigned total_bytes) {
+  // XCD-aware block order: contiguous ranges of rows per XCD in 2D; in 3D
+  // FP32, contiguous ranges of rows per XCD within each z plane (3D FP64
+  // measured 2% slower with it, and 3D with whole z slabs per XCD 1-3%)
+  const dim3 bi = block_order<L::D, sizeof(R)>();
+  const int x = bi.x * blockDim.x + threadIdx.x;
+  const int y = bi.y * blockDim.y + threadIdx.y;
+  const int z = bi.z;
+  if (x >= a.nx || y >= a.ny) return;
+  const M m(a.src, a.dst, total_bytes);
+  step_node<L, R, M, UP, NT, STD>(a, m, x, y, z);
+}
+
+// ---------------------------------------------------------------------------
+// Several steps in one cooperative launch (small grids).
+//
+// On a grid of a few thousand nodes a step is a few microseconds of work, and
+// a launch per step costs about as much again (ramp-up, drain and the cache
+// maintenance between dependent launches).  This kernel runs nsteps steps in
+// one launch: every working block updates the same nodes each step, ping-
+// ponging between the two state buffers, and a grid-wide barrier separates
+// the steps.  Only every kXcds-th block of the launch works: with workgroups
+// dispatched round-robin over the XCDs, the working blocks then share one XCD
+// and its L2.
+//
+// Two ways to separate the steps.  The full barrier brackets the arrival
+// with agent-scope release / acquire fences (an L2 writeback and invalidate),
+// which is correct wherever the blocks run.  The light one (multi_sync_light)
+// only waits for the neighbour blocks, whose stores it reads, and reads the
+// next step with device-scope loads, which miss the per-CU L1; that is enough
+// when every working block runs on one XCD, whose L2 is then the point of
+// coherence.  Each launch checks the placement: before a first, full barrier
+// every working block ORs the bit of its XCD (hardware register XCC_ID) into
+// a word of this launch, and after it every block reads the word; one bit
+// set means one XCD and the light form for the rest of the launch, else the
+// full barrier throughout.
+//
+// The full barrier's word is self-resetting: each arrival adds 1, except the
+// first block, which adds 2^31 - (nwork - 1), so the top bit flips exactly
+// when the last block arrives and the low bits return to zero.  The light
+// form numbers its rounds (gen: unique per launch and step, increasing), so
+// its words need no reset.  The placement words alternate between launches,
+// and each launch clears the next one's.  A waiter gives up after spin_limit
+// polls (co-residency is what the cooperative launch guarantees, so this only
+// fires on a fault elsewhere): it sets *err and leaves, and every later wait
+// and launch sees *err and leaves at once.  The host reports the flag at the
+// next synchronising call.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ unsigned xcc_id() {
+  return __builtin_amdgcn_s_getreg((3 << 11) | 20) & 0xfu;  // hwreg(HW_REG_XCC_ID, 0, 4)
+}
+
+// Full barrier (any placement): agent-scope fences around one atomic
+// arrival word.
+__device__ __forceinline__ bool multi_barrier_full(const MultiCtl& c, unsigned lb) {
+  __shared__ int ok;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  if (threadIdx.x == 0 && threadIdx.y == 0) {
+    const unsigned inc = lb == 0 ? 0x80000000u - (c.nwork - 1u) : 1u;
+    const unsigned old = __hip_atomic_fetch_add(c.bar, inc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int good = 1;
+    unsigned spins = 0;
+    while (((__hip_atomic_load(c.bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ^ old) & 0x80000000u) == 0u) {
+      if (++spins > c.spin_limit || __hip_atomic_load(c.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+        __hip_atomic_store(c.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        good = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    ok = good;
+  }
+  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  return ok != 0;
+}
+
+// Light synchronisation (every working block on one XCD).  A step of a block
+// reads only the nodes of the blocks around it (one node across each face,
+// edge and corner, with the periodic wraps), and overwrites the buffer those
+// blocks read in the previous step; so before step s + 1 a block waits only
+// for its neighbour blocks to have finished step s.  Each block waits for its
+// stores to reach the L2 and writes its own arrival word (the step's number,
+// gen); the first wave then polls the arrival words of the neighbours, one
+// lane each (dep: this lane's neighbour block, or -1), until each shows gen
+// or later (a neighbour can be at most one step ahead).  The next step is
+// read with device-scope loads, which miss the per-CU L1.
+__device__ __forceinline__ bool multi_sync_light(const MultiCtl& c, unsigned lb, unsigned gen, int dep) {
+  __shared__ int ok;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  const unsigned tid = threadIdx.y * blockDim.x + threadIdx.x;
+  if (tid == 0) __hip_atomic_store(c.arrive + lb, gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (tid < 64) {  // the first wave
+    int good = 1;
+    unsigned spins = 0;
+    for (;;) {
+      bool here = true;
+      if (dep >= 0) here = (int)(__hip_atomic_load(c.arrive + dep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - gen) >= 0;
+      if (__all(here)) break;
+      if (++spins > c.spin_limit || __hip_atomic_load(c.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+        good = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    if (tid == 0) {
+      if (!good) __hip_atomic_store(c.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      ok = good;
+    }
+  }
+  __syncthreads();
+  return ok != 0;
+}
+
+// The neighbour block that lane `lane` (0..26: offsets -1..1 per axis) of the
+// first wave watches, or -1 (itself, outside a walled axis, or lane >= 27).
+__device__ __forceinline__ int multi_neighbour(unsigned lane, int bx, int by, int bz, int gx, int gy, int gz,
+                                               const int (&per)[3]) {
+  if (lane >= 27) return -1;
+  const int d[3] = {(int)(lane % 3) - 1, (int)((lane / 3) % 3) - 1, (int)(lane / 9) - 1};
+  if (d[0] == 0 && d[1] == 0 && d[2] == 0) return -1;
+  int b[3] = {bx + d[0], by + d[1], bz + d[2]};
+  const int g[3] = {gx, gy, gz};
+  for (int k = 0; k < 3; ++k) {
+    if (b[k] < 0 || b[k] >= g[k]) {
+      if (!per[k]) return -1;
+      b[k] = (b[k] + g[k]) % g[k];
+    }
+  }
+  return (b[2] * gy + b[1]) * gx + b[0];
+}
+
+template <class L, class R, int UP, bool STD>
+__global__ void __launch_bounds__(256) step_multi_kernel(StepArgs<R> a, unsigned total_bytes, MultiCtl c) {
+  if (blockIdx.x % kXcds != 0) return;
+  const unsigned lb = blockIdx.x / kXcds;  // logical block of the per-step grid
+  const unsigned gx = (a.nx + blockDim.x - 1) / blockDim.x, gy = (a.ny + blockDim.y - 1) / blockDim.y;
+  const int x = (int)((lb % gx) * blockDim.x + threadIdx.x);
+  const int y = (int)(((lb / gx) % gy) * blockDim.y + threadIdx.y);
+  const int z = (int)(lb / (gx * gy));
+  const bool live = x < a.nx && y < a.ny;
+  // device-scope loads: the previous step may have been written by another CU
+  using M = Buf32<R, L::Qf + L::Qg, 16>;
+  if (__hip_atomic_load(c.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
+  __shared__ int light;
+  const bool t0 = threadIdx.x == 0 && threadIdx.y == 0;
+  unsigned* const place = c.place + (c.seq & 1);
+  if (t0) {
+    if (lb == 0) __hip_atomic_store(c.place + ((c.seq + 1) & 1), 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_or(place, 1u << xcc_id(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  if (!multi_barrier_full(c, lb)) return;
+  if (t0) {
+    const unsigned mask = __hip_atomic_load(place, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    light = (mask & (mask - 1u)) == 0u;
+  }
+  __syncthreads();
+  const bool one_xcd = light != 0;
+  const unsigned tid = threadIdx.y * blockDim.x + threadIdx.x;
+  const int dep = multi_neighbour(tid, (int)(lb % gx), (int)((lb / gx) % gy), z, (int)gx, (int)gy, a.nz, a.per);
+  for (int s = 0; s < c.nsteps; ++s) {
+    if (live) {
+      // the node's coordinates pass through an empty asm so that what the
+      // step derives from them is recomputed every step instead of being
+      // hoisted out of the loop and held in registers across it
+      int xs = x, ys = y;
+      asm volatile("" : "+v"(xs), "+v"(ys));
+      const bool odd = s & 1;
+      const M m(odd ? a.dst : a.src, odd ? const_cast<R*>(a.src) : a.dst, total_bytes);
+      step_node<L, R, M, UP, false, STD>(a, m, xs, ys, z);
+    }
+    if (s + 1 < c.nsteps && !(one_xcd ? multi_sync_light(c, lb, c.gen + (unsigned)s, dep)
+                                      : multi_barrier_full(c, lb)))
+      return;
+  }
 }
 
 // Initial state: the collision of f = w rho0, g = w^T T_init at every node.
@@ -237,6 +411,20 @@ hipError_t launch_up(const StepArgs<R>& a, const double* T_init, int mode, hipSt
   return hipGetLastError();
 }
 
+template <class L, class R, int UP>
+hipError_t launch_multi_up(const StepArgs<R>& a, const MultiCtl& c0, hipStream_t s) {
+  const int bx = a.nx >= 256 ? 256 : (a.nx >= 128 ? 128 : 64);
+  const int by = 256 / bx;
+  MultiCtl c = c0;
+  c.nwork = multi_work_blocks(a.nx, a.ny, a.nz);
+  StepArgs<R> args = a;
+  unsigned tb = (unsigned)((double)a.nxp * a.ny * a.nz * (L::Qf + L::Qg) * sizeof(R));
+  void* kargs[] = {(void*)&args, (void*)&tb, (void*)&c};
+  const dim3 grid(c.nwork * kXcds, 1, 1), block(bx, by, 1);
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&step_multi_kernel<L, R, UP, true>), grid, block,
+                                    kargs, 0, s);
+}
+
 }  // namespace
 
 // tk: thermal lattice, 0 = D2Q5 / D3Q7, 1 = the paper's D2Q9 / D3Q15 (FP64 only)
@@ -268,9 +456,28 @@ hipError_t launch_step3d(const StepArgs<R>& a, int up, int tk, const double* T_i
   return hipErrorInvalidValue;
 }
 
+// 2D in either precision and 3D FP32 (the 3D FP64 step would hold more than
+// 256 registers per lane inside the step loop; it keeps per-step launches).
+template <class R>
+hipError_t launch_step_multi(const StepArgs<R>& a, int dim, int up, const MultiCtl& c, hipStream_t s) {
+  if (dim == 2) return up == 0 ? launch_multi_up<Lat2, R, 0>(a, c, s) : launch_multi_up<Lat2, R, 1>(a, c, s);
+  if constexpr (sizeof(R) == 8) {
+    return hipErrorNotSupported;
+  } else {
+    switch (up) {
+      case 0: return launch_multi_up<Lat3, R, 0>(a, c, s);
+      case 1: return launch_multi_up<Lat3, R, 1>(a, c, s);
+      default: return launch_multi_up<Lat3, R, 2>(a, c, s);
+    }
+  }
+}
+
 template hipError_t launch_step2d<double>(const StepArgs<double>&, int, int, const double*, int, hipStream_t);
 template hipError_t launch_step2d<float>(const StepArgs<float>&, int, int, const double*, int, hipStream_t);
 template hipError_t launch_step3d<double>(const StepArgs<double>&, int, int, const double*, int, hipStream_t);
 template hipError_t launch_step3d<float>(const StepArgs<float>&, int, int, const double*, int, hipStream_t);
+
+template hipError_t launch_step_multi<double>(const StepArgs<double>&, int, int, const MultiCtl&, hipStream_t);
+template hipError_t launch_step_multi<float>(const StepArgs<float>&, int, int, const MultiCtl&, hipStream_t);
 
 }  // namespace fpc

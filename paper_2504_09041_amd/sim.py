@@ -174,6 +174,18 @@ class Simulation:
     def step(self, n=1):
         A.call("fpc_step", self._h, int(n))
 
+    def set_multistep(self, enable):
+        """Allow (True, the default) or forbid fpc_step's single-launch
+        multi-step path on small grids."""
+        A.call("fpc_set_multistep", self._h, 1 if enable else 0)
+
+    @property
+    def multistep_launches(self):
+        """Multi-step (cooperative) launches fpc_step has made so far."""
+        v = ctypes.c_longlong()
+        A.call("fpc_multistep_launches", self._h, ctypes.byref(v))
+        return v.value
+
     def step_nusselt(self, n, face, weight, acc):
         """Advance n steps; after each, acc[0] += weight * <Nu>_face of the
         new time level (acc: one-element FP64 device tensor)."""

@@ -191,3 +191,41 @@ def full_hashed_state(shape, Qf, Qg, wf, wg, seed, device, amp=1e-2, Tamp=0.5):
 
 def finite_and_close(x, tol):
     return math.isfinite(x) and x <= tol
+
+
+def pull_transpose(prm, mu_f, mu_g):
+    """pull^T mu: the transpose of the oracle's streaming step (the pull with
+    its wall rules, an affine map of the state, so its transpose does not
+    depend on the state) applied to mu, through autograd."""
+    lf, lg = prm.lattices
+    Sf = torch.zeros_like(mu_f, requires_grad=True)
+    Sg = torch.zeros_like(mu_g, requires_grad=True)
+    pf = osim.pull(Sf, lf, prm, thermal=False)
+    pg = osim.pull(Sg, lg, prm, thermal=True)
+    L = (mu_f * pf).sum() + (mu_g * pg).sum()
+    gf, gg = torch.autograd.grad(L, [Sf, Sg])
+    return gf, gg
+
+
+def adjoint_step_reference(prm, f0, g0, mu, dJdT, ke, face=None, theta=None):
+    """Oracle reference of one adjoint step in the form the library carries
+    the adjoint: from mu_n (adjoint of the pulled populations of step n + 1)
+    and the seed of level n (weights dJdT on T_n, ke on the kinetic energy),
+    mu_{n-1} = collide_n^T (pull^T mu_n + seed) at the pulled populations of
+    S_{n-1} = (f0, g0), and dJ/dtheta of the Dirichlet profile theta of
+    `face` (or None).  Returns (mu_{n-1} as one (Qf + Qg, ...) tensor,
+    dtheta or None)."""
+    Qf = f0.shape[0]
+    lam_f, lam_g = pull_transpose(prm, mu[:Qf], mu[Qf:])
+    lf, lg = prm.lattices
+    th = theta.clone().requires_grad_(True) if theta is not None else None
+    fp = osim.pull(f0, lf, prm, thermal=False)
+    gp = osim.pull(g0, lg, prm, thermal=True, wall_T={face: th} if th is not None else None)
+    fpl = fp.detach().requires_grad_(True)
+    gpl = gp.detach().requires_grad_(True)
+    fn, gn, mac = osim.collide(prm, fpl, gpl)
+    L = (lam_f * fn).sum() + (lam_g * gn).sum() + (dJdT * mac["T"]).sum() + ke * osim.kinetic_energy(mac)
+    mf, mg = torch.autograd.grad(L, [fpl, gpl])
+    dth = torch.autograd.grad(gp, th, grad_outputs=mg)[0] if th is not None else None
+    return torch.cat([mf, mg], 0), dth
+

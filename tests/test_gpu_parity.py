@@ -130,6 +130,8 @@ def test_config1_full_run_matches_oracle():
     sim = G.make_sim(cfg, "f64")
     sim.init(T.cuda())
     sim.step(cfg["steps"])
+    # the grid runs fpc_step's single-launch multi-step path: 1024 + 976 steps
+    assert sim.multistep_launches == 2
     f, g = G.read_state(sim)
     prm = params_from_config(cfg)
     fo, go = osim.init_state(prm, T)
