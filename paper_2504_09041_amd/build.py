@@ -33,6 +33,17 @@ HIPCC_FLAGS = [
 ]
 
 
+# Per-source flags.  The adjoint kernels assume finite arithmetic (no NaN,
+# infinity or signed-zero semantics): their generic reverse pass multiplies
+# and adds many moments that are zero by the structure of the standard rate
+# set, and only these assumptions let the compiler drop that arithmetic
+# (3D FP32 adjoint: 134 -> 113 VGPRs, 12% fewer instructions).  For finite
+# inputs the results are those of IEEE evaluation up to the sign of zeros.
+SOURCE_FLAGS = {
+    "fpc_adjoint.hip": ["-fno-honor-nans", "-fno-honor-infinities", "-fno-signed-zeros"],
+}
+
+
 def hipcc():
     for cand in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", shutil.which("hipcc")):
         if cand and os.path.exists(cand):
@@ -42,7 +53,8 @@ def hipcc():
 
 def _compile(src, extra, verbose):
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [hipcc(), *HIPCC_FLAGS, *extra, "-I", CSRC, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [hipcc(), *HIPCC_FLAGS, *SOURCE_FLAGS.get(src, []), *extra, "-I", CSRC, "-c", os.path.join(CSRC, src),
+           "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -188,18 +188,25 @@ __device__ __forceinline__ void forward(const R* f, const R* g, const CollParams
   using M = MS<D>;
   constexpr int NM = M::NM;
   constexpr R cs2 = R(1) / R(3);
-  R rho = R(0), j[3] = {R(0), R(0), R(0)};
+  // (each sum starts from its first term: an explicit 0 + x, or 0 * x below,
+  // would cost an IEEE operation that cannot be dropped)
+  R rho = f[M::pop(0)], j[3] = {R(0), R(0), R(0)};
+  bool hj[3] = {false, false, false};
 #pragma unroll
   for (int i = 0; i < NM; ++i) {
     const R v = f[M::pop(i)];
-    rho += v;
-    if (M::ma(i) != 1) j[0] += M::ma(i) == 2 ? v : -v;
-    if (M::mb(i) != 1) j[1] += M::mb(i) == 2 ? v : -v;
-    if (D == 3 && M::mc(i) != 1) j[2] += M::mc(i) == 2 ? v : -v;
-  }
-  R T = R(0);
+    if (i > 0) rho += v;
 #pragma unroll
-  for (int q = 0; q < 2 * D + 1; ++q) T += g[q];
+    for (int ax = 0; ax < D; ++ax) {
+      const int m = M::m(i, ax);
+      if (m == 1) continue;
+      j[ax] = hj[ax] ? (m == 2 ? j[ax] + v : j[ax] - v) : (m == 2 ? v : -v);
+      hj[ax] = true;
+    }
+  }
+  R T = g[0];
+#pragma unroll
+  for (int q = 1; q < 2 * D + 1; ++q) T += g[q];
   const R Fb = c.gbeta * (T - c.T0);
   const R ir = R(1) / rho;
   t.rho = rho;
@@ -225,7 +232,8 @@ __device__ __forceinline__ void forward(const R* f, const R* g, const CollParams
         t.kt[i] = R(0.5) * Fa;
       } else {
         const R w = om[M::slot(i)];
-        t.kt[i] = t.k[i] - w * t.k[i] + (R(1) - R(0.5) * w) * Fa;
+        t.kt[i] = t.k[i] - w * t.k[i];
+        if (ax == UP) t.kt[i] += (R(1) - R(0.5) * w) * Fa;
       }
     }
     if (s == 2 && (M::ma(i) == 1 || M::mb(i) == 1 || M::mc(i) == 1))
@@ -415,8 +423,12 @@ __device__ __forceinline__ void reverse(const Tape<R, D>& t, const CollParams<R>
     for (int i = 0; i < NM; ++i)
       if (M::order(i) == s)
 #pragma unroll
-        for (int ax = 0; ax < D; ++ax)
-          if (M::m(i, ax) > 0) ub[ax] -= kp[i] * R(M::m(i, ax)) * kpre(M::down(i, ax));
+        for (int ax = 0; ax < D; ++ax) {
+          if (M::m(i, ax) == 0) continue;
+          const int dn = M::down(i, ax);
+          if (M::order(dn) == 1 && M::m(dn, UP) != 1) continue;  // kappa_{e_ax} = 0 off the up axis
+          ub[ax] -= kp[i] * R(M::m(i, ax)) * kpre(dn);
+        }
   };
 #pragma unroll
   for (int s = 2 * D; s >= 3; --s) {
@@ -513,8 +525,9 @@ __device__ __forceinline__ void reverse(const Tape<R, D>& t, const CollParams<R>
 #pragma unroll
   for (int i = 0; i < NM; ++i) {
     R v = kp[i] + rhob;
-    v += R(M::ma(i) - 1) * jb[0] + R(M::mb(i) - 1) * jb[1];
-    if (D == 3) v += R(M::mc(i) - 1) * jb[2];
+#pragma unroll
+    for (int ax = 0; ax < D; ++ax)
+      if (M::m(i, ax) != 1) v += R(M::m(i, ax) - 1) * jb[ax];
     fb[M::pop(i)] = v;
   }
   // T enters through the buoyancy force

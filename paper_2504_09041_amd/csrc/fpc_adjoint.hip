@@ -62,11 +62,15 @@ __device__ __forceinline__ void add_seed(const adj::Tape<R, D>& t, const CollPar
     R u2 = R(0);
 #pragma unroll
     for (int ax = 0; ax < D; ++ax) u2 += t.u[ax] * t.u[ax];
+    const R base = R(-0.5) * u2;
 #pragma unroll
     for (int q = 0; q < Lk::Qf; ++q) {
-      R eu = R(Lk::ex(q)) * t.u[0] + R(Lk::ey(q)) * t.u[1];
-      if (D == 3) eu += R(Lk::ez(q)) * t.u[2];
-      fb[q] += kw * (R(-0.5) * u2 + eu);
+      // base + e_q . u over the non-zero components of e_q
+      R v = base;
+      if (Lk::ex(q) != 0) v = Lk::ex(q) > 0 ? v + t.u[0] : v - t.u[0];
+      if (Lk::ey(q) != 0) v = Lk::ey(q) > 0 ? v + t.u[1] : v - t.u[1];
+      if (D == 3 && Lk::ez(q) != 0) v = Lk::ez(q) > 0 ? v + t.u[2] : v - t.u[2];
+      fb[q] += kw * v;
     }
     gs += kw * (R(-0.5) * c.gbeta * t.u[UP]);
   }
