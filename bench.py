@@ -562,8 +562,11 @@ def main():
         # FP32 (forward step of the adjoint workload)
         extra["dhc3d_64_f64"] = time_workload("dhc3d_256", "f64", 5 * n3, w3, shape=(64, 64, 64))
         extra["mixed2d_512_f32dev"] = time_workload("mixed2d_512", "f32dev", n2, w2)
-        # the 64 x 64 cavity: launch-bound (4096 nodes per launch)
+        # the 64 x 64 cavity: latency-bound (4096 nodes); fpc_step runs it with
+        # up to 1024 steps per cooperative launch, and here also with one
+        # launch per step
         extra["dhc2d_64_f64"] = time_workload("dhc2d_64", "f64", n2, w2)
+        extra["dhc2d_64_f64_per_step_launches"] = time_workload("dhc2d_64", "f64", n2, w2, multistep=False)
         extra["copy_4GiB"] = copy_bandwidth(4096, 20)
         # the paper's own thermal lattices (FP64), and the MCM comparator on the
         # 2D workload: same step structure, more (or the same) bytes
