@@ -257,6 +257,16 @@ int fpc_step(fpc_sim* s, int nsteps);
  */
 int fpc_set_multistep(fpc_sim* s, int enable);
 
+/*
+ * Polls a barrier wait of the multi-step path may repeat before it gives up
+ * and raises the error flag (default 2^22, about a second; 0: give up at the
+ * first unmet check).  A small value exercises the failure path from the
+ * host: the waits end early, every block leaves its launch, and the next
+ * fpc_diagnostics reports FPC_ERR_HIP (the state is then invalid and the path
+ * off for this sim).  Errors: FPC_ERR_ARG (NULL).
+ */
+int fpc_set_multistep_wait_limit(fpc_sim* s, unsigned polls);
+
 /* Number of multi-step (cooperative) launches fpc_step has made on this sim. */
 int fpc_multistep_launches(const fpc_sim* s, long long* launches);
 

@@ -46,7 +46,8 @@ FPC_TREF_AUTO = -2
 EXPORTED = (
     "fpc_version", "fpc_last_error", "fpc_params_bytes", "fpc_params_default", "fpc_params_natural", "fpc_params_mixed",
     "fpc_params_conduction_reference", "fpc_storage_reference",
-    "fpc_state_bytes", "fpc_create", "fpc_destroy", "fpc_set_stream", "fpc_set_multistep", "fpc_multistep_launches",
+    "fpc_state_bytes", "fpc_create", "fpc_destroy", "fpc_set_stream", "fpc_set_multistep", "fpc_set_multistep_wait_limit",
+    "fpc_multistep_launches",
     "fpc_init", "fpc_step", "fpc_step_nusselt", "fpc_step_from",
     "fpc_get_step", "fpc_macros", "fpc_diagnostics", "fpc_nusselt_local", "fpc_diagnostics_noalloc", "fpc_save", "fpc_load", "fpc_export_fp64",
     "fpc_import_fp64", "fpc_current_buffer", "fpc_nusselt_seed", "fpc_adjoint_step", "fpc_adjoint_init",
@@ -118,6 +119,7 @@ def load():
         "fpc_destroy": (i, [vp]),
         "fpc_set_stream": (i, [vp, vp]),
         "fpc_set_multistep": (i, [vp, i]),
+        "fpc_set_multistep_wait_limit": (i, [vp, ctypes.c_uint]),
         "fpc_multistep_launches": (i, [vp, ctypes.POINTER(ll)]),
         "fpc_init": (i, [vp, vp]),
         "fpc_step": (i, [vp, i]),

@@ -41,6 +41,7 @@ struct fpc_sim {
   int multi_ok;         // the device supports cooperative launches
   int multi_used;       // a multi-step launch has been made since the flag was last read
   long long multi_launches;  // multi-step launches made by this sim
+  unsigned multi_spin_limit;  // polls of a barrier wait before it gives up
 };
 
 namespace {
@@ -294,7 +295,7 @@ int launch_multi(fpc_sim* s, int nsteps) {
   c.place = s->multi_ctl + 2;
   c.release = s->multi_ctl + 4;
   c.arrive = s->multi_ctl + 8;  // kMultiMaxWork words
-  c.spin_limit = kMultiSpinLimit;
+  c.spin_limit = s->multi_spin_limit;
   c.nwork = 0;
   c.nsteps = nsteps;
   c.seq = (int)(s->multi_launches & 1);
@@ -585,6 +586,7 @@ int fpc_create(const fpc_params* p, void* bufA, void* bufB, void* hip_stream, fp
   if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, s->device) != hipSuccess) coop = 0;
   s->multi_ok = coop != 0;
   s->multi_enabled = 1;
+  s->multi_spin_limit = kMultiSpinLimit;
   *out = s;
   return FPC_OK;
 }
@@ -609,6 +611,12 @@ int fpc_set_multistep(fpc_sim* s, int enable) {
   if (!s) return fail(FPC_ERR_ARG, "sim is NULL");
   if (enable != 0 && enable != 1) return fail(FPC_ERR_ARG, "enable must be 0 or 1");
   s->multi_enabled = enable;
+  return FPC_OK;
+}
+
+int fpc_set_multistep_wait_limit(fpc_sim* s, unsigned polls) {
+  if (!s) return fail(FPC_ERR_ARG, "sim is NULL");
+  s->multi_spin_limit = polls;
   return FPC_OK;
 }
 

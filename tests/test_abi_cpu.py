@@ -220,6 +220,7 @@ def test_null_and_invalid_arguments_fail_before_any_launch():
     assert lib.fpc_destroy(None) == A.FPC_ERR_ARG
     assert lib.fpc_set_stream(None, None) == A.FPC_ERR_ARG
     assert lib.fpc_set_multistep(None, 1) == A.FPC_ERR_ARG
+    assert lib.fpc_set_multistep_wait_limit(None, 1) == A.FPC_ERR_ARG
     assert lib.fpc_multistep_launches(None, ctypes.byref(ll)) == A.FPC_ERR_ARG
     assert lib.fpc_init(None, vp(256)) == A.FPC_ERR_ARG
     assert lib.fpc_step(None, 1) == A.FPC_ERR_ARG

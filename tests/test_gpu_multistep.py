@@ -117,3 +117,42 @@ def test_multistep_path_skips_general_rates():
     sim.step(3)
     assert sim.multistep_launches == 0
     sim.close()
+
+
+def test_multistep_wait_limit_reports_the_failure_and_falls_back():
+    """Failure path of the multi-step launch, forced from the host: with a
+    wait limit of 0 a barrier wait gives up at its first unmet check (over
+    1000 steps some block always finishes a step before a neighbour), raises
+    the error flag, and every block leaves its launch normally.  The next
+    diagnostics call reports FPC_ERR_HIP; the sim then runs one launch per
+    step, bit-identical to a sim that never used the path."""
+    import ctypes
+
+    import workloads
+    from paper_2504_09041_amd import _abi as A
+
+    lib = A.load()
+    cfg = workloads.config("dhc2d_64")
+    T = G.initial_T(cfg).cuda()
+    sim = G.make_sim(cfg, "f64")
+    sim.init(T)
+    A.check(lib.fpc_set_multistep_wait_limit(sim.handle, 0), "fpc_set_multistep_wait_limit")
+    sim.step(1000)
+    d = [ctypes.c_double() for _ in range(4)]
+    rc = lib.fpc_diagnostics(sim.handle, 0, *[ctypes.byref(v) for v in d])
+    assert rc == A.FPC_ERR_HIP
+    assert "barrier" in A.last_error()
+    # the path is off now: a fresh start runs one launch per step
+    n0 = sim.multistep_launches
+    sim.init(T)
+    sim.step(100)
+    assert sim.multistep_launches == n0
+    assert not sim.diagnostics(0)["unstable"]
+    ref = G.make_sim(cfg, "f64")
+    ref.set_multistep(False)
+    ref.init(T)
+    ref.step(100)
+    assert torch.equal(sim.export_fp64(), ref.export_fp64())
+    sim.close()
+    ref.close()
+
