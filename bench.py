@@ -54,7 +54,7 @@ def _args():
                     help="forbid fpc_step's single-launch multi-step path (small grids)")
     ap.add_argument("--cpu-sample-steps", type=int, default=24)
     ap.add_argument("--mode", choices=("bench", "single", "copy", "pmc-summary", "trace-summary", "precision", "adjoint",
-                                       "objective"),
+                                       "objective", "diagnostics"),
                     default="bench")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--fetch", help="rocprofv3 --pmc FETCH_SIZE output dir (kernel run)")
@@ -427,6 +427,55 @@ def objective_cost(name, nsteps, reps=3):
             "target_ratio": 1.3}
 
 
+def diagnostics_cost(name, precision, reps=20, rounds=3):
+    """Cost of the diagnostics of a step: a plain step, a step whose kernel
+    also reduces the diagnostics of the state it writes (fpc_step_diagnostics,
+    1 step per call), and a plain step followed by the separate diagnostics
+    pass over the stored state (fpc_diagnostics_noalloc, which reads the state
+    once more); HIP events on the stream, best of `rounds`."""
+    import ctypes
+
+    import torch
+
+    import workloads
+    from paper_2504_09041_amd import _abi as A
+    from paper_2504_09041_amd.sim import Simulation
+
+    cfg = workloads.config(name)
+    sim = Simulation(workload_params(cfg, precision))
+    sim.init(torch.tensor(workloads.initial_temperature(cfg), device="cuda"))
+    sim.step(10)
+    lib = A.load()
+    face = cfg["nu_face"]
+    out = torch.zeros(5, dtype=torch.float64, device="cuda")
+    pout = ctypes.c_void_p(out.data_ptr())
+    ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+    best = {}
+    for kind in ("plain", "fused", "separate") * rounds:
+        e0, e1 = ev(), ev()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            if kind == "plain":
+                sim.step(1)
+            elif kind == "fused":
+                sim.step_diagnostics(1, face, out)
+            else:
+                sim.step(1)
+                A.check(lib.fpc_diagnostics_noalloc(sim.handle, face, pout), "fpc_diagnostics_noalloc")
+        e1.record()
+        torch.cuda.synchronize()
+        best[kind] = min(best.get(kind, float("inf")), e0.elapsed_time(e1) / reps)
+    d = out.cpu().tolist()
+    sim.close()
+    return {"workload": name, "precision": precision, "shape": list(cfg["shape"]),
+            "plain_step_ms": best["plain"], "fused_step_diagnostics_ms": best["fused"],
+            "step_then_diagnostics_pass_ms": best["separate"],
+            "fused_over_plain": best["fused"] / best["plain"],
+            "separate_over_plain": best["separate"] / best["plain"],
+            "last": {"nu": d[0], "ke": d[1], "sumT": d[2], "umax": d[3], "non_finite": d[4]}}
+
+
 def _cpu_model():
     try:
         with open("/proc/cpuinfo") as fh:
@@ -542,6 +591,9 @@ def main():
     if a.mode == "objective":
         print(json.dumps(objective_cost(a.workload, a.steps)))
         return
+    if a.mode == "diagnostics":
+        print(json.dumps(diagnostics_cost(a.workload, a.precision)))
+        return
     head = time_workload("dhc3d_256", "f32dev", a.steps, a.warmup)
     extra = {}
     if not a.no_extra:
@@ -576,6 +628,9 @@ def main():
         # the wall-Nusselt objective accumulated during the forward run of the
         # lid-driven cavity's J window (steps 5000-10000)
         extra["objective_forward_mixed2d_512"] = objective_cost("mixed2d_512", 5001)
+        # a step that also returns the diagnostics of the state it writes,
+        # against a plain step and a step plus the separate diagnostics pass
+        extra["diagnostics_dhc3d_256_f32dev"] = diagnostics_cost("dhc3d_256", "f32dev")
         # FP32 against FP64 over the workloads' full runs (the precision half
         # of the metric): worst errors of T and of the wall Nu, pass flags
         st = precision_study("rb2d_1024x512", 50000, 5000)

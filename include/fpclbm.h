@@ -218,7 +218,9 @@ int fpc_state_bytes(const fpc_params* p, size_t* bytes_per_buffer, size_t* row_s
  * Create a simulation that borrows two device buffers of at least
  * fpc_state_bytes() bytes each (256-byte aligned) and a hipStream_t (may be
  * NULL for the null stream).  Parameters are copied and validated.  Allocates
- * only small reduction scratch.  *out is set on success.
+ * only reduction scratch: a few KiB, the wall-Nusselt slots (two doubles per
+ * wall row of each tile) and the per-tile partials of fpc_step_diagnostics
+ * (four doubles per 64-node tile, 0.5 B per node).  *out is set on success.
  */
 int fpc_create(const fpc_params* p, void* bufA, void* bufB, void* hip_stream, fpc_sim** out);
 
@@ -285,6 +287,28 @@ int fpc_multistep_launches(const fpc_sim* s, long long* launches);
  * 0..5, weight not finite), FPC_ERR_STATE (periodic face, or a z face in 2D).
  */
 int fpc_step_nusselt(fpc_sim* s, int nsteps, int wall_face, double weight, double* acc);
+
+/*
+ * Advance nsteps >= 1 time steps as fpc_step and return the diagnostics of
+ * the new time level without a separate pass over the state: the kernel of
+ * the last step forms, after its stores, each node's FP64 macros from the
+ * values it stores, exactly as fpc_diagnostics forms them from the stored
+ * state (rho = rho_r + sum f, T = T_r + sum g, rho u = sum f e - F/2), and
+ * reduces them over its 64-node tile; two small kernels then reduce the
+ * tiles in a fixed order.  Writes out[0..4] = (mean wall Nusselt number on
+ * wall_face by the fused accumulation of fpc_step_nusselt, or 0 for
+ * wall_face = -1; KE; sum T; max |u|; number of nodes with a non-finite
+ * macro), the layout of fpc_diagnostics_noalloc, to `out` (device pointer,
+ * 5 FP64 values).  The values equal those fpc_diagnostics returns at the new
+ * time level up to the order of the FP64 sums (relative differences of a few
+ * ulps of the sum).  Asynchronous: no host synchronisation, and the watchdog
+ * (out[4] != 0 or out[3] > 0.5) is left to the caller.  Uses the per-tile
+ * partials allocated by fpc_create and the library's reduction scratch, so
+ * calls on one sim are ordered by its stream.  Errors: FPC_ERR_ARG (NULL,
+ * nsteps < 1, wall_face outside -1..5), FPC_ERR_STATE (periodic face, or a z
+ * face in 2D), FPC_ERR_HIP (launch failure).
+ */
+int fpc_step_diagnostics(fpc_sim* s, int nsteps, int wall_face, double* out);
 
 /*
  * One time step from a caller-owned state into another caller-owned state:

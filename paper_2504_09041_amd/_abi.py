@@ -48,7 +48,7 @@ EXPORTED = (
     "fpc_params_conduction_reference", "fpc_storage_reference",
     "fpc_state_bytes", "fpc_create", "fpc_destroy", "fpc_set_stream", "fpc_set_multistep", "fpc_set_multistep_wait_limit",
     "fpc_multistep_launches",
-    "fpc_init", "fpc_step", "fpc_step_nusselt", "fpc_step_from",
+    "fpc_init", "fpc_step", "fpc_step_nusselt", "fpc_step_diagnostics", "fpc_step_from",
     "fpc_get_step", "fpc_macros", "fpc_diagnostics", "fpc_nusselt_local", "fpc_diagnostics_noalloc", "fpc_save", "fpc_load", "fpc_export_fp64",
     "fpc_import_fp64", "fpc_current_buffer", "fpc_nusselt_seed", "fpc_adjoint_step", "fpc_adjoint_init",
 )
@@ -124,6 +124,7 @@ def load():
         "fpc_init": (i, [vp, vp]),
         "fpc_step": (i, [vp, i]),
         "fpc_step_nusselt": (i, [vp, i, i, d, vp]),
+        "fpc_step_diagnostics": (i, [vp, i, i, vp]),
         "fpc_step_from": (i, [vp, vp, vp]),
         "fpc_params_bytes": (ctypes.c_size_t, []),
         "fpc_get_step": (i, [vp, ctypes.POINTER(ll)]),

@@ -33,6 +33,8 @@ struct fpc_sim {
   double* result_host;  // pinned, 8 doubles
   double* nu_slot;      // per-tile partial sums of the fused wall-Nusselt accumulation (kept zero between calls)
   size_t nu_slot_elems;
+  double* diag_part;    // per-tile partials of the fused diagnostics (4 doubles per tile)
+  size_t ntiles;
   int device;
   // single-launch multi-step path (small grids)
   unsigned* multi_ctl;  // device: [0] barrier word, [1] error flag, [2..3] placement words,
@@ -240,18 +242,20 @@ StepArgs<R> make_args(const fpc_sim* s, const void* src, void* dst) {
 }
 
 int launch_update(fpc_sim* s, const void* src, void* dst, const double* T_init, int mode,
-                  const NuAcc* obj = nullptr) {
+                  const NuAcc* obj = nullptr, const DiagAcc* dg = nullptr) {
   hipError_t e;
   const int up = s->p.up_axis;
   const int tk = paper_thermal(s->p.lattice) ? 1 : 0;
   if (s->p.precision == FPC_FP64) {
     StepArgs<double> a = make_args<double>(s, src, dst);
     if (obj) a.obj = *obj;
+    if (dg) a.dg = *dg;
     e = s->dim == 2 ? launch_step2d<double>(a, up, tk, T_init, mode, s->stream)
                     : launch_step3d<double>(a, up, tk, T_init, mode, s->stream);
   } else {
     StepArgs<float> a = make_args<float>(s, src, dst);
     if (obj) a.obj = *obj;
+    if (dg) a.dg = *dg;
     e = s->dim == 2 ? launch_step2d<float>(a, up, tk, T_init, mode, s->stream)
                     : launch_step3d<float>(a, up, tk, T_init, mode, s->stream);
   }
@@ -572,10 +576,13 @@ int fpc_create(const fpc_params* p, void* bufA, void* bufB, void* hip_stream, fp
   }
   e = hipMalloc(&s->nu_slot, s->nu_slot_elems * sizeof(double));
   if (e == hipSuccess) e = launch_fill_zero(s->nu_slot, s->nu_slot_elems, s->stream);
+  s->ntiles = padded_nodes(p) / 64;
+  if (e == hipSuccess) e = hipMalloc(&s->diag_part, s->ntiles * 4 * sizeof(double));
   if (e == hipSuccess) e = hipMalloc(&s->multi_ctl, kMultiCtlBytes);
   if (e == hipSuccess) e = launch_fill_zero(reinterpret_cast<double*>(s->multi_ctl), kMultiCtlBytes / 8, s->stream);
   if (e != hipSuccess) {
     if (s->multi_ctl) (void)hipFree(s->multi_ctl);
+    if (s->diag_part) (void)hipFree(s->diag_part);
     if (s->nu_slot) (void)hipFree(s->nu_slot);
     (void)hipFree(s->scratch);
     (void)hipHostFree(s->result_host);
@@ -598,6 +605,8 @@ int fpc_destroy(fpc_sim* s) {
   hipError_t e3 = hipHostFree(s->result_host);
   hipError_t e4 = hipFree(s->nu_slot);
   hipError_t e5 = hipFree(s->multi_ctl);
+  if (e4 == hipSuccess) e4 = e5;
+  e5 = hipFree(s->diag_part);
   if (e4 == hipSuccess) e4 = e5;
   delete s;
   if (e1 != hipSuccess) return hipfail(e1, "hipStreamSynchronize");
@@ -641,6 +650,27 @@ int fpc_init(fpc_sim* s, const double* T_init) {
   return FPC_OK;
 }
 
+// Arguments of the wall-Nusselt accumulation fused into a step: each step
+// adds weight <Nu>_face of the state it writes to the per-tile slots.
+NuAcc nu_acc_of(const fpc_sim* s, int wall_face, double weight) {
+  const fpc_params& p = s->p;
+  const int n[3] = {p.nx, p.ny, p.nz};
+  const int k = wall_face >> 1;
+  const double M = (double)n[(k + 1) % 3] * n[(k + 2) % 3];
+  NuAcc o;
+  std::memset(&o, 0, sizeof o);
+  o.slot = s->nu_slot;
+  o.face = wall_face;
+  o.nk = n[k];
+  o.nt = n[k == 0 ? 1 : 0];  // faster tangential axis
+  o.ns = n[k == 2 ? 1 : 2];  // slower tangential axis
+  o.scale = -((double)n[k] / p.dT_ref) * weight / M;
+  o.Tw = p.wall_T[wall_face];
+  o.Tprof = p.wall_T_profile[wall_face];
+  thermal_reference(p, o.T_o, o.Tg);
+  return o;
+}
+
 int fpc_step(fpc_sim* s, int nsteps) {
   if (!s) return fail(FPC_ERR_ARG, "sim is NULL");
   if (nsteps < 0) return fail(FPC_ERR_ARG, "nsteps < 0");
@@ -670,20 +700,7 @@ int fpc_step_nusselt(fpc_sim* s, int nsteps, int wall_face, double weight, doubl
   if (rc) return rc;
   if (!std::isfinite(weight)) return fail(FPC_ERR_ARG, "weight not finite");
   const fpc_params& p = s->p;
-  const int n[3] = {p.nx, p.ny, p.nz};
-  const int k = wall_face >> 1;
-  const double M = (double)n[(k + 1) % 3] * n[(k + 2) % 3];
-  NuAcc o;
-  std::memset(&o, 0, sizeof o);
-  o.slot = s->nu_slot;
-  o.face = wall_face;
-  o.nk = n[k];
-  o.nt = n[k == 0 ? 1 : 0];  // faster tangential axis
-  o.ns = n[k == 2 ? 1 : 2];  // slower tangential axis
-  o.scale = -((double)n[k] / p.dT_ref) * weight / M;
-  o.Tw = p.wall_T[wall_face];
-  o.Tprof = p.wall_T_profile[wall_face];
-  thermal_reference(p, o.T_o, o.Tg);
+  const NuAcc o = nu_acc_of(s, wall_face, weight);
   for (int i = 0; i < nsteps; ++i) {
     rc = launch_update(s, s->buf[s->cur], s->buf[s->cur ^ 1], nullptr, 0, &o);
     if (rc) return rc;
@@ -693,6 +710,36 @@ int fpc_step_nusselt(fpc_sim* s, int nsteps, int wall_face, double weight, doubl
   const hipError_t e =
       launch_nu_slots_reduce(s->nu_slot, nu_slot_count(p.nx, p.ny, p.nz, s->nxp, wall_face), acc, s->stream);
   if (e != hipSuccess) return hipfail(e, "wall-Nusselt reduction");
+  return FPC_OK;
+}
+
+int fpc_step_diagnostics(fpc_sim* s, int nsteps, int wall_face, double* out) {
+  if (!s || !out) return fail(FPC_ERR_ARG, "NULL argument");
+  if (nsteps < 1) return fail(FPC_ERR_ARG, "nsteps < 1");
+  int rc = check_wall_face(s, wall_face);
+  if (rc) return rc;
+  if (nsteps > 1) {
+    rc = fpc_step(s, nsteps - 1);
+    if (rc) return rc;
+  }
+  const fpc_params& p = s->p;
+  DiagAcc dg;
+  std::memset(&dg, 0, sizeof dg);
+  dg.part = s->diag_part;
+  dg.rho_r = p.precision == FPC_FP32_DEV ? p.rho0 : 0.0;
+  thermal_reference(p, dg.T_o, dg.Tg);
+  dg.gbeta = p.g_beta;
+  dg.T0 = p.T0;
+  NuAcc o;
+  if (wall_face >= 0) o = nu_acc_of(s, wall_face, 1.0);
+  rc = launch_update(s, s->buf[s->cur], s->buf[s->cur ^ 1], nullptr, 0, wall_face >= 0 ? &o : nullptr, &dg);
+  if (rc) return rc;
+  s->cur ^= 1;
+  ++s->step;
+  hipError_t e = launch_diag_tiles(s->diag_part, s->ntiles, s->scratch, out, s->stream);
+  if (e == hipSuccess && wall_face >= 0)
+    e = launch_nu_slots_reduce(s->nu_slot, nu_slot_count(p.nx, p.ny, p.nz, s->nxp, wall_face), out, s->stream);
+  if (e != hipSuccess) return hipfail(e, "fused diagnostics reduction");
   return FPC_OK;
 }
 

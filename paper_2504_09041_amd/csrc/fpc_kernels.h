@@ -38,6 +38,19 @@ struct NuAcc {
   double T_o, Tg[3];   // thermal storage reference in FP64 (zero for FP64 storage)
 };
 
+// Diagnostics fused into a step (off when part is NULL): after its stores,
+// every wavefront reduces, over its tile, the per-node FP64 values of the
+// diagnostics (kinetic energy 1/2 rho |u|^2, T, |u|, non-finite flag) formed
+// from the stored post-collision values exactly as fpc_diagnostics forms them,
+// and writes the four results to part[4 tile + k]; a fixed-order reduction
+// over the tiles follows the step.
+struct DiagAcc {
+  double* part;
+  double rho_r;         // storage offset of f (0 for FP64 storage)
+  double T_o, Tg[3];    // thermal storage reference in FP64 (zero for FP64 storage)
+  double gbeta, T0;     // buoyancy (F = gbeta (T - T0) along the up axis)
+};
+
 template <class R>
 struct StepArgs {
   const R* __restrict__ src;  // S_{n-1}
@@ -53,6 +66,7 @@ struct StepArgs {
   R Tg[3];
   FaceDev face[6];
   NuAcc obj;
+  DiagAcc dg;
 };
 
 // FP32 storage holds deviations from the references; FP64 storage holds the
@@ -211,6 +225,10 @@ size_t nu_slot_count(int nx, int ny, int nz, int nxp, int face);
 hipError_t launch_nu_slots_reduce(double* slot, size_t count, double* acc, hipStream_t s);
 // slot[0..count) = 0.
 hipError_t launch_fill_zero(double* p, size_t count, hipStream_t s);
+// Reduction of the per-tile partials of a step with fused diagnostics
+// (DiagAcc) in a fixed order: out[0] = 0, out[1..4] = (KE, sum T, max |u|,
+// non-finite nodes).  scratch: kDiagNodeBlocks * 4 doubles, not overlapping out.
+hipError_t launch_diag_tiles(const double* part, size_t ntiles, double* scratch, double* out, hipStream_t s);
 // Seeds of the adjoint of J = weight * <Nu>_face (Sec. 6.1 stencil):
 // dJdT[node] (N values, zero off the two wall layers) and, if dJdTw is not
 // NULL, dJdTw[i] = dJ / dT_w at wall node i (profile layout).

@@ -175,6 +175,30 @@ __global__ void __launch_bounds__(kBlock) diag_nodes_kernel(StateDesc d, double*
   }
 }
 
+// Stage 1 over the per-tile partials of a step with fused diagnostics: the
+// same four quantities, a fixed number of blocks striding over the tiles.
+__global__ void __launch_bounds__(kBlock) diag_tiles_kernel(const double* part, size_t ntiles, double* partials) {
+  __shared__ double sh[kBlock];
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  double ke = 0.0, st = 0.0, um = 0.0, bad = 0.0;
+  for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < ntiles; t += stride) {
+    ke += part[t * 4 + 0];
+    st += part[t * 4 + 1];
+    um = fmax(um, part[t * 4 + 2]);
+    bad += part[t * 4 + 3];
+  }
+  ke = block_reduce(ke, sh, 0);
+  st = block_reduce(st, sh, 0);
+  um = block_reduce(um, sh, 1);
+  bad = block_reduce(bad, sh, 0);
+  if (threadIdx.x == 0) {
+    partials[blockIdx.x * 4 + 0] = ke;
+    partials[blockIdx.x * 4 + 1] = st;
+    partials[blockIdx.x * 4 + 2] = um;
+    partials[blockIdx.x * 4 + 3] = bad;
+  }
+}
+
 __device__ __forceinline__ size_t face_nodes_dev(const StateDesc& d, int face) {
   const int k = face >> 1;
   const size_t n[3] = {(size_t)d.nx, (size_t)d.ny, (size_t)d.nz};
@@ -383,6 +407,15 @@ size_t nu_slot_count(int nx, int ny, int nz, int nxp, int face) {
   if (k == 0) return 2 * (size_t)ny * nz;
   if (k == 1) return 2 * (size_t)nz * nxt;
   return 2 * (size_t)ny * nxt;
+}
+
+hipError_t launch_diag_tiles(const double* part, size_t ntiles, double* scratch, double* out, hipStream_t s) {
+  size_t nb = (ntiles + kBlock - 1) / kBlock;
+  if (nb > kDiagNodeBlocks) nb = kDiagNodeBlocks;
+  if (nb == 0) nb = 1;
+  diag_tiles_kernel<<<(unsigned)nb, kBlock, 0, s>>>(part, ntiles, scratch);
+  diag_final_kernel<<<1, kBlock, 0, s>>>(scratch, (int)nb, nullptr, 0, 0.0, out);
+  return hipGetLastError();
 }
 
 hipError_t launch_nu_slots_reduce(double* slot, size_t count, double* acc, hipStream_t s) {

@@ -117,6 +117,75 @@ __device__ __forceinline__ void nu_accumulate(const StepArgs<R>& a, int x, int y
   if (__lane_id() == (unsigned)(__ffsll((long long)act) - 1)) atomicAdd(&o.slot[idx], sum);
 }
 
+// Sum (op 0) or max (op 1) of a double over the active lanes of the
+// wavefront in a fixed order: a butterfly when every lane is active, else lane
+// by lane over the active lanes (a ragged last tile).
+__device__ __forceinline__ double wave_reduce(double v, int op) {
+  const unsigned long long act = __ballot(1);
+  if (act == ~0ull) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double o = __shfl_xor(v, off);
+      v = op == 0 ? v + o : fmax(v, o);
+    }
+    return v;
+  }
+  double r = op == 0 ? 0.0 : readlane_f64(v, __ffsll((long long)act) - 1);
+  for (int l = 0; l < 64; ++l)
+    if ((act >> l) & 1ull) r = op == 0 ? r + readlane_f64(v, l) : fmax(r, readlane_f64(v, l));
+  return r;
+}
+
+// Fused diagnostics (StepArgs::dg): the per-node values fpc_diagnostics forms
+// from the stored state (rho = rho_r + sum f, T = Tr + sum g, rho u = sum f e
+// - F/2, in FP64 and in the same order), reduced over the wavefront's tile
+// and written to the tile's four partials.
+template <class L, class R, int UP>
+__device__ __forceinline__ void diag_accumulate(const StepArgs<R>& a, int x, int y, int z, unsigned node,
+                                                const R (&f)[L::Qf], const R (&g)[L::Qg]) {
+  const DiagAcc& d = a.dg;
+  double s = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll
+  for (int q = 0; q < L::Qf; ++q) {
+    const double v = (double)f[q];
+    s += v;
+    jx += L::ex(q) * v;
+    jy += L::ey(q) * v;
+    jz += L::ez(q) * v;
+  }
+  double t = 0.0;
+#pragma unroll
+  for (int q = 0; q < L::Qg; ++q) t += (double)g[q];
+  const double rho = d.rho_r + s;
+  const double T = (d.T_o + (d.Tg[0] * (double)x + d.Tg[1] * (double)y + d.Tg[2] * (double)z)) + t;
+  const double Fb = d.gbeta * (T - d.T0);
+  const double ir = 1.0 / rho;
+  double u[3];
+  u[0] = (jx - (UP == 0 ? 0.5 * Fb : 0.0)) * ir;
+  u[1] = (jy - (UP == 1 ? 0.5 * Fb : 0.0)) * ir;
+  u[2] = (jz - (UP == 2 ? 0.5 * Fb : 0.0)) * ir;
+  const double u2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  double ke = 0.0, st = 0.0, um = 0.0, bad = 0.0;
+  if (!isfinite(rho) || !isfinite(T) || !isfinite(u2)) {
+    bad = 1.0;
+  } else {
+    ke = 0.5 * rho * u2;
+    st = T;
+    um = sqrt(u2);
+  }
+  ke = wave_reduce(ke, 0);
+  st = wave_reduce(st, 0);
+  um = wave_reduce(um, 1);
+  bad = wave_reduce(bad, 0);
+  if (__lane_id() == (unsigned)(__ffsll((long long)__ballot(1)) - 1)) {
+    double* p = d.part + (size_t)(node >> 6) * 4;
+    p[0] = ke;
+    p[1] = st;
+    p[2] = um;
+    p[3] = bad;
+  }
+}
+
 template <class L, class R, class M, int UP, bool NT, bool STD>
 __device__ __forceinline__ void collide_store(const StepArgs<R>& a, const M& m, int x, int y, int z, unsigned node,
                                               R Tr, R (&f)[L::Qf], R (&g)[L::Qg]) {
@@ -138,6 +207,7 @@ __device__ __forceinline__ void collide_store(const StepArgs<R>& a, const M& m, 
     for (int q = 0; q < L::Qg; ++q) t += (double)g[q];
     nu_accumulate<L, R>(a, x, y, z, t);
   }
+  if (a.dg.part != nullptr) diag_accumulate<L, R, UP>(a, x, y, z, node, f, g);
 }
 
 

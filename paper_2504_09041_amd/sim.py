@@ -194,6 +194,18 @@ class Simulation:
         A.call("fpc_step_nusselt", self._h, int(n), int(FACE_INDEX.get(face, face)), float(weight),
                ctypes.c_void_p(acc.data_ptr()))
 
+    def step_diagnostics(self, n, face=-1, out=None):
+        """Advance n >= 1 steps; the last step's kernel also reduces the
+        diagnostics of the state it writes.  Returns the 5-element FP64 device
+        tensor (nu, ke, sumT, umax, non-finite nodes) without synchronising."""
+        if out is None:
+            out = torch.empty(5, dtype=torch.float64, device=self.device)
+        elif out.dtype != torch.float64 or not out.is_cuda or out.numel() < 5 or not out.is_contiguous():
+            raise ValueError("out must be a contiguous FP64 device tensor of 5 elements")
+        A.call("fpc_step_diagnostics", self._h, int(n), int(FACE_INDEX.get(face, face)),
+               ctypes.c_void_p(out.data_ptr()))
+        return out
+
     def nusselt_seed(self, face, weight=1.0):
         """Adjoint seeds of weight * <Nu>_face: (dJ/dT as an (nz, ny, nx)
         tensor, dJ/dT_w per wall node in the profile layout, flat)."""

@@ -225,6 +225,8 @@ def test_null_and_invalid_arguments_fail_before_any_launch():
     assert lib.fpc_init(None, vp(256)) == A.FPC_ERR_ARG
     assert lib.fpc_step(None, 1) == A.FPC_ERR_ARG
     assert lib.fpc_step_from(None, vp(256), vp(512)) == A.FPC_ERR_ARG
+    assert lib.fpc_step_nusselt(None, 1, 2, ctypes.c_double(1.0), vp(256)) == A.FPC_ERR_ARG
+    assert lib.fpc_step_diagnostics(None, 1, -1, vp(256)) == A.FPC_ERR_ARG
     assert lib.fpc_get_step(None, ctypes.byref(ll)) == A.FPC_ERR_ARG
     assert lib.fpc_macros(None, None, None, None) == A.FPC_ERR_ARG
     assert lib.fpc_diagnostics(None, 0, ctypes.byref(d), ctypes.byref(d), ctypes.byref(d),
