@@ -707,8 +707,8 @@ int fpc_step_nusselt(fpc_sim* s, int nsteps, int wall_face, double weight, doubl
     s->cur ^= 1;
     ++s->step;
   }
-  const hipError_t e =
-      launch_nu_slots_reduce(s->nu_slot, nu_slot_count(p.nx, p.ny, p.nz, s->nxp, wall_face), acc, s->stream);
+  const hipError_t e = launch_nu_slots_reduce(s->nu_slot, nu_slot_count(p.nx, p.ny, p.nz, s->nxp, wall_face),
+                                              s->scratch, acc, s->stream);
   if (e != hipSuccess) return hipfail(e, "wall-Nusselt reduction");
   return FPC_OK;
 }
@@ -736,9 +736,10 @@ int fpc_step_diagnostics(fpc_sim* s, int nsteps, int wall_face, double* out) {
   if (rc) return rc;
   s->cur ^= 1;
   ++s->step;
-  hipError_t e = launch_diag_tiles(s->diag_part, s->ntiles, s->scratch, out, s->stream);
-  if (e == hipSuccess && wall_face >= 0)
-    e = launch_nu_slots_reduce(s->nu_slot, nu_slot_count(p.nx, p.ny, p.nz, s->nxp, wall_face), out, s->stream);
+  const hipError_t e =
+      launch_diag_tiles(s->diag_part, s->ntiles, wall_face >= 0 ? s->nu_slot : nullptr,
+                        wall_face >= 0 ? nu_slot_count(p.nx, p.ny, p.nz, s->nxp, wall_face) : 0, s->scratch, out,
+                        s->stream);
   if (e != hipSuccess) return hipfail(e, "fused diagnostics reduction");
   return FPC_OK;
 }

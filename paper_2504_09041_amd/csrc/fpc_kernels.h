@@ -221,14 +221,19 @@ hipError_t launch_nu_local(const StateDesc& d, int face, const FaceDev& fd, doub
 // Slots of the fused wall-Nusselt accumulation for `face` (see NuAcc): one per
 // tile of the two wall layers.  nu_slot_count is the number a face needs.
 size_t nu_slot_count(int nx, int ny, int nz, int nxp, int face);
-// acc[0] += sum of slot[0..count) in a fixed order; the slots are zeroed.
-hipError_t launch_nu_slots_reduce(double* slot, size_t count, double* acc, hipStream_t s);
+// acc[0] += sum of slot[0..count) in a fixed order (two stages, at most
+// kDiagFaceBlocks blocks, partials in scratch[kDiagNodeBlocks * 4 ...]); the
+// slots are zeroed.
+hipError_t launch_nu_slots_reduce(double* slot, size_t count, double* scratch, double* acc, hipStream_t s);
 // slot[0..count) = 0.
 hipError_t launch_fill_zero(double* p, size_t count, hipStream_t s);
 // Reduction of the per-tile partials of a step with fused diagnostics
-// (DiagAcc) in a fixed order: out[0] = 0, out[1..4] = (KE, sum T, max |u|,
-// non-finite nodes).  scratch: kDiagNodeBlocks * 4 doubles, not overlapping out.
-hipError_t launch_diag_tiles(const double* part, size_t ntiles, double* scratch, double* out, hipStream_t s);
+// (DiagAcc) in a fixed order: out[0] = the sum of the wall-Nusselt slots
+// slot[0..nslots) (which are zeroed), or 0 when slot is NULL; out[1..4] =
+// (KE, sum T, max |u|, non-finite nodes).  scratch: kDiagNodeBlocks * 4 +
+// kDiagFaceBlocks doubles, not overlapping out.
+hipError_t launch_diag_tiles(const double* part, size_t ntiles, double* slot, size_t nslots, double* scratch,
+                             double* out, hipStream_t s);
 // Seeds of the adjoint of J = weight * <Nu>_face (Sec. 6.1 stencil):
 // dJdT[node] (N values, zero off the two wall layers) and, if dJdTw is not
 // NULL, dJdTw[i] = dJ / dT_w at wall node i (profile layout).

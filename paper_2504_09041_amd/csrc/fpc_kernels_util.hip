@@ -284,14 +284,25 @@ __global__ void __launch_bounds__(kBlock) diag_final_kernel(const double* pn, in
   }
 }
 
-// acc[0] += sum of the wall-Nusselt slots (fixed order); slots reset to 0.
-__global__ void __launch_bounds__(kBlock) nu_slots_reduce_kernel(double* slot, size_t count, double* acc) {
+// Stage 1 of the wall-Nusselt slot reduction: each block sums its slots
+// (grid-stride, fixed order) into partials[blockIdx.x] and resets them to 0.
+__global__ void __launch_bounds__(kBlock) nu_slots_partial_kernel(double* slot, size_t count, double* partials) {
   __shared__ double sh[kBlock];
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
   double v = 0.0;
-  for (size_t i = threadIdx.x; i < count; i += kBlock) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) {
     v += slot[i];
     slot[i] = 0.0;
   }
+  v = block_reduce(v, sh, 0);
+  if (threadIdx.x == 0) partials[blockIdx.x] = v;
+}
+
+// Stage 2: acc[0] += the sum of the nb partials (fixed order).
+__global__ void __launch_bounds__(kBlock) nu_slots_final_kernel(const double* partials, int nb, double* acc) {
+  __shared__ double sh[kBlock];
+  double v = 0.0;
+  for (int b = threadIdx.x; b < nb; b += kBlock) v += partials[b];
   v = block_reduce(v, sh, 0);
   if (threadIdx.x == 0) acc[0] += v;
 }
@@ -409,17 +420,35 @@ size_t nu_slot_count(int nx, int ny, int nz, int nxp, int face) {
   return 2 * (size_t)ny * nxt;
 }
 
-hipError_t launch_diag_tiles(const double* part, size_t ntiles, double* scratch, double* out, hipStream_t s) {
+namespace {
+unsigned nu_slot_blocks(size_t count) {
+  const size_t b = (count + kBlock - 1) / kBlock;
+  return (unsigned)(b == 0 ? 1 : (b < kDiagFaceBlocks ? b : kDiagFaceBlocks));
+}
+}  // namespace
+
+hipError_t launch_diag_tiles(const double* part, size_t ntiles, double* slot, size_t nslots, double* scratch,
+                             double* out, hipStream_t s) {
   size_t nb = (ntiles + kBlock - 1) / kBlock;
   if (nb > kDiagNodeBlocks) nb = kDiagNodeBlocks;
   if (nb == 0) nb = 1;
   diag_tiles_kernel<<<(unsigned)nb, kBlock, 0, s>>>(part, ntiles, scratch);
-  diag_final_kernel<<<1, kBlock, 0, s>>>(scratch, (int)nb, nullptr, 0, 0.0, out);
+  double* pf = scratch + (size_t)kDiagNodeBlocks * 4;
+  unsigned nf = 0;
+  if (slot != nullptr) {
+    nf = nu_slot_blocks(nslots);
+    nu_slots_partial_kernel<<<nf, kBlock, 0, s>>>(slot, nslots, pf);
+  }
+  // the slots already carry the 1 / (nodes on the face) of the mean
+  diag_final_kernel<<<1, kBlock, 0, s>>>(scratch, (int)nb, pf, (int)nf, 1.0, out);
   return hipGetLastError();
 }
 
-hipError_t launch_nu_slots_reduce(double* slot, size_t count, double* acc, hipStream_t s) {
-  nu_slots_reduce_kernel<<<1, kBlock, 0, s>>>(slot, count, acc);
+hipError_t launch_nu_slots_reduce(double* slot, size_t count, double* scratch, double* acc, hipStream_t s) {
+  double* pf = scratch + (size_t)kDiagNodeBlocks * 4;
+  const unsigned nf = nu_slot_blocks(count);
+  nu_slots_partial_kernel<<<nf, kBlock, 0, s>>>(slot, count, pf);
+  nu_slots_final_kernel<<<1, kBlock, 0, s>>>(pf, (int)nf, acc);
   return hipGetLastError();
 }
 
