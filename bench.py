@@ -50,6 +50,8 @@ def _args():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--shape", type=int, nargs=3, help="grid (nx ny nz) of --mode single instead of the workload's")
+    ap.add_argument("--pair", help="lattice pair of --mode single / precision instead of the workload's "
+                                   "(D2Q9-D2Q5, D2Q9-D2Q9, D3Q27-D3Q7, D3Q27-D3Q15)")
     ap.add_argument("--no-multistep", action="store_true",
                     help="forbid fpc_step's single-launch multi-step path (small grids)")
     ap.add_argument("--cpu-sample-steps", type=int, default=24)
@@ -579,11 +581,12 @@ def main():
         print(json.dumps(copy_bandwidth(a.mib, a.reps)))
         return
     if a.mode == "single":
-        print(json.dumps(time_workload(a.workload, a.precision, a.steps, a.warmup, shape=a.shape,
+        print(json.dumps(time_workload(a.workload, a.precision, a.steps, a.warmup, shape=a.shape, pair=a.pair,
                                        multistep=not a.no_multistep)))
         return
     if a.mode == "precision":
-        print(json.dumps(precision_study(a.workload, a.steps, max(1, a.steps // 50))))
+        kw = {"pair": a.pair} if a.pair else {}
+        print(json.dumps(precision_study(a.workload, a.steps, max(1, a.steps // 50), shape=a.shape, **kw)))
         return
     if a.mode == "adjoint":
         print(json.dumps(adjoint_cost(a.workload, a.steps, max(1, int(round(a.steps ** 0.5))))))
@@ -624,6 +627,9 @@ def main():
         # 2D workload: same step structure, more (or the same) bytes
         extra["rb2d_1024x512_f64_D2Q9thermal"] = time_workload("rb2d_1024x512", "f64", n2, w2, pair="D2Q9-D2Q9")
         extra["rb3d_128_f64_D3Q15thermal"] = time_workload("rb3d_128", "f64", n3, w3, pair="D3Q27-D3Q15")
+        extra["rb2d_1024x512_f32dev_D2Q9thermal"] = time_workload("rb2d_1024x512", "f32dev", n2, w2,
+                                                                  pair="D2Q9-D2Q9")
+        extra["rb3d_128_f32dev_D3Q15thermal"] = time_workload("rb3d_128", "f32dev", n3, w3, pair="D3Q27-D3Q15")
         extra["rb2d_1024x512_f64_MCM"] = time_workload("rb2d_1024x512", "f64", n2, w2, model="MCM")
         # the wall-Nusselt objective accumulated during the forward run of the
         # lid-driven cavity's J window (steps 5000-10000)
@@ -637,6 +643,11 @@ def main():
         extra["fp32_vs_fp64_rb2d_1024x512"] = precision_summary(st, 50000)
         st = precision_study("dhc3d_256", 20000, 5000, shape=(64, 64, 64))
         extra["fp32_vs_fp64_dhc3d_64"] = precision_summary(st, 20000)
+        # the FP32 deviation form on the paper's own thermal lattices
+        st = precision_study("rb2d_1024x512", 50000, 5000, pair="D2Q9-D2Q9")
+        extra["fp32_vs_fp64_rb2d_1024x512_D2Q9thermal"] = precision_summary(st, 50000)
+        st = precision_study("dhc3d_256", 20000, 5000, shape=(64, 64, 64), pair="D3Q27-D3Q15")
+        extra["fp32_vs_fp64_dhc3d_64_D3Q15thermal"] = precision_summary(st, 20000)
         for pe in (1e3, 1e4, 1e5):
             st = precision_study("mixed2d_512", 10000, 5000, Pe=pe)
             extra[f"fp32_vs_fp64_mixed2d_512_Pe{pe:.0e}"] = precision_summary(st, 10000, Pe=pe)

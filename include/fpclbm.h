@@ -50,8 +50,8 @@ extern "C" {
 /* Lattice pairs (fluid + thermal). */
 #define FPC_D2Q9_D2Q5 1   /* D2Q9 fluid (Eqs. ex, ey) + D2Q5 thermal (axis subset of D2Q9) */
 #define FPC_D3Q27_D3Q7 2  /* D3Q27 fluid (Sec. 5.2) + D3Q7 thermal (axis subset of D3Q27) */
-#define FPC_D2Q9_D2Q9 3   /* D2Q9 fluid + the paper's D2Q9 thermal lattice (Sec. 4.4, App. B); FP64 only */
-#define FPC_D3Q27_D3Q15 4 /* D3Q27 fluid + the paper's D3Q15 thermal lattice (Sec. 5.4, App. C); FP64 only */
+#define FPC_D2Q9_D2Q9 3   /* D2Q9 fluid + the paper's D2Q9 thermal lattice (Sec. 4.4, App. B) */
+#define FPC_D3Q27_D3Q15 4 /* D3Q27 fluid + the paper's D3Q15 thermal lattice (Sec. 5.4, App. C) */
 
 /* Collision models (fpc_params.model). */
 #define FPC_MODEL_FP 0  /* Fokker-Planck central-moment attractors (the method) */

@@ -106,8 +106,6 @@ int validate(const fpc_params* p) {
   if (rc) return rc;
   if (p->precision != FPC_FP64 && p->precision != FPC_FP32_DEV)
     return fail(FPC_ERR_ARG, "unknown precision %d", p->precision);
-  if (p->precision == FPC_FP32_DEV && paper_thermal(p->lattice))
-    return fail(FPC_ERR_ARG, "the D2Q9 / D3Q15 thermal lattices run in FP64 only");
   if (p->model != FPC_MODEL_FP && p->model != FPC_MODEL_MCM) return fail(FPC_ERR_ARG, "unknown model %d", p->model);
   if (p->thermal_option != FPC_THERMAL_OPTION_A && p->thermal_option != FPC_THERMAL_OPTION_B)
     return fail(FPC_ERR_ARG, "unknown thermal option %d", p->thermal_option);

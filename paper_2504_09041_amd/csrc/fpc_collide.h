@@ -174,8 +174,15 @@ __device__ __forceinline__ R rho_ref(const CollParams<R>& c) {
 // ---------------------------------------------------------------------------
 
 // D2Q9 thermal: central moments by 1D shifts (x per row, then y), as for f.
+// In the FP32 deviation form g holds g - w^T Tr (Tr: the node's storage
+// reference): the shifts are linear, so they give the central moments of the
+// deviations, e - Tr kw with kw_ij = c_i(u_x) c_j(u_y) the central moments of
+// w^T (c_0 = 1, c_1 = -u, c_2 = c^_s^2 + u^2), and the moments relax as
+// deviations toward attractor deviations m - Tr kw formed analytically; the
+// inverse shifts of those give the stored post-collision deviations.
+// T = Tr + dT, with dT the sum of the stored deviations.
 template <class R, bool STD>
-__device__ __forceinline__ void thermal_d2q9(R (&g)[kQ2], R ux, R uy, R T, const CollParams<R>& c) {
+__device__ __forceinline__ void thermal_d2q9(R (&g)[kQ2], R ux, R uy, R T, R Tr, R dT, const CollParams<R>& c) {
   R x0m, x1m, x2m, x0z, x1z, x2z, x0p, x1p, x2p;
   shift_fwd(g[7], g[4], g[8], ux, x0m, x1m, x2m);  // ey = -1
   shift_fwd(g[3], g[0], g[1], ux, x0z, x1z, x2z);  // ey =  0
@@ -184,34 +191,78 @@ __device__ __forceinline__ void thermal_d2q9(R (&g)[kQ2], R ux, R uy, R T, const
   shift_fwd(x0m, x0z, x0p, uy, e00, e01, e02);
   shift_fwd(x1m, x1z, x1p, uy, e10, e11, e12);
   shift_fwd(x2m, x2z, x2p, uy, e20, e21, e22);
-  (void)e00;  // equals T
+  (void)e00;  // equals T (the deviation T - Tr in the deviation form)
   auto og = [&](int k) -> R { return rate_g<2, STD>(c, k); };
   const R cT = c.cs2T;
-  // orders 1-2 (App. B Step 3): first order and 11 toward 0; 2s toward 2 c^2 T, 2d toward 0
-  const R t10 = (R(1) - og(1)) * e10, t01 = (R(1) - og(2)) * e01;
-  const R s2 = e20 + e02, d2 = e20 - e02;
-  const R ts = s2 + og(3) * (R(2) * cT * T - s2), td = (R(1) - og(4)) * d2;
-  const R t20 = R(0.5) * (ts + td), t02 = R(0.5) * (ts - td);
-  const R t11 = (R(1) - og(5)) * e11;
-  R m21, m12, m22;
-  if (mcm<STD>(c)) {  // MCM
-    m21 = R(0);
-    m12 = R(0);
-    m22 = cT * cT * T;
-  } else if (option_b<STD>(c)) {  // option B (Eq. MvT2DoptionB)
-    const R iT = R(1) / T;
-    m21 = R(2) / R(3) * iT * (t20 * t01 + R(2) * t11 * t10);
-    m12 = R(2) / R(3) * iT * (t02 * t10 + R(2) * t11 * t01);
-    m22 = iT * (t20 * t02 + R(2) * t11 * t11);
-  } else {  // option A (Eq. MvT2D)
-    m21 = R(2) / R(3) * cT * t01;
-    m12 = R(2) / R(3) * cT * t10;
-    m22 = R(0.5) * cT * (t20 + t02);
+  R t00, t10, t01, t20, t02, t11, t21, t12, t22;
+  if constexpr (sizeof(R) == 8) {  // FP64 storage: plain populations
+    (void)Tr;
+    (void)dT;
+    // orders 1-2 (App. B Step 3): first order and 11 toward 0; 2s toward 2 c^2 T, 2d toward 0
+    t00 = T;
+    t10 = (R(1) - og(1)) * e10;
+    t01 = (R(1) - og(2)) * e01;
+    const R s2 = e20 + e02, d2 = e20 - e02;
+    const R ts = s2 + og(3) * (R(2) * cT * T - s2), td = (R(1) - og(4)) * d2;
+    t20 = R(0.5) * (ts + td);
+    t02 = R(0.5) * (ts - td);
+    t11 = (R(1) - og(5)) * e11;
+    R m21, m12, m22;
+    if (mcm<STD>(c)) {  // MCM
+      m21 = R(0);
+      m12 = R(0);
+      m22 = cT * cT * T;
+    } else if (option_b<STD>(c)) {  // option B (Eq. MvT2DoptionB)
+      const R iT = R(1) / T;
+      m21 = R(2) / R(3) * iT * (t20 * t01 + R(2) * t11 * t10);
+      m12 = R(2) / R(3) * iT * (t02 * t10 + R(2) * t11 * t01);
+      m22 = iT * (t20 * t02 + R(2) * t11 * t11);
+    } else {  // option A (Eq. MvT2D)
+      m21 = R(2) / R(3) * cT * t01;
+      m12 = R(2) / R(3) * cT * t10;
+      m22 = R(0.5) * cT * (t20 + t02);
+    }
+    t21 = e21 + og(6) * (m21 - e21);
+    t12 = e12 + og(7) * (m12 - e12);
+    t22 = e22 + og(8) * (m22 - e22);
+  } else {
+    const R uxx = ux * ux, uyy = uy * uy, uxy = ux * uy;
+    const R ax = cT + uxx, ay = cT + uyy;  // kw_20, kw_02
+    t00 = dT;
+    t10 = e10 + og(1) * (Tr * ux - e10);
+    t01 = e01 + og(2) * (Tr * uy - e01);
+    const R s2 = e20 + e02, d2 = e20 - e02;
+    const R ts = s2 + og(3) * ((R(2) * cT * dT - Tr * (uxx + uyy)) - s2);
+    const R td = d2 + og(4) * (-Tr * (uxx - uyy) - d2);
+    t20 = R(0.5) * (ts + td);
+    t02 = R(0.5) * (ts - td);
+    t11 = e11 + og(5) * (-Tr * uxy - e11);
+    // third- and fourth-order attractor deviations (kw_21 = -u_y ax,
+    // kw_12 = -u_x ay, kw_22 = ax ay)
+    R d21, d12, d22;
+    if (mcm<STD>(c)) {  // MCM
+      d21 = Tr * uy * ax;
+      d12 = Tr * ux * ay;
+      d22 = cT * cT * dT - Tr * (cT * (uxx + uyy) + uxx * uyy);
+    } else if (option_b<STD>(c)) {  // option B, from the full post-collision moments
+      const R iT = R(1) / T;
+      const R f10 = t10 - Tr * ux, f01 = t01 - Tr * uy, f11 = t11 + Tr * uxy;
+      const R f20 = t20 + Tr * ax, f02 = t02 + Tr * ay;
+      d21 = R(2) / R(3) * iT * (f20 * f01 + R(2) * f11 * f10) + Tr * uy * ax;
+      d12 = R(2) / R(3) * iT * (f02 * f10 + R(2) * f11 * f01) + Tr * ux * ay;
+      // (f20 f02 + 2 f11^2) / T - Tr ax ay without the cancellation of its
+      // leading Tr^2 ax ay terms
+      d22 = iT * ((Tr * (ax * t02 + ay * t20) - Tr * ax * ay * dT) + t20 * t02 + R(2) * f11 * f11);
+    } else {  // option A
+      d21 = R(2) / R(3) * cT * t01 + Tr * uy * (cT / R(3) + uxx);
+      d12 = R(2) / R(3) * cT * t10 + Tr * ux * (cT / R(3) + uyy);
+      d22 = R(0.5) * cT * (t20 + t02) - Tr * (R(0.5) * cT * (uxx + uyy) + uxx * uyy);
+    }
+    t21 = e21 + og(6) * (d21 - e21);
+    t12 = e12 + og(7) * (d12 - e12);
+    t22 = e22 + og(8) * (d22 - e22);
   }
-  const R t21 = e21 + og(6) * (m21 - e21);
-  const R t12 = e12 + og(7) * (m12 - e12);
-  const R t22 = e22 + og(8) * (m22 - e22);
-  shift_inv(T, t01, t02, uy, x0m, x0z, x0p);
+  shift_inv(t00, t01, t02, uy, x0m, x0z, x0p);
   shift_inv(t10, t11, t12, uy, x1m, x1z, x1p);
   shift_inv(t20, t21, t22, uy, x2m, x2z, x2p);
   shift_inv(x0m, x1m, x2m, ux, g[7], g[4], g[8]);
@@ -264,7 +315,8 @@ __device__ __forceinline__ R t15_shift(const R (&r)[kQ15], const R (&nux)[3], co
 }
 
 template <class R, bool STD>
-__device__ __forceinline__ void thermal_d3q15(R (&g)[kQ15], R ux, R uy, R uz, R T, const CollParams<R>& c) {
+__device__ __forceinline__ void thermal_d3q15(R (&g)[kQ15], R ux, R uy, R uz, R T, R Tr, R dT,
+                                              const CollParams<R>& c) {
   // raw moments: corner Walsh-Hadamard transform h[px + 2py + 4pz] =
   // sum_corners g s_x^px s_y^py s_z^pz, plus the axis pairs and the rest
   R h[8];
@@ -308,37 +360,90 @@ __device__ __forceinline__ void thermal_d3q15(R (&g)[kQ15], R ux, R uy, R uz, R 
   auto og = [&](int k) -> R { return rate_g<3, STD>(c, k); };
   const R cT = c.cs2T;
   R t[kQ15];
-  t[0] = T;
+  if constexpr (sizeof(R) == 8) {  // FP64 storage: plain populations
+    (void)Tr;
+    (void)dT;
+    t[0] = T;
 #pragma unroll
-  for (int k = 1; k <= 6; ++k) t[k] = (R(1) - og(k)) * e[k];  // first order, off-diagonal second order
+    for (int k = 1; k <= 6; ++k) t[k] = (R(1) - og(k)) * e[k];  // first order, off-diagonal second order
 #pragma unroll
-  for (int k = 7; k <= 9; ++k) t[k] = e[k] + og(k) * (cT * T - e[k]);
-  R m120, m012, m201, m111, m220;
-  if (mcm<STD>(c)) {  // MCM
-    m120 = m012 = m201 = m111 = R(0);
-    m220 = cT * cT * T;
-  } else if (option_b<STD>(c)) {  // option B
-    const R f = R(2) / (R(3) * T);
-    m120 = f * (t[8] * t[1] + R(2) * t[4] * t[2]);
-    m012 = f * (t[9] * t[2] + R(2) * t[6] * t[3]);
-    m201 = f * (t[7] * t[3] + R(2) * t[5] * t[1]);
-    m111 = f * (t[4] * t[3] + t[5] * t[2] + t[6] * t[1]);
-    m220 = (t[7] * t[8] + R(2) * t[4] * t[4]) / T;
-  } else {  // option A
-    m120 = R(2) / R(3) * cT * t[1];
-    m012 = R(2) / R(3) * cT * t[2];
-    m201 = R(2) / R(3) * cT * t[3];
-    m111 = R(0);
-    m220 = R(0.5) * cT * (t[7] + t[8]);
+    for (int k = 7; k <= 9; ++k) t[k] = e[k] + og(k) * (cT * T - e[k]);
+    R m120, m012, m201, m111, m220;
+    if (mcm<STD>(c)) {  // MCM
+      m120 = m012 = m201 = m111 = R(0);
+      m220 = cT * cT * T;
+    } else if (option_b<STD>(c)) {  // option B
+      const R f = R(2) / (R(3) * T);
+      m120 = f * (t[8] * t[1] + R(2) * t[4] * t[2]);
+      m012 = f * (t[9] * t[2] + R(2) * t[6] * t[3]);
+      m201 = f * (t[7] * t[3] + R(2) * t[5] * t[1]);
+      m111 = f * (t[4] * t[3] + t[5] * t[2] + t[6] * t[1]);
+      m220 = (t[7] * t[8] + R(2) * t[4] * t[4]) / T;
+    } else {  // option A
+      m120 = R(2) / R(3) * cT * t[1];
+      m012 = R(2) / R(3) * cT * t[2];
+      m201 = R(2) / R(3) * cT * t[3];
+      m111 = R(0);
+      m220 = R(0.5) * cT * (t[7] + t[8]);
+    }
+    t[10] = e[10] + og(10) * (m120 - e[10]);
+    t[11] = e[11] + og(11) * (m012 - e[11]);
+    t[12] = e[12] + og(12) * (m201 - e[12]);
+    t[13] = e[13] + og(13) * (m111 - e[13]);
+    t[14] = e[14] + og(14) * (m220 - e[14]);
+  } else {
+    // deviation form (g holds g - w^T Tr): e are the central moments of the
+    // deviations, e - Tr kw with kw_m = prod_d c_(m_d)(u_d) the central
+    // moments of w^T (c_0 = 1, c_1 = -u, c_2 = c^_s^2 + u^2); relax toward
+    // the attractor deviations m - Tr kw, formed analytically
+    const R uxx = ux * ux, uyy = uy * uy, uzz = uz * uz;
+    const R ax = cT + uxx, ay = cT + uyy, az = cT + uzz;
+    t[0] = dT;
+    t[1] = e[1] + og(1) * (Tr * ux - e[1]);
+    t[2] = e[2] + og(2) * (Tr * uy - e[2]);
+    t[3] = e[3] + og(3) * (Tr * uz - e[3]);
+    t[4] = e[4] + og(4) * (-Tr * (ux * uy) - e[4]);
+    t[5] = e[5] + og(5) * (-Tr * (ux * uz) - e[5]);
+    t[6] = e[6] + og(6) * (-Tr * (uy * uz) - e[6]);
+    t[7] = e[7] + og(7) * ((cT * dT - Tr * uxx) - e[7]);
+    t[8] = e[8] + og(8) * ((cT * dT - Tr * uyy) - e[8]);
+    t[9] = e[9] + og(9) * ((cT * dT - Tr * uzz) - e[9]);
+    const R uxyz = ux * uy * uz;
+    R d120, d012, d201, d111, d220;
+    if (mcm<STD>(c)) {  // MCM
+      d120 = Tr * ux * ay;
+      d012 = Tr * uy * az;
+      d201 = Tr * uz * ax;
+      d111 = Tr * uxyz;
+      d220 = cT * cT * dT - Tr * (cT * (uxx + uyy) + uxx * uyy);
+    } else if (option_b<STD>(c)) {  // option B, from the full post-collision moments
+      const R f = R(2) / (R(3) * T);
+      const R F1 = t[1] - Tr * ux, F2 = t[2] - Tr * uy, F3 = t[3] - Tr * uz;
+      const R F4 = t[4] + Tr * (ux * uy), F5 = t[5] + Tr * (ux * uz), F6 = t[6] + Tr * (uy * uz);
+      const R F7 = t[7] + Tr * ax, F8 = t[8] + Tr * ay, F9 = t[9] + Tr * az;
+      d120 = f * (F8 * F1 + R(2) * F4 * F2) + Tr * ux * ay;
+      d012 = f * (F9 * F2 + R(2) * F6 * F3) + Tr * uy * az;
+      d201 = f * (F7 * F3 + R(2) * F5 * F1) + Tr * uz * ax;
+      d111 = f * (F4 * F3 + F5 * F2 + F6 * F1) + Tr * uxyz;
+      // (F7 F8 + 2 F4^2) / T - Tr ax ay without the cancellation of its
+      // leading Tr^2 ax ay terms
+      d220 = ((Tr * (ax * t[8] + ay * t[7]) - Tr * ax * ay * dT) + t[7] * t[8] + R(2) * F4 * F4) / T;
+    } else {  // option A
+      d120 = R(2) / R(3) * cT * t[1] + Tr * ux * (cT / R(3) + uyy);
+      d012 = R(2) / R(3) * cT * t[2] + Tr * uy * (cT / R(3) + uzz);
+      d201 = R(2) / R(3) * cT * t[3] + Tr * uz * (cT / R(3) + uxx);
+      d111 = Tr * uxyz;
+      d220 = R(0.5) * cT * (t[7] + t[8]) - Tr * (R(0.5) * cT * (uxx + uyy) + uxx * uyy);
+    }
+    t[10] = e[10] + og(10) * (d120 - e[10]);
+    t[11] = e[11] + og(11) * (d012 - e[11]);
+    t[12] = e[12] + og(12) * (d201 - e[12]);
+    t[13] = e[13] + og(13) * (d111 - e[13]);
+    t[14] = e[14] + og(14) * (d220 - e[14]);
   }
-  t[10] = e[10] + og(10) * (m120 - e[10]);
-  t[11] = e[11] + og(11) * (m012 - e[11]);
-  t[12] = e[12] + og(12) * (m201 - e[12]);
-  t[13] = e[13] + og(13) * (m111 - e[13]);
-  t[14] = e[14] + og(14) * (m220 - e[14]);
   // raw moments back: the central map is unit lower triangular in this order,
   // so r_m = t_m - (terms of lower members), member by member
-  r[0] = T;
+  r[0] = t[0];
 #define FPC_T15I(K) r[K] = t[K] - t15_shift<R, K, true>(r, nux, nuy, nuz);
   FPC_T15I(1) FPC_T15I(2) FPC_T15I(3) FPC_T15I(4) FPC_T15I(5) FPC_T15I(6) FPC_T15I(7) FPC_T15I(8) FPC_T15I(9)
   FPC_T15I(10) FPC_T15I(11) FPC_T15I(12) FPC_T15I(13) FPC_T15I(14)
@@ -463,7 +568,7 @@ __device__ __forceinline__ void collide2d(R (&f)[kQ2], R (&g)[QG], const CollPar
   shift_inv(x0p, x1p, x2p, ux, f[6], f[2], f[5]);
 
   if constexpr (QG != kQ2T) {
-    thermal_d2q9<R, STD>(g, ux, uy, T, c);
+    thermal_d2q9<R, STD>(g, ux, uy, T, Tr, dT, c);
     return;
   } else {
   // thermal D2Q5: raw moments (00, 10, 01, 20, 02) -> central -> relax -> back
@@ -736,7 +841,7 @@ __device__ __forceinline__ void collide3d(R (&f)[kQ3], R (&g)[QG], const CollPar
                 f[d3_index(-1, ey, ez)], f[d3_index(0, ey, ez)], f[d3_index(1, ey, ez)]);
 
   if constexpr (QG != kQ3T) {
-    thermal_d3q15<R, STD>(g, ux, uy, uz, T, c);
+    thermal_d3q15<R, STD>(g, ux, uy, uz, T, Tr, dT, c);
     return;
   } else {
   // thermal D3Q7: links 1/2 = +-x, 3/4 = +-y, 5/6 = +-z

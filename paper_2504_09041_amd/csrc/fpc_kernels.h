@@ -144,7 +144,7 @@ inline bool standard_rates(const StepArgs<R>& a, int D, int Qg) {
 }
 
 // Launchers of the fused step (defined in fpc_step.hip).
-// tk: thermal lattice, 0 = D2Q5 / D3Q7, 1 = D2Q9 / D3Q15 (FP64 only).
+// tk: thermal lattice, 0 = D2Q5 / D3Q7, 1 = D2Q9 / D3Q15.
 // mode: 0 = step (pull from args.src), 1 = init (equilibrium from T_init).
 template <class R>
 hipError_t launch_step2d(const StepArgs<R>& a, int up, int tk, const double* T_init, int mode, hipStream_t s);

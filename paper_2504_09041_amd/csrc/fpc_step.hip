@@ -497,14 +497,12 @@ hipError_t launch_multi_up(const StepArgs<R>& a, const MultiCtl& c0, hipStream_t
 
 }  // namespace
 
-// tk: thermal lattice, 0 = D2Q5 / D3Q7, 1 = the paper's D2Q9 / D3Q15 (FP64 only)
+// tk: thermal lattice, 0 = D2Q5 / D3Q7, 1 = the paper's D2Q9 / D3Q15
 template <class R>
 hipError_t launch_step2d(const StepArgs<R>& a, int up, int tk, const double* T_init, int mode, hipStream_t s) {
   if (tk == 0)
     return up == 0 ? launch_up<Lat2, R, 0>(a, T_init, mode, s) : launch_up<Lat2, R, 1>(a, T_init, mode, s);
-  if constexpr (sizeof(R) == 8)
-    return up == 0 ? launch_up<Lat2T9, R, 0>(a, T_init, mode, s) : launch_up<Lat2T9, R, 1>(a, T_init, mode, s);
-  return hipErrorInvalidValue;
+  return up == 0 ? launch_up<Lat2T9, R, 0>(a, T_init, mode, s) : launch_up<Lat2T9, R, 1>(a, T_init, mode, s);
 }
 
 template <class R>
@@ -516,14 +514,11 @@ hipError_t launch_step3d(const StepArgs<R>& a, int up, int tk, const double* T_i
       default: return launch_up<Lat3, R, 2>(a, T_init, mode, s);
     }
   }
-  if constexpr (sizeof(R) == 8) {
-    switch (up) {
-      case 0: return launch_up<Lat3T15, R, 0>(a, T_init, mode, s);
-      case 1: return launch_up<Lat3T15, R, 1>(a, T_init, mode, s);
-      default: return launch_up<Lat3T15, R, 2>(a, T_init, mode, s);
-    }
+  switch (up) {
+    case 0: return launch_up<Lat3T15, R, 0>(a, T_init, mode, s);
+    case 1: return launch_up<Lat3T15, R, 1>(a, T_init, mode, s);
+    default: return launch_up<Lat3T15, R, 2>(a, T_init, mode, s);
   }
-  return hipErrorInvalidValue;
 }
 
 // 2D in either precision and 3D FP32 (the 3D FP64 step would hold more than
