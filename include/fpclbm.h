@@ -426,9 +426,10 @@ int fpc_nusselt_seed(fpc_sim* s, int wall_face, double weight, double* dJdT, dou
  * node is written (padding is not).  Each node reads mu_in along the reversed
  * links (the transpose of the pull, with the wall rules: -1 on Dirichlet
  * links) and writes only its own slots.  The method is not part of the paper:
- * this is the exact adjoint of the discrete update above.  Available for the
- * FP model on FPC_D2Q9_D2Q5 / FPC_D3Q27_D3Q7; other configurations return
- * FPC_ERR_STATE (as does fpc_adjoint_init).
+ * this is the exact adjoint of the discrete update above.  Available on
+ * FPC_D2Q9_D2Q5 / FPC_D3Q27_D3Q7 with the FP model or the MCM comparator; the
+ * D2Q9 / D3Q15 thermal lattices return FPC_ERR_STATE (as does
+ * fpc_adjoint_init).
  */
 int fpc_adjoint_step(fpc_sim* s, const void* S_prev, const void* mu_in, void* mu_out, const double* dJdT,
                      double ke_weight, double* const* dJdtheta);

@@ -7,7 +7,8 @@
 //   u = (j + F/2) / rho                                         (App. A Step 7)
 //   kappa = C(u) f        (central moments, tensor product of 1D shifts)
 //   kappa~: relaxation order by order, attractors from the recurrence with
-//           D' = c_s^2 I up to second order and D'_ab = kappa~_ab / rho above,
+//           D' = c_s^2 I up to second order and D'_ab = kappa~_ab / rho above
+//           (FP), or the Maxwellian central moments rho prod c(m_d) (MCM),
 //           sources sigma_m = m_up (F/rho) kappa_{m - e_up}     (Eq. sourceCM2D)
 //   f~ = C(u)^-1 kappa~
 //   eta = C_g(u) g, eta~ (option A), g~ = C_g(u)^-1 eta~.
@@ -162,6 +163,18 @@ struct Terms {
   }
 };
 
+// Maxwellian central moment of exponents m over rho (the MCM comparator's
+// attractor, Sec. 7): prod_d c(m_d) with c(0) = 1, c(1) = 0, c(2) = c_s^2.
+template <int D>
+__device__ constexpr double maxwell_cm(int i) {
+  double v = 1.0;
+  for (int ax = 0; ax < D; ++ax) {
+    const int m = MS<D>::m(i, ax);
+    v *= m == 0 ? 1.0 : (m == 1 ? 0.0 : 1.0 / 3.0);
+  }
+  return v;
+}
+
 // Forward collision on plain populations with everything the reverse needs.
 template <class R, int D>
 struct Tape {
@@ -265,10 +278,14 @@ __device__ __forceinline__ void forward(const R* f, const R* g, const CollParams
     for (int i = 0; i < NM; ++i) {
       if (M::order(i) != s) continue;
       R mv = R(0);
+      if (mcm<STD>(c)) {
+        mv = R(maxwell_cm<D>(i)) * rho;
+      } else {
 #pragma unroll
-      for (int p = 0; p < Terms<D>::npairs; ++p)
-        if (Terms<D>::valid(i, p)) mv += R(Terms<D>::coef(i, p)) * t.kt[Terms<D>::A(p)] * t.kt[Terms<D>::B(i, p)];
-      mv = mv * (ir * (R(1) / R(s)));
+        for (int p = 0; p < Terms<D>::npairs; ++p)
+          if (Terms<D>::valid(i, p)) mv += R(Terms<D>::coef(i, p)) * t.kt[Terms<D>::A(p)] * t.kt[Terms<D>::B(i, p)];
+        mv = mv * (ir * (R(1) / R(s)));
+      }
       R sig = R(0);
       const int mu = M::m(i, UP);
       if (mu > 0 && M::order(M::down(i, UP)) >= 2) sig = R(mu) * Fr * t.k[M::down(i, UP)];
@@ -441,18 +458,22 @@ __device__ __forceinline__ void reverse(const Tape<R, D>& t, const CollParams<R>
       if (!unit) kp[i] += (R(1) - w) * ktb;
       // attractor
       const R mvb = unit ? ktb : w * ktb;
-      const R irs = t.ir * (R(1) / R(s));
-      R mv = R(0);
+      if (mcm<STD>(c)) {
+        if (maxwell_cm<D>(i) != 0.0) rhob += mvb * R(maxwell_cm<D>(i));
+      } else {
+        const R irs = t.ir * (R(1) / R(s));
+        R mv = R(0);
 #pragma unroll
-      for (int p = 0; p < Terms<D>::npairs; ++p)
-        if (Terms<D>::valid(i, p)) {
-          const int A = Terms<D>::A(p), B = Terms<D>::B(i, p);
-          const R cf = R(Terms<D>::coef(i, p)) * irs;
-          mv += cf * t.kt[A] * t.kt[B];
-          kb[A] += mvb * cf * t.kt[B];
-          kb[B] += mvb * cf * t.kt[A];
-        }
-      rhob -= mvb * mv * t.ir;
+        for (int p = 0; p < Terms<D>::npairs; ++p)
+          if (Terms<D>::valid(i, p)) {
+            const int A = Terms<D>::A(p), B = Terms<D>::B(i, p);
+            const R cf = R(Terms<D>::coef(i, p)) * irs;
+            mv += cf * t.kt[A] * t.kt[B];
+            kb[A] += mvb * cf * t.kt[B];
+            kb[B] += mvb * cf * t.kt[A];
+          }
+        rhob -= mvb * mv * t.ir;
+      }
       // source
       const int mu = M::m(i, UP);
       if (mu > 0 && M::order(M::down(i, UP)) >= 2) {

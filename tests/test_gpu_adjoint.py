@@ -54,15 +54,16 @@ def _ptr(t):
 
 @pytest.mark.parametrize("case", list(G.SMALL_CASES))
 @pytest.mark.parametrize("precision,tol", [("f64", 1e-12), ("f32uni", 2e-5), ("f32dev", 2e-5)])
-def test_adjoint_step_matches_oracle_vjp(case, precision, tol):
+@pytest.mark.parametrize("model", ["FP", "MCM"])
+def test_adjoint_step_matches_oracle_vjp(case, precision, tol, model):
     """mu_{n-1} = collide_n^T (pull^T mu_n + seed) and the wall-temperature
     gradient of one step against the oracle's autograd."""
     from paper_2504_09041_amd import _abi as A
 
-    print(f"case={case} precision={precision}", flush=True)
+    print(f"case={case} precision={precision} model={model}", flush=True)
     cfg = G.small_config(case)
-    prm = params_from_config(cfg)
-    f0, g0 = G.perturbed_state(cfg, seed=31)
+    prm = params_from_config(cfg, model=model)
+    f0, g0 = G.perturbed_state(cfg, seed=31, model=model)
     face = _dirichlet_face(cfg)
     theta = None
     if face is not None:
@@ -74,7 +75,7 @@ def test_adjoint_step_matches_oracle_vjp(case, precision, tol):
     ke = 0.7
     ref, dth_ref = G.adjoint_step_reference(prm, f0, g0, mu, dJdT, ke, face, theta)
     # GPU adjoint step
-    sim = G.make_sim(cfg, precision, wall_profiles={face: theta} if theta is not None else None)
+    sim = G.make_sim(cfg, precision, wall_profiles={face: theta} if theta is not None else None, model=model)
     G.load_state(sim, f0, g0)
     S_prev = sim.save()
     dt = torch.float64 if precision == "f64" else torch.float32
@@ -101,13 +102,14 @@ def test_adjoint_step_matches_oracle_vjp(case, precision, tol):
 
 
 @pytest.mark.parametrize("case", list(G.SMALL_CASES))
-def test_adjoint_init_matches_oracle(case):
+@pytest.mark.parametrize("model", ["FP", "MCM"])
+def test_adjoint_init_matches_oracle(case, model):
     """dJ/dT_init from mu_0: lambda_0 = pull^T mu_0, then the adjoint of the
     initial collision with the level-0 seed."""
     from paper_2504_09041_amd import _abi as A
 
     cfg = G.small_config(case)
-    prm = params_from_config(cfg)
+    prm = params_from_config(cfg, model=model)
     T0 = G.initial_T(cfg) + 0.2 * torch.tensor(workloads.uniform_field(tuple(cfg["shape"][::-1]), 41))
     T = T0.clone().requires_grad_(True)
     fo, go = osim.init_state(prm, T)
@@ -118,7 +120,7 @@ def test_adjoint_init_matches_oracle(case):
     mac = osim.macros_of_state(prm, fo, go)
     L = (lam_f * fo).sum() + (lam_g * go).sum() + (dJdT * mac["T"]).sum() + 0.3 * osim.kinetic_energy(mac)
     (gT,) = torch.autograd.grad(L, [T])
-    sim = G.make_sim(cfg, "f64")
+    sim = G.make_sim(cfg, "f64", model=model)
     lin = _lam_buffer(sim, mu, torch.float64)
     out = torch.empty(tuple(fo.shape[1:]), dtype=torch.float64, device="cuda")
     Tc = T0.cuda().contiguous()
@@ -140,11 +142,11 @@ GRAD_CASES = {
 }
 
 
-def _solver(cfg, precision, kind, face, window, N, K, theta_face):
+def _solver(cfg, precision, kind, face, window, N, K, theta_face, model="FP"):
     from paper_2504_09041_amd import adjoint as adj
     from paper_2504_09041_amd.sim import params_from_workload
 
-    p = params_from_workload(cfg, precision)
+    p = params_from_workload(cfg, precision, model=model)
     obj = adj.WallNusselt(face, *window) if kind == "nu" else adj.KineticEnergy(window)
     return adj.AdjointSolver(p, N, K, obj, theta_face=theta_face)
 
@@ -154,17 +156,18 @@ def _theta0(cfg, face, seed):
     return cfg["faces"][face]["T"] + 0.05 * torch.tensor(workloads.uniform_field(shp, seed))
 
 
-@pytest.mark.parametrize("name", list(GRAD_CASES))
-def test_checkpointed_gradient_matches_oracle_autograd(name):
+@pytest.mark.parametrize("name,model", [(n, "FP") for n in GRAD_CASES] +
+                         [("mixed2d_nu_bottom_theta", "MCM"), ("rb3d_ke", "MCM")])
+def test_checkpointed_gradient_matches_oracle_autograd(name, model):
     wl, shape, (kind, face, window), N, K, tf = GRAD_CASES[name]
-    print(f"case={name}", flush=True)
+    print(f"case={name} model={model}", flush=True)
     cfg = workloads.config(wl, shape=shape)
-    prm = params_from_config(cfg)
+    prm = params_from_config(cfg, model=model)
     T0 = G.initial_T(cfg) + 0.05 * torch.tensor(workloads.uniform_field(tuple(shape[::-1]), 51))
     th0 = _theta0(cfg, tf, 52)
     J_o, gth_o, gT_o = ograd.gradient(prm, T0, N, kind, face=face, window=window if kind == "nu" else None,
                                       theta_face=tf, theta=th0, at=window if kind == "ke" else None)
-    s = _solver(cfg, "f64", kind, face, window, N, K, tf)
+    s = _solver(cfg, "f64", kind, face, window, N, K, tf, model=model)
     J = s.forward(th0.cuda(), T0.cuda())
     gth, gT = s.backward()
     print(f"  J gpu {J:.15e} oracle {J_o:.15e}")

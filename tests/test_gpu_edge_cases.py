@@ -98,7 +98,8 @@ def test_zero_steps_leave_the_state_alone():
 def test_state_above_4GiB_on_sampled_nodes(workload, precision, shape, tol):
     """One step of a state larger than 4 GiB (64-bit element offsets instead
     of buffer descriptors), checked at ~2000 sampled nodes plus corners and
-    face bands."""
+    face bands; then one step with fused diagnostics against the separate
+    pass."""
     print(f"workload={workload} precision={precision} shape={shape}", flush=True)
     cfg = workloads.config(workload, shape=shape)
     prm = params_from_config(cfg)
@@ -119,6 +120,25 @@ def test_state_above_4GiB_on_sampled_nodes(workload, precision, shape, tol):
     fo, go, _ = osim.step_at(prm, gf, gg, (x, y, z))
     assert G.rel_err(got[: lf.Q], fo) < tol
     assert G.rel_err(got[lf.Q:], go) < tol
+    # the diagnostics fused into a step on the 64-bit addressing path equal
+    # the separate pass over the state that step writes
+    import ctypes
+
+    from paper_2504_09041_amd import _abi as A
+
+    face = cfg["nu_face"]
+    fused = sim.step_diagnostics(1, face).cpu().tolist()
+    ref = torch.full((5,), float("nan"), dtype=torch.float64, device="cuda")
+    A.check(A.load().fpc_diagnostics_noalloc(sim.handle, face, ctypes.c_void_p(ref.data_ptr())),
+            "fpc_diagnostics_noalloc")
+    ref = ref.cpu().tolist()
+    sum_abs_T = float(sim.macros()["T"].abs().sum())
+    print(f"  fused {fused}\n  ref   {ref}")
+    assert abs(fused[0] - ref[0]) <= 1e-12 * max(1.0, abs(ref[0]))
+    assert abs(fused[1] - ref[1]) <= 1e-13 * abs(ref[1])
+    assert abs(fused[2] - ref[2]) <= 1e-13 * sum_abs_T
+    assert abs(fused[3] - ref[3]) <= 1e-13 * abs(ref[3])
+    assert fused[4] == ref[4]
     sim.close()
     torch.cuda.empty_cache()
 

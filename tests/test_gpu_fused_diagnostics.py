@@ -149,6 +149,31 @@ def test_fused_diagnostics_on_larger_grids(wl, shape, precision, n):
     b.close()
 
 
+@pytest.mark.parametrize("case,face", [("mixed2d", 3), ("rb2d_tiles", 2), ("dhc3d_tiles", 1)])
+@pytest.mark.parametrize("precision", ["f64", "f32dev"])
+def test_fused_diagnostics_with_a_wall_temperature_profile(case, face, precision):
+    """A per-node Dirichlet temperature on the Nusselt face: the fused wall
+    term reads the profile as the separate pass does."""
+    print(f"case={case} face={face} precision={precision}", flush=True)
+    cfg = G.small_config(case)
+    nx, ny, nz = cfg["shape"]
+    shp = {0: (nz, ny), 1: (nz, nx), 2: (ny, nx)}[face // 2]
+    Tw = cfg["faces"][face]["T"] + 0.1 * torch.tensor(workloads.uniform_field(shp, 91))
+    f0, g0 = G.perturbed_state(cfg, seed=92)
+    a = G.make_sim(cfg, precision, wall_profiles={face: Tw})
+    b = G.make_sim(cfg, precision, wall_profiles={face: Tw})
+    G.load_state(a, f0, g0)
+    G.load_state(b, f0, g0)
+    got = a.step_diagnostics(3, face).cpu().tolist()
+    b.step(2)
+    b.step(1)
+    ref = _noalloc(b, face)
+    _pair(a, b, precision)
+    _compare(got, ref, _sum_abs_T(b))
+    a.close()
+    b.close()
+
+
 @pytest.mark.parametrize("case", ["rb2d_tiles", "dhc3d_tiles"])
 @pytest.mark.parametrize("precision", ["f64", "f32dev"])
 def test_fused_diagnostics_count_non_finite_nodes(case, precision):
