@@ -69,9 +69,9 @@ size_t elem_size(int precision) { return precision == FPC_FP64 ? 8 : 4; }
 // the paper's own thermal lattices (D2Q9 / D3Q15)
 bool paper_thermal(int lattice) { return lattice == FPC_D2Q9_D2Q9 || lattice == FPC_D3Q27_D3Q15; }
 
-// the hand-written adjoint covers the D2Q5 / D3Q7 thermal lattices (FP model
-// and the MCM comparator)
-bool adjoint_supported(const fpc_params& p) { return !paper_thermal(p.lattice); }
+// the hand-written adjoint covers the D2Q5 / D3Q7 thermal lattices and the
+// paper's D2Q9 (FP model, option A or B, and the MCM comparator)
+bool adjoint_supported(const fpc_params& p) { return p.lattice != FPC_D3Q27_D3Q15; }
 
 int lattice_dims(int lattice, int* Qf, int* Qg, int* dim) {
   if (lattice == FPC_D2Q9_D2Q5) {
@@ -860,7 +860,7 @@ int fpc_import_fp64(fpc_sim* s, const double* src, long long step) {
 int fpc_adjoint_step(fpc_sim* s, const void* S_prev, const void* mu_in, void* mu_out, const double* dJdT,
                      double ke_weight, double* const* dJdtheta) {
   if (!s || !S_prev || !mu_in || !mu_out) return fail(FPC_ERR_ARG, "NULL argument");
-  if (!adjoint_supported(s->p)) return fail(FPC_ERR_STATE, "adjoint: D2Q5 / D3Q7 thermal lattices only");
+  if (!adjoint_supported(s->p)) return fail(FPC_ERR_STATE, "adjoint: not available on the D3Q15 thermal lattice");
   if (mu_in == mu_out || mu_out == S_prev) return fail(FPC_ERR_ARG, "mu_out must not alias mu_in or S_prev");
   if (!std::isfinite(ke_weight)) return fail(FPC_ERR_ARG, "ke_weight not finite");
   double* dth[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
@@ -869,13 +869,14 @@ int fpc_adjoint_step(fpc_sim* s, const void* S_prev, const void* mu_in, void* mu
   for (int f = 0; f < 6; ++f)
     if (dth[f] && !(s->p.bc[f] == FPC_BC_NOSLIP_DIRICHLET || s->p.bc[f] == FPC_BC_LID_DIRICHLET))
       return fail(FPC_ERR_STATE, "dJdtheta[%d] given for a face without a Dirichlet temperature", f);
+  const int tk = paper_thermal(s->p.lattice) ? 1 : 0;
   hipError_t e;
   if (s->p.precision == FPC_FP64) {
     const StepArgs<double> a = make_args<double>(s, S_prev, nullptr);
-    e = launch_adjoint_step<double>(a, s->dim, s->p.up_axis, mu_in, mu_out, dJdT, ke_weight, dth, s->stream);
+    e = launch_adjoint_step<double>(a, s->dim, s->p.up_axis, tk, mu_in, mu_out, dJdT, ke_weight, dth, s->stream);
   } else {
     const StepArgs<float> a = make_args<float>(s, S_prev, nullptr);
-    e = launch_adjoint_step<float>(a, s->dim, s->p.up_axis, mu_in, mu_out, dJdT, ke_weight, dth, s->stream);
+    e = launch_adjoint_step<float>(a, s->dim, s->p.up_axis, tk, mu_in, mu_out, dJdT, ke_weight, dth, s->stream);
   }
   if (e != hipSuccess) return hipfail(e, "adjoint step kernel");
   return FPC_OK;
@@ -884,15 +885,16 @@ int fpc_adjoint_step(fpc_sim* s, const void* S_prev, const void* mu_in, void* mu
 int fpc_adjoint_init(fpc_sim* s, const double* T_init, const void* mu0, const double* dJdT, double ke_weight,
                      double* dJdT_init) {
   if (!s || !T_init || !mu0 || !dJdT_init) return fail(FPC_ERR_ARG, "NULL argument");
-  if (!adjoint_supported(s->p)) return fail(FPC_ERR_STATE, "adjoint: D2Q5 / D3Q7 thermal lattices only");
+  if (!adjoint_supported(s->p)) return fail(FPC_ERR_STATE, "adjoint: not available on the D3Q15 thermal lattice");
   if (!std::isfinite(ke_weight)) return fail(FPC_ERR_ARG, "ke_weight not finite");
+  const int tk = paper_thermal(s->p.lattice) ? 1 : 0;
   hipError_t e;
   if (s->p.precision == FPC_FP64) {
     const StepArgs<double> a = make_args<double>(s, nullptr, nullptr);
-    e = launch_adjoint_init<double>(a, s->dim, s->p.up_axis, T_init, mu0, dJdT, ke_weight, dJdT_init, s->stream);
+    e = launch_adjoint_init<double>(a, s->dim, s->p.up_axis, tk, T_init, mu0, dJdT, ke_weight, dJdT_init, s->stream);
   } else {
     const StepArgs<float> a = make_args<float>(s, nullptr, nullptr);
-    e = launch_adjoint_init<float>(a, s->dim, s->p.up_axis, T_init, mu0, dJdT, ke_weight, dJdT_init, s->stream);
+    e = launch_adjoint_init<float>(a, s->dim, s->p.up_axis, tk, T_init, mu0, dJdT, ke_weight, dJdT_init, s->stream);
   }
   if (e != hipSuccess) return hipfail(e, "adjoint init kernel");
   return FPC_OK;

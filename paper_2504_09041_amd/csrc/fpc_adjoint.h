@@ -176,16 +176,45 @@ __device__ constexpr double maxwell_cm(int i) {
 }
 
 // Forward collision on plain populations with everything the reverse needs.
-template <class R, int D>
+// QG: thermal lattice, 2D + 1 (D2Q5 / D3Q7) or 9 (the paper's D2Q9, whose
+// moments use the work layout of MS<2>).
+template <class R, int D, int QG = 2 * D + 1>
 struct Tape {
   static constexpr int NM = MS<D>::NM;
-  static constexpr int NG = 2 * D + 1;
+  static constexpr int NG = QG;
   R rho, ir, T, Fb, u[3];  // ir = 1 / rho
   R k[NM];   // pre-collision central moments
   R kt[NM];  // post-collision central moments
-  R e[NG];   // thermal central moments (0, +-axis order 1, order 2 per axis)
+  R e[NG];   // thermal central moments (D2Q5 / D3Q7: 0, +-axis order 1, order 2 per axis)
   R et[NG];  // post-collision thermal central moments
 };
+
+// Thermal attractors of the paper's D2Q9 lattice above second order
+// (Eq. Mvcmattractor2D_g): option A (c^_s^2 I at every order), option B
+// (post-collision second order over T), MCM (T prod c(m_d)); et holds the
+// post-collision moments up to second order (work layout of MS<2>).
+template <class R, bool STD>
+__device__ __forceinline__ void thermal9_attractors(const CollParams<R>& c, R T, const R (&et)[9], R& m21, R& m12,
+                                                    R& m22) {
+  using M = MS<2>;
+  constexpr int i10 = M::at(1, 0, 0), i01 = M::at(0, 1, 0), i20 = M::at(2, 0, 0), i02 = M::at(0, 2, 0),
+                i11 = M::at(1, 1, 0);
+  const R cT = c.cs2T;
+  if (mcm<STD>(c)) {
+    m21 = R(0);
+    m12 = R(0);
+    m22 = cT * cT * T;
+  } else if (option_b<STD>(c)) {
+    const R iT = R(1) / T;
+    m21 = R(2) / R(3) * iT * (et[i20] * et[i01] + R(2) * et[i11] * et[i10]);
+    m12 = R(2) / R(3) * iT * (et[i02] * et[i10] + R(2) * et[i11] * et[i01]);
+    m22 = iT * (et[i20] * et[i02] + R(2) * et[i11] * et[i11]);
+  } else {
+    m21 = R(2) / R(3) * cT * et[i01];
+    m12 = R(2) / R(3) * cT * et[i10];
+    m22 = R(0.5) * cT * (et[i20] + et[i02]);
+  }
+}
 
 // Thermal moment layout (D2Q5 / D3Q7): e[0] = eta_0, e[1+ax] = eta_{e_ax},
 // e[1+D+ax] = eta_{2 e_ax}.  Populations: g[0] rest, g[1+2ax] = +ax link,
@@ -196,8 +225,8 @@ __device__ constexpr int tlink(int ax, int sgn) {
   return D == 2 ? (sgn > 0 ? 1 + ax : 3 + ax) : (sgn > 0 ? 1 + 2 * ax : 2 + 2 * ax);
 }
 
-template <class R, int D, int UP, bool STD = false>
-__device__ __forceinline__ void forward(const R* f, const R* g, const CollParams<R>& c, Tape<R, D>& t) {
+template <class R, int D, int UP, bool STD = false, int QG = 2 * D + 1>
+__device__ __forceinline__ void forward(const R* f, const R* g, const CollParams<R>& c, Tape<R, D, QG>& t) {
   using M = MS<D>;
   constexpr int NM = M::NM;
   constexpr R cs2 = R(1) / R(3);
@@ -219,7 +248,7 @@ __device__ __forceinline__ void forward(const R* f, const R* g, const CollParams
   }
   R T = g[0];
 #pragma unroll
-  for (int q = 1; q < 2 * D + 1; ++q) T += g[q];
+  for (int q = 1; q < QG; ++q) T += g[q];
   const R Fb = c.gbeta * (T - c.T0);
   const R ir = R(1) / rho;
   t.rho = rho;
@@ -297,6 +326,33 @@ __device__ __forceinline__ void forward(const R* f, const R* g, const CollParams
       }
     }
   }
+  if constexpr (QG != 2 * D + 1) {
+    // thermal D2Q9: the same tensor-product shifts as the fluid, then the
+    // relaxation of the paper's D2Q9 thermal collision (App. B Step 3)
+    static_assert(D == 2 && QG == kQ2, "thermal D2Q9 only");
+    constexpr int i00 = M::at(0, 0, 0), i10 = M::at(1, 0, 0), i01 = M::at(0, 1, 0), i20 = M::at(2, 0, 0),
+                  i02 = M::at(0, 2, 0), i11 = M::at(1, 1, 0), i21 = M::at(2, 1, 0), i12 = M::at(1, 2, 0),
+                  i22 = M::at(2, 2, 0);
+#pragma unroll
+    for (int i = 0; i < QG; ++i) t.e[i] = g[M::pop(i)];
+    apply<R, 2, 0>(t.e, t.u);
+    auto og = [&](int k) -> R { return rate_g<2, STD>(c, k); };
+    const R cT = c.cs2T;
+    t.et[i00] = T;
+    t.et[i10] = (R(1) - og(1)) * t.e[i10];
+    t.et[i01] = (R(1) - og(2)) * t.e[i01];
+    const R s2 = t.e[i20] + t.e[i02], d2 = t.e[i20] - t.e[i02];
+    const R ts = s2 + og(3) * (R(2) * cT * T - s2), td = (R(1) - og(4)) * d2;
+    t.et[i20] = R(0.5) * (ts + td);
+    t.et[i02] = R(0.5) * (ts - td);
+    t.et[i11] = (R(1) - og(5)) * t.e[i11];
+    R m21, m12, m22;
+    thermal9_attractors<R, STD>(c, T, t.et, m21, m12, m22);
+    t.et[i21] = t.e[i21] + og(6) * (m21 - t.e[i21]);
+    t.et[i12] = t.e[i12] + og(7) * (m12 - t.e[i12]);
+    t.et[i22] = t.e[i22] + og(8) * (m22 - t.e[i22]);
+    return;
+  } else {
   // thermal: raw -> central
   R n[2 * D + 1];
   n[0] = T;
@@ -327,12 +383,13 @@ __device__ __forceinline__ void forward(const R* f, const R* g, const CollParams
     for (int ax = 0; ax < 3; ++ax)
       t.et[4 + ax] = unit_g<D, STD>(4 + ax) ? c.cs2T * T : t.e[4 + ax] + og[4 + ax] * (c.cs2T * T - t.e[4 + ax]);
   }
+  }
 }
 
 // Reverse of forward(): given fb (= f~bar) and gb (= g~bar) on the post-collision
 // populations, overwrite them with the adjoints of the pre-collision ones.
-template <class R, int D, int UP, bool STD = false>
-__device__ __forceinline__ void reverse(const Tape<R, D>& t, const CollParams<R>& c, R* fb, R* gb) {
+template <class R, int D, int UP, bool STD = false, int QG = 2 * D + 1>
+__device__ __forceinline__ void reverse(const Tape<R, D, QG>& t, const CollParams<R>& c, R* fb, R* gb) {
   using M = MS<D>;
   constexpr int NM = M::NM;
   constexpr R cs2 = R(1) / R(3);
@@ -341,7 +398,68 @@ __device__ __forceinline__ void reverse(const Tape<R, D>& t, const CollParams<R>
   const R* og = c.omg;
 
   // ---- thermal: g~ = P_g^-1 F_g(u)^-1 eta~ ----
-  {
+  if constexpr (QG != 2 * D + 1) {
+    // thermal D2Q9: g~ = C(u)^-1 eta~, eta = C(u) g (tensor-product shifts)
+    constexpr int i00 = M::at(0, 0, 0), i10 = M::at(1, 0, 0), i01 = M::at(0, 1, 0), i20 = M::at(2, 0, 0),
+                  i02 = M::at(0, 2, 0), i11 = M::at(1, 1, 0), i21 = M::at(2, 1, 0), i12 = M::at(1, 2, 0),
+                  i22 = M::at(2, 2, 0);
+    auto og = [&](int k) -> R { return rate_g<2, STD>(c, k); };
+    const R cT = c.cs2T;
+    R tb[QG];  // adjoint of the post-collision thermal moments
+#pragma unroll
+    for (int i = 0; i < QG; ++i) tb[i] = gb[M::pop(i)];
+    apply<R, 2, 3>(tb, t.u);
+#pragma unroll
+    for (int i = 0; i < QG; ++i)
+#pragma unroll
+      for (int ax = 0; ax < 2; ++ax)
+        if (M::m(i, ax) > 0) ub[ax] += tb[i] * R(M::m(i, ax)) * t.et[M::down(i, ax)];
+    // orders 3-4: eta~_m = (1 - w) eta_m + w m_m, attractors from eta~ up to second order and T
+    R eb[QG];
+    eb[i22] = (R(1) - og(8)) * tb[i22];
+    eb[i21] = (R(1) - og(6)) * tb[i21];
+    eb[i12] = (R(1) - og(7)) * tb[i12];
+    const R m22b = og(8) * tb[i22], m21b = og(6) * tb[i21], m12b = og(7) * tb[i12];
+    if (mcm<STD>(c)) {
+      Tb += cT * cT * m22b;
+    } else if (option_b<STD>(c)) {
+      const R iT = R(1) / t.T, f = R(2) / R(3) * iT;
+      R m21, m12, m22;
+      thermal9_attractors<R, STD>(c, t.T, t.et, m21, m12, m22);
+      tb[i20] += iT * t.et[i02] * m22b + f * t.et[i01] * m21b;
+      tb[i02] += iT * t.et[i20] * m22b + f * t.et[i10] * m12b;
+      tb[i11] += R(4) * iT * t.et[i11] * m22b + R(2) * f * (t.et[i10] * m21b + t.et[i01] * m12b);
+      tb[i01] += f * t.et[i20] * m21b + R(2) * f * t.et[i11] * m12b;
+      tb[i10] += f * t.et[i02] * m12b + R(2) * f * t.et[i11] * m21b;
+      Tb -= iT * (m22 * m22b + m21 * m21b + m12 * m12b);
+    } else {
+      tb[i20] += R(0.5) * cT * m22b;
+      tb[i02] += R(0.5) * cT * m22b;
+      tb[i01] += R(2) / R(3) * cT * m21b;
+      tb[i10] += R(2) / R(3) * cT * m12b;
+    }
+    // second order: 11 toward 0; 2s toward 2 c^2 T; 2d toward 0
+    eb[i11] = (R(1) - og(5)) * tb[i11];
+    const R tsb = R(0.5) * (tb[i20] + tb[i02]), tdb = R(0.5) * (tb[i20] - tb[i02]);
+    const R s2b = (R(1) - og(3)) * tsb, d2b = (R(1) - og(4)) * tdb;
+    Tb += og(3) * R(2) * cT * tsb;
+    eb[i20] = s2b + d2b;
+    eb[i02] = s2b - d2b;
+    // first order toward 0; eta~_0 = T
+    eb[i10] = (R(1) - og(1)) * tb[i10];
+    eb[i01] = (R(1) - og(2)) * tb[i01];
+    Tb += tb[i00];
+    eb[i00] = R(0);
+    // eta = C(u) g: ubar_i -= sum_m etabar_m m_i eta_{m - e_i}; gbar = C^T etabar
+#pragma unroll
+    for (int i = 0; i < QG; ++i)
+#pragma unroll
+      for (int ax = 0; ax < 2; ++ax)
+        if (M::m(i, ax) > 0) ub[ax] -= eb[i] * R(M::m(i, ax)) * t.e[M::down(i, ax)];
+    apply<R, 2, 2>(eb, t.u);
+#pragma unroll
+    for (int i = 0; i < QG; ++i) gb[M::pop(i)] = eb[i];
+  } else {
     R mb[2 * D + 1];  // adjoint of the post-collision raw moments
     R etb[2 * D + 1];
     // g~_0 = m0 - sum_ax m_{2ax};  g~_{+-ax} = (m_{2ax} +- m_{ax}) / 2
@@ -554,7 +672,7 @@ __device__ __forceinline__ void reverse(const Tape<R, D>& t, const CollParams<R>
   // T enters through the buoyancy force
   Tb += c.gbeta * Fbb;
 #pragma unroll
-  for (int q = 0; q < 2 * D + 1; ++q) gb[q] += Tb;
+  for (int q = 0; q < QG; ++q) gb[q] += Tb;
 }
 
 }  // namespace adj

@@ -40,22 +40,12 @@ namespace {
 
 using namespace stream;
 
-template <int D>
-struct LinkOf {
-  static constexpr int Qf = D == 2 ? kQ2 : kQ3;
-  static constexpr int Qg = D == 2 ? kQ2T : kQ3T;
-  static constexpr int ex(int a) { return D == 2 ? D2_EX[a] : D3_EX[a]; }
-  static constexpr int ey(int a) { return D == 2 ? D2_EY[a] : D3_EY[a]; }
-  static constexpr int ez(int a) { return D == 2 ? 0 : D3_EZ[a]; }
-  static constexpr int opp(int a) { return D == 2 ? D2_OPP[a] : d3_opp(a); }
-  static constexpr double w(int a) { return D == 2 ? w2(a) : w3(a); }
-};
-
 // Seed of the objective on S_n(x): weights on T_n(x) and on the kinetic energy.
-template <class R, int D, int UP>
-__device__ __forceinline__ void add_seed(const adj::Tape<R, D>& t, const CollParams<R>& c, double dJdT, double ke,
-                                         R* fb, R* gb) {
-  using Lk = LinkOf<D>;
+template <class L, class R, int UP>
+__device__ __forceinline__ void add_seed(const adj::Tape<R, L::D, L::Qg>& t, const CollParams<R>& c, double dJdT,
+                                         double ke, R* fb, R* gb) {
+  constexpr int D = L::D;
+  using Lk = L;
   R gs = R(dJdT);
   if (ke != 0.0) {
     const R kw = R(ke);
@@ -120,8 +110,20 @@ __device__ __forceinline__ void tgather(const StepArgs<R>& a, const M& m, int x,
 }
 
 // Wall-temperature gradient: each thermal link of x that met a Dirichlet face
-// in the forward pull (g_a = -g~_abar + 2 w^T_a T_w) adds 2 w^T_a = c^_s^2
-// times its adjoint mu(x, a) to the face's entry of x.
+// in the forward pull (g_a = -g~_abar + 2 w^T_a T_w, T_w the mean over the
+// nd Dirichlet faces the link crosses: one for an axis link, up to two for a
+// diagonal link of D2Q9 at an edge) adds 2 w^T_a / nd times its adjoint
+// mu(x, a) to the entry of x on each of those faces (2 w^T_a = c^_s^2 on the
+// axis links of D2Q5 / D3Q7).
+template <class L, class R, int F>
+__device__ __forceinline__ void theta_face(const AdjArgs<R>& AA, int x, int y, int z, R v) {
+  constexpr int k = F >> 1;
+  const StepArgs<R>& a = AA.s;
+  if (AA.dtheta[F]) {
+    const size_t t = k == 0 ? (size_t)z * a.ny + y : (k == 1 ? (size_t)z * a.nx + x : (size_t)y * a.nx + x);
+    AA.dtheta[F][t] += (double)v;
+  }
+}
 template <class L, class R, bool CX, bool CY, bool CZ, bool PX, int A>
 __device__ __forceinline__ void theta_link(const AdjArgs<R>& AA, const Edges<L, R, CX, CY, CZ, PX>& e, int x, int y,
                                            int z, R v) {
@@ -132,12 +134,18 @@ __device__ __forceinline__ void theta_link(const AdjArgs<R>& AA, const Edges<L, 
     bool wx = false, wy = false, wz = false;
     (void)e.template source<A, true>(wx, wy, wz);
     constexpr int ex = L::tex(A), ey = L::tey(A), ez = L::tez(A);
-    constexpr int F = ex > 0 ? 0 : (ex < 0 ? 1 : (ey > 0 ? 2 : (ey < 0 ? 3 : (ez > 0 ? 4 : 5))));
-    constexpr int k = F >> 1;
-    if ((wx || wy || wz) && a.face[F].dirichlet && AA.dtheta[F]) {
-      const size_t t = k == 0 ? (size_t)z * a.ny + y : (k == 1 ? (size_t)z * a.nx + x : (size_t)y * a.nx + x);
-      AA.dtheta[F][t] += (double)(a.c.cs2T * v);
-    }
+    constexpr int FX = ex > 0 ? 0 : 1, FY = ey > 0 ? 2 : 3, FZ = ez > 0 ? 4 : 5;
+    constexpr int nax = (ex != 0) + (ey != 0) + (ez != 0);
+    const bool dx = ex != 0 && wx && a.face[FX].dirichlet;
+    const bool dy = ey != 0 && wy && a.face[FY].dirichlet;
+    const bool dz = ez != 0 && wz && a.face[FZ].dirichlet;
+    const int nd = (int)dx + (int)dy + (int)dz;
+    if (nd == 0) return;
+    R s = R(2) * L::template wT<R>(A, a.c.cs2T) * v;
+    if (nax > 1 && nd > 1) s = s / R(nd);
+    if (ex != 0 && dx) theta_face<L, R, FX>(AA, x, y, z, s);
+    if (ey != 0 && dy) theta_face<L, R, FY>(AA, x, y, z, s);
+    if (ez != 0 && dz) theta_face<L, R, FZ>(AA, x, y, z, s);
   }
 }
 template <class L, class R, bool CX, bool CY, bool CZ, bool PX, size_t... I>
@@ -188,8 +196,8 @@ __device__ __forceinline__ void adjoint_step(const AdjArgs<R>& A, unsigned total
 #pragma unroll
     for (int q = 0; q < L::Qg; ++q) g[q] += L::template wT<R>(q, a.c.cs2T) * Tr;
   }
-  adj::Tape<R, D> t;
-  adj::forward<R, D, UP, STD>(f, g, a.c, t);
+  adj::Tape<R, D, L::Qg> t;
+  adj::forward<R, D, UP, STD, L::Qg>(f, g, a.c, t);
   R fb[L::Qf], gb[L::Qg];
   if (variant == 0)
     tgather<L, R, M, false, false, false>(a, mL, x, y, z, node, fb, gb);
@@ -200,8 +208,8 @@ __device__ __forceinline__ void adjoint_step(const AdjArgs<R>& A, unsigned total
   else
     tgather<L, R, M, true, true, D == 3>(a, mL, x, y, z, node, fb, gb);
   const size_t cell = ((size_t)z * a.ny + y) * a.nx + x;  // index of the unpadded node fields
-  add_seed<R, D, UP>(t, a.c, A.dJdT ? A.dJdT[cell] : 0.0, A.ke, fb, gb);
-  adj::reverse<R, D, UP, STD>(t, a.c, fb, gb);
+  add_seed<L, R, UP>(t, a.c, A.dJdT ? A.dJdT[cell] : 0.0, A.ke, fb, gb);
+  adj::reverse<R, D, UP, STD, L::Qg>(t, a.c, fb, gb);
   auto cur = mL.cursor(node);
 #pragma unroll
   for (int q = 0; q < L::Qf; ++q) mL.template store_next<false>(cur, fb[q]);
@@ -241,10 +249,10 @@ struct AdjInitArgs {
 // lambda_0 = pull^T mu_0 (mu_0: the adjoint of the pulled populations of step
 // 1), then the adjoint of the initial collision.  Blocks are whole multiples
 // of 64 along x, so a wavefront owns one tile as in the step kernels.
-template <int D, class R, int UP>
+template <class L, class R, int UP>
 __global__ void __launch_bounds__(256) adjoint_init_kernel(AdjInitArgs<R> A) {
-  using Lk = LinkOf<D>;
-  using L = typename std::conditional<D == 2, Lat2, Lat3>::type;
+  constexpr int D = L::D;
+  using Lk = L;
   const StepArgs<R>& a = A.s;
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
@@ -261,11 +269,11 @@ __global__ void __launch_bounds__(256) adjoint_init_kernel(AdjInitArgs<R> A) {
   const R Ti = R(A.T_init[node]);
 #pragma unroll
   for (int q = 0; q < Lk::Qg; ++q) {
-    wg[q] = q == 0 ? R(1) - R(D) * a.c.cs2T : R(0.5) * a.c.cs2T;
+    wg[q] = L::template wT<R>(q, a.c.cs2T);
     g[q] = wg[q] * Ti;
   }
-  adj::Tape<R, D> t;
-  adj::forward<R, D, UP>(f, g, a.c, t);
+  adj::Tape<R, D, L::Qg> t;
+  adj::forward<R, D, UP, false, L::Qg>(f, g, a.c, t);
   R fb[Lk::Qf], gb[Lk::Qg];
   using M = Glob64<R, Q>;
   const M m(A.lam0, nullptr, 0u);
@@ -279,17 +287,17 @@ __global__ void __launch_bounds__(256) adjoint_init_kernel(AdjInitArgs<R> A) {
   } else {
     tgather<L, R, M, true, true, D == 3>(a, m, x, y, z, n, fb, gb);
   }
-  add_seed<R, D, UP>(t, a.c, A.dJdT ? A.dJdT[node] : 0.0, A.ke, fb, gb);
-  adj::reverse<R, D, UP>(t, a.c, fb, gb);
+  add_seed<L, R, UP>(t, a.c, A.dJdT ? A.dJdT[node] : 0.0, A.ke, fb, gb);
+  adj::reverse<R, D, UP, false, L::Qg>(t, a.c, fb, gb);
   double s = 0.0;
 #pragma unroll
   for (int q = 0; q < Lk::Qg; ++q) s += (double)(wg[q] * gb[q]);
   A.dTinit[node] = s;
 }
 
-template <int D, class R, int UP>
+template <class L, class R, int UP>
 hipError_t launch_adj(const AdjArgs<R>* step, const AdjInitArgs<R>* init, hipStream_t st) {
-  using L = typename std::conditional<D == 2, Lat2, Lat3>::type;
+  constexpr int D = L::D;
   const StepArgs<R>& a = step ? step->s : init->s;
   const int bx = a.nx >= 256 ? 256 : (a.nx >= 128 ? 128 : 64);
   const int by = 256 / bx;
@@ -319,23 +327,27 @@ hipError_t launch_adj(const AdjArgs<R>* step, const AdjInitArgs<R>* init, hipStr
       }
     }
   } else {
-    adjoint_init_kernel<D, R, UP><<<grid, block, 0, st>>>(*init);
+    adjoint_init_kernel<L, R, UP><<<grid, block, 0, st>>>(*init);
   }
   return hipGetLastError();
 }
 
+// tk: thermal lattice, 0 = D2Q5 / D3Q7, 1 = the paper's D2Q9 (2D only)
 template <class R>
-hipError_t dispatch(int dim, int up, const AdjArgs<R>* step, const AdjInitArgs<R>* init, hipStream_t st) {
-  if (dim == 2) return up == 0 ? launch_adj<2, R, 0>(step, init, st) : launch_adj<2, R, 1>(step, init, st);
-  if (up == 0) return launch_adj<3, R, 0>(step, init, st);
-  if (up == 1) return launch_adj<3, R, 1>(step, init, st);
-  return launch_adj<3, R, 2>(step, init, st);
+hipError_t dispatch(int dim, int up, int tk, const AdjArgs<R>* step, const AdjInitArgs<R>* init, hipStream_t st) {
+  if (dim == 2 && tk == 1)
+    return up == 0 ? launch_adj<Lat2T9, R, 0>(step, init, st) : launch_adj<Lat2T9, R, 1>(step, init, st);
+  if (tk != 0) return hipErrorInvalidValue;
+  if (dim == 2) return up == 0 ? launch_adj<Lat2, R, 0>(step, init, st) : launch_adj<Lat2, R, 1>(step, init, st);
+  if (up == 0) return launch_adj<Lat3, R, 0>(step, init, st);
+  if (up == 1) return launch_adj<Lat3, R, 1>(step, init, st);
+  return launch_adj<Lat3, R, 2>(step, init, st);
 }
 
 }  // namespace
 
 template <class R>
-hipError_t launch_adjoint_step(const StepArgs<R>& a, int dim, int up, const void* lam_in, void* lam_out,
+hipError_t launch_adjoint_step(const StepArgs<R>& a, int dim, int up, int tk, const void* lam_in, void* lam_out,
                                const double* dJdT, double ke, double* const dtheta[6], hipStream_t st) {
   AdjArgs<R> A;
   A.s = a;
@@ -344,11 +356,11 @@ hipError_t launch_adjoint_step(const StepArgs<R>& a, int dim, int up, const void
   A.dJdT = dJdT;
   A.ke = ke;
   for (int f = 0; f < 6; ++f) A.dtheta[f] = dtheta ? dtheta[f] : nullptr;
-  return dispatch<R>(dim, up, &A, nullptr, st);
+  return dispatch<R>(dim, up, tk, &A, nullptr, st);
 }
 
 template <class R>
-hipError_t launch_adjoint_init(const StepArgs<R>& a, int dim, int up, const double* T_init, const void* lam0,
+hipError_t launch_adjoint_init(const StepArgs<R>& a, int dim, int up, int tk, const double* T_init, const void* lam0,
                                const double* dJdT, double ke, double* dTinit, hipStream_t st) {
   AdjInitArgs<R> A;
   A.s = a;
@@ -357,16 +369,16 @@ hipError_t launch_adjoint_init(const StepArgs<R>& a, int dim, int up, const doub
   A.dJdT = dJdT;
   A.ke = ke;
   A.dTinit = dTinit;
-  return dispatch<R>(dim, up, nullptr, &A, st);
+  return dispatch<R>(dim, up, tk, nullptr, &A, st);
 }
 
-template hipError_t launch_adjoint_step<double>(const StepArgs<double>&, int, int, const void*, void*, const double*,
-                                                double, double* const[6], hipStream_t);
-template hipError_t launch_adjoint_step<float>(const StepArgs<float>&, int, int, const void*, void*, const double*,
-                                               double, double* const[6], hipStream_t);
-template hipError_t launch_adjoint_init<double>(const StepArgs<double>&, int, int, const double*, const void*,
+template hipError_t launch_adjoint_step<double>(const StepArgs<double>&, int, int, int, const void*, void*,
+                                                const double*, double, double* const[6], hipStream_t);
+template hipError_t launch_adjoint_step<float>(const StepArgs<float>&, int, int, int, const void*, void*,
+                                               const double*, double, double* const[6], hipStream_t);
+template hipError_t launch_adjoint_init<double>(const StepArgs<double>&, int, int, int, const double*, const void*,
                                                 const double*, double, double*, hipStream_t);
-template hipError_t launch_adjoint_init<float>(const StepArgs<float>&, int, int, const double*, const void*,
+template hipError_t launch_adjoint_init<float>(const StepArgs<float>&, int, int, int, const double*, const void*,
                                                const double*, double, double*, hipStream_t);
 
 }  // namespace fpc

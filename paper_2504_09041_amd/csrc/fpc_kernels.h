@@ -177,12 +177,13 @@ template <class R>
 hipError_t launch_step_multi(const StepArgs<R>& a, int dim, int up, const MultiCtl& c, hipStream_t s);
 
 // Adjoint kernels (fpc_adjoint.hip).  `a.src` is S_{n-1} (adjoint step) or
-// unused (adjoint of the initial collision).
+// unused (adjoint of the initial collision).  tk: thermal lattice, 0 = D2Q5 /
+// D3Q7, 1 = the paper's D2Q9 (2D only; hipErrorInvalidValue otherwise).
 template <class R>
-hipError_t launch_adjoint_step(const StepArgs<R>& a, int dim, int up, const void* lam_in, void* lam_out,
+hipError_t launch_adjoint_step(const StepArgs<R>& a, int dim, int up, int tk, const void* lam_in, void* lam_out,
                                const double* dJdT, double ke, double* const dtheta[6], hipStream_t s);
 template <class R>
-hipError_t launch_adjoint_init(const StepArgs<R>& a, int dim, int up, const double* T_init, const void* lam0,
+hipError_t launch_adjoint_init(const StepArgs<R>& a, int dim, int up, int tk, const double* T_init, const void* lam0,
                                const double* dJdT, double ke, double* dTinit, hipStream_t s);
 
 // Node-level utilities (fpc_kernels_util.hip).

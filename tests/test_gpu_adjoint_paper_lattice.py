@@ -1,0 +1,177 @@
+"""The hand-written adjoint on the paper's D2Q9 thermal lattice (Sec. 4.4,
+App. B), through the C ABI, against the oracle's autograd gradients.
+
+The thermal moments are the tensor-product central moments of D2Q9 (the
+same shifts as the fluid); above second order they relax toward option A,
+option B or the Maxwellian (MCM) attractors.  A diagonal thermal link that
+crosses a Dirichlet face is anti-bounced toward the mean temperature of the
+Dirichlet faces it crosses, so the wall-temperature gradient of a corner link
+is shared between two faces: the "box" case (Dirichlet walls on all four
+faces) checks that split.
+
+Bars as for the D2Q5 adjoint: one adjoint step and the adjoint of the initial
+collision equal the oracle's vector-Jacobian products to 1e-12 (FP64) and
+2e-5 (FP32 deviations); a checkpointed gradient equals the oracle's autograd
+gradient to 1e-10.  Temperatures are raised by 1.5 so that option B's
+division by T stays away from zero.
+"""
+
+import ctypes
+
+import pytest
+import torch
+
+import workloads
+from oracle import gradient as ograd
+from oracle import sim as osim
+from oracle.params import params_from_config
+from tests import gpu_common as G
+
+pytestmark = pytest.mark.gpu
+
+MODELS = [("FP", "A"), ("FP", "B"), ("MCM", "A")]
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    G.need_gpu()
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _cfg(case):
+    if case == "box2d":
+        # Dirichlet walls on all four faces: corner links cross two of them
+        cfg = G.small_config("dhc2d")
+        cfg["faces"][2] = {"fluid": "noslip", "thermal": "dirichlet", "T": 0.2, "u_w": (0.0, 0.0, 0.0)}
+        cfg["faces"][3] = {"fluid": "noslip", "thermal": "dirichlet", "T": -0.1, "u_w": (0.0, 0.0, 0.0)}
+    else:
+        cfg = G.small_config(case)
+    return G.with_pair(G.shift_temperature(cfg, 1.5), True)
+
+
+def _faces(cfg):
+    return [f for f, fd in enumerate(cfg["faces"]) if fd["thermal"] == "dirichlet"]
+
+
+def _profile_shape(cfg, face):
+    nx, ny, nz = cfg["shape"]
+    return {0: (nz, ny), 1: (nz, nx), 2: (ny, nx)}[face // 2]
+
+
+@pytest.mark.parametrize("case", ["dhc2d", "rb2d", "mixed2d", "rb2d_tiles", "box2d"])
+@pytest.mark.parametrize("model,opt", MODELS)
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-12), ("f32dev", 2e-5)])
+def test_adjoint_step_matches_oracle_vjp(case, model, opt, precision, tol):
+    from paper_2504_09041_amd import _abi as A
+
+    print(f"case={case} model={model} option={opt} precision={precision}", flush=True)
+    cfg = _cfg(case)
+    kw = dict(model=model, thermal_option=opt)
+    prm = params_from_config(cfg, **kw)
+    f0, g0 = G.perturbed_state(cfg, seed=71, **kw)
+    faces = _faces(cfg)
+    face = faces[0] if faces else None
+    theta = None
+    if face is not None:
+        theta = cfg["faces"][face]["T"] + 0.1 * torch.tensor(workloads.uniform_field(_profile_shape(cfg, face), 72))
+    Q = f0.shape[0] + g0.shape[0]
+    mu = torch.tensor(workloads.uniform_field((Q,) + tuple(f0.shape[1:]), 73))
+    dJdT = torch.tensor(workloads.uniform_field(tuple(f0.shape[1:]), 74))
+    ke = 0.7
+    ref, dth_ref = G.adjoint_step_reference(prm, f0, g0, mu, dJdT, ke, face, theta)
+    sim = G.make_sim(cfg, precision, wall_profiles={face: theta} if theta is not None else None, **kw)
+    G.load_state(sim, f0, g0)
+    S_prev = sim.save()
+    dt = torch.float64 if precision == "f64" else torch.float32
+    lin = sim.to_storage(mu, dt)
+    lout = torch.full_like(lin, float("nan"))
+    dth = torch.zeros(theta.shape, dtype=torch.float64, device="cuda") if theta is not None else None
+    arr = (ctypes.c_void_p * 6)()
+    if dth is not None:
+        arr[face] = dth.data_ptr()
+    w = dJdT.cuda().contiguous()
+    A.check(A.load().fpc_adjoint_step(sim.handle, _ptr(S_prev), _ptr(lin), _ptr(lout), _ptr(w),
+                                      ctypes.c_double(ke), arr), "fpc_adjoint_step")
+    torch.cuda.synchronize()
+    got = sim.from_storage(lout).double().cpu()
+    assert torch.isfinite(got).all(), "a slot of mu_{n-1} was not written"
+    err = G.rel_err(got, ref)
+    print(f"  rel err mu {err:.2e}")
+    assert err < tol
+    if theta is not None:
+        e2 = G.rel_err(dth.cpu(), dth_ref)
+        print(f"  rel err dtheta {e2:.2e}")
+        assert e2 < tol
+    sim.close()
+
+
+@pytest.mark.parametrize("case", ["dhc2d", "mixed2d", "box2d"])
+@pytest.mark.parametrize("model,opt", MODELS)
+def test_adjoint_init_matches_oracle(case, model, opt):
+    from paper_2504_09041_amd import _abi as A
+
+    cfg = _cfg(case)
+    kw = dict(model=model, thermal_option=opt)
+    prm = params_from_config(cfg, **kw)
+    T0 = G.initial_T(cfg) + 0.2 * torch.tensor(workloads.uniform_field(tuple(cfg["shape"][::-1]), 75))
+    T = T0.clone().requires_grad_(True)
+    fo, go = osim.init_state(prm, T)
+    Q = fo.shape[0] + go.shape[0]
+    mu = torch.tensor(workloads.uniform_field((Q,) + tuple(fo.shape[1:]), 76))
+    lam_f, lam_g = G.pull_transpose(prm, mu[: fo.shape[0]], mu[fo.shape[0]:])
+    dJdT = torch.tensor(workloads.uniform_field(tuple(fo.shape[1:]), 77))
+    mac = osim.macros_of_state(prm, fo, go)
+    L = (lam_f * fo).sum() + (lam_g * go).sum() + (dJdT * mac["T"]).sum() + 0.3 * osim.kinetic_energy(mac)
+    (gT,) = torch.autograd.grad(L, [T])
+    sim = G.make_sim(cfg, "f64", **kw)
+    lin = sim.to_storage(mu, torch.float64)
+    out = torch.empty(tuple(fo.shape[1:]), dtype=torch.float64, device="cuda")
+    Tc = T0.cuda().contiguous()  # kept alive over the call: the ABI takes raw pointers
+    w = dJdT.cuda().contiguous()
+    A.check(A.load().fpc_adjoint_init(sim.handle, _ptr(Tc), _ptr(lin), _ptr(w), ctypes.c_double(0.3), _ptr(out)),
+            "fpc_adjoint_init")
+    torch.cuda.synchronize()
+    err = G.rel_err(out.cpu(), gT)
+    print(f"case={case} model={model} option={opt}: rel err {err:.2e}")
+    assert err < 1e-12
+    sim.close()
+
+
+@pytest.mark.parametrize("case,kind,face,window,tf", [
+    # wall Nusselt number of the top lid over levels 10..25, gradient on the
+    # bottom-wall profile (whose corner links share the side walls' faces in
+    # the box)
+    ("mixed2d", "nu", 3, (10, 25), 2),
+    ("box2d", "nu", 1, (10, 25), 0),
+    ("dhc2d", "ke", None, 20, 0),
+])
+@pytest.mark.parametrize("model,opt", MODELS)
+def test_checkpointed_gradient_matches_oracle_autograd(case, kind, face, window, tf, model, opt):
+    from paper_2504_09041_amd import adjoint as adj
+    from paper_2504_09041_amd.sim import params_from_workload
+
+    print(f"case={case} kind={kind} model={model} option={opt}", flush=True)
+    cfg = _cfg(case)
+    kw = dict(model=model, thermal_option=opt)
+    prm = params_from_config(cfg, **kw)
+    N, K = 25, 6
+    shape = cfg["shape"]
+    T0 = G.initial_T(cfg) + 0.05 * torch.tensor(workloads.uniform_field(tuple(shape[::-1]), 78))
+    th0 = cfg["faces"][tf]["T"] + 0.05 * torch.tensor(workloads.uniform_field(_profile_shape(cfg, tf), 79))
+    J_o, gth_o, gT_o = ograd.gradient(prm, T0, N, kind, face=face, window=window if kind == "nu" else None,
+                                      theta_face=tf, theta=th0, at=window if kind == "ke" else None)
+    p = params_from_workload(cfg, "f64", **kw)
+    obj = adj.WallNusselt(face, *window) if kind == "nu" else adj.KineticEnergy(window)
+    s = adj.AdjointSolver(p, N, K, obj, theta_face=tf)
+    J = s.forward(th0.cuda(), T0.cuda())
+    gth, gT = s.backward()
+    print(f"  J gpu {J:.15e} oracle {J_o:.15e}")
+    assert abs(J - J_o) <= 1e-12 * max(1.0, abs(J_o))
+    e1 = G.rel_err(gT.cpu(), gT_o)
+    e2 = G.rel_err(gth.cpu(), gth_o)
+    print(f"  rel err dJ/dT_init {e1:.2e}  dJ/dtheta {e2:.2e}")
+    assert e1 < 1e-10
+    assert e2 < 1e-10

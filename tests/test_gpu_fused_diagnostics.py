@@ -82,8 +82,6 @@ CASES = [
 @pytest.mark.parametrize("case,paper_thermal,n", CASES)
 @pytest.mark.parametrize("precision", ["f64", "f32dev"])
 def test_fused_diagnostics_equal_the_separate_pass(case, paper_thermal, n, precision):
-    if paper_thermal and precision != "f64":
-        pytest.skip("the paper's thermal lattices run in FP64 storage only")
     print(f"case={case} paper_thermal={paper_thermal} n={n} precision={precision}", flush=True)
     cfg = G.with_pair(G.small_config(case), paper_thermal)
     f0, g0 = G.perturbed_state(cfg, seed=83)

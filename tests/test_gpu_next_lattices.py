@@ -145,12 +145,12 @@ def test_paper_thermal_fp32_meets_the_bars_over_a_long_run():
         sim.close()
 
 
-def test_adjoint_rejects_the_paper_thermal_lattices():
+def test_adjoint_rejects_the_d3q15_thermal_lattice():
     import ctypes
 
     from paper_2504_09041_amd import _abi as A
 
-    cfg = G.with_pair(G.small_config("dhc2d"), True)
+    cfg = G.with_pair(G.small_config("dhc3d"), True)
     sim = G.make_sim(cfg, "f64")
     S = sim.save()
     lam = torch.zeros_like(S)
