@@ -426,10 +426,9 @@ int fpc_nusselt_seed(fpc_sim* s, int wall_face, double weight, double* dJdT, dou
  * node is written (padding is not).  Each node reads mu_in along the reversed
  * links (the transpose of the pull, with the wall rules: -1 on Dirichlet
  * links) and writes only its own slots.  The method is not part of the paper:
- * this is the exact adjoint of the discrete update above.  Available on
- * FPC_D2Q9_D2Q5, FPC_D3Q27_D3Q7 and FPC_D2Q9_D2Q9 (every model and thermal
- * option); FPC_D3Q27_D3Q15 returns FPC_ERR_STATE (as does fpc_adjoint_init).
- * On D2Q9 thermal, a diagonal link crossing two Dirichlet faces (a corner)
+ * this is the exact adjoint of the discrete update above, on every lattice
+ * pair, model and thermal option.  On the D2Q9 / D3Q15 thermal lattices a
+ * diagonal link crossing two or three Dirichlet faces (an edge or corner)
  * takes their mean temperature, so its gradient is split between them.
  */
 int fpc_adjoint_step(fpc_sim* s, const void* S_prev, const void* mu_in, void* mu_out, const double* dJdT,

@@ -69,10 +69,6 @@ size_t elem_size(int precision) { return precision == FPC_FP64 ? 8 : 4; }
 // the paper's own thermal lattices (D2Q9 / D3Q15)
 bool paper_thermal(int lattice) { return lattice == FPC_D2Q9_D2Q9 || lattice == FPC_D3Q27_D3Q15; }
 
-// the hand-written adjoint covers the D2Q5 / D3Q7 thermal lattices and the
-// paper's D2Q9 (FP model, option A or B, and the MCM comparator)
-bool adjoint_supported(const fpc_params& p) { return p.lattice != FPC_D3Q27_D3Q15; }
-
 int lattice_dims(int lattice, int* Qf, int* Qg, int* dim) {
   if (lattice == FPC_D2Q9_D2Q5) {
     *Qf = 9; *Qg = 5; *dim = 2;
@@ -860,7 +856,6 @@ int fpc_import_fp64(fpc_sim* s, const double* src, long long step) {
 int fpc_adjoint_step(fpc_sim* s, const void* S_prev, const void* mu_in, void* mu_out, const double* dJdT,
                      double ke_weight, double* const* dJdtheta) {
   if (!s || !S_prev || !mu_in || !mu_out) return fail(FPC_ERR_ARG, "NULL argument");
-  if (!adjoint_supported(s->p)) return fail(FPC_ERR_STATE, "adjoint: not available on the D3Q15 thermal lattice");
   if (mu_in == mu_out || mu_out == S_prev) return fail(FPC_ERR_ARG, "mu_out must not alias mu_in or S_prev");
   if (!std::isfinite(ke_weight)) return fail(FPC_ERR_ARG, "ke_weight not finite");
   double* dth[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
@@ -885,7 +880,6 @@ int fpc_adjoint_step(fpc_sim* s, const void* S_prev, const void* mu_in, void* mu
 int fpc_adjoint_init(fpc_sim* s, const double* T_init, const void* mu0, const double* dJdT, double ke_weight,
                      double* dJdT_init) {
   if (!s || !T_init || !mu0 || !dJdT_init) return fail(FPC_ERR_ARG, "NULL argument");
-  if (!adjoint_supported(s->p)) return fail(FPC_ERR_STATE, "adjoint: not available on the D3Q15 thermal lattice");
   if (!std::isfinite(ke_weight)) return fail(FPC_ERR_ARG, "ke_weight not finite");
   const int tk = paper_thermal(s->p.lattice) ? 1 : 0;
   hipError_t e;

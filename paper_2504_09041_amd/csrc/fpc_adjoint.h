@@ -176,18 +176,147 @@ __device__ constexpr double maxwell_cm(int i) {
 }
 
 // Forward collision on plain populations with everything the reverse needs.
-// QG: thermal lattice, 2D + 1 (D2Q5 / D3Q7) or 9 (the paper's D2Q9, whose
-// moments use the work layout of MS<2>).
+// QG: thermal lattice, 2D + 1 (D2Q5 / D3Q7), 9 (the paper's D2Q9, whose
+// moments use the work layout of MS<2>) or 15 (the paper's D3Q15, moments in
+// the order of t15::kM).
 template <class R, int D, int QG = 2 * D + 1>
 struct Tape {
   static constexpr int NM = MS<D>::NM;
-  static constexpr int NG = QG;
+  // D3Q15: the 15 moments of the set and, last, the central moment 210
+  static constexpr int NG = QG == kQ15 ? QG + 1 : QG;
   R rho, ir, T, Fb, u[3];  // ir = 1 / rho
   R k[NM];   // pre-collision central moments
   R kt[NM];  // post-collision central moments
   R e[NG];   // thermal central moments (D2Q5 / D3Q7: 0, +-axis order 1, order 2 per axis)
   R et[NG];  // post-collision thermal central moments
 };
+
+// ---- the paper's D3Q15 thermal lattice (App. C) ----
+// Raw moments r = H g (H[m][q] = prod_d e_qd^m_d over the moment set) and
+// central moments e = S(u) r, S unit lower triangular in the set's order
+// (binomial shift about u, raw moments aliased into the set).  For the
+// reverse, H^T, H^-T and S(u)^T, S(u)^-T; H^-1 is inverted at compile time.
+namespace q15 {
+struct Mat {
+  double a[kQ15][kQ15];
+};
+constexpr int ipow(int e, int m) { return m == 0 ? 1 : (m == 1 ? e : e * e); }
+constexpr Mat raw_matrix() {
+  Mat H{};
+  for (int m = 0; m < kQ15; ++m)
+    for (int q = 0; q < kQ15; ++q)
+      H.a[m][q] = ipow(T15_EX[q], t15::kM[m][0]) * ipow(T15_EY[q], t15::kM[m][1]) * ipow(T15_EZ[q], t15::kM[m][2]);
+  return H;
+}
+constexpr double cabs(double v) { return v < 0 ? -v : v; }
+// Gauss-Jordan elimination with partial pivoting (H is an invertible integer matrix)
+constexpr Mat inverse(Mat A) {
+  Mat I{};
+  for (int i = 0; i < kQ15; ++i) I.a[i][i] = 1.0;
+  for (int c = 0; c < kQ15; ++c) {
+    int p = c;
+    for (int r = c + 1; r < kQ15; ++r)
+      if (cabs(A.a[r][c]) > cabs(A.a[p][c])) p = r;
+    for (int j = 0; j < kQ15; ++j) {
+      const double ta = A.a[c][j], ti = I.a[c][j];
+      A.a[c][j] = A.a[p][j];
+      I.a[c][j] = I.a[p][j];
+      A.a[p][j] = ta;
+      I.a[p][j] = ti;
+    }
+    const double d = A.a[c][c];
+    for (int j = 0; j < kQ15; ++j) {
+      A.a[c][j] /= d;
+      I.a[c][j] /= d;
+    }
+    for (int r = 0; r < kQ15; ++r) {
+      if (r == c) continue;
+      const double f = A.a[r][c];
+      if (f == 0.0) continue;
+      for (int j = 0; j < kQ15; ++j) {
+        A.a[r][j] -= f * A.a[c][j];
+        I.a[r][j] -= f * I.a[c][j];
+      }
+    }
+  }
+  return I;
+}
+struct Tables {
+  static constexpr Mat H = raw_matrix();
+  static constexpr Mat Hi = inverse(raw_matrix());
+};
+// index in the set of the exponents (a, b, c), or kQ15 for (2, 1, 0) (the
+// only m - e_d of a member that is not a member), -1 otherwise
+constexpr int index_of(int a, int b, int c) {
+  for (int k = 0; k < kQ15; ++k)
+    if (t15::kM[k][0] == a && t15::kM[k][1] == b && t15::kM[k][2] == c) return k;
+  return (a == 2 && b == 1 && c == 0) ? kQ15 : -1;
+}
+constexpr int m(int k, int ax) { return k == kQ15 ? (ax == 0 ? 2 : (ax == 1 ? 1 : 0)) : t15::kM[k][ax]; }
+constexpr int down(int k, int ax) {
+  return index_of(m(k, 0) - (ax == 0), m(k, 1) - (ax == 1), m(k, 2) - (ax == 2));
+}
+// central moment (MX, MY, MZ) from raw moments r (the self term left out when SKIP_SELF)
+template <class R, int MX, int MY, int MZ, bool SKIP_SELF>
+__device__ __forceinline__ R shift(const R (&r)[kQ15], const R (&nux)[3], const R (&nuy)[3], const R (&nuz)[3]) {
+  R acc = R(0);
+#pragma unroll
+  for (int i = 0; i <= MX; ++i)
+#pragma unroll
+    for (int j = 0; j <= MY; ++j)
+#pragma unroll
+      for (int k = 0; k <= MZ; ++k) {
+        if (SKIP_SELF && i == MX && j == MY && k == MZ) continue;
+        acc += R(t15::binom(MX, i) * t15::binom(MY, j) * t15::binom(MZ, k)) * nux[MX - i] * nuy[MY - j] *
+               nuz[MZ - k] * r[t15::alias(i, j, k)];
+      }
+  return acc;
+}
+// rb += (row (MX, MY, MZ) of S, the self term left out when SKIP_SELF)^T v
+template <class R, int MX, int MY, int MZ, bool SKIP_SELF>
+__device__ __forceinline__ void shift_T(R (&rb)[kQ15], R v, const R (&nux)[3], const R (&nuy)[3],
+                                        const R (&nuz)[3]) {
+#pragma unroll
+  for (int i = 0; i <= MX; ++i)
+#pragma unroll
+    for (int j = 0; j <= MY; ++j)
+#pragma unroll
+      for (int k = 0; k <= MZ; ++k) {
+        if (SKIP_SELF && i == MX && j == MY && k == MZ) continue;
+        rb[t15::alias(i, j, k)] += R(t15::binom(MX, i) * t15::binom(MY, j) * t15::binom(MZ, k)) * nux[MX - i] *
+                                   nuy[MY - j] * nuz[MZ - k] * v;
+      }
+}
+}  // namespace q15
+
+#define FPC_Q15_SET(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14)
+#define FPC_Q15_SET_DESC(X) X(14) X(13) X(12) X(11) X(10) X(9) X(8) X(7) X(6) X(5) X(4) X(3) X(2) X(1)
+#define FPC_Q15_M(K) t15::kM[K][0], t15::kM[K][1], t15::kM[K][2]
+
+// Thermal attractors of the paper's D3Q15 lattice above second order
+// (120, 012, 201, 111, 220), from the post-collision moments up to second
+// order and T: option A, option B, MCM (as in fpc_collide.h).
+template <class R, bool STD>
+__device__ __forceinline__ void thermal15_attractors(const CollParams<R>& c, R T, const R* et, R (&mv)[5]) {
+  const R cT = c.cs2T;
+  if (mcm<STD>(c)) {
+    mv[0] = mv[1] = mv[2] = mv[3] = R(0);
+    mv[4] = cT * cT * T;
+  } else if (option_b<STD>(c)) {
+    const R f = R(2) / (R(3) * T);
+    mv[0] = f * (et[8] * et[1] + R(2) * et[4] * et[2]);
+    mv[1] = f * (et[9] * et[2] + R(2) * et[6] * et[3]);
+    mv[2] = f * (et[7] * et[3] + R(2) * et[5] * et[1]);
+    mv[3] = f * (et[4] * et[3] + et[5] * et[2] + et[6] * et[1]);
+    mv[4] = (et[7] * et[8] + R(2) * et[4] * et[4]) / T;
+  } else {
+    mv[0] = R(2) / R(3) * cT * et[1];
+    mv[1] = R(2) / R(3) * cT * et[2];
+    mv[2] = R(2) / R(3) * cT * et[3];
+    mv[3] = R(0);
+    mv[4] = R(0.5) * cT * (et[7] + et[8]);
+  }
+}
 
 // Thermal attractors of the paper's D2Q9 lattice above second order
 // (Eq. Mvcmattractor2D_g): option A (c^_s^2 I at every order), option B
@@ -326,7 +455,46 @@ __device__ __forceinline__ void forward(const R* f, const R* g, const CollParams
       }
     }
   }
-  if constexpr (QG != 2 * D + 1) {
+  if constexpr (QG == kQ15) {
+    // thermal D3Q15: raw moments, central moments by the aliased binomial
+    // shift, relaxation of App. C Step 3; the post-collision raw moments
+    // (inverse of the shift) give kappa~_210 for the reverse
+    static_assert(D == 3, "D3Q15 is a 3D lattice");
+    R r[kQ15];
+#pragma unroll
+    for (int mm = 0; mm < kQ15; ++mm) {
+      R v = R(0);
+#pragma unroll
+      for (int q = 0; q < kQ15; ++q)
+        if (q15::Tables::H.a[mm][q] != 0.0) v += R(q15::Tables::H.a[mm][q]) * g[q];
+      r[mm] = v;
+    }
+    const R nux[3] = {R(1), -t.u[0], t.u[0] * t.u[0]}, nuy[3] = {R(1), -t.u[1], t.u[1] * t.u[1]},
+            nuz[3] = {R(1), -t.u[2], t.u[2] * t.u[2]};
+    t.e[0] = T;
+#define FPC_E15(K) t.e[K] = q15::shift<R, FPC_Q15_M(K), false>(r, nux, nuy, nuz);
+    FPC_Q15_SET(FPC_E15)
+#undef FPC_E15
+    t.e[kQ15] = q15::shift<R, 2, 1, 0, false>(r, nux, nuy, nuz);
+    auto og = [&](int k) -> R { return rate_g<3, STD>(c, k); };
+    const R cT = c.cs2T;
+    t.et[0] = T;
+#pragma unroll
+    for (int k = 1; k <= 6; ++k) t.et[k] = (R(1) - og(k)) * t.e[k];
+#pragma unroll
+    for (int k = 7; k <= 9; ++k) t.et[k] = t.e[k] + og(k) * (cT * T - t.e[k]);
+    R mv[5];
+    thermal15_attractors<R, STD>(c, T, t.et, mv);
+#pragma unroll
+    for (int k = 10; k <= 14; ++k) t.et[k] = t.e[k] + og(k) * (mv[k - 10] - t.e[k]);
+    R rt[kQ15];
+    rt[0] = t.et[0];
+#define FPC_R15(K) rt[K] = t.et[K] - q15::shift<R, FPC_Q15_M(K), true>(rt, nux, nuy, nuz);
+    FPC_Q15_SET(FPC_R15)
+#undef FPC_R15
+    t.et[kQ15] = q15::shift<R, 2, 1, 0, false>(rt, nux, nuy, nuz);
+    return;
+  } else if constexpr (QG != 2 * D + 1) {
     // thermal D2Q9: the same tensor-product shifts as the fluid, then the
     // relaxation of the paper's D2Q9 thermal collision (App. B Step 3)
     static_assert(D == 2 && QG == kQ2, "thermal D2Q9 only");
@@ -398,7 +566,108 @@ __device__ __forceinline__ void reverse(const Tape<R, D, QG>& t, const CollParam
   const R* og = c.omg;
 
   // ---- thermal: g~ = P_g^-1 F_g(u)^-1 eta~ ----
-  if constexpr (QG != 2 * D + 1) {
+  if constexpr (QG == kQ15) {
+    // thermal D3Q15: g~ = H^-1 S(u)^-1 eta~, eta = S(u) H g
+    auto og = [&](int k) -> R { return rate_g<3, STD>(c, k); };
+    const R cT = c.cs2T;
+    const R nux[3] = {R(1), -t.u[0], t.u[0] * t.u[0]}, nuy[3] = {R(1), -t.u[1], t.u[1] * t.u[1]},
+            nuz[3] = {R(1), -t.u[2], t.u[2] * t.u[2]};
+    R tb[kQ15];  // H^-T g~bar, then S^-T of it: the adjoint of eta~
+#pragma unroll
+    for (int mm = 0; mm < kQ15; ++mm) {
+      R v = R(0);
+#pragma unroll
+      for (int q = 0; q < kQ15; ++q)
+        if (q15::Tables::Hi.a[q][mm] != 0.0) v += R(q15::Tables::Hi.a[q][mm]) * gb[q];
+      tb[mm] = v;
+    }
+#define FPC_TB15(K) q15::shift_T<R, FPC_Q15_M(K), true>(tb, -tb[K], nux, nuy, nuz);
+    FPC_Q15_SET_DESC(FPC_TB15)
+#undef FPC_TB15
+#pragma unroll
+    for (int k = 1; k < kQ15; ++k)
+#pragma unroll
+      for (int ax = 0; ax < 3; ++ax)
+        if (q15::m(k, ax) > 0) ub[ax] += tb[k] * R(q15::m(k, ax)) * t.et[q15::down(k, ax)];
+    // relaxation, highest orders first
+    R eb[kQ15];
+    R mb[5];
+#pragma unroll
+    for (int k = 10; k <= 14; ++k) {
+      eb[k] = (R(1) - og(k)) * tb[k];
+      mb[k - 10] = og(k) * tb[k];
+    }
+    const R* et = t.et;
+    if (mcm<STD>(c)) {
+      Tb += cT * cT * mb[4];
+    } else if (option_b<STD>(c)) {
+      const R iT = R(1) / t.T, f = R(2) / R(3) * iT;
+      R mv[5];
+      thermal15_attractors<R, STD>(c, t.T, t.et, mv);
+      // m120 = f (et8 et1 + 2 et4 et2)
+      tb[8] += f * et[1] * mb[0];
+      tb[1] += f * et[8] * mb[0];
+      tb[4] += R(2) * f * et[2] * mb[0];
+      tb[2] += R(2) * f * et[4] * mb[0];
+      // m012 = f (et9 et2 + 2 et6 et3)
+      tb[9] += f * et[2] * mb[1];
+      tb[2] += f * et[9] * mb[1];
+      tb[6] += R(2) * f * et[3] * mb[1];
+      tb[3] += R(2) * f * et[6] * mb[1];
+      // m201 = f (et7 et3 + 2 et5 et1)
+      tb[7] += f * et[3] * mb[2];
+      tb[3] += f * et[7] * mb[2];
+      tb[5] += R(2) * f * et[1] * mb[2];
+      tb[1] += R(2) * f * et[5] * mb[2];
+      // m111 = f (et4 et3 + et5 et2 + et6 et1)
+      tb[4] += f * et[3] * mb[3];
+      tb[3] += f * et[4] * mb[3];
+      tb[5] += f * et[2] * mb[3];
+      tb[2] += f * et[5] * mb[3];
+      tb[6] += f * et[1] * mb[3];
+      tb[1] += f * et[6] * mb[3];
+      // m220 = (et7 et8 + 2 et4^2) / T
+      tb[7] += iT * et[8] * mb[4];
+      tb[8] += iT * et[7] * mb[4];
+      tb[4] += R(4) * iT * et[4] * mb[4];
+      Tb -= iT * (mv[0] * mb[0] + mv[1] * mb[1] + mv[2] * mb[2] + mv[3] * mb[3] + mv[4] * mb[4]);
+    } else {
+      tb[1] += R(2) / R(3) * cT * mb[0];
+      tb[2] += R(2) / R(3) * cT * mb[1];
+      tb[3] += R(2) / R(3) * cT * mb[2];
+      tb[7] += R(0.5) * cT * mb[4];
+      tb[8] += R(0.5) * cT * mb[4];
+    }
+#pragma unroll
+    for (int k = 7; k <= 9; ++k) {
+      eb[k] = (R(1) - og(k)) * tb[k];
+      Tb += og(k) * cT * tb[k];
+    }
+#pragma unroll
+    for (int k = 1; k <= 6; ++k) eb[k] = (R(1) - og(k)) * tb[k];
+    Tb += tb[0];
+    eb[0] = R(0);
+    // eta = S(u) r: ubar -= sum eb_m m_d eta_{m - e_d}; rbar = S^T eb; gbar = H^T rbar
+#pragma unroll
+    for (int k = 1; k < kQ15; ++k)
+#pragma unroll
+      for (int ax = 0; ax < 3; ++ax)
+        if (q15::m(k, ax) > 0) ub[ax] -= eb[k] * R(q15::m(k, ax)) * t.e[q15::down(k, ax)];
+    R rb[kQ15];
+#pragma unroll
+    for (int k = 0; k < kQ15; ++k) rb[k] = R(0);
+#define FPC_RB15(K) q15::shift_T<R, FPC_Q15_M(K), false>(rb, eb[K], nux, nuy, nuz);
+    FPC_Q15_SET(FPC_RB15)
+#undef FPC_RB15
+#pragma unroll
+    for (int q = 0; q < kQ15; ++q) {
+      R v = R(0);
+#pragma unroll
+      for (int mm = 0; mm < kQ15; ++mm)
+        if (q15::Tables::H.a[mm][q] != 0.0) v += R(q15::Tables::H.a[mm][q]) * rb[mm];
+      gb[q] = v;
+    }
+  } else if constexpr (QG != 2 * D + 1) {
     // thermal D2Q9: g~ = C(u)^-1 eta~, eta = C(u) g (tensor-product shifts)
     constexpr int i00 = M::at(0, 0, 0), i10 = M::at(1, 0, 0), i01 = M::at(0, 1, 0), i20 = M::at(2, 0, 0),
                   i02 = M::at(0, 2, 0), i11 = M::at(1, 1, 0), i21 = M::at(2, 1, 0), i12 = M::at(1, 2, 0),

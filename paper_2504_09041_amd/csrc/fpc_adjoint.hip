@@ -332,13 +332,19 @@ hipError_t launch_adj(const AdjArgs<R>* step, const AdjInitArgs<R>* init, hipStr
   return hipGetLastError();
 }
 
-// tk: thermal lattice, 0 = D2Q5 / D3Q7, 1 = the paper's D2Q9 (2D only)
+// tk: thermal lattice, 0 = D2Q5 / D3Q7, 1 = the paper's D2Q9 / D3Q15
 template <class R>
 hipError_t dispatch(int dim, int up, int tk, const AdjArgs<R>* step, const AdjInitArgs<R>* init, hipStream_t st) {
-  if (dim == 2 && tk == 1)
-    return up == 0 ? launch_adj<Lat2T9, R, 0>(step, init, st) : launch_adj<Lat2T9, R, 1>(step, init, st);
-  if (tk != 0) return hipErrorInvalidValue;
-  if (dim == 2) return up == 0 ? launch_adj<Lat2, R, 0>(step, init, st) : launch_adj<Lat2, R, 1>(step, init, st);
+  if (dim == 2) {
+    if (tk == 1)
+      return up == 0 ? launch_adj<Lat2T9, R, 0>(step, init, st) : launch_adj<Lat2T9, R, 1>(step, init, st);
+    return up == 0 ? launch_adj<Lat2, R, 0>(step, init, st) : launch_adj<Lat2, R, 1>(step, init, st);
+  }
+  if (tk == 1) {
+    if (up == 0) return launch_adj<Lat3T15, R, 0>(step, init, st);
+    if (up == 1) return launch_adj<Lat3T15, R, 1>(step, init, st);
+    return launch_adj<Lat3T15, R, 2>(step, init, st);
+  }
   if (up == 0) return launch_adj<Lat3, R, 0>(step, init, st);
   if (up == 1) return launch_adj<Lat3, R, 1>(step, init, st);
   return launch_adj<Lat3, R, 2>(step, init, st);

@@ -178,7 +178,7 @@ hipError_t launch_step_multi(const StepArgs<R>& a, int dim, int up, const MultiC
 
 // Adjoint kernels (fpc_adjoint.hip).  `a.src` is S_{n-1} (adjoint step) or
 // unused (adjoint of the initial collision).  tk: thermal lattice, 0 = D2Q5 /
-// D3Q7, 1 = the paper's D2Q9 (2D only; hipErrorInvalidValue otherwise).
+// D3Q7, 1 = the paper's D2Q9 / D3Q15.
 template <class R>
 hipError_t launch_adjoint_step(const StepArgs<R>& a, int dim, int up, int tk, const void* lam_in, void* lam_out,
                                const double* dJdT, double ke, double* const dtheta[6], hipStream_t s);

@@ -1,13 +1,16 @@
-"""The hand-written adjoint on the paper's D2Q9 thermal lattice (Sec. 4.4,
-App. B), through the C ABI, against the oracle's autograd gradients.
+"""The hand-written adjoint on the paper's thermal lattices, D2Q9 (Sec. 4.4,
+App. B) and D3Q15 (Sec. 5.4, App. C), through the C ABI, against the
+oracle's autograd gradients.
 
-The thermal moments are the tensor-product central moments of D2Q9 (the
-same shifts as the fluid); above second order they relax toward option A,
-option B or the Maxwellian (MCM) attractors.  A diagonal thermal link that
-crosses a Dirichlet face is anti-bounced toward the mean temperature of the
-Dirichlet faces it crosses, so the wall-temperature gradient of a corner link
-is shared between two faces: the "box" case (Dirichlet walls on all four
-faces) checks that split.
+The D2Q9 thermal moments are the tensor-product central moments (the same
+shifts as the fluid); the D3Q15 ones come from the raw moments by the
+aliased binomial shift, and their reverse needs one central moment outside
+the set (210).  Above second order the moments relax toward option A, option
+B or the Maxwellian (MCM) attractors.  A diagonal thermal link that crosses a
+Dirichlet face is anti-bounced toward the mean temperature of the Dirichlet
+faces it crosses, so the wall-temperature gradient of an edge or corner link
+is shared between two or three faces: the "box" cases (Dirichlet walls on
+every face) check that split.
 
 Bars as for the D2Q5 adjoint: one adjoint step and the adjoint of the initial
 collision equal the oracle's vector-Jacobian products to 1e-12 (FP64) and
@@ -42,11 +45,13 @@ def _ptr(t):
 
 
 def _cfg(case):
-    if case == "box2d":
-        # Dirichlet walls on all four faces: corner links cross two of them
-        cfg = G.small_config("dhc2d")
-        cfg["faces"][2] = {"fluid": "noslip", "thermal": "dirichlet", "T": 0.2, "u_w": (0.0, 0.0, 0.0)}
-        cfg["faces"][3] = {"fluid": "noslip", "thermal": "dirichlet", "T": -0.1, "u_w": (0.0, 0.0, 0.0)}
+    if case in ("box2d", "box3d"):
+        # Dirichlet walls on every face: corner links cross two (2D) or
+        # three (3D) of them
+        cfg = G.small_config("dhc2d" if case == "box2d" else "dhc3d")
+        temps = [0.2, -0.1, 0.3, -0.25]
+        for f in range(2, 4 if case == "box2d" else 6):
+            cfg["faces"][f] = {"fluid": "noslip", "thermal": "dirichlet", "T": temps[f - 2], "u_w": (0.0, 0.0, 0.0)}
     else:
         cfg = G.small_config(case)
     return G.with_pair(G.shift_temperature(cfg, 1.5), True)
@@ -61,7 +66,8 @@ def _profile_shape(cfg, face):
     return {0: (nz, ny), 1: (nz, nx), 2: (ny, nx)}[face // 2]
 
 
-@pytest.mark.parametrize("case", ["dhc2d", "rb2d", "mixed2d", "rb2d_tiles", "box2d"])
+@pytest.mark.parametrize("case", ["dhc2d", "rb2d", "mixed2d", "rb2d_tiles", "box2d",
+                                  "dhc3d", "rb3d", "lid3d", "dhc3d_tiles", "box3d"])
 @pytest.mark.parametrize("model,opt", MODELS)
 @pytest.mark.parametrize("precision,tol", [("f64", 1e-12), ("f32dev", 2e-5)])
 def test_adjoint_step_matches_oracle_vjp(case, model, opt, precision, tol):
@@ -108,7 +114,7 @@ def test_adjoint_step_matches_oracle_vjp(case, model, opt, precision, tol):
     sim.close()
 
 
-@pytest.mark.parametrize("case", ["dhc2d", "mixed2d", "box2d"])
+@pytest.mark.parametrize("case", ["dhc2d", "mixed2d", "box2d", "rb3d", "box3d"])
 @pytest.mark.parametrize("model,opt", MODELS)
 def test_adjoint_init_matches_oracle(case, model, opt):
     from paper_2504_09041_amd import _abi as A
@@ -147,6 +153,8 @@ def test_adjoint_init_matches_oracle(case, model, opt):
     ("mixed2d", "nu", 3, (10, 25), 2),
     ("box2d", "nu", 1, (10, 25), 0),
     ("dhc2d", "ke", None, 20, 0),
+    ("box3d", "nu", 1, (10, 25), 0),
+    ("rb3d", "ke", None, 20, 4),
 ])
 @pytest.mark.parametrize("model,opt", MODELS)
 def test_checkpointed_gradient_matches_oracle_autograd(case, kind, face, window, tf, model, opt):

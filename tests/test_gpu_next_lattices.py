@@ -145,21 +145,6 @@ def test_paper_thermal_fp32_meets_the_bars_over_a_long_run():
         sim.close()
 
 
-def test_adjoint_rejects_the_d3q15_thermal_lattice():
-    import ctypes
-
-    from paper_2504_09041_amd import _abi as A
-
-    cfg = G.with_pair(G.small_config("dhc3d"), True)
-    sim = G.make_sim(cfg, "f64")
-    S = sim.save()
-    lam = torch.zeros_like(S)
-    lam2 = torch.zeros_like(S)
-    rc = A.load().fpc_adjoint_step(sim.handle, ctypes.c_void_p(S.data_ptr()), ctypes.c_void_p(lam.data_ptr()),
-                                   ctypes.c_void_p(lam2.data_ptr()), None, ctypes.c_double(0.0), None)
-    assert rc == A.FPC_ERR_STATE
-
-
 @pytest.mark.parametrize("workload,pair", [("rb2d_1024x512", "D2Q9-D2Q9"), ("dhc3d_256", "D3Q27-D3Q15")])
 def test_paper_thermal_full_size_step_on_sampled_nodes(workload, pair):
     """One FP64 step at the full workload size (the 256^3 D3Q27 + D3Q15 state,
