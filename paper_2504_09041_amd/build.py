@@ -17,7 +17,9 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libfpclbm.so")
-SOURCES = ["fpc_abi.hip", "fpc_step.hip", "fpc_adjoint.hip", "fpc_kernels_util.hip"]
+# longest compiles first: they run in parallel
+SOURCES = ["fpc_adjoint_d3q15.hip", "fpc_step.hip", "fpc_adjoint.hip", "fpc_adjoint_d2q9.hip", "fpc_kernels_util.hip",
+           "fpc_abi.hip"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [
@@ -39,8 +41,11 @@ HIPCC_FLAGS = [
 # set, and only these assumptions let the compiler drop that arithmetic
 # (3D FP32 adjoint: 134 -> 113 VGPRs, 12% fewer instructions).  For finite
 # inputs the results are those of IEEE evaluation up to the sign of zeros.
+_FINITE = ["-fno-honor-nans", "-fno-honor-infinities", "-fno-signed-zeros"]
 SOURCE_FLAGS = {
-    "fpc_adjoint.hip": ["-fno-honor-nans", "-fno-honor-infinities", "-fno-signed-zeros"],
+    "fpc_adjoint.hip": _FINITE,
+    "fpc_adjoint_d2q9.hip": _FINITE,
+    "fpc_adjoint_d3q15.hip": _FINITE,
 }
 
 
@@ -67,7 +72,7 @@ def _compile(src, extra, verbose):
 
 def build_library(verbose=False, extra_flags=()):
     os.makedirs(BUILD, exist_ok=True)
-    with concurrent.futures.ThreadPoolExecutor(max_workers=min(4, len(SOURCES))) as ex:
+    with concurrent.futures.ThreadPoolExecutor(max_workers=min(6, len(SOURCES))) as ex:
         objs = list(ex.map(lambda s: _compile(s, list(extra_flags), verbose), SOURCES))
     tmp = LIB + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
