@@ -240,8 +240,8 @@ int fpc_init(fpc_sim* s, const double* T_init);
 /*
  * Advance nsteps >= 0 time steps (fused pull-stream-collide, Eq.
  * LBMsteps-stream / LBMsteps-streamg with the collision of Sec. 4-5),
- * asynchronously.  Small grids (at most 16 blocks of 256 nodes; the D2Q5 /
- * D3Q7 thermal pair in 2D, or in 3D with FP32 storage; standard rate set)
+ * asynchronously.  Small grids (at most 16 blocks of 256 nodes; any lattice
+ * pair in 2D, or in 3D with FP32 storage; standard rate set)
  * advance up to 1024 steps per cooperative launch, with a grid-wide barrier
  * between steps, when the device supports cooperative launches; otherwise,
  * and on every other grid, one launch per step.  Both paths compute the

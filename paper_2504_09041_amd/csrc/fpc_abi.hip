@@ -272,7 +272,7 @@ constexpr unsigned kMultiSpinLimit = 1u << 22;  // barrier polls before giving u
 
 bool multi_eligible(const fpc_sim* s) {
   const fpc_params& p = s->p;
-  if (!s->multi_enabled || !s->multi_ok || paper_thermal(p.lattice)) return false;
+  if (!s->multi_enabled || !s->multi_ok) return false;
   if (s->dim == 3 && p.precision == FPC_FP64) return false;
   if (multi_work_blocks(p.nx, p.ny, p.nz) > kMultiMaxWork) return false;
   if ((double)s->bytes > 128.0 * 1024.0 * 1024.0) return false;
@@ -301,11 +301,14 @@ int launch_multi(fpc_sim* s, int nsteps) {
   // light-barrier numbers: kMultiMaxSteps per launch, unique for 2^21 launches
   c.gen = (unsigned)((s->multi_launches & 0x1fffff) * kMultiMaxSteps) + 1u;
   const int up = s->p.up_axis;
+  const int tk = paper_thermal(s->p.lattice) ? 1 : 0;
   hipError_t e;
   if (s->p.precision == FPC_FP64)
-    e = launch_step_multi<double>(make_args<double>(s, s->buf[s->cur], s->buf[s->cur ^ 1]), s->dim, up, c, s->stream);
+    e = launch_step_multi<double>(make_args<double>(s, s->buf[s->cur], s->buf[s->cur ^ 1]), s->dim, up, tk, c,
+                                 s->stream);
   else
-    e = launch_step_multi<float>(make_args<float>(s, s->buf[s->cur], s->buf[s->cur ^ 1]), s->dim, up, c, s->stream);
+    e = launch_step_multi<float>(make_args<float>(s, s->buf[s->cur], s->buf[s->cur ^ 1]), s->dim, up, tk, c,
+                                 s->stream);
   if (e == hipErrorCooperativeLaunchTooLarge || e == hipErrorNotSupported) {
     (void)hipGetLastError();
     s->multi_ok = 0;

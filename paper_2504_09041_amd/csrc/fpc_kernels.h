@@ -174,7 +174,7 @@ inline unsigned multi_work_blocks(int nx, int ny, int nz) {
   return (unsigned)((nx + bx - 1) / bx) * (unsigned)((ny + by - 1) / by) * (unsigned)nz;
 }
 template <class R>
-hipError_t launch_step_multi(const StepArgs<R>& a, int dim, int up, const MultiCtl& c, hipStream_t s);
+hipError_t launch_step_multi(const StepArgs<R>& a, int dim, int up, int tk, const MultiCtl& c, hipStream_t s);
 
 // Adjoint kernels (fpc_adjoint.hip).  `a.src` is S_{n-1} (adjoint step) or
 // unused (adjoint of the initial collision).  tk: thermal lattice, 0 = D2Q5 /

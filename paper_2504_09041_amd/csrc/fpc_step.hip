@@ -524,11 +524,21 @@ hipError_t launch_step3d(const StepArgs<R>& a, int up, int tk, const double* T_i
 // 2D in either precision and 3D FP32 (the 3D FP64 step would hold more than
 // 256 registers per lane inside the step loop; it keeps per-step launches).
 template <class R>
-hipError_t launch_step_multi(const StepArgs<R>& a, int dim, int up, const MultiCtl& c, hipStream_t s) {
-  if (dim == 2) return up == 0 ? launch_multi_up<Lat2, R, 0>(a, c, s) : launch_multi_up<Lat2, R, 1>(a, c, s);
+hipError_t launch_step_multi(const StepArgs<R>& a, int dim, int up, int tk, const MultiCtl& c, hipStream_t s) {
+  if (dim == 2) {
+    if (tk == 1) return up == 0 ? launch_multi_up<Lat2T9, R, 0>(a, c, s) : launch_multi_up<Lat2T9, R, 1>(a, c, s);
+    return up == 0 ? launch_multi_up<Lat2, R, 0>(a, c, s) : launch_multi_up<Lat2, R, 1>(a, c, s);
+  }
   if constexpr (sizeof(R) == 8) {
     return hipErrorNotSupported;
   } else {
+    if (tk == 1) {
+      switch (up) {
+        case 0: return launch_multi_up<Lat3T15, R, 0>(a, c, s);
+        case 1: return launch_multi_up<Lat3T15, R, 1>(a, c, s);
+        default: return launch_multi_up<Lat3T15, R, 2>(a, c, s);
+      }
+    }
     switch (up) {
       case 0: return launch_multi_up<Lat3, R, 0>(a, c, s);
       case 1: return launch_multi_up<Lat3, R, 1>(a, c, s);
@@ -542,7 +552,7 @@ template hipError_t launch_step2d<float>(const StepArgs<float>&, int, int, const
 template hipError_t launch_step3d<double>(const StepArgs<double>&, int, int, const double*, int, hipStream_t);
 template hipError_t launch_step3d<float>(const StepArgs<float>&, int, int, const double*, int, hipStream_t);
 
-template hipError_t launch_step_multi<double>(const StepArgs<double>&, int, int, const MultiCtl&, hipStream_t);
-template hipError_t launch_step_multi<float>(const StepArgs<float>&, int, int, const MultiCtl&, hipStream_t);
+template hipError_t launch_step_multi<double>(const StepArgs<double>&, int, int, int, const MultiCtl&, hipStream_t);
+template hipError_t launch_step_multi<float>(const StepArgs<float>&, int, int, int, const MultiCtl&, hipStream_t);
 
 }  // namespace fpc

@@ -1,7 +1,7 @@
 """fpc_step's single-launch multi-step path on small grids.
 
-Small grids (at most 16 blocks of 256 nodes, the D2Q5 / D3Q7 thermal pair in
-2D or in 3D FP32, the standard rate set) advance up to 1024 steps per
+Small grids (at most 16 blocks of 256 nodes, any lattice pair in 2D or in 3D
+FP32, the standard rate set) advance up to 1024 steps per
 cooperative launch with a grid-wide barrier between the steps.  Each step is
 the arithmetic of the one-launch-per-step kernel; the two kernels are
 compiled separately, so the compiler may fuse multiply-adds differently and
@@ -36,15 +36,20 @@ CASES = [
     ("dhc3d_tiles", None, "f32uni"),
     ("rb3d_128", (8, 8, 8), "f32dev"),  # periodic x and y
     ("lid3d", None, "f32dev"),
+    # the paper's thermal lattices (D2Q9 in 2D, D3Q15 in 3D)
+    ("dhc2d_64:paper", (64, 64, 1), "f64"),
+    ("mixed2d:paper", None, "f32dev"),
+    ("dhc3d:paper", None, "f32dev"),
+    ("rb3d_128:paper", (8, 8, 8), "f32dev"),
 ]
 
 
 def _config(name, shape):
     import workloads
 
-    if shape is None:
-        return G.small_config(name)
-    return workloads.config(name, shape=shape)
+    base, _, paper = name.partition(":")
+    cfg = G.small_config(base) if shape is None else workloads.config(base, shape=shape)
+    return G.with_pair(cfg, paper == "paper")
 
 
 def _run(cfg, precision, nsteps, multistep):
