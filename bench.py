@@ -259,8 +259,9 @@ def time_workload(name, precision, steps, warmup, shape=None, pair=None, model="
     return out
 
 
-def adjoint_cost(name, nsteps, every, reps=20):
-    """Cost of the adjoint relative to the forward step (FP32-deviation form).
+def adjoint_cost(name, nsteps, every, reps=20, pair=None):
+    """Cost of the adjoint relative to the forward step (FP32-deviation form;
+    ``pair`` another lattice pair than the workload's).
 
     kernel_ratio: one adjoint_step launch / one forward step launch (HIP events);
     sweep_ratio: the whole checkpointed reverse sweep (segment recompute, state
@@ -274,7 +275,7 @@ def adjoint_cost(name, nsteps, every, reps=20):
     from paper_2504_09041_amd import adjoint as adj
     from paper_2504_09041_amd.sim import params_from_workload
 
-    cfg = workloads.config(name)
+    cfg = workloads.config(name, **({"pair": pair} if pair else {}))
     p = params_from_workload(cfg, "f32dev")
     if name.startswith("mixed"):
         obj = adj.WallNusselt(cfg["nu_face"], nsteps // 2, nsteps)
@@ -321,7 +322,7 @@ def adjoint_cost(name, nsteps, every, reps=20):
     t_sweep = (time.perf_counter() - t0) * 1e3 / nsteps
     sim.close()
     return {
-        "workload": name, "precision": "f32dev", "steps": nsteps, "checkpoint_every": every,
+        "workload": name, "pair": cfg["pair"], "precision": "f32dev", "steps": nsteps, "checkpoint_every": every,
         "forward_ms_per_step": t_fwd, "adjoint_kernel_ms": t_adj, "sweep_ms_per_step": t_sweep,
         "kernel_ratio": t_adj / t_fwd, "sweep_ratio": t_sweep / t_fwd,
     }
@@ -589,7 +590,7 @@ def main():
         print(json.dumps(precision_study(a.workload, a.steps, max(1, a.steps // 50), shape=a.shape, **kw)))
         return
     if a.mode == "adjoint":
-        print(json.dumps(adjoint_cost(a.workload, a.steps, max(1, int(round(a.steps ** 0.5))))))
+        print(json.dumps(adjoint_cost(a.workload, a.steps, max(1, int(round(a.steps ** 0.5))), pair=a.pair)))
         return
     if a.mode == "objective":
         print(json.dumps(objective_cost(a.workload, a.steps)))
@@ -654,6 +655,9 @@ def main():
     if not a.no_extra and not a.no_adjoint:
         extra["adjoint_mixed2d_512_f32dev"] = adjoint_cost("mixed2d_512", 400, 100)
         extra["adjoint_rb3d_128_f32dev"] = adjoint_cost("rb3d_128", 64, 8)
+        # the same on the paper's thermal lattices (general-rate adjoint build)
+        extra["adjoint_mixed2d_512_f32dev_D2Q9thermal"] = adjoint_cost("mixed2d_512", 400, 100, pair="D2Q9-D2Q9")
+        extra["adjoint_rb3d_128_f32dev_D3Q15thermal"] = adjoint_cost("rb3d_128", 64, 8, pair="D3Q27-D3Q15")
     tr = _traffic_record().get("dhc3d_256_f32dev")
     if tr and tr.get("sources") != kernel_fingerprint():
         tr = None  # the kernels changed since the counters were taken

@@ -313,11 +313,14 @@ hipError_t launch_adj(const AdjArgs<R>* step, const AdjInitArgs<R>* init, hipStr
   if (step) {
     constexpr int Q = L::Qf + L::Qg;
     const double bytes = (double)a.nxp * a.ny * a.nz * Q * sizeof(R);
-    // the standard-rate specialisation is built for the D2Q5 / D3Q7 pairs only
-    const bool std_rates = L::Qg == 2 * D + 1 && standard_rates(a, D, L::Qg);
+    // the standard-rate specialisation: for every pair in FP32, and for the
+    // D2Q5 / D3Q7 pairs in FP64 (the paper's lattices in FP64 hold about 256
+    // VGPRs either way, and the specialisation doubles their compile time)
+    constexpr bool kStd = L::Qg == 2 * D + 1 || sizeof(R) == 4;
+    const bool std_rates = kStd && standard_rates(a, D, L::Qg);
     if constexpr (D == 3 && sizeof(R) == 4) {
       if (bytes < 4294967296.0) {
-        if constexpr (L::Qg == 2 * D + 1) {
+        if constexpr (kStd) {
           if (std_rates) {
             adjoint_step_kernel_3f<L, Buf32<R, Q>, UP, true><<<grid, block, 0, st>>>(*step, (unsigned)bytes);
             return hipGetLastError();
@@ -329,7 +332,7 @@ hipError_t launch_adj(const AdjArgs<R>* step, const AdjInitArgs<R>* init, hipStr
       }
     } else {
       if (bytes < 4294967296.0) {
-        if constexpr (L::Qg == 2 * D + 1) {
+        if constexpr (kStd) {
           if (std_rates) {
             adjoint_step_kernel<L, R, Buf32<R, Q>, UP, true><<<grid, block, 0, st>>>(*step, (unsigned)bytes);
             return hipGetLastError();
