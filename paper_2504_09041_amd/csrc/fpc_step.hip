@@ -186,7 +186,9 @@ __device__ __forceinline__ void diag_accumulate(const StepArgs<R>& a, int x, int
   }
 }
 
-template <class L, class R, class M, int UP, bool NT, bool STD>
+// HOOKS: the optional fused wall-Nusselt and diagnostics hooks (absent from
+// the multi-step kernel, which never takes them)
+template <class L, class R, class M, int UP, bool NT, bool STD, bool HOOKS = true>
 __device__ __forceinline__ void collide_store(const StepArgs<R>& a, const M& m, int x, int y, int z, unsigned node,
                                               R Tr, R (&f)[L::Qf], R (&g)[L::Qg]) {
   if constexpr (L::D == 2)
@@ -201,20 +203,22 @@ __device__ __forceinline__ void collide_store(const StepArgs<R>& a, const M& m, 
   // the fused wall-Nusselt accumulation needs only the sum of the stored
   // thermal values; it is formed after the stores, so that its branch does
   // not split the collision (and its scheduling) in two
-  if (a.obj.slot != nullptr) {
-    double t = 0.0;
+  if constexpr (HOOKS) {
+    if (a.obj.slot != nullptr) {
+      double t = 0.0;
 #pragma unroll
-    for (int q = 0; q < L::Qg; ++q) t += (double)g[q];
-    nu_accumulate<L, R>(a, x, y, z, t);
+      for (int q = 0; q < L::Qg; ++q) t += (double)g[q];
+      nu_accumulate<L, R>(a, x, y, z, t);
+    }
+    if (a.dg.part != nullptr) diag_accumulate<L, R, UP>(a, x, y, z, node, f, g);
   }
-  if (a.dg.part != nullptr) diag_accumulate<L, R, UP>(a, x, y, z, node, f, g);
 }
 
 
 // One node's update: pull S_{n-1} (m's source), collide, store S_n (m's
 // destination).  Lanes outside the box must not call it (the edge ballots
 // count the calling lanes only).
-template <class L, class R, class M, int UP, bool NT, bool STD>
+template <class L, class R, class M, int UP, bool NT, bool STD, bool HOOKS = true>
 __device__ __forceinline__ void step_node(const StepArgs<R>& a, const M& m, int x, int y, int z) {
   const unsigned node = node_of(x, y, z, a.nxp, a.ny);
   const R Tr = tref(a, x, y, z);
@@ -233,7 +237,7 @@ __device__ __forceinline__ void step_node(const StepArgs<R>& a, const M& m, int 
   } else {
     gather<L, R, M, true, true, L::D == 3>(a, m, x, y, z, node, Tr, f, g);
   }
-  collide_store<L, R, M, UP, NT, STD>(a, m, x, y, z, node, Tr, f, g);
+  collide_store<L, R, M, UP, NT, STD, HOOKS>(a, m, x, y, z, node, Tr, f, g);
 }
 
 // M: addressing policy (Buf32 when the buffer is below 4 GiB, else Glob64).
@@ -412,7 +416,7 @@ __global__ void __launch_bounds__(256) step_multi_kernel(StepArgs<R> a, unsigned
       asm volatile("" : "+v"(xs), "+v"(ys));
       const bool odd = s & 1;
       const M m(odd ? a.dst : a.src, odd ? const_cast<R*>(a.src) : a.dst, total_bytes);
-      step_node<L, R, M, UP, false, STD>(a, m, xs, ys, z);
+      step_node<L, R, M, UP, false, STD, false>(a, m, xs, ys, z);
     }
     if (s + 1 < c.nsteps && !(one_xcd ? multi_sync_light(c, lb, c.gen + (unsigned)s, dep)
                                       : multi_barrier_full(c, lb)))
