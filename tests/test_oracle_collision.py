@@ -12,7 +12,11 @@
   counterpart carries);
 * collision invariants: mass, momentum + F, temperature;
 * the rest state as a fixed point;
-* with every rate 1 and no force, the closed-form product equilibrium.
+* with every rate 1 and no force, the closed-form product equilibrium;
+* FP: with unit rates above second order, the higher-order post-collision
+  moments are the Gaussian (Isserlis) moments of the post-collision
+  covariance, in 2D and 3D; likewise the thermal option B moments on the
+  paper's D2Q9 and D3Q15 lattices.
 """
 
 import pytest
@@ -253,6 +257,101 @@ def test_mcm_fluid_high_orders_are_maxwellian(lat):
     ft_fp, _, _ = fluid_collide(f, F, lat, w, model="FP")
     top = (2, 2) if lat.d == 2 else (2, 2, 0)
     assert float((_central(lat, ft_fp, u)[top] - _maxwell_cm(top, rho, 1 / 3)).abs().max()) > 1e-6
+
+
+def _gaussian_moment(axes, S):
+    """E[prod_k x_axes[k]] of a centred Gaussian with covariance S (Isserlis'
+    theorem: the sum over pairings of the products of covariances)."""
+    if not axes:
+        return torch.ones_like(S[0][0])
+    if len(axes) % 2:
+        return torch.zeros_like(S[0][0])
+    a, rest = axes[0], axes[1:]
+    acc = torch.zeros_like(S[0][0])
+    for j in range(len(rest)):
+        acc = acc + S[a][rest[j]] * _gaussian_moment(rest[:j] + rest[j + 1:], S)
+    return acc
+
+
+@pytest.mark.parametrize("lat", [L.D2Q9, L.D3Q27])
+def test_fp_fluid_high_orders_are_gaussian_moments(lat):
+    """FP (Sec. 4.1): the attractors above second order are the moments of the
+    stationary solution of a Fokker-Planck equation with constant diffusion
+    tensor D' = kappa~_2 / rho, a centred Gaussian.  With unit rates above
+    second order and no force, every post-collision central moment of order
+    3-6 is therefore rho times the Gaussian moment given by Isserlis' theorem
+    (odd orders vanish; e.g. kappa~_220 = rho (S_xx S_yy + 2 S_xy^2) and
+    kappa~_222 = rho (S_xx S_yy S_zz + 2 (S_xx S_yz^2 + S_yy S_xz^2 + S_zz S_xy^2)
+    + 8 S_xy S_xz S_yz)), a closed form independent of the recurrence that the
+    oracle evaluates.  The second-order rates are off 1 (the viscous slots and
+    the bulk / trace slot), so the covariance is not the isotropic c_s^2 I."""
+    f = _rand_state(lat, 25, 73, amp=0.1)
+    w = [1.0] * lat.Q
+    second = {3: 1.3, 4: 1.7, 5: 0.8} if lat.d == 2 else {4: 1.7, 5: 0.8, 6: 1.2, 7: 1.4, 8: 0.9, 9: 1.6}
+    for k, v in second.items():
+        w[k] = v
+    F = torch.zeros(25, lat.d, dtype=DT)
+    ft, rho, u = fluid_collide(f, F, lat, w, model="FP")
+    cm = _central(lat, ft, u)
+
+    def unit2(i, j):
+        m = [0] * lat.d
+        m[i] += 1
+        m[j] += 1
+        return tuple(m)
+
+    S = [[cm[unit2(i, j)] / rho for j in range(lat.d)] for i in range(lat.d)]
+    # the second order is not isotropic: the check is not the unit-rate equilibrium
+    assert float((S[0][1]).abs().max()) > 1e-4
+    checked = 0
+    for m in lat.M:
+        if sum(m) < 3:
+            continue
+        axes = [i for i in range(lat.d) for _ in range(m[i])]
+        ref = rho * _gaussian_moment(axes, S)
+        assert torch.allclose(cm[m], ref, atol=1e-15, rtol=1e-12), m
+        checked += 1
+    assert checked == (3 if lat.d == 2 else 17)
+
+
+@pytest.mark.parametrize("lat", [L.D2Q9_T, L.D3Q15_T])
+def test_thermal_option_b_high_orders_are_gaussian_moments(lat):
+    """Thermal option B (Sec. 4.4, 5.4): the attractors above second order use
+    D'_ab = eta~_ab / T, so with unit rates on the first order and above second
+    order the post-collision moments of order >= 3 are T times the moments of a
+    centred Gaussian of covariance eta~_2 / T (Isserlis' theorem: the odd
+    members vanish, eta~_22 = T (S_xx S_yy + 2 S_xy^2)), on D2Q9 and on the
+    D3Q15 set (120, 012, 201, 111, 220)."""
+    g = torch.Generator().manual_seed(75)
+    n = 25
+    c2 = 0.3
+    w = rest_weights(lat, thermal=True, cs2=c2)
+    T0 = 1.5 + 0.2 * torch.rand(n, generator=g, dtype=DT)
+    gin = T0[:, None] * w[None, :] * (1.0 + 0.2 * (torch.rand(n, lat.Q, generator=g, dtype=DT) - 0.5))
+    u = (torch.rand(n, lat.d, generator=g, dtype=DT) - 0.5) * 0.1
+    om = [1.0] * lat.Q
+    second = [k for k, m in enumerate(lat.M) if sum(m) == 2]
+    for i, k in enumerate(second):
+        om[k] = 0.6 + 0.25 * i  # never 1
+    gt, T = thermal_collide(gin, u, lat, om, c2, option="B", model="FP")
+    cm = _central(lat, gt, u)
+
+    def unit2(i, j):
+        m = [0] * lat.d
+        m[i] += 1
+        m[j] += 1
+        return tuple(m)
+
+    S = [[cm[unit2(i, j)] / T for j in range(lat.d)] for i in range(lat.d)]
+    assert float((S[0][1]).abs().max()) > 1e-4
+    checked = 0
+    for m in lat.M:
+        if sum(m) < 3:
+            continue
+        axes = [i for i in range(lat.d) for _ in range(m[i])]
+        assert torch.allclose(cm[m], T * _gaussian_moment(axes, S), atol=1e-15, rtol=1e-12), m
+        checked += 1
+    assert checked == (3 if lat.d == 2 else 5)
 
 
 @pytest.mark.parametrize("lat", [L.D2Q9_T, L.D3Q15_T])
