@@ -18,7 +18,8 @@
 //      kinetic energy 1/2 rho |u|^2),
 //   5. back-propagate through the collision (fpc_adjoint.h): mu_{n-1}(x),
 //      stored in x's own tile, and the Dirichlet wall temperature of each of
-//      x's own Dirichlet links receives 2 w^T_a = c^_s^2 times its adjoint.
+//      x's own Dirichlet links receives 2 w^T_a times its adjoint (see
+//      theta_link).
 // Every access of a node is a run of its own tile (stores) or a pulled run
 // (loads), as in the forward step; each wall-temperature gradient entry has a
 // single owner thread per launch.
