@@ -259,7 +259,7 @@ int launch_update(fpc_sim* s, const void* src, void* dst, const double* T_init, 
 }
 
 // Single-launch multi-step path (step_multi_kernel): grids of at most
-// kMultiMaxWork blocks of 256 threads, the D2Q5 / D3Q7 pairs in 2D (either
+// kMultiMaxWork blocks of 256 threads, every lattice pair in 2D (either
 // precision) and 3D FP32, the standard rate set and states below the
 // non-temporal threshold.  The working blocks share one XCD, so the limit is
 // low: at 64 blocks (a 128^2 grid) the single XCD made a step slower (5.1 us)

@@ -13,7 +13,8 @@
 //    (Eq. sourceCM2D, Sec. 5.2);
 //  * thermal (option A, Eq. Dij2D_goptionA): eta~_0 = T, first order relaxed
 //    toward 0, second order toward c^_s^2 T (App. B / App. C Step 3), on the
-//    D2Q5 / D3Q7 moment sets.
+//    D2Q5 / D3Q7 moment sets; the paper's D2Q9 / D3Q15 thermal lattices, with
+//    option A or B and the MCM comparator above second order, further below.
 //
 // GPU design (not the paper's):
 //  * The raw -> central map F(u) P and its inverse are applied as products of
@@ -164,7 +165,8 @@ __device__ __forceinline__ R rho_ref(const CollParams<R>& c) {
 
 
 // ---------------------------------------------------------------------------
-// The paper's thermal lattices, on plain populations (FP64 storage):
+// The paper's thermal lattices, on plain populations (FP64 storage) or on
+// the deviations g - w^T Tr (FP32 storage, see thermal_d2q9):
 // D2Q9 (Sec. 4.3-4.4, App. B) and D3Q15 (Sec. 5.3-5.4, App. C).
 // Higher-order attractors (Eq. Mvcmattractor2D_g with Eq. Dij2D_goptionA /
 // Dij2D_g, and their 3D forms): option A uses c^_s^2 I at every order, option

@@ -151,8 +151,9 @@ hipError_t launch_step2d(const StepArgs<R>& a, int up, int tk, const double* T_i
 template <class R>
 hipError_t launch_step3d(const StepArgs<R>& a, int up, int tk, const double* T_init, int mode, hipStream_t s);
 
-// Several steps in one cooperative launch (small grids, D2Q5 / D3Q7 pairs,
-// standard rate set, state below the non-temporal threshold): see
+// Several steps in one cooperative launch (small grids, every lattice pair in
+// 2D and in 3D FP32, standard rate set, state below the non-temporal
+// threshold): see
 // step_multi_kernel in fpc_step.hip.  The host fills everything but nwork,
 // which the launcher sets.
 struct MultiCtl {
