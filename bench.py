@@ -632,6 +632,17 @@ def main():
                                                                   pair="D2Q9-D2Q9")
         extra["rb3d_128_f32dev_D3Q15thermal"] = time_workload("rb3d_128", "f32dev", n3, w3, pair="D3Q27-D3Q15")
         extra["rb2d_1024x512_f64_MCM"] = time_workload("rb2d_1024x512", "f64", n2, w2, model="MCM")
+        # context, not a target: the paper's only performance figure is its
+        # C++/MPI code on 512 CPU cores for a 128^3 D3Q27 + D3Q15 run, 5e6
+        # steps in about 30.7 h (Sec. 6.2), i.e. about 94.9 MLUPS
+        r15 = extra["rb3d_128_f64_D3Q15thermal"]
+        extra["paper_cpu_cluster_context_128cube_D3Q15"] = {
+            "paper_mlups_512_cores": 2097152 * 5e6 / (30.7 * 3600) / 1e6,
+            "this_gpu_mlups_f64": r15["mlups"],
+            "this_gpu_mlups_f32dev": extra["rb3d_128_f32dev_D3Q15thermal"]["mlups"],
+            "ratio_f64": r15["mlups"] / (2097152 * 5e6 / (30.7 * 3600) / 1e6),
+            "note": "other hardware and precision not stated in the paper; context only",
+        }
         # the wall-Nusselt objective accumulated during the forward run of the
         # lid-driven cavity's J window (steps 5000-10000)
         extra["objective_forward_mixed2d_512"] = objective_cost("mixed2d_512", 5001)
