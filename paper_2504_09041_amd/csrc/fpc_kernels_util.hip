@@ -142,24 +142,57 @@ __device__ double block_reduce(double v, double* sh, int op) {
 }
 
 // Stage 1 over nodes: partials[b * 4 + (KE, sumT, umax, nonfinite)].  A
-// fixed number of blocks (a function of N only) strides over the nodes, so
+// fixed number of blocks (a function of N only) strides over the storage
+// tiles, one wavefront per 64-node tile (its loads are the tile's runs), so
 // the partials fit a fixed scratch size for every grid and the summation
-// order is the same on every call.
-template <class R>
+// order is the same on every call.  LAT: the lattice pair code (compile-time
+// link vectors and population counts).
+template <class R, int LAT>
 __global__ void __launch_bounds__(kBlock) diag_nodes_kernel(StateDesc d, double* partials) {
+  constexpr bool k2d = LAT == 1 || LAT == 3;
+  constexpr int QF = k2d ? kQ2 : kQ3;
+  constexpr int QG = LAT == 1 ? kQ2T : (LAT == 2 ? kQ3T : (LAT == 3 ? kQ2 : kQ15));
+  constexpr int Q = QF + QG;
+  constexpr int kWaves = kBlock / 64;
   __shared__ double sh[kBlock];
-  const size_t N = (size_t)d.nx * d.ny * d.nz;
-  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  const int lane = (int)(threadIdx.x & 63);
+  const size_t tiles_x = (size_t)d.nxp / 64;
+  const size_t ntiles = tiles_x * d.ny * d.nz;
+  const size_t wstride = (size_t)gridDim.x * kWaves;
+  const R* src = static_cast<const R*>(d.src);
   double ke = 0.0, st = 0.0, um = 0.0, bad = 0.0;
-  for (size_t node = (size_t)blockIdx.x * blockDim.x + threadIdx.x; node < N; node += stride) {
-    double r, u[3], t;
-    node_macros<R>(d, node, r, u, t);
-    const double u2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-    if (!isfinite(r) || !isfinite(t) || !isfinite(u2)) {
+  for (size_t t = (size_t)blockIdx.x * kWaves + (threadIdx.x >> 6); t < ntiles; t += wstride) {
+    const size_t row = t / tiles_x;  // z ny + y
+    const int x = (int)(t - row * tiles_x) * 64 + lane;
+    if (x >= d.nx) continue;  // padding node
+    const int y = (int)(row % (size_t)d.ny), z = (int)(row / (size_t)d.ny);
+    const R* p = src + t * (size_t)Q * 64 + lane;
+    // the macros of node_macros, in the same order
+    double s = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll
+    for (int q = 0; q < QF; ++q) {
+      const double v = (double)p[(size_t)q * 64];
+      s += v;
+      jx += (k2d ? D2_EX[q] : D3_EX[q]) * v;
+      jy += (k2d ? D2_EY[q] : D3_EY[q]) * v;
+      jz += (k2d ? 0 : D3_EZ[q]) * v;
+    }
+    double tt = 0.0;
+#pragma unroll
+    for (int q = 0; q < QG; ++q) tt += (double)p[(size_t)(QF + q) * 64];
+    const double r = d.rho_r + s;
+    const double T = (d.T_o + (d.Tg[0] * (double)x + d.Tg[1] * (double)y + d.Tg[2] * (double)z)) + tt;
+    const double Fb = d.gbeta * (T - d.T0);
+    const double ir = 1.0 / r;
+    const double ux = (jx - (d.up == 0 ? 0.5 * Fb : 0.0)) * ir;
+    const double uy = (jy - (d.up == 1 ? 0.5 * Fb : 0.0)) * ir;
+    const double uz = (jz - (d.up == 2 ? 0.5 * Fb : 0.0)) * ir;
+    const double u2 = ux * ux + uy * uy + uz * uz;
+    if (!isfinite(r) || !isfinite(T) || !isfinite(u2)) {
       bad += 1.0;
     } else {
       ke += 0.5 * r * u2;
-      st += t;
+      st += T;
       um = fmax(um, sqrt(u2));
     }
   }
@@ -172,6 +205,16 @@ __global__ void __launch_bounds__(kBlock) diag_nodes_kernel(StateDesc d, double*
     partials[blockIdx.x * 4 + 1] = st;
     partials[blockIdx.x * 4 + 2] = um;
     partials[blockIdx.x * 4 + 3] = bad;
+  }
+}
+
+template <class R>
+void launch_diag_nodes(const StateDesc& d, unsigned nb, double* partials, hipStream_t s) {
+  switch (d.lattice) {
+    case 1: diag_nodes_kernel<R, 1><<<nb, kBlock, 0, s>>>(d, partials); break;
+    case 2: diag_nodes_kernel<R, 2><<<nb, kBlock, 0, s>>>(d, partials); break;
+    case 3: diag_nodes_kernel<R, 3><<<nb, kBlock, 0, s>>>(d, partials); break;
+    default: diag_nodes_kernel<R, 4><<<nb, kBlock, 0, s>>>(d, partials); break;
   }
 }
 
@@ -397,9 +440,9 @@ hipError_t launch_diagnostics(const StateDesc& d, int face, const FaceDev& fd, d
   unsigned nf = 0;
   double inv_m = 0.0;
   if (d.precision == 0)
-    diag_nodes_kernel<double><<<nb, kBlock, 0, s>>>(d, scratch);
+    launch_diag_nodes<double>(d, nb, scratch, s);
   else
-    diag_nodes_kernel<float><<<nb, kBlock, 0, s>>>(d, scratch);
+    launch_diag_nodes<float>(d, nb, scratch, s);
   if (face >= 0) {
     nf = diag_face_blocks(d, face);
     inv_m = 1.0 / (double)face_nodes(d, face);
