@@ -62,23 +62,56 @@ __device__ __forceinline__ double ld(const StateDesc& d, int q, size_t node) {
   return (double)static_cast<const R*>(d.src)[slot(d, q, node)];
 }
 
-// FP64 macros of one node (rho, u[3], T).
-template <class R>
-__device__ void node_macros(const StateDesc& d, size_t node, double& rho, double u[3], double& T) {
-  const int Qf = qf_of(d.lattice);
-  const int Qg = qg_of(d.lattice);
+// Compile-time lattice pair (code LAT as in StateDesc::lattice).
+template <int LAT>
+struct Pair {
+  static constexpr bool k2d = LAT == 1 || LAT == 3;
+  static constexpr int QF = k2d ? kQ2 : kQ3;
+  static constexpr int QG = LAT == 1 ? kQ2T : (LAT == 2 ? kQ3T : (LAT == 3 ? kQ2 : kQ15));
+  static constexpr int Q = QF + QG;
+  static constexpr int ex(int q) { return k2d ? D2_EX[q] : D3_EX[q]; }
+  static constexpr int ey(int q) { return k2d ? D2_EY[q] : D3_EY[q]; }
+  static constexpr int ez(int q) { return k2d ? 0 : D3_EZ[q]; }
+};
+
+// Padded node n of the storage layout: its coordinates and unpadded index
+// (z ny + y) nx + x; false for a padding node (x >= nx).
+__device__ __forceinline__ bool tile_node(const StateDesc& d, size_t n, int& x, int& y, int& z, size_t& node) {
+  const size_t row = n / (size_t)d.nxp;  // z ny + y
+  x = (int)(n - row * (size_t)d.nxp);
+  if (x >= d.nx) return false;
+  y = (int)(row % (size_t)d.ny);
+  z = (int)(row / (size_t)d.ny);
+  node = row * (size_t)d.nx + (size_t)x;
+  return true;
+}
+
+// First element of padded node n's populations (population q at q * 64).
+template <class R, int LAT>
+__device__ __forceinline__ size_t tile_base(size_t n) {
+  return (n >> 6) * (size_t)Pair<LAT>::Q * 64 + (n & 63);
+}
+
+// FP64 macros of one node (rho, u[3], T) from its stored populations p[q * 64]:
+// rho = rho_r + sum f, T = Tr(x) + sum g, rho u = sum f e - F/2.
+template <class R, int LAT>
+__device__ __forceinline__ void node_macros(const StateDesc& d, const R* p, int x, int y, int z, double& rho,
+                                            double u[3], double& T) {
+  using P = Pair<LAT>;
   double s = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
-  for (int q = 0; q < Qf; ++q) {
-    const double v = ld<R>(d, q, node);
+#pragma unroll
+  for (int q = 0; q < P::QF; ++q) {
+    const double v = (double)p[(size_t)q * 64];
     s += v;
-    jx += ex_of(d.lattice, q) * v;
-    jy += ey_of(d.lattice, q) * v;
-    jz += ez_of(d.lattice, q) * v;
+    jx += P::ex(q) * v;
+    jy += P::ey(q) * v;
+    jz += P::ez(q) * v;
   }
   double t = 0.0;
-  for (int q = 0; q < Qg; ++q) t += ld<R>(d, Qf + q, node);
+#pragma unroll
+  for (int q = 0; q < P::QG; ++q) t += (double)p[(size_t)(P::QF + q) * 64];
   rho = d.rho_r + s;
-  T = tref_node(d, node) + t;
+  T = (d.T_o + (d.Tg[0] * (double)x + d.Tg[1] * (double)y + d.Tg[2] * (double)z)) + t;
   const double Fb = d.gbeta * (T - d.T0);
   const double ir = 1.0 / rho;
   u[0] = (jx - (d.up == 0 ? 0.5 * Fb : 0.0)) * ir;
@@ -86,45 +119,58 @@ __device__ void node_macros(const StateDesc& d, size_t node, double& rho, double
   u[2] = (jz - (d.up == 2 ? 0.5 * Fb : 0.0)) * ir;
 }
 
-template <class R>
+// One thread per padded node of the storage layout (consecutive lanes read
+// and write consecutive elements of a tile's runs).
+template <class R, int LAT>
 __global__ void __launch_bounds__(kBlock) macros_kernel(StateDesc d, double* rho, double* u, double* T) {
+  const size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const size_t N = (size_t)d.nx * d.ny * d.nz;
-  const size_t node = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (node >= N) return;
+  int x, y, z;
+  size_t node;
+  if (n >= (size_t)d.nxp * d.ny * d.nz || !tile_node(d, n, x, y, z, node)) return;
   double r, uu[3], t;
-  node_macros<R>(d, node, r, uu, t);
+  node_macros<R, LAT>(d, static_cast<const R*>(d.src) + tile_base<R, LAT>(n), x, y, z, r, uu, t);
   if (rho) rho[node] = r;
   if (T) T[node] = t;
   if (u) {
-    const int dim = is2d(d.lattice) ? 2 : 3;
+    constexpr int dim = Pair<LAT>::k2d ? 2 : 3;
+#pragma unroll
     for (int i = 0; i < dim; ++i) u[i * N + node] = uu[i];
   }
 }
 
-template <class R>
+template <class R, int LAT>
 __global__ void __launch_bounds__(kBlock) export_kernel(StateDesc d, double* dst) {
+  using P = Pair<LAT>;
+  const size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const size_t N = (size_t)d.nx * d.ny * d.nz;
-  const size_t node = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (node >= N) return;
-  const int Qf = qf_of(d.lattice);
-  const int Qg = qg_of(d.lattice);
-  for (int q = 0; q < Qf; ++q) dst[q * N + node] = ld<R>(d, q, node) + wfluid(d.lattice, q) * d.rho_r;
-  const double tr = tref_node(d, node);
-  for (int q = 0; q < Qg; ++q)
-    dst[(Qf + q) * N + node] = ld<R>(d, Qf + q, node) + wtherm(d.lattice, d.cs2T, q) * tr;
+  int x, y, z;
+  size_t node;
+  if (n >= (size_t)d.nxp * d.ny * d.nz || !tile_node(d, n, x, y, z, node)) return;
+  const R* p = static_cast<const R*>(d.src) + tile_base<R, LAT>(n);
+#pragma unroll
+  for (int q = 0; q < P::QF; ++q) dst[q * N + node] = (double)p[(size_t)q * 64] + wfluid(LAT, q) * d.rho_r;
+  const double tr = d.T_o + (d.Tg[0] * (double)x + d.Tg[1] * (double)y + d.Tg[2] * (double)z);
+#pragma unroll
+  for (int q = 0; q < P::QG; ++q)
+    dst[(P::QF + q) * N + node] = (double)p[(size_t)(P::QF + q) * 64] + wtherm(LAT, d.cs2T, q) * tr;
 }
 
-template <class R>
+template <class R, int LAT>
 __global__ void __launch_bounds__(kBlock) import_kernel(StateDesc d, R* out, const double* src) {
+  using P = Pair<LAT>;
+  const size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const size_t N = (size_t)d.nx * d.ny * d.nz;
-  const size_t node = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (node >= N) return;
-  const int Qf = qf_of(d.lattice);
-  const int Qg = qg_of(d.lattice);
-  for (int q = 0; q < Qf; ++q) out[slot(d, q, node)] = (R)(src[q * N + node] - wfluid(d.lattice, q) * d.rho_r);
-  const double tr = tref_node(d, node);
-  for (int q = 0; q < Qg; ++q)
-    out[slot(d, Qf + q, node)] = (R)(src[(Qf + q) * N + node] - wtherm(d.lattice, d.cs2T, q) * tr);
+  int x, y, z;
+  size_t node;
+  if (n >= (size_t)d.nxp * d.ny * d.nz || !tile_node(d, n, x, y, z, node)) return;
+  R* p = out + tile_base<R, LAT>(n);
+#pragma unroll
+  for (int q = 0; q < P::QF; ++q) p[(size_t)q * 64] = (R)(src[q * N + node] - wfluid(LAT, q) * d.rho_r);
+  const double tr = d.T_o + (d.Tg[0] * (double)x + d.Tg[1] * (double)y + d.Tg[2] * (double)z);
+#pragma unroll
+  for (int q = 0; q < P::QG; ++q)
+    p[(size_t)(P::QF + q) * 64] = (R)(src[(P::QF + q) * N + node] - wtherm(LAT, d.cs2T, q) * tr);
 }
 
 // Deterministic block reduction: sum (op 0) or max (op 1) over kBlock values.
@@ -149,10 +195,7 @@ __device__ double block_reduce(double v, double* sh, int op) {
 // link vectors and population counts).
 template <class R, int LAT>
 __global__ void __launch_bounds__(kBlock) diag_nodes_kernel(StateDesc d, double* partials) {
-  constexpr bool k2d = LAT == 1 || LAT == 3;
-  constexpr int QF = k2d ? kQ2 : kQ3;
-  constexpr int QG = LAT == 1 ? kQ2T : (LAT == 2 ? kQ3T : (LAT == 3 ? kQ2 : kQ15));
-  constexpr int Q = QF + QG;
+  constexpr int Q = Pair<LAT>::Q;
   constexpr int kWaves = kBlock / 64;
   __shared__ double sh[kBlock];
   const int lane = (int)(threadIdx.x & 63);
@@ -166,27 +209,9 @@ __global__ void __launch_bounds__(kBlock) diag_nodes_kernel(StateDesc d, double*
     const int x = (int)(t - row * tiles_x) * 64 + lane;
     if (x >= d.nx) continue;  // padding node
     const int y = (int)(row % (size_t)d.ny), z = (int)(row / (size_t)d.ny);
-    const R* p = src + t * (size_t)Q * 64 + lane;
-    // the macros of node_macros, in the same order
-    double s = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
-#pragma unroll
-    for (int q = 0; q < QF; ++q) {
-      const double v = (double)p[(size_t)q * 64];
-      s += v;
-      jx += (k2d ? D2_EX[q] : D3_EX[q]) * v;
-      jy += (k2d ? D2_EY[q] : D3_EY[q]) * v;
-      jz += (k2d ? 0 : D3_EZ[q]) * v;
-    }
-    double tt = 0.0;
-#pragma unroll
-    for (int q = 0; q < QG; ++q) tt += (double)p[(size_t)(QF + q) * 64];
-    const double r = d.rho_r + s;
-    const double T = (d.T_o + (d.Tg[0] * (double)x + d.Tg[1] * (double)y + d.Tg[2] * (double)z)) + tt;
-    const double Fb = d.gbeta * (T - d.T0);
-    const double ir = 1.0 / r;
-    const double ux = (jx - (d.up == 0 ? 0.5 * Fb : 0.0)) * ir;
-    const double uy = (jy - (d.up == 1 ? 0.5 * Fb : 0.0)) * ir;
-    const double uz = (jz - (d.up == 2 ? 0.5 * Fb : 0.0)) * ir;
+    double r, uu[3], T;
+    node_macros<R, LAT>(d, src + t * (size_t)Q * 64 + lane, x, y, z, r, uu, T);
+    const double ux = uu[0], uy = uu[1], uz = uu[2];
     const double u2 = ux * ux + uy * uy + uz * uz;
     if (!isfinite(r) || !isfinite(T) || !isfinite(u2)) {
       bad += 1.0;
@@ -399,39 +424,50 @@ unsigned diag_face_blocks(const StateDesc& d, int face) {
   return (unsigned)(b < kDiagFaceBlocks ? b : kDiagFaceBlocks);
 }
 
-size_t node_blocks(const StateDesc& d) {
-  const size_t N = (size_t)d.nx * d.ny * d.nz;
-  return (N + kBlock - 1) / kBlock;
-}
-
 }  // namespace
 
+namespace {
+// blocks of kBlock threads over the padded nodes of the storage layout
+unsigned padded_blocks(const StateDesc& d) {
+  return (unsigned)(((size_t)d.nxp * d.ny * d.nz + kBlock - 1) / kBlock);
+}
+}  // namespace
+
+#define FPC_BY_LATTICE(KERNEL, R, ...)                                                          \
+  switch (d.lattice) {                                                                          \
+    case 1: KERNEL<R, 1><<<padded_blocks(d), kBlock, 0, s>>>(__VA_ARGS__); break;              \
+    case 2: KERNEL<R, 2><<<padded_blocks(d), kBlock, 0, s>>>(__VA_ARGS__); break;              \
+    case 3: KERNEL<R, 3><<<padded_blocks(d), kBlock, 0, s>>>(__VA_ARGS__); break;              \
+    default: KERNEL<R, 4><<<padded_blocks(d), kBlock, 0, s>>>(__VA_ARGS__); break;             \
+  }
+
 hipError_t launch_macros(const StateDesc& d, double* rho, double* u, double* T, hipStream_t s) {
-  const unsigned nb = (unsigned)node_blocks(d);
-  if (d.precision == 0)
-    macros_kernel<double><<<nb, kBlock, 0, s>>>(d, rho, u, T);
-  else
-    macros_kernel<float><<<nb, kBlock, 0, s>>>(d, rho, u, T);
+  if (d.precision == 0) {
+    FPC_BY_LATTICE(macros_kernel, double, d, rho, u, T)
+  } else {
+    FPC_BY_LATTICE(macros_kernel, float, d, rho, u, T)
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_export(const StateDesc& d, double* dst, hipStream_t s) {
-  const unsigned nb = (unsigned)node_blocks(d);
-  if (d.precision == 0)
-    export_kernel<double><<<nb, kBlock, 0, s>>>(d, dst);
-  else
-    export_kernel<float><<<nb, kBlock, 0, s>>>(d, dst);
+  if (d.precision == 0) {
+    FPC_BY_LATTICE(export_kernel, double, d, dst)
+  } else {
+    FPC_BY_LATTICE(export_kernel, float, d, dst)
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_import(const StateDesc& d, void* dst, const double* src, hipStream_t s) {
-  const unsigned nb = (unsigned)node_blocks(d);
-  if (d.precision == 0)
-    import_kernel<double><<<nb, kBlock, 0, s>>>(d, static_cast<double*>(dst), src);
-  else
-    import_kernel<float><<<nb, kBlock, 0, s>>>(d, static_cast<float*>(dst), src);
+  if (d.precision == 0) {
+    FPC_BY_LATTICE(import_kernel, double, d, static_cast<double*>(dst), src)
+  } else {
+    FPC_BY_LATTICE(import_kernel, float, d, static_cast<float*>(dst), src)
+  }
   return hipGetLastError();
 }
+#undef FPC_BY_LATTICE
 
 hipError_t launch_diagnostics(const StateDesc& d, int face, const FaceDev& fd, double dT_ref, double* scratch,
                               double* out, hipStream_t s) {
