@@ -69,7 +69,7 @@ def _profile_shape(cfg, face):
 @pytest.mark.parametrize("case", ["dhc2d", "rb2d", "mixed2d", "rb2d_tiles", "box2d",
                                   "dhc3d", "rb3d", "lid3d", "dhc3d_tiles", "box3d"])
 @pytest.mark.parametrize("model,opt", MODELS)
-@pytest.mark.parametrize("precision,tol", [("f64", 1e-12), ("f32dev", 2e-5)])
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-12), ("f32dev", 2e-5), ("f32uni", 2e-5)])
 def test_adjoint_step_matches_oracle_vjp(case, model, opt, precision, tol):
     from paper_2504_09041_amd import _abi as A
 
