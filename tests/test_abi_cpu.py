@@ -33,6 +33,17 @@ def test_header_declares_binding_names():
     assert declared_functions() == sorted(A.EXPORTED)
 
 
+def test_build_compiles_every_hip_source():
+    """Every HIP translation unit of the package is in the build (the adjoint
+    kernels are split over several files that compile in parallel)."""
+    from paper_2504_09041_amd import build as B
+
+    on_disk = sorted(f for f in os.listdir(B.CSRC) if f.endswith(".hip"))
+    assert sorted(B.SOURCES) == on_disk
+    for f in ("fpc_adjoint.hip", "fpc_adjoint_d2q9.hip", "fpc_adjoint_d3q15.hip"):
+        assert "-fno-honor-nans" in B.SOURCE_FLAGS[f]
+
+
 def test_library_exports_every_declared_symbol():
     lib = _lib()
     for name in declared_functions():
