@@ -185,32 +185,41 @@ def test_checkpointed_gradient_matches_oracle_autograd(case, kind, face, window,
     assert e2 < 1e-10
 
 
-def test_d3q15_gradient_matches_central_differences():
-    """3D Rayleigh-Benard at 32^3 on the paper's D3Q15 thermal lattice (FP64,
-    option A): J = kinetic energy at step 200, gradient with respect to the
-    whole initial temperature field through the checkpointed sweep (K = 14),
-    against central differences of the GPU forward run along 4 seeded unit
-    directions (1e-6 relative at the best step h) -- a size the oracle's
+@pytest.mark.parametrize("wl,shape,pair,N,K", [
+    ("rb3d_128", (32, 32, 32), "D3Q27-D3Q15", 200, 14),
+    ("rb2d_1024x512", (128, 64, 1), "D2Q9-D2Q9", 300, 17),
+])
+def test_gradient_matches_central_differences(wl, shape, pair, N, K):
+    """Rayleigh-Benard at 32^3 on the paper's D3Q15 thermal lattice and at
+    128 x 64 on its D2Q9 one (FP64, option A): J = kinetic energy at step N,
+    gradient with respect to the whole initial temperature field through the
+    checkpointed sweep, against central differences of the GPU forward run
+    along 4 seeded unit directions (1e-6 relative at the best step h, against
+    at least a tenth of the typical |grad| / sqrt(n)) -- sizes the oracle's
     autograd does not reach."""
     from paper_2504_09041_amd import adjoint as adj
     from paper_2504_09041_amd.sim import params_from_workload
 
-    cfg = workloads.config("rb3d_128", shape=(32, 32, 32), pair="D3Q27-D3Q15")
-    N, K = 200, 14
+    print(f"{wl} {shape} {pair} N={N} K={K}", flush=True)
+    cfg = workloads.config(wl, shape=shape, pair=pair)
     T0 = G.initial_T(cfg).cuda()
     s = adj.AdjointSolver(params_from_workload(cfg, "f64"), N, K, adj.KineticEnergy(N))
     J = s.forward(None, T0)
     _, gT = s.backward()
     dirs = torch.tensor(workloads.unit_directions(T0.numel(), 4, seed0=400)).cuda()
+    # a random unit direction has a directional derivative of about
+    # |grad| / sqrt(n); one far below that is made of cancelling terms, so
+    # errors are measured against at least a tenth of it
+    floor = 0.1 * float(gT.norm()) / T0.numel() ** 0.5
     worst = 0.0
     for i in range(dirs.shape[0]):
         d = dirs[i].reshape(gT.shape)
         an = float((gT * d).sum())
         best = float("inf")
-        for h in (1e-1, 3e-2, 1e-2, 3e-3):
+        for h in (1e-1, 3e-2, 1e-2, 3e-3, 1e-3, 3e-4):
             fd = (s.forward(None, T0 + h * d) - s.forward(None, T0 - h * d)) / (2 * h)
-            best = min(best, abs(fd - an) / max(abs(an), 1e-30))
-        print(f"  direction {i}: dJ {an:.6e}, best relative error {best:.2e}", flush=True)
+            best = min(best, abs(fd - an) / max(abs(an), floor))
+        print(f"  direction {i}: dJ {an:.6e} (floor {floor:.3e}), best relative error {best:.2e}", flush=True)
         worst = max(worst, best)
     print(f"J {J:.6e}; worst directional relative error {worst:.2e}")
     assert worst < 1e-6
