@@ -106,7 +106,8 @@ def kernel_fingerprint(kind="step"):
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2504_09041_amd", "csrc")
     common = ("fpc_gather.h", "fpc_collide.h", "fpc_kernels.h", "fpc_lattice.h")
-    own = ("fpc_step.hip",) if kind == "step" else ("fpc_adjoint.hip", "fpc_adjoint_kernels.h", "fpc_adjoint.h")
+    own = ("fpc_step.hip",) if kind == "step" else ("fpc_adjoint.hip", "fpc_adjoint_d3q7.hip", "fpc_adjoint_kernels.h",
+                                                     "fpc_adjoint.h")
     for name in own + common:
         with open(os.path.join(csrc, name), "rb") as fh:
             h.update(name.encode() + b"\0" + fh.read())

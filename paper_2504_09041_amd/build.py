@@ -18,8 +18,11 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libfpclbm.so")
 # longest compiles first: they run in parallel
-SOURCES = ["fpc_adjoint_d3q15.hip", "fpc_step.hip", "fpc_adjoint.hip", "fpc_adjoint_d2q9.hip", "fpc_kernels_util.hip",
-           "fpc_abi.hip"]
+SOURCES = ["fpc_adjoint_d3q15.hip", "fpc_adjoint_d3q7.hip", "fpc_step.hip", "fpc_adjoint.hip", "fpc_adjoint_d2q9.hip",
+           "fpc_kernels_util.hip", "fpc_abi.hip"]
+# Sources compiled once per storage precision (FPC_ADJ_REAL), one object
+# each: the 3D adjoint kernels are the longest compiles by far.
+PER_PRECISION = {"fpc_adjoint_d3q15.hip", "fpc_adjoint_d3q7.hip"}
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [
@@ -44,6 +47,7 @@ HIPCC_FLAGS = [
 _FINITE = ["-fno-honor-nans", "-fno-honor-infinities", "-fno-signed-zeros"]
 SOURCE_FLAGS = {
     "fpc_adjoint.hip": _FINITE,
+    "fpc_adjoint_d3q7.hip": _FINITE,
     "fpc_adjoint_d2q9.hip": _FINITE,
     "fpc_adjoint_d3q15.hip": _FINITE,
 }
@@ -56,10 +60,23 @@ def hipcc():
     raise RuntimeError("hipcc not found (ROCm toolchain required to build libfpclbm.so)")
 
 
-def _compile(src, extra, verbose):
-    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [hipcc(), *HIPCC_FLAGS, *SOURCE_FLAGS.get(src, []), *extra, "-I", CSRC, "-c", os.path.join(CSRC, src),
-           "-o", obj]
+def _units():
+    """(source, object name, defines) of every compile, longest first."""
+    units = []
+    for src in SOURCES:
+        base = os.path.splitext(src)[0]
+        if src in PER_PRECISION:
+            units += [(src, f"{base}_{r}.o", [f"-DFPC_ADJ_REAL={r}"]) for r in ("double", "float")]
+        else:
+            units.append((src, base + ".o", []))
+    return units
+
+
+def _compile(unit, extra, verbose):
+    src, name, defines = unit
+    obj = os.path.join(BUILD, name)
+    cmd = [hipcc(), *HIPCC_FLAGS, *SOURCE_FLAGS.get(src, []), *defines, *extra, "-I", CSRC, "-c",
+           os.path.join(CSRC, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -72,8 +89,9 @@ def _compile(src, extra, verbose):
 
 def build_library(verbose=False, extra_flags=()):
     os.makedirs(BUILD, exist_ok=True)
-    with concurrent.futures.ThreadPoolExecutor(max_workers=min(6, len(SOURCES))) as ex:
-        objs = list(ex.map(lambda s: _compile(s, list(extra_flags), verbose), SOURCES))
+    units = _units()
+    with concurrent.futures.ThreadPoolExecutor(max_workers=min(8, len(units))) as ex:
+        objs = list(ex.map(lambda u: _compile(u, list(extra_flags), verbose), units))
     tmp = LIB + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     if verbose:

@@ -1,6 +1,7 @@
 // Adjoint stream-collide step and adjoint of the initial collision: the
-// launchers of the C ABI, and the kernels of the D2Q5 / D3Q7 pairs (the
-// kernels themselves: fpc_adjoint_kernels.h).
+// launchers of the C ABI, and the kernels of the D2Q9 + D2Q5 pair (the
+// kernels themselves: fpc_adjoint_kernels.h; the other pairs are instantiated
+// in fpc_adjoint_d3q7.hip, fpc_adjoint_d2q9.hip and fpc_adjoint_d3q15.hip).
 #include "fpc_adjoint_kernels.h"
 
 namespace fpc {
@@ -11,10 +12,8 @@ namespace {
 template <class R>
 hipError_t dispatch(int dim, int up, int tk, const AdjArgs<R>* step, const AdjInitArgs<R>* init, hipStream_t st) {
   if (tk == 1) return dim == 2 ? launch_adj_d2q9<R>(up, step, init, st) : launch_adj_d3q15<R>(up, step, init, st);
-  if (dim == 2) return up == 0 ? launch_adj<Lat2, R, 0>(step, init, st) : launch_adj<Lat2, R, 1>(step, init, st);
-  if (up == 0) return launch_adj<Lat3, R, 0>(step, init, st);
-  if (up == 1) return launch_adj<Lat3, R, 1>(step, init, st);
-  return launch_adj<Lat3, R, 2>(step, init, st);
+  if (dim == 3) return launch_adj_d3q7<R>(up, step, init, st);
+  return up == 0 ? launch_adj<Lat2, R, 0>(step, init, st) : launch_adj<Lat2, R, 1>(step, init, st);
 }
 
 }  // namespace

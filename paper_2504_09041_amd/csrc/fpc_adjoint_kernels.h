@@ -25,9 +25,10 @@
 // single owner thread per launch.
 //
 // The kernels and their launch for one lattice pair (launch_adj); each
-// group of lattice pairs is instantiated in a source file of its own
-// (fpc_adjoint.hip: D2Q5 / D3Q7; fpc_adjoint_d2q9.hip, fpc_adjoint_d3q15.hip:
-// the paper's thermal lattices), so that they compile in parallel.
+// lattice pair is instantiated in a source file of its own (fpc_adjoint.hip:
+// D2Q9 + D2Q5; fpc_adjoint_d3q7.hip; fpc_adjoint_d2q9.hip and
+// fpc_adjoint_d3q15.hip: the paper's thermal lattices), so that they compile
+// in parallel.
 #pragma once
 
 #include <type_traits>
@@ -350,7 +351,10 @@ hipError_t launch_adj(const AdjArgs<R>* step, const AdjInitArgs<R>* init, hipStr
   return hipGetLastError();
 }
 
-// Launchers of the paper's thermal lattices (one source file each).
+// Launchers of the D3Q27 + D3Q7 pair and of the paper's thermal lattices (one
+// source file each).
+template <class R>
+hipError_t launch_adj_d3q7(int up, const AdjArgs<R>* step, const AdjInitArgs<R>* init, hipStream_t st);
 template <class R>
 hipError_t launch_adj_d2q9(int up, const AdjArgs<R>* step, const AdjInitArgs<R>* init, hipStream_t st);
 template <class R>

@@ -40,8 +40,14 @@ def test_build_compiles_every_hip_source():
 
     on_disk = sorted(f for f in os.listdir(B.CSRC) if f.endswith(".hip"))
     assert sorted(B.SOURCES) == on_disk
-    for f in ("fpc_adjoint.hip", "fpc_adjoint_d2q9.hip", "fpc_adjoint_d3q15.hip"):
+    for f in ("fpc_adjoint.hip", "fpc_adjoint_d3q7.hip", "fpc_adjoint_d2q9.hip", "fpc_adjoint_d3q15.hip"):
         assert "-fno-honor-nans" in B.SOURCE_FLAGS[f]
+    # the per-precision sources yield one object per precision, all named apart
+    objs = [name for _, name, _ in B._units()]
+    assert len(objs) == len(set(objs)) == len(B.SOURCES) + len(B.PER_PRECISION)
+    for f in B.PER_PRECISION:
+        text = open(os.path.join(B.CSRC, f)).read()
+        assert "FPC_ADJ_REAL" in text
 
 
 def test_library_exports_every_declared_symbol():
