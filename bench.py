@@ -97,18 +97,24 @@ def copy_bandwidth(mib, reps):
             "GBs": nbytes / (ms * 1e-3) / 1e9}
 
 
+def fingerprint_sources(kind="step"):
+    """Source files of the step kernel (kind "step") or of the adjoint step
+    kernels whose counters are recorded (kind "adjoint": the D2Q9 + D2Q5 and
+    D3Q27 + D3Q7 pairs), with everything they include."""
+    common = ("fpc_gather.h", "fpc_collide.h", "fpc_kernels.h", "fpc_lattice.h")
+    own = ("fpc_step.hip",) if kind == "step" else ("fpc_adjoint.hip", "fpc_adjoint_d3q7.hip", "fpc_adjoint_kernels.h",
+                                                     "fpc_adjoint.h")
+    return own + common
+
+
 def kernel_fingerprint(kind="step"):
-    """sha256 over the sources of the step kernel (kind "step") or of the
-    adjoint step kernel (kind "adjoint"), everything they include: counters
-    recorded for other sources do not describe the kernel that runs."""
+    """sha256 over fingerprint_sources(kind): counters recorded for other
+    sources do not describe the kernel that runs."""
     import hashlib
 
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2504_09041_amd", "csrc")
-    common = ("fpc_gather.h", "fpc_collide.h", "fpc_kernels.h", "fpc_lattice.h")
-    own = ("fpc_step.hip",) if kind == "step" else ("fpc_adjoint.hip", "fpc_adjoint_d3q7.hip", "fpc_adjoint_kernels.h",
-                                                     "fpc_adjoint.h")
-    for name in own + common:
+    for name in fingerprint_sources(kind):
         with open(os.path.join(csrc, name), "rb") as fh:
             h.update(name.encode() + b"\0" + fh.read())
     return h.hexdigest()[:16]

@@ -50,6 +50,39 @@ def test_build_compiles_every_hip_source():
         assert "FPC_ADJ_REAL" in text
 
 
+def _local_includes(csrc, name, seen):
+    """Transitive closure of the package-local #include "..." of a source."""
+    if name in seen:
+        return seen
+    seen.add(name)
+    for inc in re.findall(r'^#include "([^"/]+)"', open(os.path.join(csrc, name)).read(), flags=re.M):
+        _local_includes(csrc, inc, seen)
+    return seen
+
+
+@pytest.mark.parametrize("kind,roots", [("step", ["fpc_step.hip"]),
+                                        ("adjoint", ["fpc_adjoint.hip", "fpc_adjoint_d3q7.hip"])])
+def test_counter_records_match_the_kernel_sources(kind, roots):
+    """The HBM-traffic records that the benchmark reports are fingerprinted by
+    the kernel's sources: the fingerprint covers every file those sources
+    include, and the committed records carry the fingerprint of the sources
+    in the tree (they were taken on this code)."""
+    import json
+
+    import bench
+    from paper_2504_09041_amd import build as B
+
+    covered = set(bench.fingerprint_sources(kind))
+    for root in roots:
+        assert _local_includes(B.CSRC, root, set()) <= covered
+    with open(os.path.join(ROOT, "profiles", "traffic.json")) as fh:
+        records = json.load(fh)
+    mine = [r for k, r in records.items() if k.startswith("adjoint_") == (kind == "adjoint")]
+    assert mine
+    for r in mine:
+        assert r["sources"] == bench.kernel_fingerprint(kind)
+
+
 def test_library_exports_every_declared_symbol():
     lib = _lib()
     for name in declared_functions():
